@@ -1,0 +1,139 @@
+/*
+ * FP64 CPU oracle for the energy-conserving (EC) electrostatic PIC/MCC step
+ * of Wang, Sun, Jiang & Kong, "On the energy conservation electrostatic
+ * PIC/MC simulating" (arXiv:1310.5284).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, obviously-correct
+ * restatement of the method used to check the GPU library.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark load it.
+ * It shares no code, header, table or constant with the GPU path.
+ *
+ * Every floating-point quantity is double precision.  Positions are kept as
+ * xi = x / dx (cell units, node g sits at xi = g, cell j spans [j, j+1)).
+ * Velocities are in m/s, fields in V/m, charge densities in C/m^3 and areal
+ * macro-particle weights in physical particles per macro-particle per m^2.
+ *
+ * Functions whose result is not pinned by an independent check say so in
+ * their comment ("parity unpinned").
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_DIRICHLET = 0, ORC_BC_PERIODIC = 1 };
+enum { ORC_EXPLICIT = 0, ORC_IMPLICIT = 1 };
+enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1 };
+enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONIZATION = 2, ORC_CHARGE_EXCHANGE = 3 };
+
+typedef struct {
+    int32_t n_cells;        /* N cells, N+1 nodes                                  */
+    int32_t bc;             /* ORC_BC_*                                            */
+    int32_t scheme;         /* ORC_EXPLICIT or ORC_IMPLICIT (D1, beta = 1/2)       */
+    int32_t gather;         /* ORC_GATHER_EC (Eq. 3) or ORC_GATHER_MC (CIC)        */
+    int32_t collisions;     /* 0 / 1                                               */
+    int32_t pad0;
+    double gap_m;           /* L                                                   */
+    double dt_s;
+    int64_t step0;          /* absolute index of the first step to take            */
+    double rf_volts;        /* V(t) = V0 sin(2 pi f t) on the node at x = 0        */
+    double rf_freq_hz;
+    double gas_density_m3;
+    double gas_temp_K;
+    double gas_mass_kg;     /* neutral mass (elastic recoil, neutral velocities)   */
+    double background_rho;  /* fixed uniform charge density, C/m^3                 */
+    double opal_B_eV;       /* energy-sharing parameter of ionization              */
+    uint64_t seed;          /* Philox key                                          */
+} orc_case;
+
+/* Per-step energy and particle ledger (all energies J/m^2). */
+typedef struct {
+    double K_before[2];     /* kinetic energy of the particles alive at step start  */
+    double K_after[2];      /* kinetic energy at n+1/2 of the particles alive after */
+    double work[2];         /* sum over pushed particles of the field work          */
+    double coll_dK[2];      /* kinetic-energy change from collisions incl. children */
+    double absorbed_K[2][2];/* [species][electrode 0 = x=0, 1 = x=L]                */
+    double WE;              /* field energy sum 1/2 eps0 E^2 dx of this step's solve*/
+    int64_t absorbed_n[2][2];
+    int64_t n_coll[2][4];   /* real collisions by process kind                      */
+    int64_t n_candidates[2];
+    int64_t n_created[2];
+    int64_t n_over_table[2];
+} orc_ledger;
+
+typedef struct orc_sim orc_sim;
+
+/* ---- building blocks, used by the step and called directly by the pins ---- */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* (2*(r>>9)+1) * 2^-24: an odd multiple of 2^-24 in (0,1). */
+double orc_u01(uint32_t r);
+
+/* Eq. (2) with the linear spline S_1: Q[g] += S_1(g - xi_p) (dimensionless).
+ * Q has N+1 entries; periodic mode folds node N onto node 0. */
+void orc_deposit_linear(int32_t N, int32_t periodic, int64_t n, const double* xi,
+                        double* Q);
+/* Particle count per cell (floor(xi)) for the susceptibility. */
+void orc_count_cells(int32_t N, int64_t n, const double* xi, double* cnt);
+
+/* Field solves.  rho has N+1 node values; chi (may be NULL) has N cell values
+ * chi_{j+1/2}.  Output phi (N+1) and the staggered field E_{j+1/2} (N). */
+void orc_solve_dirichlet(int32_t N, double dx, const double* rho, const double* chi,
+                         double phi0, double phiN, double* phi, double* E);
+void orc_solve_periodic(int32_t N, double dx, const double* rho, const double* chi,
+                        double* phi, double* E);
+
+/* Eq. (3) gathers at one particle. */
+double orc_gather_ec(int32_t N, const double* E, double xi);
+double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi);
+
+/* ---- the simulation object ---- */
+orc_sim* orc_create(const orc_case* c);
+void orc_destroy(orc_sim* s);
+/* species 0 = electrons, 1 = ions.  Arrays are copied.  abar may be NULL. */
+int orc_set_species(orc_sim* s, int32_t sp, double q, double m, double w, int64_t n,
+                    const double* xi, const double* vx, const double* vy,
+                    const double* vz, const double* abar, const uint64_t* id);
+/* One collision process on a uniform energy grid e0 + k*de, k = 0..n-1. */
+int orc_add_process(orc_sim* s, int32_t sp, int32_t kind, double threshold_eV,
+                    double e0_eV, double de_eV, int32_t n, const double* sigma_m2);
+/* Computes the null-collision frequencies; must follow the last add_process. */
+int orc_prepare(orc_sim* s);
+/* D1 start-up: with loaded (x_0, v_{-1/2}) and abar = 0 store the first
+ * prediction x~_1 = x_0 + dt v_{-1/2}; particles predicted outside are removed. */
+int orc_implicit_startup(orc_sim* s);
+/* Deposit + field solve of the current state without moving anything. */
+int orc_compute_fields(orc_sim* s);
+/* Take n steps (scheme from the case).  Returns 0, or a negative error. */
+int orc_step(orc_sim* s, int64_t n);
+
+int64_t orc_count(const orc_sim* s, int32_t sp);
+int64_t orc_step_index(const orc_sim* s);
+void orc_get_species(const orc_sim* s, int32_t sp, double* xi, double* vx, double* vy,
+                     double* vz, double* abar, uint64_t* id);
+/* Fields of the most recent solve: rho (N+1), phi (N+1), E (N), chi (N),
+ * Q per species (N+1, dimensionless deposit), cell counts per species (N). */
+void orc_get_fields(const orc_sim* s, double* rho, double* phi, double* E, double* chi,
+                    double* Qe, double* Qi, double* cnt_e, double* cnt_i);
+void orc_get_ledger(const orc_sim* s, orc_ledger* out);
+/* Cumulative per-cell field work (J/m^2) per species since creation (N each). */
+void orc_get_heating(const orc_sim* s, double* he, double* hi);
+double orc_numax(const orc_sim* s, int32_t sp);
+
+/* ---- collision kernels exposed for the statistical pins ---- */
+/* Applies O-6 to one particle with velocity v (m/s, in place).  Returns the
+ * process kind that happened, or -1 (no candidate) / -2 (null collision).
+ * On ionization writes the ejected electron's velocity to ve and the new ion's
+ * velocity to vi.  eps_over counts over-table energies. */
+int orc_collide_one(orc_sim* s, int32_t sp, uint64_t id, int64_t step, double* v,
+                    double* ve, double* vi, int* eps_over);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,118 @@
+"""Pins of the oracle against conservation laws and the behaviours the paper
+reports (Sec. I and Sec. III):
+
+* EC scheme: field + kinetic energy is conserved up to the leap-frog time
+  error, which shrinks like dt^2 at fixed dx even at dx = 20 lambda_D;
+* MC scheme (CIC deposit and gather of a centred-difference nodal field):
+  total momentum is conserved to round-off, and the thermal plasma heats at a
+  rate that does not shrink with dt once dx >> lambda_D (grid heating);
+* the energy ledger closes to round-off with collisions and absorption on;
+* counts close: n_after = n_before - absorbed + created;
+* a run split into two halves through an exported state equals the whole run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def thermal(orc, ratio, gather, wdt, T=40.0, n_cells=32, ppc=64):
+    wl = W.c2(ratio=ratio, gather=gather, ppc=ppc, n_cells=n_cells, wdt=wdt, seed=7)
+    case, sps, procs = W.to_oracle(wl)
+    sim = orc.Sim(case, sps, procs)
+    nsteps = int(round(T / wdt))
+    tot, mom = [], []
+    for _ in range(nsteps):
+        sim.step(1)
+        L = sim.ledger()
+        # kinetic energy at integer time n: mean of the two half steps
+        tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+        st = sim.species(0)
+        mom.append(st["vx"].sum())
+    tot = np.array(tot)
+    err = np.abs(tot - tot[0]).max() / tot[0]
+    rate = np.polyfit(np.arange(nsteps) * wdt, tot / tot[0], 1)[0]
+    return err, rate, np.array(mom), sim
+
+
+@pytest.mark.parametrize("ratio", [5.0, 20.0])
+def test_ec_energy_error_shrinks_like_dt_squared(orc, ratio):
+    errs = [thermal(orc, ratio, 0, w)[0] for w in (0.2, 0.1, 0.05)]
+    for a, b in zip(errs, errs[1:]):
+        assert 3.0 <= a / b <= 5.5, errs
+
+
+def test_mc_grid_heating_does_not_shrink_with_dt(orc):
+    r = [thermal(orc, 20.0, 1, w) for w in (0.2, 0.1)]
+    rate_mc = [x[1] for x in r]
+    # secular heating, essentially independent of dt
+    assert rate_mc[0] > 1e-3 and rate_mc[1] > 1e-3
+    assert 0.7 < rate_mc[0] / rate_mc[1] < 1.4
+    # while the EC scheme on the same grid does not heat
+    rate_ec = thermal(orc, 20.0, 0, 0.1)[1]
+    assert abs(rate_ec) < 0.05 * rate_mc[1]
+
+
+def test_mc_conserves_momentum_ec_does_not(orc):
+    _, _, mom_mc, _ = thermal(orc, 5.0, 1, 0.2, T=20.0)
+    _, _, mom_ec, sim = thermal(orc, 5.0, 0, 0.2, T=20.0)
+    st = sim.species(0)
+    scale = np.abs(st["vx"]).sum()
+    assert np.abs(mom_mc - mom_mc[0]).max() < 1e-11 * scale
+    assert np.abs(mom_ec - mom_ec[0]).max() > 1e-6 * scale
+
+
+def _check_ledger(sim, steps):
+    n_prev = [sim.count(0), sim.count(1)]
+    for _ in range(steps):
+        sim.step(1)
+        L = sim.ledger()
+        for sp in range(2):
+            lhs = L["K_after"][sp] - L["K_before"][sp]
+            rhs = L["work"][sp] - L["absorbed_K"][sp].sum() + L["coll_dK"][sp]
+            assert abs(lhs - rhs) <= 1e-11 * max(L["K_before"][sp], 1e-300)
+            n_now = sim.count(sp)
+            assert n_now == n_prev[sp] - L["absorbed_n"][sp].sum() + L["n_created"][sp]
+            n_prev[sp] = n_now
+
+
+def test_ledger_closes_explicit_ccp(orc):
+    wl = W.c1(np_per_species=2048)
+    case, sps, procs = W.to_oracle(wl)
+    # a hot, dense gas so every process and both electrodes show up in 300 steps
+    case = dict(case, gas_density_m3=W.gas_density(500.0))
+    for s in sps[:1]:
+        s["vx"] = s["vx"] * 4
+        s["vy"] = s["vy"] * 4
+        s["vz"] = s["vz"] * 4
+    sim = orc.Sim(case, sps, procs)
+    _check_ledger(sim, 300)
+
+
+def test_ledger_closes_implicit_ccp(orc):
+    wl = W.c3(ppc=16, wdt=2.0)
+    case, sps, procs = W.to_oracle(wl)
+    sim = orc.Sim(case, sps, procs)
+    _check_ledger(sim, 200)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_split_run_equals_whole_run(orc, scheme):
+    wl = W.c1(np_per_species=1024, scheme=scheme)
+    case, sps, procs = W.to_oracle(wl)
+    whole = orc.Sim(case, sps, procs)
+    whole.step(60)
+    a = orc.Sim(case, sps, procs)
+    a.step(25)
+    state = [a.species(k) for k in range(2)]
+    for k in range(2):
+        state[k].update(q=sps[k]["q"], m=sps[k]["m"], w=sps[k]["w"])
+    b = orc.Sim(dict(case, step0=a.step_index), state, procs, startup=False)
+    b.step(35)
+    for k in range(2):
+        x, y = whole.species(k), b.species(k)
+        ox, oy = np.argsort(x["id"]), np.argsort(y["id"])
+        for f in ("xi", "vx", "vy", "vz", "abar", "id"):
+            assert np.array_equal(x[f][ox], y[f][oy]), f

@@ -1,0 +1,144 @@
+"""Pins of the oracle's grid operations: Eq. (2) weighting, Eq. (3)
+interpolation, the explicit and susceptibility-modified field solves.
+
+Each check uses a formulation other than the oracle's own: brute force over
+every (particle, node) pair with the spline functions, closed-form potentials,
+and dense linear solves of the finite-difference systems."""
+import numpy as np
+import pytest
+
+EPS0 = 8.8541878128e-12
+
+
+def S1(x):
+    return np.maximum(0.0, 1.0 - np.abs(x))
+
+
+def S0(x):
+    # half-open top hat: a particle exactly on a node belongs to the cell above
+    return ((x >= -0.5) & (x < 0.5)).astype(np.float64)
+
+
+@pytest.mark.parametrize("N,n,periodic", [(5, 37, False), (8, 200, True), (3, 9, False)])
+def test_deposit_is_eq2_brute_force(orc, N, n, periodic):
+    rng = np.random.default_rng(N * 1000 + n)
+    xi = rng.random(n) * N
+    xi[:3] = [0.0, N - 1e-9, float(N // 2)]  # node hits and the last edge
+    Q = orc.deposit_linear(N, xi, periodic=periodic)
+    g = np.arange(N + 1)
+    ref = S1(g[:, None] - xi[None, :]).sum(axis=1)
+    if periodic:
+        # node N is node 0; a particle in the last cell also weights node 0 via N
+        ref[0] += ref[N]
+        ref[N] = ref[0]
+    np.testing.assert_allclose(Q, ref, rtol=0, atol=1e-12)
+    # total charge is one per particle (node N duplicates node 0 when periodic)
+    tot = Q[:N].sum() if periodic else Q.sum()
+    assert abs(tot - n) < 1e-10
+
+
+def test_ec_gather_is_eq3_brute_force(orc):
+    N = 7
+    rng = np.random.default_rng(3)
+    E = rng.standard_normal(N)
+    xi = np.concatenate([rng.random(50) * N, np.arange(N, dtype=float)])
+    for x in xi:
+        # sum over the half-grid points x_{g+1/2} with S_0
+        ref = sum(E[g] * S0(x - g - 0.5) for g in range(N))
+        assert orc.gather_ec(N, E, x) == pytest.approx(ref, abs=0, rel=0)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_mc_gather_brute_force(orc, periodic):
+    N = 6
+    rng = np.random.default_rng(4)
+    E = rng.standard_normal(N)
+    # nodal field by centred differences of the potential: (phi_{g-1}-phi_{g+1})/2dx
+    Eg = np.zeros(N + 1)
+    for g in range(N + 1):
+        if periodic:
+            Eg[g] = 0.5 * (E[(g - 1) % N] + E[g % N])
+        else:
+            Eg[g] = E[0] if g == 0 else (E[N - 1] if g == N else 0.5 * (E[g - 1] + E[g]))
+    for x in rng.random(40) * N:
+        ref = sum(Eg[g] * S1(x - g) for g in range(N + 1))
+        assert orc.gather_mc(N, E, x, periodic=periodic) == pytest.approx(ref, rel=1e-13,
+                                                                         abs=1e-13)
+
+
+def test_dirichlet_uniform_rho_closed_form(orc):
+    # -eps0 phi'' = rho with phi(0)=V, phi(L)=0 has the quadratic solution
+    # phi = V (1 - x/L) + rho x (L - x) / (2 eps0), exact for the 3-point stencil
+    N, L, V, rho0 = 64, 0.025, 100.0, 3.2e-5
+    dx = L / N
+    rho = np.full(N + 1, rho0)
+    phi, E = orc.solve_dirichlet(N, dx, rho, V, 0.0)
+    x = np.arange(N + 1) * dx
+    ref = V * (1 - x / L) + rho0 * x * (L - x) / (2 * EPS0)
+    np.testing.assert_allclose(phi, ref, rtol=1e-12, atol=1e-12 * abs(ref).max())
+    np.testing.assert_allclose(E, (ref[:-1] - ref[1:]) / dx, rtol=1e-10,
+                               atol=1e-10 * abs(E).max())
+
+
+def _dense_dirichlet(N, dx, rho, chi, V0, VN):
+    k = 1.0 + chi
+    A = np.zeros((N + 1, N + 1))
+    b = np.zeros(N + 1)
+    A[0, 0] = 1.0; b[0] = V0
+    A[N, N] = 1.0; b[N] = VN
+    for g in range(1, N):
+        # -(eps0/dx^2) [k_g (phi_{g+1}-phi_g) - k_{g-1}(phi_g - phi_{g-1})] = rho_g
+        A[g, g - 1] = -EPS0 * k[g - 1] / dx ** 2
+        A[g, g] = EPS0 * (k[g - 1] + k[g]) / dx ** 2
+        A[g, g + 1] = -EPS0 * k[g] / dx ** 2
+        b[g] = rho[g]
+    return np.linalg.solve(A, b)
+
+
+@pytest.mark.parametrize("with_chi", [False, True])
+def test_dirichlet_dense_solve(orc, with_chi):
+    rng = np.random.default_rng(11 + with_chi)
+    N, dx = 12, 1e-4
+    rho = rng.standard_normal(N + 1) * 1e-4
+    chi = rng.random(N) * 30 if with_chi else np.zeros(N)
+    phi, E = orc.solve_dirichlet(N, dx, rho, 37.0, -5.0, chi=chi if with_chi else None)
+    ref = _dense_dirichlet(N, dx, rho, chi, 37.0, -5.0)
+    np.testing.assert_allclose(phi, ref, rtol=1e-11, atol=1e-11 * abs(ref).max())
+
+
+def test_constant_chi_scales_permittivity(orc):
+    # constant chi is the plain Poisson equation with eps0 -> eps0 (1+chi)
+    rng = np.random.default_rng(2)
+    N, dx, c = 20, 2e-4, 4.5
+    rho = rng.standard_normal(N + 1) * 1e-5
+    phi1, _ = orc.solve_dirichlet(N, dx, rho, 0.0, 0.0, chi=np.full(N, c))
+    phi2, _ = orc.solve_dirichlet(N, dx, rho / (1 + c), 0.0, 0.0)
+    np.testing.assert_allclose(phi1, phi2, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("with_chi", [False, True])
+def test_periodic_dense_solve(orc, with_chi):
+    rng = np.random.default_rng(5 + with_chi)
+    N, dx = 10, 3e-4
+    rho = rng.standard_normal(N + 1) * 1e-5
+    rho[:N] -= rho[:N].mean()
+    rho[N] = rho[0]
+    chi = rng.random(N) * 7 if with_chi else np.zeros(N)
+    phi, E = orc.solve_periodic(N, dx, rho, chi=chi if with_chi else None)
+    # dense periodic system for phi_0..phi_{N-1} with gauge phi_0 = 0
+    k = 1.0 + chi
+    A = np.zeros((N, N))
+    b = np.zeros(N)
+    for g in range(N):
+        gl, gr = (g - 1) % N, (g + 1) % N
+        A[g, gl] += -EPS0 * k[gl] / dx ** 2
+        A[g, g] += EPS0 * (k[gl] + k[g]) / dx ** 2
+        A[g, gr] += -EPS0 * k[g] / dx ** 2
+        b[g] = rho[g]
+    A[0, :] = 0.0
+    A[0, 0] = 1.0
+    b[0] = 0.0
+    ref = np.linalg.solve(A, b)
+    np.testing.assert_allclose(phi[:N], ref, rtol=1e-10, atol=1e-10 * abs(ref).max())
+    assert abs(phi[N]) < 1e-9 * abs(ref).max()   # periodic potential
+    assert abs(E.sum()) < 1e-9 * abs(E).max()
