@@ -1,0 +1,178 @@
+"""Throughput of the EC PIC/MCC hot path on one MI355X.
+
+A step is one pass of the whole hot path over the discharge: EC gather, push,
+electrode absorption, null-collision MCC, int64 deposit and the FP64 field
+solve of every case, plus the periodic compaction/cell sort.  Inputs are
+synthetic and already resident in HBM when the timed region starts.
+
+Prints one JSON line.  Default workload: the production-size explicit RF
+discharge (2048 cells, 1e7 electrons + 1e7 ions, 30 mTorr, 300 V at
+13.56 MHz, dt = 1/(2000 f)).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per particle-step of the explicit pass: read cell, off,
+# vx, vy, vz (4 B each) and id (8 B); write cell, off, vx (4 B each)
+ALG_BYTES_EXPLICIT = 40
+# implicit pass also reads and writes abar (4 B each)
+ALG_BYTES_IMPLICIT = 48
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name, scale):
+    import workloads as W
+    if name == "ccp2048_explicit":
+        return [W.c4(np_per_species=int(10_000_000 * scale))]
+    if name == "ccp64_explicit":
+        return [W.c1()]
+    if name == "ccp256_implicit":
+        return [W.c3()]
+    if name == "sweep64":
+        return W.c5(np_scale=scale)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05):
+    """The FP64 oracle (single thread) on a particle sample of the workload."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    case, sps, procs = W.to_oracle(wl)
+    rng = np.random.default_rng(1)
+    sub = []
+    for sp in sps:
+        n = sp["xi"].size
+        k = max(1, int(n * frac))
+        idx = np.sort(rng.choice(n, size=k, replace=False)) if n else np.zeros(0, int)
+        d = dict(sp)
+        for key in ("xi", "vx", "vy", "vz", "id"):
+            d[key] = sp[key][idx]
+        d["abar"] = None
+        d["w"] = sp["w"] / frac          # same densities with fewer particles
+        sub.append(d)
+    sim = oracle.Sim(case, sub, procs)
+    sim.step(2)
+    n_ps = 0
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < steps_budget_s:
+        n_ps += sim.count(0) + sim.count(1)
+        sim.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=n_ps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{frac:g} of the particles of the same discharge (weights scaled "
+                       f"to keep the densities), {steps} steps, FP64, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="ccp2048_explicit")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1310_5284_amd as P
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log(f"[bench] building inputs: {args.workload} scale {args.scale}")
+    wls = make_workload(args.workload, args.scale)
+    log("[bench] pic_init")
+    ctx = P.PicContext(wls)
+    tile = args.tile or 8192
+    sort_every = args.sort_every or 64
+    ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+    implicit = all(w["case"]["scheme"] == 1 for w in wls)
+    stepper = ctx.step
+
+    def live():
+        return sum(sum(ctx.counts(k)["n"]) for k in range(len(wls)))
+
+    log(f"[bench] warmup {args.warmup} steps")
+    done = 0
+    while done < args.warmup:
+        k = min(50, args.warmup - done)
+        stepper(k)
+        done += k
+        log(f"[bench] warmup {done}/{args.warmup}")
+    n_before = live()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps, {n_before} particles")
+    t0 = time.perf_counter()
+    stepper(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches = ctx.last_timing()
+    n_after = live()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    particles = 0.5 * (n_before + n_after)
+    value = particles * args.steps / (t1 - t0)
+
+    bpp = ALG_BYTES_IMPLICIT if implicit else ALG_BYTES_EXPLICIT
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    launches_per_step = launches / args.steps
+    alg_bytes = bpp * particles / launches_per_step
+    achieved = alg_bytes / avg_launch_s / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
+                kernel="k_step<%d,false>" % (1 if implicit else 0),
+                avg_launch_ms=round(avg_launch_s * 1e3, 4),
+                alg_bytes_per_particle_step=bpp)
+    tprof = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tprof):
+        try:
+            t = json.load(open(tprof))
+            if t.get("workload") == args.workload and t.get("kernel") == roof["kernel"]:
+                roof["traffic"] = t.get("bytes_per_launch")
+        except Exception:
+            pass
+
+    out = dict(metric="particle-steps/sec (push+deposit+MCC) vs plain FP64 GPU form at "
+                      "matched EEDF",
+               value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload=args.workload, cases=len(wls),
+                           cells=[w["case"]["n_cells"] for w in wls][:4],
+                           particles=int(particles), tile=tile, sort_every=sort_every,
+                           scheme="implicit" if implicit else "explicit"),
+               roofline=roof)
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * pic.h -- C-ABI of the MI355X (gfx950) hot path of the energy-conserving
+ * (EC) electrostatic PIC/MCC method of Wang, Sun, Jiang & Kong,
+ * arXiv:1310.5284 ("On the energy conservation electrostatic PIC/MC
+ * simulating").
+ *
+ * One call advances every discharge ("case") held by a context by whole
+ * steps.  A step of one case is, per particle: the field gathered from the
+ * potential difference across the particle's own cell (Sec. II, Eq. (3) with
+ * S_0 of the half-grid field; or the momentum-conserving CIC gather of the
+ * conventional scheme, Sec. II scheme (1)), the leap-frog push (explicit) or
+ * the D1 direct-implicit push (Sec. II schemes (3)-(4)), absorption at the
+ * electrodes (Sec. III), null-collision Monte Carlo collisions against the
+ * neutral gas (Sec. III), and linear-weighted charge deposition (Sec. II,
+ * Eq. (2) with S_1) -- plus, per case, the FP64 field solve.
+ *
+ * Conventions
+ *   - Cells j = 0..N-1 span [j dx, (j+1) dx), dx = gap / N; nodes g = 0..N.
+ *     A particle position is an int32 cell index and a float offset in [0,1).
+ *   - Species 0 is the electron species, species 1 the ion species, of every
+ *     case.  Either may be empty.
+ *   - All pointers passed in may be host or device pointers (the library
+ *     copies with hipMemcpyDefault).  Nothing passed in is retained: every
+ *     input array may be freed once the call returns.
+ *   - Status: every int-returning call returns PIC_OK (0) or a negative
+ *     PIC_E_* code and never throws.  pic_last_error() gives a text.
+ *   - Threading: a context is used by one host thread at a time.  Step calls
+ *     are asynchronous on the context's stream; pic_diagnostics synchronises
+ *     it.  A device fault makes the context sticky-failed (PIC_E_STATE).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PIC_OK = 0,
+    PIC_E_INVAL = -1,      /* bad argument or configuration                    */
+    PIC_E_NOMEM = -2,      /* device allocation failed                         */
+    PIC_E_CAPACITY = -3,   /* particle capacity exceeded (children were lost)  */
+    PIC_E_UNSTABLE = -4,   /* explicit case violates omega_p dt < 2 (Eq. (1))  */
+    PIC_E_DEVICE = -5,     /* HIP runtime error                                */
+    PIC_E_STATE = -6,      /* context unusable after an earlier failure        */
+    PIC_E_DIVERGED = -7    /* non-finite field or energy detected              */
+};
+
+enum { PIC_BC_DIRICHLET_RF = 0, PIC_BC_PERIODIC = 1 };
+enum { PIC_EXPLICIT = 0, PIC_IMPLICIT_D1 = 1 };
+enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1 };
+enum { PIC_ELASTIC = 0, PIC_EXCITATION = 1, PIC_IONIZATION = 2, PIC_CHARGE_EXCHANGE = 3 };
+
+/* pic_init flags */
+enum {
+    /* skip the omega_p dt < 2 check of explicit cases (Eq. (1)) */
+    PIC_FLAG_ALLOW_UNSTABLE = 1u << 0,
+    /* particle arrays hold a state exported by pic_diagnostics(PIC_DIAG_STATE):
+     * velocities in cells per step, abar in cells per step^2, and for implicit
+     * cases the already-predicted position and velocity (no start-up push) */
+    PIC_FLAG_INTERNAL_UNITS = 1u << 1
+};
+
+/* One discharge (Sec. III): planar gap, RF-driven electrode at x = 0 with
+ * V(t) = rf_volts sin(2 pi rf_freq_hz t), grounded electrode at x = L; or a
+ * periodic box.  t_n = n dt with n the absolute step index. */
+typedef struct {
+    int32_t n_cells;        /* N >= 2 and N <= PIC_MAX_CELLS                    */
+    int32_t bc;             /* PIC_BC_*                                         */
+    int32_t scheme;         /* PIC_EXPLICIT | PIC_IMPLICIT_D1 (beta = 1/2)      */
+    int32_t gather;         /* PIC_GATHER_EC (Eq. (3), S_0) | PIC_GATHER_MC     */
+    int32_t collisions;     /* 0 / 1                                            */
+    int32_t history_steps;  /* ledger rows kept on the device (ring), >= 0      */
+    double gap_m;
+    double dt_s;
+    int64_t start_step;     /* absolute index of the next step                  */
+    double rf_volts;
+    double rf_freq_hz;
+    double gas_density_m3;
+    double gas_temp_K;
+    double gas_mass_kg;     /* neutral mass: elastic recoil, neutral velocities */
+    double background_rho;  /* fixed uniform charge density, C/m^3              */
+    double opal_B_eV;       /* energy-sharing parameter of ionization (10 eV)   */
+    uint64_t seed;          /* Philox4x32-10 key of this case                   */
+} pic_case_config;
+
+#define PIC_MAX_CELLS 4096
+
+/* One species of one case.  q_C, m_kg per physical particle; weight =
+ * physical particles per macro-particle per m^2 of electrode area.
+ * Positions: cell in [0, N), off in [0, 1).  Velocities in m/s unless
+ * PIC_FLAG_INTERNAL_UNITS.  id: unique per species (the random stream of a
+ * particle is keyed by (id, step)).  abar may be NULL (zero). */
+typedef struct {
+    double q_C, m_kg, weight;
+    int64_t n;              /* particles given                                  */
+    int64_t capacity;       /* slots reserved (>= n); ionization appends        */
+    const int32_t* cell;
+    const float* off;
+    const float* vx;
+    const float* vy;
+    const float* vz;
+    const uint64_t* id;
+    const float* abar;
+} pic_species_init;
+
+/* Cross-section table of one process on the uniform energy grid
+ * e0_eV + k de_eV (k < n), linear in between, held constant outside.  For
+ * electrons the energy is 1/2 m v^2; for ions 1/2 M g^2 with g the speed
+ * relative to a neutral drawn from the gas Maxwellian.  A process with
+ * threshold_eV > 0 cannot happen at or below its threshold.  All processes of
+ * one species must share one grid; ions support PIC_CHARGE_EXCHANGE only.
+ * The same tables serve every case of a context. */
+typedef struct {
+    int32_t species;
+    int32_t kind;           /* PIC_ELASTIC ... PIC_CHARGE_EXCHANGE              */
+    double threshold_eV;
+    double e0_eV;
+    double de_eV;
+    int32_t n;
+    const double* sigma_m2;
+} pic_xsec;
+
+/* Energy and particle ledger of one step of one case (energies J/m^2).
+ * K_after[s] = K_before[s] + work[s] - sum absorbed_K[s][:] + coll_dK[s]. */
+typedef struct {
+    int64_t step;               /* index of the step this row describes         */
+    double K_before[2];         /* kinetic energy at n-1/2                      */
+    double K_after[2];          /* kinetic energy at n+1/2                      */
+    double work[2];             /* field work on the particles                  */
+    double coll_dK[2];          /* change from collisions, children included    */
+    double absorbed_K[2][2];    /* [species][electrode: 0 at x=0, 1 at x=L]     */
+    double WE;                  /* sum 1/2 eps0 E^2 dx of the solve this step used */
+    int64_t absorbed_n[2][2];
+    int64_t n_coll[2][4];       /* real collisions by process kind              */
+    int64_t n_candidates[2];
+    int64_t n_created[2];
+    int64_t n_over_table[2];    /* candidates beyond the last table energy      */
+    int64_t n_lost[2];          /* children dropped for lack of capacity        */
+} pic_ledger;
+
+/* pic_diagnostics what_mask bits */
+enum {
+    PIC_DIAG_FIELDS = 1u << 0,   /* rho, phi, E, chi, fixed-point deposits     */
+    PIC_DIAG_LEDGER = 1u << 1,   /* last step's ledger (+ history if given)    */
+    PIC_DIAG_STATE = 1u << 2,    /* particle export                            */
+    PIC_DIAG_DENSITY = 1u << 3,  /* time-averaged node densities               */
+    PIC_DIAG_HEATING = 1u << 4,  /* cumulative field work per cell             */
+    PIC_DIAG_EEDF = 1u << 5      /* electron energy histogram                  */
+};
+
+/* Caller-owned output buffers (host or device pointers; NULL = skip). */
+typedef struct {
+    /* always filled */
+    int64_t step;               /* absolute index of the next step              */
+    int64_t n_particles[2];     /* live particles                               */
+    int64_t n_slots[2];         /* occupied slots (live + not yet compacted)    */
+    double vel_unit;            /* m/s per internal velocity unit (dx/dt)       */
+    double acc_unit;            /* m/s^2 per internal abar unit (dx/dt^2)       */
+    /* PIC_DIAG_FIELDS: the fields of the solve the next step uses */
+    double* rho;                /* [N+1] C/m^3                                  */
+    double* phi;                /* [N+1] V                                      */
+    double* E;                  /* [N]   V/m at x_{j+1/2}                       */
+    double* chi;                /* [N]   susceptibility (implicit), else 0      */
+    int64_t* qfix[2];           /* [N+1] node deposits in units of 2^-24 particle */
+    int64_t* cell_count[2];     /* [N]   particles per cell                     */
+    /* PIC_DIAG_LEDGER */
+    pic_ledger ledger;
+    pic_ledger* history;        /* [history_cap] rows, oldest first             */
+    int64_t history_cap;
+    int64_t history_n;          /* rows written                                 */
+    /* PIC_DIAG_STATE: live particles in slot order, internal units */
+    int64_t state_cap[2];       /* capacity of the arrays below                 */
+    int32_t* cell[2];
+    float* off[2];
+    float* vx[2];
+    float* vy[2];
+    float* vz[2];
+    uint64_t* id[2];
+    float* abar[2];
+    /* PIC_DIAG_DENSITY: mean over sampled steps of the node density (m^-3) */
+    double* density[2];         /* [N+1]                                        */
+    int64_t density_samples;
+    /* PIC_DIAG_HEATING: sum over sampled steps of the field work per cell */
+    double* heating[2];         /* [N]   J/m^2                                  */
+    /* PIC_DIAG_EEDF: electron energy histogram summed over sampled steps */
+    int32_t eedf_bins;          /* out: bins held by the context                */
+    double eedf_bin_eV;         /* out: bin width                               */
+    int64_t* eedf;              /* [eedf_bins]                                  */
+    int64_t eedf_samples;
+} pic_diag;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Creates a context holding n_cases discharges.  species points to
+ * 2*n_cases entries: [case][0 = electrons, 1 = ions].  hip_stream is a
+ * hipStream_t (NULL = the default stream).  Validation: N range, dt > 0,
+ * positions in range, ids present, tables consistent, capacity >= n, and for
+ * explicit cases omega_p,max dt < 2 (Eq. (1)) unless PIC_FLAG_ALLOW_UNSTABLE.
+ * On error *out is NULL and nothing is leaked. */
+int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* cases,
+             const pic_species_init* species, const pic_xsec* xs, int32_t n_xs,
+             void* hip_stream, uint32_t flags);
+
+/* Advance every case of the context by n_steps.  Every case must be
+ * PIC_EXPLICIT (resp. PIC_IMPLICIT_D1), else PIC_E_INVAL. */
+int pic_step_explicit(pic_ctx* ctx, int64_t n_steps);
+int pic_step_implicit(pic_ctx* ctx, int64_t n_steps);
+/* Advance a mixed batch: each case by its own scheme, one launch per step. */
+int pic_step(pic_ctx* ctx, int64_t n_steps);
+
+/* Synchronises the stream and copies what what_mask asks for, for one case,
+ * into the caller's buffers.  Returns PIC_E_CAPACITY if a state buffer is
+ * too small (out->n_particles then tells the size needed). */
+int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what_mask, pic_diag* out);
+
+/* Tuning and diagnostics cadence.  sort_every: steps between compaction and
+ * cell sorting of the particle arrays (>= 1).  diag_every: steps between
+ * samples of density, heating and EEDF (0 = off).  tile: particles per
+ * workgroup (multiple of 256, <= 32768; 0 = keep). */
+int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_every, int32_t tile);
+/* Zero the density, heating and EEDF accumulators of every case. */
+int pic_reset_accumulators(pic_ctx* ctx);
+
+/* Plain FP64 GPU form of the same explicit method (fp64 absolute positions
+ * and velocities, fp64 global-atomic deposit, no sort, one launch per phase),
+ * used as the throughput comparison point.  Advances its own copy of the
+ * context's initial state. */
+int pic_fp64_reference_init(pic_ctx* ctx);
+int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
+int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,
+                             double* xi, double* vx, double* vy, double* vz, uint64_t* id,
+                             int64_t* n_out);
+
+void pic_destroy(pic_ctx* ctx);
+const char* pic_last_error(const pic_ctx* ctx);
+/* Timing of the most recent pic_step* call: milliseconds of device time
+ * spent in the particle kernel (HIP events on the context's stream) and the
+ * number of particle-kernel launches it made. */
+int pic_last_timing(const pic_ctx* ctx, double* particle_kernel_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

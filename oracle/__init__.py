@@ -105,6 +105,7 @@ def lib():
         L.orc_implicit_startup.argtypes = [C.c_void_p]
         L.orc_compute_fields.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_step_with_field.argtypes = [C.c_void_p, _D]
         L.orc_count.argtypes = [C.c_void_p, C.c_int32]
         L.orc_count.restype = C.c_int64
         L.orc_step_index.argtypes = [C.c_void_p]
@@ -243,6 +244,12 @@ class Sim:
 
     def step(self, n: int = 1):
         lib().orc_step(self._h, n)
+
+    def step_with_field(self, E):
+        E = _f64(E)
+        if E.size != self.N:
+            raise ValueError("field must have N values")
+        lib().orc_step_with_field(self._h, _dp(E))
 
     def compute_fields(self):
         lib().orc_compute_fields(self._h)

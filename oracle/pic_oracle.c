@@ -58,6 +58,7 @@ struct orc_sim {
     /* fields of the most recent solve */
     double *rho, *phi, *E, *chi, *Q[2], *cnt[2];
     double* heat[2];
+    const double* ext_E;   /* when set, the next step uses this field (N values) */
     orc_ledger led;
 };
 
@@ -394,6 +395,16 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
 {
     int32_t N = s->c.n_cells;
     int periodic = s->c.bc == ORC_BC_PERIODIC;
+    if (s->ext_E) {
+        /* field supplied by the caller (a sample of a larger discharge) */
+        double we = 0.0;
+        for (int32_t j = 0; j < N; ++j) {
+            s->E[j] = s->ext_E[j];
+            we += 0.5 * EPS0 * s->E[j] * s->E[j] * s->dx;
+        }
+        s->led.WE = we;
+        return;
+    }
     for (int k = 0; k < 2; ++k) {
         memset(s->Q[k], 0, sizeof(double) * ((size_t)N + 1));
         memset(s->cnt[k], 0, sizeof(double) * (size_t)N);
@@ -781,6 +792,14 @@ int orc_step(orc_sim* s, int64_t n)
         if (s->c.scheme == ORC_IMPLICIT) step_implicit(s);
         else step_explicit(s);
     }
+    return 0;
+}
+
+int orc_step_with_field(orc_sim* s, const double* E)
+{
+    s->ext_E = E;
+    orc_step(s, 1);
+    s->ext_E = NULL;
     return 0;
 }
 

@@ -111,6 +111,10 @@ int orc_implicit_startup(orc_sim* s);
 int orc_compute_fields(orc_sim* s);
 /* Take n steps (scheme from the case).  Returns 0, or a negative error. */
 int orc_step(orc_sim* s, int64_t n);
+/* One step in which the gather uses the given field E (N values, V/m) instead
+ * of depositing and solving: for checking a particle sample of a discharge
+ * too large for the oracle against the field of the whole discharge. */
+int orc_step_with_field(orc_sim* s, const double* E);
 
 int64_t orc_count(const orc_sim* s, int32_t sp);
 int64_t orc_step_index(const orc_sim* s);
@@ -126,7 +130,7 @@ void orc_get_heating(const orc_sim* s, double* he, double* hi);
 double orc_numax(const orc_sim* s, int32_t sp);
 
 /* ---- collision kernels exposed for the statistical pins ---- */
-/* Applies O-6 to one particle with velocity v (m/s, in place).  Returns the
+/* Null-collision MCC of one particle with velocity v (m/s, in place).  Returns the
  * process kind that happened, or -1 (no candidate) / -2 (null collision).
  * On ionization writes the ejected electron's velocity to ve and the new ion's
  * velocity to vi.  eps_over counts over-table energies. */

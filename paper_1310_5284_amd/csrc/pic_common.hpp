@@ -1,0 +1,147 @@
+// Device helpers shared by the kernels of the library: the counter-based
+// generator, sampling helpers, position normalisation and workgroup-wide
+// reductions and scans (kBlock threads).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic_device.hpp"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with the round keys bumped by the Weyl constants.
+// The key is per case (uniform across the wavefront), so the key schedule
+// stays in scalar registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// odd multiple of 2^-24 in (0,1), exact in fp32
+__device__ __forceinline__ float u01(uint32_t r)
+{
+    return (float)((r >> 9) * 2u + 1u) * 5.9604644775390625e-08f;
+}
+
+__device__ __forceinline__ void iso_dir(float ua, float ub, float& dx, float& dy, float& dz)
+{
+    const float ct = 1.0f - 2.0f * ua;
+    const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    float sp, cp;
+    sincospif(2.0f * ub, &sp, &cp);
+    dx = st * cp;
+    dy = st * sp;
+    dz = ct;
+}
+
+__device__ __forceinline__ void box_muller(float ua, float ub, float& n1, float& n2)
+{
+    const float r = sqrtf(-2.0f * logf(ua));
+    float sp, cp;
+    sincospif(2.0f * ub, &sp, &cp);
+    n1 = r * cp;
+    n2 = r * sp;
+}
+
+__device__ __forceinline__ uint64_t child_id(uint64_t parent, uint32_t step, uint32_t sp_child,
+                                             uint32_t k0, uint32_t k1)
+{
+    const uint4 r = philox((uint32_t)parent, (uint32_t)(parent >> 32), step,
+                           (sp_child << 28) | 0x0FFFFFFu, k0, k1);
+    return ((uint64_t)r.x | ((uint64_t)r.y << 32)) | (1ull << 63);
+}
+
+// ---------------------------------------------------------------------------
+// block-wide helpers (kBlock threads)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    T r = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) r += red[w];
+    return r;
+}
+
+// inclusive prefix sum of a[0..n) in LDS, fixed summation order
+template <typename T>
+__device__ void block_scan(T* a, int n, T* red)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + kBlock - 1) / kBlock;
+    const int lo = min(tid * per, n), hi = min(lo + per, n);
+    T loc = 0;
+    for (int i = lo; i < hi; ++i) loc += a[i];
+    T inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    __syncthreads();
+    if (lane == 63) red[wave] = inc;
+    __syncthreads();
+    T run = inc - loc;
+    for (int w = 0; w < wave; ++w) run += red[w];
+    for (int i = lo; i < hi; ++i) {
+        run += a[i];
+        a[i] = run;
+    }
+    __syncthreads();
+}
+
+// "no cell touched" marker of the range trackers; far from INT_MAX so that
+// lo + threadIdx.x cannot overflow
+constexpr int kNoCell = 0x3fffffff;
+
+__device__ __forceinline__ void range_note(int& lo, int& hi, int c)
+{
+    lo = min(lo, c);
+    hi = max(hi, c);
+}
+
+// Normalise (cell, off) after a move: off in [0,1), an offset that rounds to
+// 1.0f moves to the next cell.
+__device__ __forceinline__ void renorm(int& c, float& o)
+{
+    const float fl = floorf(o);
+    c += (int)fl;
+    o -= fl;
+    if (o >= 1.0f) {
+        o = 0.0f;
+        c += 1;
+    }
+}
+
+}  // namespace pic

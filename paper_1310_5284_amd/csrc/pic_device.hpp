@@ -1,0 +1,145 @@
+// Device-side data layout of the EC PIC/MCC hot path (gfx950).
+//
+// Internal units: positions as (int32 cell, float offset in [0,1)); velocities
+// in cells per step (v dt/dx); accelerations in cells per step^2 (a dt^2/dx).
+// Charge deposits are int64 fixed point with 2^-24 of a particle per unit:
+// every block accumulates, per cell j, the count of particles in the cell and
+// the sum of their right-node weights W = rint(off * 2^24); the node charge in
+// particle units is then count_g * 2^24 - W_g + W_{g-1} (Eq. (2), linear S_1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kFixBits = 24;                // deposit weight resolution
+constexpr double kFixScale = 16777216.0;    // 2^24
+constexpr unsigned long long kCountOne = 1ull << 40;  // packed LDS count unit
+constexpr unsigned long long kWMask = kCountOne - 1;
+constexpr int kMaxProc = 4;                 // electron processes per table row
+constexpr int kEedfBins = 256;
+constexpr int kMaxTile = 32767;             // keeps packed LDS counts < 2^16
+
+// One species of one case.  Particle pointers are swapped by the compaction.
+struct Species {
+    int32_t* cell;
+    float* off;
+    float* vx;
+    float* vy;
+    float* vz;
+    uint64_t* id;
+    float* abar;
+    int32_t* cell2;
+    float* off2;
+    float* vx2;
+    float* vy2;
+    float* vz2;
+    uint64_t* id2;
+    float* abar2;
+    int64_t capacity;
+    double accel;        // cells/step^2 per (V/m): (q/m) dt^2 / dx
+    double qw_dx;        // C/m^3 per particle of deposit: q w / dx
+    double kin_unit;     // J/m^2 per unit v^2: m w (dx/dt)^2 / 2
+    double chi_coef;     // beta dt^2 q^2 w / (m eps0 dx) per particle in a cell
+    double dens_unit;    // m^-3 per particle of deposit: w / dx
+    float eps_unit;      // eV per unit v^2: m (dx/dt)^2 / (2 e)
+    float t_scale;       // table index per unit v^2: eps_unit / de
+    float t_off;         // -e0 / de
+    float t_max;         // n - 1
+    float thr_v2[kMaxProc];  // process possible only for v^2 above this
+    int32_t kind[kMaxProc];  // process kinds in table order (-1 unused)
+    int32_t n_proc;
+    uint32_t cand_thr;   // candidate iff (r >> 9) < cand_thr  (u0 < P_null)
+    float vth_neutral;   // sqrt(k T_gas / M_gas) dt/dx (ions: neutral partner)
+    float vth_newion;    // sqrt(k T_gas / M_ion) dt/dx (ion born by ionization)
+    float recoil2;       // 2 m_e / M_gas (elastic energy loss)
+    float opal_B;        // eV
+    const float4* tab_e; // electron table: per energy point, sigma_k * sig_scale
+    const float* tab_i;  // ion table (charge exchange), sigma * sig_scale
+    float eedf_scale;    // EEDF bins per eV
+    int32_t pad;
+};
+
+// Everything a kernel needs to know about one case.
+struct Case {
+    int32_t n_cells;
+    int32_t bc;           // 0 Dirichlet RF, 1 periodic
+    int32_t scheme;       // 0 explicit, 1 D1 implicit
+    int32_t gather;       // 0 EC, 1 MC
+    int32_t collisions;
+    int32_t first_block;  // this case's workgroups in its launch
+    int32_t n_blocks;
+    int32_t history_len;
+    double dx, dt;
+    double rf_volts, rf_omega;
+    double background_rho;
+    uint32_t key0, key1;  // Philox key = seed
+    Species sp[2];
+    // per-case device arrays
+    unsigned long long* dep_cnt[2];  // [N] particles per cell (accumulating)
+    unsigned long long* dep_w[2];    // [N] sum of right-node weights
+    float* ehat[2];                  // [N] accel * E of the next step, per species
+    double* E;                       // [N] V/m
+    double* phi;                     // [N+1]
+    double* rho;                     // [N+1]
+    double* chi;                     // [N]
+    long long* qfix[2];              // [N+1] node deposits (export)
+    long long* ccount[2];            // [N] particles per cell (export)
+    unsigned long long* dens_acc[2]; // [N+1] accumulated node deposits (diagnostics)
+    double* heat_acc[2];             // [N] accumulated field work per cell (J/m^2)
+    unsigned long long* eedf_acc;    // [kEedfBins]
+    void* history;                   // pic_ledger ring
+};
+
+// Mutable per-case counters, written by the finalizing workgroup.
+struct State {
+    long long step;          // absolute index of the next step
+    int32_t n_slots[2];      // occupied slots
+    int32_t n_child[2];      // children appended during the running step
+    int32_t n_live[2];
+    uint32_t done;           // workgroups finished in the running step
+    int32_t flags;           // bit 0: non-finite field, bit 1: capacity
+    double K[2];             // kinetic energy at the current half step (J/m^2)
+    double WE;               // field energy of the solve the next step uses
+    long long dens_samples;
+    long long eedf_samples;
+    long long history_n;
+    long long lost_total[2];
+    long long sort_live[2];  // live counts found by the last compaction
+    double sortK[2];         // exact kinetic energy found by the last compaction
+};
+
+struct Work {
+    int32_t c;   // case
+    int32_t s;   // species
+    int32_t b;   // workgroup index within (case, species)
+    int32_t nb;  // workgroups of (case, species)
+};
+
+// Per-workgroup partial sums of the ledger (both species).
+struct Partial {
+    double work[2];
+    double coll_dK[2];
+    double absK[2][2];
+    double v2sum[2];     // compaction: exact sum of v^2 of live particles
+    long long abs_n[2][2];
+    long long n_coll[2][4];
+    long long n_cand[2];
+    long long n_created[2];
+    long long n_over[2];
+    long long n_lost[2];
+};
+
+struct Params {
+    Case* cases;
+    State* state;
+    const Work* work;
+    Partial* partials;
+    int32_t n_cases;
+    int32_t mode;        // kernel-specific
+};
+
+}  // namespace pic

@@ -1,0 +1,874 @@
+// Host runtime and C-ABI of the EC PIC/MCC hot path (see include/pic.h).
+//
+// Owns all device memory of a context: per case and species a structure-of-
+// arrays particle store (two copies for the compaction), the fixed-point
+// deposit accumulators, fields, per-case tables and counters.  Launches one
+// k_step per scheme group per step, and the compaction every sort_every steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_device.hpp"
+
+namespace pic {
+template <int SCHEME, bool DIAG>
+__global__ void k_step(Params P);
+__global__ void k_init_species(Params P, double vscale0, double vscale1);
+__global__ void k_compact_hist(Params P, uint32_t* hist_all, const int64_t* hist_off);
+__global__ void k_compact_scan(Params P, uint32_t* hist_all, uint32_t* cursor_all,
+                               const int64_t* hist_off);
+__global__ void k_compact_scatter(Params P, uint32_t* cursor_all, const int64_t* hist_off);
+__global__ void k_compact_finish(Params P);
+__global__ void k_deposit(Params P);
+__global__ void k_solve(Params P);
+}  // namespace pic
+
+using namespace pic;
+
+namespace {
+
+constexpr double QE = 1.602176634e-19;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double KB = 1.380649e-23;
+constexpr double ME_LIMIT = 1e-27;  // species lighter than this are "electron-like"
+
+struct HostCase {
+    pic_case_config cfg;
+    double scale[2];        // n_g (dx/dt) / nu_max per species (collision tables)
+    double q[2], m[2], w[2];
+    int64_t cap[2];
+    int64_t n0[2];
+    double vscale;          // (m/s) -> cells/step
+    size_t hist_off[2];
+    // device allocations owned by the case
+    std::vector<void*> allocs;
+};
+
+struct FP64Ref;  // plain FP64 GPU form (pic_fp64.hip)
+
+}  // namespace
+
+struct pic_ctx {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool failed = false;
+    std::string err;
+    int n_cases = 0;
+    std::vector<HostCase> hc;
+    std::vector<Case> cases_h;      // host mirror (pointers valid after set-up)
+    Case* d_cases = nullptr;
+    State* d_state = nullptr;
+    Work* d_work = nullptr;
+    Partial* d_partials = nullptr;
+    uint32_t* d_hist = nullptr;
+    uint32_t* d_cursor = nullptr;
+    int64_t* d_hist_off = nullptr;
+    std::vector<Work> work;
+    int n_blocks = 0;
+    int grp_off[2] = {0, 0}, grp_cnt[2] = {0, 0};   // explicit, implicit workgroups
+    int grp_maxN[2] = {0, 0};
+    int maxN = 0;
+    int tile = 8192;
+    int sort_every = 64;
+    int diag_every = 0;
+    int64_t since_sort = 0;
+    int64_t steps_taken = 0;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+    double last_ms = 0.0;
+    int64_t last_launches = 0;
+    bool timing = true;
+    void* fp64 = nullptr;          // FP64 reference form (pic_fp64.hip)
+    std::vector<void*> allocs;     // context-level allocations
+    std::vector<std::vector<double>> sigma[2];   // float64 copy of the input tables
+};
+
+namespace {
+
+int fail(pic_ctx* c, int code, const std::string& msg)
+{
+    if (c) {
+        c->err = msg;
+        if (code == PIC_E_DEVICE || code == PIC_E_STATE) c->failed = true;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(ctx, PIC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// inside pic_init: report, free the partial context and return
+#define INITCHK(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return bail(fail(c, PIC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+template <typename T>
+int dalloc(pic_ctx* c, std::vector<void*>& list, T** p, size_t n)
+{
+    void* q = nullptr;
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    if (hipMemset(q, 0, bytes) != hipSuccess) {
+        (void)hipFree(q);
+        return fail(c, PIC_E_DEVICE, "hipMemset failed");
+    }
+    list.push_back(q);
+    *p = (T*)q;
+    return PIC_OK;
+}
+
+size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+size_t step_lds(int N, bool diag)
+{
+    size_t b = a16(4 * (size_t)N) + a16(8 * (size_t)N);
+    if (diag) b += a16(4 * (size_t)N) + 4 * (size_t)kEedfBins;
+    return std::max(b, 8 * ((size_t)N + 1) + 16);
+}
+
+// Null-collision bound: n_g max over table intervals of
+// max(sigma_T(e_i), sigma_T(e_{i+1})) v(e_{i+1}), v = sqrt(2 e eps / m).
+double nu_max(const std::vector<const pic_xsec*>& pr, double ng, double mass)
+{
+    if (pr.empty()) return 0.0;
+    const pic_xsec* a = pr[0];
+    double best = 0.0;
+    for (int32_t i = 0; i + 1 < a->n; ++i) {
+        double sl = 0.0, sr = 0.0;
+        for (const pic_xsec* p : pr) {
+            sl += p->sigma_m2[i];
+            sr += p->sigma_m2[i + 1];
+        }
+        double er = a->e0_eV + (double)(i + 1) * a->de_eV;
+        double v = std::sqrt(2.0 * QE * (er > 0.0 ? er : 0.0) / mass);
+        best = std::max(best, std::max(sl, sr) * v);
+    }
+    return ng * best;
+}
+
+uint32_t candidate_threshold(double pnull)
+{
+    // number of k in [0, 2^23) with (2k+1) 2^-24 < pnull
+    double t = (pnull * 16777216.0 - 1.0) / 2.0;
+    double c = std::ceil(t);
+    if (c < 0.0) c = 0.0;
+    if (c > 8388608.0) c = 8388608.0;
+    return (uint32_t)c;
+}
+
+int build_work(pic_ctx* c)
+{
+    c->work.clear();
+    for (int g = 0; g < 2; ++g) {
+        c->grp_off[g] = (int)c->work.size();
+        c->grp_maxN[g] = 0;
+        for (int k = 0; k < c->n_cases; ++k) {
+            HostCase& h = c->hc[k];
+            if (h.cfg.scheme != g) continue;
+            Case& C = c->cases_h[k];
+            C.first_block = (int)c->work.size();
+            for (int s = 0; s < 2; ++s) {
+                int nb = (int)std::max<int64_t>(1, (h.cap[s] + c->tile - 1) / c->tile);
+                for (int b = 0; b < nb; ++b) c->work.push_back(Work{k, s, b, nb});
+            }
+            C.n_blocks = (int)c->work.size() - C.first_block;
+            c->grp_maxN[g] = std::max(c->grp_maxN[g], (int)h.cfg.n_cells);
+        }
+        c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
+    }
+    c->n_blocks = (int)c->work.size();
+    return PIC_OK;
+}
+
+int upload_work(pic_ctx* c)
+{
+    if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    c->d_work = nullptr;
+    c->d_partials = nullptr;
+    HIPCHK(c, hipMalloc(&c->d_work, sizeof(Work) * c->work.size()));
+    HIPCHK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(Work) * c->work.size(),
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&c->d_partials, sizeof(Partial) * c->work.size()));
+    HIPCHK(c, hipMemset(c->d_partials, 0, sizeof(Partial) * c->work.size()));
+    return PIC_OK;
+}
+
+Params params(pic_ctx* c, int mode)
+{
+    Params p;
+    p.cases = c->d_cases;
+    p.state = c->d_state;
+    p.work = c->d_work;
+    p.partials = c->d_partials;
+    p.n_cases = c->n_cases;
+    p.mode = mode;
+    return p;
+}
+
+int compaction(pic_ctx* c)
+{
+    Params p = params(c, 0);
+    size_t l1 = 4 * (size_t)c->maxN, l2 = 8 * (size_t)c->maxN;
+    hipLaunchKernelGGL(k_compact_hist, dim3(c->n_blocks), dim3(kBlock), l1, c->stream, p,
+                       c->d_hist, (const int64_t*)c->d_hist_off);
+    hipLaunchKernelGGL(k_compact_scan, dim3(2 * c->n_cases), dim3(kBlock), l1, c->stream, p,
+                       c->d_hist, c->d_cursor, (const int64_t*)c->d_hist_off);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(c->n_blocks), dim3(kBlock), l2, c->stream, p,
+                       c->d_cursor, (const int64_t*)c->d_hist_off);
+    hipLaunchKernelGGL(k_compact_finish, dim3(c->n_cases), dim3(kBlock), 0, c->stream, p);
+    HIPCHK(c, hipGetLastError());
+    c->since_sort = 0;
+    return PIC_OK;
+}
+
+// Dynamic LDS above the default 64 KiB needs an explicit opt-in per kernel.
+int set_lds_limits(pic_ctx* c, size_t need)
+{
+    if (need <= 65536) return PIC_OK;
+    const int v = (int)need;
+    const void* ks[] = {(const void*)k_step<0, false>, (const void*)k_step<0, true>,
+                        (const void*)k_step<1, false>, (const void*)k_step<1, true>,
+                        (const void*)k_compact_scatter, (const void*)k_compact_hist,
+                        (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve};
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, PIC_E_INVAL, std::string("LDS opt-in of ") + std::to_string(need) +
+                                            " bytes refused: " + hipGetErrorString(e));
+        }
+    }
+    return PIC_OK;
+}
+
+void destroy_ctx(pic_ctx* c);
+
+}  // namespace
+
+// defined in pic_fp64.hip
+extern "C" void pic__fp64_free(pic_ctx* ctx);
+
+extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* cases,
+                        const pic_species_init* species, const pic_xsec* xs, int32_t n_xs,
+                        void* hip_stream, uint32_t flags)
+{
+    if (!out) return PIC_E_INVAL;
+    *out = nullptr;
+    if (n_cases <= 0 || !cases || !species || (n_xs > 0 && !xs) || n_xs < 0) return PIC_E_INVAL;
+    pic_ctx* c = new pic_ctx();
+    auto bail = [&](int code) {
+        if (!c->err.empty()) fprintf(stderr, "pic_init: %s\n", c->err.c_str());
+        destroy_ctx(c);
+        return code;
+    };
+    c->n_cases = n_cases;
+    c->hc.resize(n_cases);
+    c->cases_h.resize(n_cases);
+    // ---- validation ----
+    for (int k = 0; k < n_cases; ++k) {
+        const pic_case_config& g = cases[k];
+        if (g.n_cells < 2 || g.n_cells > PIC_MAX_CELLS || !(g.gap_m > 0) || !(g.dt_s > 0) ||
+            (g.bc != PIC_BC_DIRICHLET_RF && g.bc != PIC_BC_PERIODIC) ||
+            (g.scheme != PIC_EXPLICIT && g.scheme != PIC_IMPLICIT_D1) ||
+            (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC) || g.history_steps < 0 ||
+            g.start_step < 0) {
+            fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
+            return bail(PIC_E_INVAL);
+        }
+        for (int s = 0; s < 2; ++s) {
+            const pic_species_init& sp = species[2 * k + s];
+            if (sp.n < 0 || sp.capacity < sp.n || sp.capacity > 0x7ffffff0LL || !(sp.m_kg > 0) ||
+                (sp.n > 0 && (!sp.cell || !sp.off || !sp.vx || !sp.vy || !sp.vz || !sp.id))) {
+                fprintf(stderr, "pic_init: case %d species %d: bad arrays\n", k, s);
+                return bail(PIC_E_INVAL);
+            }
+        }
+        if (g.collisions && (!(g.gas_density_m3 >= 0) || !(g.gas_temp_K > 0) ||
+                             !(g.gas_mass_kg > 0) || !(g.opal_B_eV > 0))) {
+            fprintf(stderr, "pic_init: case %d: bad gas\n", k);
+            return bail(PIC_E_INVAL);
+        }
+    }
+    std::vector<const pic_xsec*> proc[2];
+    for (int i = 0; i < n_xs; ++i) {
+        const pic_xsec& x = xs[i];
+        if (x.species < 0 || x.species > 1 || x.n < 2 || !(x.de_eV > 0) || !x.sigma_m2 ||
+            (x.species == 1 && x.kind != PIC_CHARGE_EXCHANGE) ||
+            (x.species == 0 && (x.kind < PIC_ELASTIC || x.kind > PIC_IONIZATION)))
+            return bail(PIC_E_INVAL);
+        proc[x.species].push_back(&x);
+    }
+    for (int s = 0; s < 2; ++s) {
+        if ((int)proc[s].size() > (s == 0 ? kMaxProc : 1)) return bail(PIC_E_INVAL);
+        for (const pic_xsec* p : proc[s])
+            if (p->n != proc[s][0]->n || p->e0_eV != proc[s][0]->e0_eV ||
+                p->de_eV != proc[s][0]->de_eV)
+                return bail(PIC_E_INVAL);
+    }
+    for (int s = 0; s < 2; ++s)
+        for (const pic_xsec* p : proc[s])
+            c->sigma[s].emplace_back(p->sigma_m2, p->sigma_m2 + p->n);
+    // ---- stream ----
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(c, PIC_E_DEVICE, "stream"));
+        c->own_stream = true;
+    }
+    (void)hipGetLastError();   // start from a clean error state
+    // ---- per case ----
+    size_t hist_total = 0;
+    for (int k = 0; k < n_cases; ++k) {
+        const pic_case_config& g = cases[k];
+        HostCase& h = c->hc[k];
+        Case& C = c->cases_h[k];
+        std::memset(&C, 0, sizeof(Case));
+        h.cfg = g;
+        const int N = g.n_cells;
+        const double dx = g.gap_m / N, dt = g.dt_s;
+        h.vscale = dt / dx;
+        C.n_cells = N;
+        C.bc = g.bc;
+        C.scheme = g.scheme;
+        C.gather = g.gather;
+        C.collisions = g.collisions;
+        C.history_len = g.history_steps;
+        C.dx = dx;
+        C.dt = dt;
+        C.rf_volts = g.rf_volts;
+        C.rf_omega = 6.283185307179586476925286766559 * g.rf_freq_hz;
+        C.background_rho = g.background_rho;
+        C.key0 = (uint32_t)g.seed;
+        C.key1 = (uint32_t)(g.seed >> 32);
+        c->maxN = std::max(c->maxN, N);
+        // Eq. (1): omega_p dt < 2 for the explicit leap-frog
+        if (g.scheme == PIC_EXPLICIT && !(flags & PIC_FLAG_ALLOW_UNSTABLE)) {
+            const pic_species_init& e = species[2 * k];
+            std::vector<int64_t> cnt(N, 0);
+            std::vector<int32_t> cells(e.n);
+            if (e.n > 0 && hipMemcpy(cells.data(), e.cell, sizeof(int32_t) * e.n,
+                                     hipMemcpyDefault) != hipSuccess)
+                return bail(fail(c, PIC_E_DEVICE, "copy cells"));
+            for (int32_t cc : cells)
+                if (cc >= 0 && cc < N) cnt[cc]++;
+            int64_t mx = cnt.empty() ? 0 : *std::max_element(cnt.begin(), cnt.end());
+            double ne = mx * e.weight / dx;
+            double wp = std::sqrt(ne * e.q_C * e.q_C / (EPS0 * e.m_kg));
+            if (wp * dt >= 2.0) {
+                c->err = "explicit case violates omega_p dt < 2";
+                destroy_ctx(c);
+                return PIC_E_UNSTABLE;
+            }
+        }
+        for (int s = 0; s < 2; ++s) {
+            const pic_species_init& sp = species[2 * k + s];
+            Species& S = C.sp[s];
+            h.q[s] = sp.q_C;
+            h.m[s] = sp.m_kg;
+            h.w[s] = sp.weight;
+            h.cap[s] = std::max<int64_t>(sp.capacity, 1);
+            h.n0[s] = sp.n;
+            S.capacity = h.cap[s];
+            const double m = sp.m_kg, q = sp.q_C, w = sp.weight;
+            S.accel = q / m * dt * dt / dx;
+            S.qw_dx = q * w / dx;
+            S.kin_unit = 0.5 * m * w * (dx / dt) * (dx / dt);
+            S.chi_coef = 0.5 * dt * dt * q * q * w / (m * EPS0 * dx);
+            S.dens_unit = w / dx;
+            const double eps_unit = 0.5 * m * (dx / dt) * (dx / dt) / QE;
+            S.eps_unit = (float)eps_unit;
+            S.opal_B = (float)g.opal_B_eV;
+            S.recoil2 = (float)(2.0 * species[2 * k].m_kg / (g.gas_mass_kg > 0 ? g.gas_mass_kg : 1.0));
+            S.vth_neutral = (float)(std::sqrt(KB * g.gas_temp_K / (g.gas_mass_kg > 0 ? g.gas_mass_kg : 1.0)) * dt / dx);
+            S.vth_newion = (float)(std::sqrt(KB * g.gas_temp_K / species[2 * k + 1].m_kg) * dt / dx);
+            S.eedf_scale = 2.0f;   // 0.5 eV bins
+            for (int p = 0; p < kMaxProc; ++p) {
+                S.kind[p] = -1;
+                S.thr_v2[p] = -1.0f;
+            }
+            S.n_proc = g.collisions ? (int32_t)proc[s].size() : 0;
+            // per-case collision table: sigma * n_g (dx/dt) / nu_max
+            if (S.n_proc > 0) {
+                const pic_xsec* a = proc[s][0];
+                const double numax = nu_max(proc[s], g.gas_density_m3, m);
+                const double pnull = 1.0 - std::exp(-numax * dt);
+                S.cand_thr = numax > 0 ? candidate_threshold(pnull) : 0u;
+                const double scale = numax > 0 ? g.gas_density_m3 * (dx / dt) / numax : 0.0;
+                h.scale[s] = scale;
+                S.t_scale = (float)(eps_unit / a->de_eV);
+                S.t_off = (float)(-a->e0_eV / a->de_eV);
+                S.t_max = (float)(a->n - 1);
+                for (int p = 0; p < S.n_proc; ++p) {
+                    S.kind[p] = proc[s][p]->kind;
+                    S.thr_v2[p] = proc[s][p]->threshold_eV > 0
+                                      ? (float)(proc[s][p]->threshold_eV / eps_unit)
+                                      : -1.0f;
+                }
+                if (s == 0) {
+                    std::vector<float> t(4 * (size_t)a->n, 0.0f);
+                    for (int32_t i = 0; i < a->n; ++i)
+                        for (int p = 0; p < S.n_proc; ++p)
+                            t[4 * i + p] = (float)(proc[s][p]->sigma_m2[i] * scale);
+                    float4* d = nullptr;
+                    if (dalloc(c, h.allocs, &d, (size_t)a->n)) return bail(PIC_E_NOMEM);
+                    INITCHK(hipMemcpy(d, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+                    S.tab_e = d;
+                } else {
+                    std::vector<float> t((size_t)a->n);
+                    for (int32_t i = 0; i < a->n; ++i) t[i] = (float)(proc[s][0]->sigma_m2[i] * scale);
+                    float* d = nullptr;
+                    if (dalloc(c, h.allocs, &d, (size_t)a->n)) return bail(PIC_E_NOMEM);
+                    INITCHK(hipMemcpy(d, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+                    S.tab_i = d;
+                }
+            }
+            // particle store (two copies)
+            const size_t cap = (size_t)h.cap[s];
+            int rc = 0;
+            rc |= dalloc(c, h.allocs, &S.cell, cap);
+            rc |= dalloc(c, h.allocs, &S.off, cap);
+            rc |= dalloc(c, h.allocs, &S.vx, cap);
+            rc |= dalloc(c, h.allocs, &S.vy, cap);
+            rc |= dalloc(c, h.allocs, &S.vz, cap);
+            rc |= dalloc(c, h.allocs, &S.id, cap);
+            rc |= dalloc(c, h.allocs, &S.abar, cap);
+            rc |= dalloc(c, h.allocs, &S.cell2, cap);
+            rc |= dalloc(c, h.allocs, &S.off2, cap);
+            rc |= dalloc(c, h.allocs, &S.vx2, cap);
+            rc |= dalloc(c, h.allocs, &S.vy2, cap);
+            rc |= dalloc(c, h.allocs, &S.vz2, cap);
+            rc |= dalloc(c, h.allocs, &S.id2, cap);
+            rc |= dalloc(c, h.allocs, &S.abar2, cap);
+            if (rc) return bail(PIC_E_NOMEM);
+            if (sp.n > 0) {
+                const size_t n = (size_t)sp.n;
+                INITCHK(hipMemcpy(S.cell, sp.cell, 4 * n, hipMemcpyDefault));
+                INITCHK(hipMemcpy(S.off, sp.off, 4 * n, hipMemcpyDefault));
+                INITCHK(hipMemcpy(S.vx, sp.vx, 4 * n, hipMemcpyDefault));
+                INITCHK(hipMemcpy(S.vy, sp.vy, 4 * n, hipMemcpyDefault));
+                INITCHK(hipMemcpy(S.vz, sp.vz, 4 * n, hipMemcpyDefault));
+                INITCHK(hipMemcpy(S.id, sp.id, 8 * n, hipMemcpyDefault));
+                if (sp.abar) INITCHK(hipMemcpy(S.abar, sp.abar, 4 * n, hipMemcpyDefault));
+                // positions must lie inside the gap / box
+                std::vector<int32_t> cc(n);
+                std::vector<float> oo(n);
+                INITCHK(hipMemcpy(cc.data(), S.cell, 4 * n, hipMemcpyDeviceToHost));
+                INITCHK(hipMemcpy(oo.data(), S.off, 4 * n, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < n; ++i)
+                    if (cc[i] < 0 || cc[i] >= N || !(oo[i] >= 0.0f) || !(oo[i] < 1.0f)) {
+                        fprintf(stderr, "pic_init: case %d species %d particle %zu out of range\n",
+                                k, s, i);
+                        return bail(PIC_E_INVAL);
+                    }
+            }
+        }
+        // grids
+        int rc = 0;
+        for (int s = 0; s < 2; ++s) {
+            rc |= dalloc(c, h.allocs, &C.dep_cnt[s], N);
+            rc |= dalloc(c, h.allocs, &C.dep_w[s], N);
+            rc |= dalloc(c, h.allocs, &C.ehat[s], N);
+            rc |= dalloc(c, h.allocs, &C.qfix[s], N + 1);
+            rc |= dalloc(c, h.allocs, &C.ccount[s], N);
+            rc |= dalloc(c, h.allocs, &C.dens_acc[s], N + 1);
+            rc |= dalloc(c, h.allocs, &C.heat_acc[s], N);
+        }
+        rc |= dalloc(c, h.allocs, &C.E, N);
+        rc |= dalloc(c, h.allocs, &C.phi, N + 1);
+        rc |= dalloc(c, h.allocs, &C.rho, N + 1);
+        rc |= dalloc(c, h.allocs, &C.chi, N);
+        rc |= dalloc(c, h.allocs, &C.eedf_acc, kEedfBins);
+        pic_ledger* hist = nullptr;
+        rc |= dalloc(c, h.allocs, &hist, (size_t)g.history_steps + 1);
+        C.history = hist;
+        if (rc) return bail(PIC_E_NOMEM);
+        h.hist_off[0] = hist_total;
+        h.hist_off[1] = hist_total + N;
+        hist_total += 2 * (size_t)N;
+    }
+    if (set_lds_limits(c, std::max(step_lds(c->maxN, true), 8 * (size_t)c->maxN)))
+        return bail(PIC_E_INVAL);
+    // ---- context arrays ----
+    if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
+        dalloc(c, c->allocs, &c->d_hist, hist_total) ||
+        dalloc(c, c->allocs, &c->d_cursor, hist_total) ||
+        dalloc(c, c->allocs, &c->d_hist_off, 2 * (size_t)n_cases))
+        return bail(PIC_E_NOMEM);
+    {
+        std::vector<int64_t> ho(2 * n_cases);
+        for (int k = 0; k < n_cases; ++k) {
+            ho[2 * k] = (int64_t)c->hc[k].hist_off[0];
+            ho[2 * k + 1] = (int64_t)c->hc[k].hist_off[1];
+        }
+        INITCHK(hipMemcpy(c->d_hist_off, ho.data(), 8 * ho.size(), hipMemcpyHostToDevice));
+    }
+    build_work(c);
+    if (upload_work(c)) return bail(PIC_E_DEVICE);
+    INITCHK(hipMemcpy(c->d_cases, c->cases_h.data(), sizeof(Case) * n_cases,
+                        hipMemcpyHostToDevice));
+    {
+        std::vector<State> st(n_cases);
+        std::memset(st.data(), 0, sizeof(State) * n_cases);
+        for (int k = 0; k < n_cases; ++k) {
+            st[k].step = cases[k].start_step;
+            for (int s = 0; s < 2; ++s) {
+                st[k].n_slots[s] = (int32_t)species[2 * k + s].n;
+                st[k].n_live[s] = (int32_t)species[2 * k + s].n;
+            }
+        }
+        INITCHK(hipMemcpy(c->d_state, st.data(), sizeof(State) * n_cases,
+                            hipMemcpyHostToDevice));
+    }
+    // ---- set-up on the device: units, D1 start-up, sort, deposit, solve ----
+    {
+        int mode = (flags & PIC_FLAG_INTERNAL_UNITS) ? 0 : 3;
+        // one kernel per case scale: vscale differs per case, so pass per launch
+        for (int k = 0; k < n_cases; ++k) {
+            if (mode == 0) break;
+            // restrict the launch to this case's workgroups
+            Params p = params(c, mode);
+            p.work = c->d_work + c->cases_h[k].first_block;
+            hipLaunchKernelGGL(k_init_species, dim3(c->cases_h[k].n_blocks), dim3(kBlock), 0,
+                               c->stream, p, c->hc[k].vscale, c->hc[k].vscale);
+        }
+        INITCHK(hipGetLastError());
+        if (compaction(c)) return bail(PIC_E_DEVICE);
+        Params p = params(c, 0);
+        hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock), 8 * (size_t)c->maxN,
+                           c->stream, p);
+        hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kBlock), 8 * ((size_t)c->maxN + 1) + 16,
+                           c->stream, p);
+        INITCHK(hipGetLastError());
+        INITCHK(hipStreamSynchronize(c->stream));
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+namespace {
+
+void destroy_ctx(pic_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    pic__fp64_free(c);
+    for (auto& h : c->hc)
+        for (void* p : h.allocs) (void)hipFree(p);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int check_flags(pic_ctx* c)
+{
+    std::vector<State> st(c->n_cases);
+    HIPCHK(c, hipMemcpy(st.data(), c->d_state, sizeof(State) * c->n_cases, hipMemcpyDeviceToHost));
+    int rc = PIC_OK;
+    for (int k = 0; k < c->n_cases; ++k) {
+        if (st[k].flags & 1) return fail(c, PIC_E_DIVERGED, "non-finite field or energy");
+        if (st[k].flags & 2) rc = fail(c, PIC_E_CAPACITY, "particle capacity exceeded");
+    }
+    return rc;
+}
+
+int run_steps(pic_ctx* c, int64_t n, int which)
+{
+    if (c->failed) return fail(c, PIC_E_STATE, "context failed earlier: " + c->err);
+    if (n < 0) return fail(c, PIC_E_INVAL, "negative step count");
+    for (int k = 0; k < c->n_cases; ++k)
+        if (which >= 0 && c->hc[k].cfg.scheme != which)
+            return fail(c, PIC_E_INVAL, "a case of the context uses the other scheme");
+    int needed = 0;
+    for (int g = 0; g < 2; ++g) needed += c->grp_cnt[g] ? 2 : 0;
+    needed *= (int)std::min<int64_t>(n, 1 << 20);
+    while ((int)c->ev.size() < needed) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    c->ev_used = 0;
+    for (int64_t it = 0; it < n; ++it) {
+        const bool diag = c->diag_every > 0 && (c->steps_taken % c->diag_every == 0);
+        for (int g = 0; g < 2; ++g) {
+            if (!c->grp_cnt[g]) continue;
+            Params p = params(c, c->grp_off[g]);
+            const size_t lds = step_lds(c->grp_maxN[g], diag);
+            auto kern = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
+                               : (diag ? k_step<1, true> : k_step<1, false>);
+            const bool rec = c->timing && c->ev_used + 2 <= (int)c->ev.size();
+            if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+            hipLaunchKernelGGL(kern, dim3(c->grp_cnt[g]), dim3(kBlock), lds, c->stream, p);
+            if (rec) {
+                (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+                c->ev_used += 2;
+            }
+        }
+        HIPCHK(c, hipGetLastError());
+        c->steps_taken++;
+        if (++c->since_sort >= c->sort_every)
+            if (compaction(c)) return PIC_E_DEVICE;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms = 0.0;
+    for (int e = 0; e + 1 < c->ev_used; e += 2) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->ev[e], c->ev[e + 1]) == hipSuccess) ms += t;
+    }
+    c->last_ms = ms;
+    c->last_launches = c->ev_used / 2;
+    return check_flags(c);
+}
+
+}  // namespace
+
+extern "C" int pic_step_explicit(pic_ctx* ctx, int64_t n)
+{
+    if (!ctx) return PIC_E_INVAL;
+    return run_steps(ctx, n, PIC_EXPLICIT);
+}
+
+extern "C" int pic_step_implicit(pic_ctx* ctx, int64_t n)
+{
+    if (!ctx) return PIC_E_INVAL;
+    return run_steps(ctx, n, PIC_IMPLICIT_D1);
+}
+
+extern "C" int pic_step(pic_ctx* ctx, int64_t n)
+{
+    if (!ctx) return PIC_E_INVAL;
+    return run_steps(ctx, n, -1);
+}
+
+extern "C" int pic_last_timing(const pic_ctx* ctx, double* ms, int64_t* launches)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ms) *ms = ctx->last_ms;
+    if (launches) *launches = ctx->last_launches;
+    return PIC_OK;
+}
+
+extern "C" int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_every, int32_t tile)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
+    if (sort_every < 1 || diag_every < 0 || tile < 0 || (tile > 0 && (tile % kBlock || tile > kMaxTile + 1)))
+        return fail(ctx, PIC_E_INVAL, "bad schedule");
+    ctx->sort_every = sort_every;
+    ctx->diag_every = diag_every;
+    if (tile > 0 && tile != ctx->tile) {
+        // the device case table holds the current buffer pointers: read it back
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipMemcpy(ctx->cases_h.data(), ctx->d_cases, sizeof(Case) * ctx->n_cases,
+                              hipMemcpyDeviceToHost));
+        ctx->tile = std::min(tile, kMaxTile);
+        build_work(ctx);
+        if (upload_work(ctx)) return PIC_E_DEVICE;
+        HIPCHK(ctx, hipMemcpy(ctx->d_cases, ctx->cases_h.data(), sizeof(Case) * ctx->n_cases,
+                              hipMemcpyHostToDevice));
+    }
+    return PIC_OK;
+}
+
+extern "C" int pic_reset_accumulators(pic_ctx* ctx)
+{
+    if (!ctx) return PIC_E_INVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < ctx->n_cases; ++k) {
+        const Case& C = ctx->cases_h[k];
+        const size_t N = (size_t)C.n_cells;
+        for (int s = 0; s < 2; ++s) {
+            HIPCHK(ctx, hipMemset(C.dens_acc[s], 0, 8 * (N + 1)));
+            HIPCHK(ctx, hipMemset(C.heat_acc[s], 0, 8 * N));
+        }
+        HIPCHK(ctx, hipMemset(C.eedf_acc, 0, 8 * (size_t)kEedfBins));
+    }
+    std::vector<State> st(ctx->n_cases);
+    HIPCHK(ctx, hipMemcpy(st.data(), ctx->d_state, sizeof(State) * ctx->n_cases, hipMemcpyDeviceToHost));
+    for (auto& s : st) s.dens_samples = s.eedf_samples = 0;
+    HIPCHK(ctx, hipMemcpy(ctx->d_state, st.data(), sizeof(State) * ctx->n_cases, hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic_diag* out)
+{
+    if (!ctx || !out || case_id < 0 || case_id >= ctx->n_cases) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    Case C;
+    State st;
+    HIPCHK(ctx, hipMemcpy(&C, ctx->d_cases + case_id, sizeof(Case), hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(&st, ctx->d_state + case_id, sizeof(State), hipMemcpyDeviceToHost));
+    const HostCase& h = ctx->hc[case_id];
+    const size_t N = (size_t)C.n_cells;
+    out->step = st.step;
+    out->n_particles[0] = st.n_live[0];
+    out->n_particles[1] = st.n_live[1];
+    out->n_slots[0] = st.n_slots[0];
+    out->n_slots[1] = st.n_slots[1];
+    out->vel_unit = C.dx / C.dt;
+    out->acc_unit = C.dx / (C.dt * C.dt);
+    if (what & PIC_DIAG_FIELDS) {
+        if (out->rho) HIPCHK(ctx, hipMemcpy(out->rho, C.rho, 8 * (N + 1), hipMemcpyDefault));
+        if (out->phi) HIPCHK(ctx, hipMemcpy(out->phi, C.phi, 8 * (N + 1), hipMemcpyDefault));
+        if (out->E) HIPCHK(ctx, hipMemcpy(out->E, C.E, 8 * N, hipMemcpyDefault));
+        if (out->chi) HIPCHK(ctx, hipMemcpy(out->chi, C.chi, 8 * N, hipMemcpyDefault));
+        for (int s = 0; s < 2; ++s) {
+            if (out->qfix[s]) HIPCHK(ctx, hipMemcpy(out->qfix[s], C.qfix[s], 8 * (N + 1), hipMemcpyDefault));
+            if (out->cell_count[s])
+                HIPCHK(ctx, hipMemcpy(out->cell_count[s], C.ccount[s], 8 * N, hipMemcpyDefault));
+        }
+    }
+    if (what & PIC_DIAG_LEDGER) {
+        HIPCHK(ctx, hipMemcpy(&out->ledger, C.history, sizeof(pic_ledger), hipMemcpyDeviceToHost));
+        out->history_n = 0;
+        if (out->history && out->history_cap > 0 && C.history_len > 0) {
+            const int64_t have = std::min<int64_t>(st.history_n, C.history_len);
+            const int64_t take = std::min<int64_t>(have, out->history_cap);
+            std::vector<pic_ledger> ring((size_t)C.history_len);
+            HIPCHK(ctx, hipMemcpy(ring.data(), (pic_ledger*)C.history + 1,
+                                  sizeof(pic_ledger) * C.history_len, hipMemcpyDeviceToHost));
+            std::vector<pic_ledger> rows((size_t)take);
+            for (int64_t r = 0; r < take; ++r) {
+                const int64_t idx = st.history_n - take + r;
+                rows[r] = ring[(size_t)(idx % C.history_len)];
+            }
+            if (take > 0)
+                HIPCHK(ctx, hipMemcpy(out->history, rows.data(), sizeof(pic_ledger) * take,
+                                      hipMemcpyDefault));
+            out->history_n = take;
+        }
+    }
+    if (what & PIC_DIAG_STATE) {
+        int rc = PIC_OK;
+        for (int s = 0; s < 2; ++s) {
+            const size_t ns = (size_t)st.n_slots[s];
+            std::vector<int32_t> cell(ns);
+            std::vector<float> off(ns), vx(ns), vy(ns), vz(ns), ab(ns);
+            std::vector<uint64_t> id(ns);
+            const Species& S = C.sp[s];
+            if (ns) {
+                HIPCHK(ctx, hipMemcpy(cell.data(), S.cell, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(off.data(), S.off, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(vx.data(), S.vx, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(vy.data(), S.vy, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(vz.data(), S.vz, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(ab.data(), S.abar, 4 * ns, hipMemcpyDeviceToHost));
+                HIPCHK(ctx, hipMemcpy(id.data(), S.id, 8 * ns, hipMemcpyDeviceToHost));
+            }
+            size_t k = 0;
+            for (size_t i = 0; i < ns; ++i) {
+                if (cell[i] < 0) continue;
+                cell[k] = cell[i]; off[k] = off[i]; vx[k] = vx[i]; vy[k] = vy[i];
+                vz[k] = vz[i]; ab[k] = ab[i]; id[k] = id[i];
+                ++k;
+            }
+            out->n_particles[s] = (int64_t)k;
+            if ((int64_t)k > out->state_cap[s]) {
+                rc = PIC_E_CAPACITY;
+                continue;
+            }
+            if (k == 0) continue;
+            if (out->cell[s]) HIPCHK(ctx, hipMemcpy(out->cell[s], cell.data(), 4 * k, hipMemcpyDefault));
+            if (out->off[s]) HIPCHK(ctx, hipMemcpy(out->off[s], off.data(), 4 * k, hipMemcpyDefault));
+            if (out->vx[s]) HIPCHK(ctx, hipMemcpy(out->vx[s], vx.data(), 4 * k, hipMemcpyDefault));
+            if (out->vy[s]) HIPCHK(ctx, hipMemcpy(out->vy[s], vy.data(), 4 * k, hipMemcpyDefault));
+            if (out->vz[s]) HIPCHK(ctx, hipMemcpy(out->vz[s], vz.data(), 4 * k, hipMemcpyDefault));
+            if (out->id[s]) HIPCHK(ctx, hipMemcpy(out->id[s], id.data(), 8 * k, hipMemcpyDefault));
+            if (out->abar[s]) HIPCHK(ctx, hipMemcpy(out->abar[s], ab.data(), 4 * k, hipMemcpyDefault));
+        }
+        if (rc) return fail(ctx, rc, "state buffers too small");
+    }
+    if (what & PIC_DIAG_DENSITY) {
+        out->density_samples = st.dens_samples;
+        for (int s = 0; s < 2; ++s) {
+            if (!out->density[s]) continue;
+            std::vector<long long> acc(N + 1);
+            HIPCHK(ctx, hipMemcpy(acc.data(), C.dens_acc[s], 8 * (N + 1), hipMemcpyDeviceToHost));
+            std::vector<double> d(N + 1);
+            for (size_t g = 0; g <= N; ++g) {
+                double vol = (C.bc == PIC_BC_DIRICHLET_RF && (g == 0 || g == N)) ? 0.5 : 1.0;
+                d[g] = st.dens_samples > 0
+                           ? (double)acc[g] / kFixScale * C.sp[s].dens_unit / vol / st.dens_samples
+                           : 0.0;
+            }
+            HIPCHK(ctx, hipMemcpy(out->density[s], d.data(), 8 * (N + 1), hipMemcpyDefault));
+        }
+    }
+    if (what & PIC_DIAG_HEATING) {
+        for (int s = 0; s < 2; ++s)
+            if (out->heating[s]) HIPCHK(ctx, hipMemcpy(out->heating[s], C.heat_acc[s], 8 * N, hipMemcpyDefault));
+    }
+    if (what & PIC_DIAG_EEDF) {
+        out->eedf_bins = kEedfBins;
+        out->eedf_bin_eV = 1.0 / C.sp[0].eedf_scale;
+        out->eedf_samples = st.eedf_samples;
+        if (out->eedf) HIPCHK(ctx, hipMemcpy(out->eedf, C.eedf_acc, 8 * (size_t)kEedfBins, hipMemcpyDefault));
+    }
+    (void)h;
+    return PIC_OK;
+}
+
+extern "C" void pic_destroy(pic_ctx* ctx) { destroy_ctx(ctx); }
+
+// ---- internal accessors for the FP64 reference form (not part of pic.h) ----
+extern "C" int pic__ctx_export(pic_ctx* ctx, void** cases_h_out, int* n_cases,
+                               hipStream_t* stream, void*** fp64_slot)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess ||
+        hipMemcpy(ctx->cases_h.data(), ctx->d_cases, sizeof(Case) * ctx->n_cases,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_E_DEVICE;
+    *cases_h_out = ctx->cases_h.data();
+    *n_cases = ctx->n_cases;
+    *stream = ctx->stream;
+    *fp64_slot = &ctx->fp64;
+    return PIC_OK;
+}
+
+extern "C" int pic__ctx_case_info(pic_ctx* ctx, int32_t k, pic_case_config* cfg, double* scale,
+                                  int64_t* cap)
+{
+    if (!ctx || k < 0 || k >= ctx->n_cases) return PIC_E_INVAL;
+    *cfg = ctx->hc[k].cfg;
+    for (int s = 0; s < 2; ++s) {
+        scale[s] = ctx->hc[k].scale[s];
+        cap[s] = ctx->hc[k].cap[s];
+    }
+    return PIC_OK;
+}
+
+extern "C" void** pic__ctx_fp64_slot(pic_ctx* ctx) { return ctx ? &ctx->fp64 : nullptr; }
+
+extern "C" int pic__ctx_table(pic_ctx* ctx, int32_t s, int32_t p, int32_t* n,
+                              const double** sigma)
+{
+    if (!ctx || s < 0 || s > 1 || p < 0 || p >= (int)ctx->sigma[s].size()) return PIC_E_INVAL;
+    *n = (int32_t)ctx->sigma[s][p].size();
+    *sigma = ctx->sigma[s][p].data();
+    return PIC_OK;
+}
+
+extern "C" const char* pic_last_error(const pic_ctx* ctx)
+{
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}

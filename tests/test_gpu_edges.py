@@ -1,0 +1,160 @@
+"""GPU edge cases, determinism, resume and closed-form checks through the C-ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import assert_report, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+E = 1.602176634e-19
+ME = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+
+
+def P():
+    import paper_1310_5284_amd as P
+    return P
+
+
+def ctx_for(wl, tile=1024, sort_every=16, **kw):
+    ctx = P().PicContext([wl], **kw)
+    ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+    return ctx
+
+
+def sorted_state(ctx, case=0):
+    st = ctx.state(case)
+    out = []
+    for sp in st["species"]:
+        o = np.argsort(sp["id"])
+        out.append({k: v[o] for k, v in sp.items()})
+    return out
+
+
+def test_cold_plasma_exact_omega_p_on_gpu():
+    # EC cold plasma: each cell oscillates at exactly omega_p (see the oracle
+    # pin); the GPU's float32 state must follow A cos(n theta) to 1e-5 cells
+    N, ppc, wdt, A = 32, 16, 0.3, 0.1
+    n0 = 1e15
+    wp = math.sqrt(n0 * E * E / (EPS0 * ME))
+    dt, dx = wdt / wp, 1e-3
+    offs = (0.25 + 0.5 * (np.arange(ppc) + 0.5) / ppc)
+    j = np.repeat(np.arange(N), ppc)
+    amp = A * np.sin(2 * np.pi * 3 * j / N)
+    xi = j + np.tile(offs, N) + amp
+    v = amp * (0.5 * wdt ** 2) * dx / dt
+    n = xi.size
+    cell = np.floor(xi).astype(np.int32)
+    e = dict(q=-E, m=ME, w=n0 * dx / ppc, cell=cell, off=(xi - cell).astype(np.float32),
+             vx=v.astype(np.float32), vy=np.zeros(n, np.float32), vz=np.zeros(n, np.float32),
+             id=np.arange(n, dtype=np.uint64), capacity=n)
+    wl = dict(case=dict(n_cells=N, gap_m=N * dx, bc=1, dt_s=dt, background_rho=n0 * E),
+              species=[e, W.empty_species(E, W.M_AR)], processes=[])
+    ctx = ctx_for(wl, tile=256)
+    theta = math.acos(1 - 0.5 * wdt ** 2)
+    base = j + np.tile(offs, N)
+    for step in range(1, 101):
+        ctx.step(1)
+        s = sorted_state(ctx)[0]
+        x = s["cell"].astype(np.float64) + s["off"]
+        err = np.abs(x - (base + amp * math.cos(step * theta))).max()
+        assert err < 1e-5, (step, err)
+
+
+def test_empty_ion_species_and_two_cells():
+    wl = W.c1(collisions=1, np_per_species=2000)
+    wl["case"]["n_cells"] = 2
+    for sp in wl["species"]:
+        sp["cell"] = (sp["cell"] % 2).astype(np.int32)
+    wl["species"][1] = W.empty_species(E, W.M_AR, w=wl["species"][0]["w"], capacity=4000)
+    ctx = ctx_for(wl, tile=256)
+    rep = teacher_forced(ctx, wl, 20)
+    assert_report(rep)
+
+
+def test_particles_on_cell_edges_and_ragged_tail():
+    wl = W.c1(collisions=0, np_per_species=777)
+    for sp in wl["species"]:
+        sp["off"][::3] = 0.0                         # exactly on a node
+        sp["off"][1::7] = np.nextafter(np.float32(1.0), np.float32(0.0))
+    ctx = ctx_for(wl, tile=256)
+    rep = teacher_forced(ctx, wl, 30)
+    assert_report(rep)
+
+
+def test_determinism_of_state_and_fields():
+    wl = W.c1(collisions=1, np_per_species=8192)
+    outs = []
+    for _ in range(2):
+        ctx = ctx_for(wl, tile=512, sort_every=7)
+        ctx.step(60)
+        outs.append((sorted_state(ctx), ctx.fields()))
+        ctx.close()
+    (s1, f1), (s2, f2) = outs
+    for a, b in zip(s1, s2):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    for k in ("rho", "phi", "E"):
+        assert np.array_equal(f1[k], f2[k]), k
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_resume_equals_uninterrupted(scheme):
+    wl = W.c1(collisions=1, np_per_species=4096, scheme=scheme)
+    a = ctx_for(wl, sort_every=1000)
+    a.step(40)
+    st = a.state()
+    b_wl = dict(wl)
+    b_wl["case"] = dict(wl["case"], step0=st["step"])
+    b_wl["species"] = [dict(wl["species"][s], **st["species"][s]) for s in range(2)]
+    b = ctx_for(b_wl, sort_every=1000, flags=P().FLAG_INTERNAL_UNITS)
+    a.step(30)
+    b.step(30)
+    for x, y in zip(sorted_state(a), sorted_state(b)):
+        for k in x:
+            assert np.array_equal(x[k], y[k]), k
+    fa, fb = a.fields(), b.fields()
+    for k in ("rho", "E"):
+        np.testing.assert_array_equal(fa[k], fb[k])
+
+
+def test_capacity_overflow_is_reported():
+    wl = W.c1(collisions=1, np_per_species=3000)
+    wl["case"]["gas_density_m3"] = W.gas_density(3000.0)
+    for sp in wl["species"]:
+        sp["capacity"] = sp["cell"].size + 2
+        sp["vx"] = sp["vx"] * (10.0 if sp["m"] < 1e-27 else 1.0)
+    ctx = ctx_for(wl, tile=256)
+    with pytest.raises(P().PicError) as ei:
+        ctx.step(50)
+    assert ei.value.code == P().PIC_E_CAPACITY
+
+
+def test_unstable_explicit_case_is_rejected():
+    wl = W.c1(collisions=0, np_per_species=2000)
+    wl["case"]["dt_s"] = 2.5 / 1.784e9 * 8   # omega_p dt >> 2 at the load density
+    with pytest.raises(P().PicError) as ei:
+        P().PicContext([wl])
+    assert ei.value.code == P().PIC_E_UNSTABLE
+    P().PicContext([wl], flags=P().FLAG_ALLOW_UNSTABLE).close()
+
+
+def test_invalid_inputs_are_rejected():
+    wl = W.c1(collisions=0, np_per_species=100)
+    wl["species"][0]["cell"][5] = 64          # outside [0, N)
+    with pytest.raises(P().PicError) as ei:
+        P().PicContext([wl])
+    assert ei.value.code == P().PIC_E_INVAL
+    wl = W.c1(collisions=0, np_per_species=100)
+    wl["species"][1]["off"][0] = 1.0          # offset must be < 1
+    with pytest.raises(P().PicError):
+        P().PicContext([wl])
+    wl = W.c1(collisions=0, np_per_species=100)
+    ctx = P().PicContext([wl])
+    with pytest.raises(P().PicError) as ei:
+        ctx.step_implicit(1)                  # explicit case
+    assert ei.value.code == P().PIC_E_INVAL

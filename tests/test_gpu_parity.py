@@ -1,0 +1,47 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle,
+teacher-forced one step at a time (see tests/parity.py for the protocol).
+
+Sizes span several workgroups and a ragged tail: the tile is set small so a
+species of a few thousand particles runs on many workgroups."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import assert_report, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_for(wl, tile=1024, sort_every=16, **kw):
+    import paper_1310_5284_amd as P
+    ctx = P.PicContext([wl], **kw)
+    ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+    return ctx
+
+
+@pytest.mark.parametrize("collisions", [0, 1])
+def test_ccp64_explicit_teacher_forced(collisions):
+    wl = W.c1(collisions=collisions, np_per_species=16384 + 77)
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 100)
+    print(rep)
+    assert_report(rep)
+
+
+@pytest.mark.parametrize("gather", [0, 1])
+def test_periodic_thermal_teacher_forced(gather):
+    wl = W.c2(ratio=5.0, gather=gather, ppc=100, n_cells=32)
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 100)
+    print(rep)
+    assert_report(rep)
+
+
+def test_ccp256_implicit_teacher_forced():
+    wl = W.c3(ppc=40, wdt=5.0)
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 100)
+    print(rep)
+    assert_report(rep)
