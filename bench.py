@@ -97,12 +97,7 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
     import paper_1310_5284_amd as P
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
 
     log(f"[bench] building inputs: {args.workload} scale {args.scale}")
     wls = make_workload(args.workload, args.scale)
@@ -125,11 +120,11 @@ def main():
         done += k
         log(f"[bench] warmup {done}/{args.warmup}")
     n_before = live()
-    torch.cuda.synchronize()
+    ctx.sync()
     log(f"[bench] timing {args.steps} steps, {n_before} particles")
     t0 = time.perf_counter()
     stepper(args.steps)
-    torch.cuda.synchronize()
+    ctx.sync()
     t1 = time.perf_counter()
     kern_ms, launches = ctx.last_timing()
     n_after = live()

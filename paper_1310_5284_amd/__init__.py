@@ -2,9 +2,12 @@
 energy-conserving electrostatic PIC/MCC method of arXiv:1310.5284.
 
 Argument marshalling only: every step of the method runs in the HIP kernels
-behind the C-ABI declared in include/pic.h.  PyTorch, when present, supplies
-the HIP stream.  There is no CPU fallback: if the library or a GPU is missing
-the constructor raises.
+behind the C-ABI declared in include/pic.h.  The library owns its device
+memory and, unless a raw hipStream_t handle is passed, its own HIP stream.
+This module does not import torch: the ROCm torch wheel bundles a second HIP
+runtime, and two runtimes in one process do not share streams or memory.
+There is no CPU fallback: if the library or a GPU is missing the constructor
+raises.
 """
 from __future__ import annotations
 
@@ -125,16 +128,6 @@ class PicError(RuntimeError):
         self.code = code
 
 
-def _torch_stream():
-    try:
-        import torch
-        if torch.cuda.is_available():
-            return int(torch.cuda.current_stream().cuda_stream)
-    except Exception:
-        pass
-    return None
-
-
 def _ptr(a):
     return None if a is None else a.ctypes.data
 
@@ -147,7 +140,7 @@ class PicContext:
     collision ``processes`` (shared by all cases).
     """
 
-    def __init__(self, workloads, *, flags=0, history_steps=0, stream="torch",
+    def __init__(self, workloads, *, flags=0, history_steps=0, stream=None,
                  processes=None):
         L = lib()
         self._keep = []
@@ -188,9 +181,8 @@ class PicContext:
             self._keep.append(sig)
             xs[i] = Xsec(species=p["species"], kind=p["kind"], threshold_eV=p["threshold_eV"],
                          e0_eV=p["e0_eV"], de_eV=p["de_eV"], n=sig.size, sigma_m2=sig.ctypes.data)
-        st = _torch_stream() if stream == "torch" else stream
         h = C.c_void_p()
-        rc = L.pic_init(C.byref(h), n, cfgs, sps, xs, len(procs), st, flags)
+        rc = L.pic_init(C.byref(h), n, cfgs, sps, xs, len(procs), stream, flags)
         self._keep = None
         if rc != PIC_OK:
             raise PicError(rc, "pic_init failed")
@@ -230,6 +222,10 @@ class PicContext:
 
     def reset_accumulators(self):
         self._check(lib().pic_reset_accumulators(self._h), "pic_reset_accumulators")
+
+    def sync(self):
+        """Wait for the context's stream (pic_diagnostics synchronises it)."""
+        self._diag(0, 0, Diag())
 
     def last_timing(self):
         ms = C.c_double()

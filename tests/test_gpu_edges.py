@@ -70,7 +70,9 @@ def test_empty_ion_species_and_two_cells():
     wl["case"]["n_cells"] = 2
     for sp in wl["species"]:
         sp["cell"] = (sp["cell"] % 2).astype(np.int32)
-    wl["species"][1] = W.empty_species(E, W.M_AR, w=wl["species"][0]["w"], capacity=4000)
+    # two 1.25 cm cells: electrons fall through the whole RF voltage and ionize
+    wl["species"][0]["capacity"] = 16000
+    wl["species"][1] = W.empty_species(E, W.M_AR, w=wl["species"][0]["w"], capacity=16000)
     ctx = ctx_for(wl, tile=256)
     rep = teacher_forced(ctx, wl, 20)
     assert_report(rep)

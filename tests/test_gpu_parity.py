@@ -39,9 +39,15 @@ def test_periodic_thermal_teacher_forced(gather):
     assert_report(rep)
 
 
-def test_ccp256_implicit_teacher_forced():
-    wl = W.c3(ppc=40, wdt=5.0)
+@pytest.mark.parametrize("wdt,steps", [(2.0, 100), (5.0, 60)])
+def test_ccp256_implicit_teacher_forced(wdt, steps):
+    # at omega_p dt = 5 the D1/EC discharge heats and ionizes without bound
+    # (the oracle does the same; the paper reports no convergence for
+    # dt > 2/omega_p), so that run gets room for the children
+    wl = W.c3(ppc=40, wdt=wdt)
+    for sp in wl["species"]:
+        sp["capacity"] = 4 * sp["cell"].size
     ctx = ctx_for(wl)
-    rep = teacher_forced(ctx, wl, 100)
+    rep = teacher_forced(ctx, wl, steps)
     print(rep)
     assert_report(rep)
