@@ -80,7 +80,9 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-template <typename T>
+// Sum over a workgroup of NT threads; every thread gets the result.  red
+// holds NT/64 values.
+template <typename T, int NT = kBlock>
 __device__ __forceinline__ T block_sum(T v, T* red)
 {
     v = wave_sum(v);
@@ -90,16 +92,16 @@ __device__ __forceinline__ T block_sum(T v, T* red)
     __syncthreads();
     T r = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) r += red[w];
+    for (int w = 0; w < NT / 64; ++w) r += red[w];
     return r;
 }
 
-// inclusive prefix sum of a[0..n) in LDS, fixed summation order
-template <typename T>
+// inclusive prefix sum of a[0..n) in LDS by NT threads, fixed summation order
+template <typename T, int NT = kBlock>
 __device__ void block_scan(T* a, int n, T* red)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per = (n + kBlock - 1) / kBlock;
+    const int per = (n + NT - 1) / NT;
     const int lo = min(tid * per, n), hi = min(lo + per, n);
     T loc = 0;
     for (int i = lo; i < hi; ++i) loc += a[i];

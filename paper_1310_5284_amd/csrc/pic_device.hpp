@@ -70,11 +70,11 @@ struct Case {
     int32_t scheme;       // 0 explicit, 1 D1 implicit
     int32_t gather;       // 0 EC, 1 MC
     int32_t collisions;
-    int32_t first_block;  // this case's workgroups in its launch
+    int32_t first_block;  // this case's first workgroup in the work table
     int32_t n_blocks;
     int32_t history_len;
     double dx, dt;
-    double rf_volts, rf_omega;
+    double rf_volts, rf_omega, rf_freq;
     double background_rho;
     uint32_t key0, key1;  // Philox key = seed
     Species sp[2];
@@ -100,7 +100,6 @@ struct State {
     int32_t n_slots[2];      // occupied slots
     int32_t n_child[2];      // children appended during the running step
     int32_t n_live[2];
-    uint32_t done;           // workgroups finished in the running step
     int32_t flags;           // bit 0: non-finite field, bit 1: capacity
     double K[2];             // kinetic energy at the current half step (J/m^2)
     double WE;               // field energy of the solve the next step uses
@@ -119,27 +118,40 @@ struct Work {
     int32_t nb;  // workgroups of (case, species)
 };
 
-// Per-workgroup partial sums of the ledger (both species).
-struct Partial {
-    double work[2];
-    double coll_dK[2];
-    double absK[2][2];
-    double v2sum[2];     // compaction: exact sum of v^2 of live particles
-    long long abs_n[2][2];
-    long long n_coll[2][4];
-    long long n_cand[2];
-    long long n_created[2];
-    long long n_over[2];
-    long long n_lost[2];
+// Ledger partial sums of one workgroup, stored field-major: field f of
+// workgroup b lives at pd[f * stride + b] (doubles) or pu[f * stride + b]
+// (counters), so that a reduction over workgroups reads contiguous memory.
+// Energies are in units of v^2 (cells per step squared) of the species.
+enum PartD {
+    PD_WORK = 0,      // [2] field work per species
+    PD_COLL = 2,      // [2] collisional kinetic-energy change (children included)
+    PD_ABSK = 4,      // [2][2] absorbed kinetic energy, species x electrode
+    PD_V2 = 8,        // [2] compaction: exact sum of v^2 of live particles
+    PD_N = 10
+};
+enum PartU {
+    PU_ABS = 0,       // [2][2] absorbed particles
+    PU_COLL = 4,      // [2][4] real collisions by process kind
+    PU_CAND = 12,     // [2] candidates
+    PU_CREATED = 14,  // [2] children created
+    PU_OVER = 16,     // [2] candidates beyond the table
+    PU_LOST = 18,     // [2] children lost for lack of capacity
+    PU_N = 20
 };
 
 struct Params {
     Case* cases;
     State* state;
     const Work* work;
-    Partial* partials;
+    double* pd;          // workgroup partials, PD_N fields x stride
+    unsigned* pu;        // workgroup partials, PU_N fields x stride
+    int32_t stride;      // workgroups in the work table
     int32_t n_cases;
     int32_t mode;        // kernel-specific
 };
+
+constexpr int kFinBlock = 1024;   // threads of the per-case finalizing workgroup
+constexpr int kILP = 4;           // particles in flight per thread in k_step
+constexpr int kQCap = 64 * (kILP + 1);   // candidate-queue entries per wavefront
 
 }  // namespace pic

@@ -30,75 +30,110 @@ namespace pic {
 // ---------------------------------------------------------------------------
 constexpr double kEps0 = 8.8541878128e-12;
 
-__device__ void solve_case(Case* C, State* st, long long next_step, bool sample_density,
+template <int NT>
+__device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step, bool sample_density,
                            double* S, double* red)
 {
+    constexpr int kPer = (PIC_MAX_CELLS + 1 + NT - 1) / NT;   // nodes per thread
     const int N = C->n_cells, tid = threadIdx.x;
     const bool periodic = C->bc == 1;
     const bool implicit = C->scheme == 1;
     const double dx = C->dx;
-    // node charges from the per-cell counts and weights
-    for (int g = tid; g <= N; g += kBlock) {
-        double rho = C->background_rho;
+    // X: chi_{j+1/2} of the cells (LDS, after the N+1 values of S)
+    double* X = S + N + 1;
+    // node g = tid + k NT: counts and weights of cells g and g-1 (the loads of
+    // one node are issued together)
+#pragma unroll 1
+    for (int k = 0; k < kPer; ++k) {
+        const int g = tid + k * NT;
+        if (g > N) break;
         const int gg = (periodic && g == N) ? 0 : g;
+        const int gl = gg > 0 ? gg - 1 : (periodic ? N - 1 : -1);
+        long long cn[2], wr[2], wl[2];
+#pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const long long cg = gg < N ? (long long)C->dep_cnt[s][gg] : 0;
-            const long long wg = gg < N ? (long long)C->dep_w[s][gg] : 0;
-            long long wl = 0;
-            if (gg > 0) wl = (long long)C->dep_w[s][gg - 1];
-            else if (periodic) wl = (long long)C->dep_w[s][N - 1];
-            const long long q = cg * (1ll << kFixBits) - wg + wl;
+            cn[s] = gg < N ? (long long)C->dep_cnt[s][gg] : 0;
+            wr[s] = gg < N ? (long long)C->dep_w[s][gg] : 0;
+            wl[s] = gl >= 0 ? (long long)C->dep_w[s][gl] : 0;
+        }
+        double rho = C->background_rho;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const long long q = cn[s] * (1ll << kFixBits) - wr[s] + wl[s];
             C->qfix[s][g] = q;
             if (sample_density) atomicAdd(&C->dens_acc[s][g], (unsigned long long)q);
             rho += (double)q * (C->sp[s].qw_dx / kFixScale);
         }
         C->rho[g] = rho;
-        S[g] = rho;
+        // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
+        S[g] = g == 0 ? 0.0 : rho * dx;
+        if (g < N) {
+            C->ccount[0][g] = cn[0];
+            C->ccount[1][g] = cn[1];
+            const double chi = implicit ? C->sp[0].chi_coef * (double)cn[0] +
+                                              C->sp[1].chi_coef * (double)cn[1]
+                                        : 0.0;
+            X[g] = chi;
+            C->chi[g] = chi;
+        }
     }
-    for (int j = tid; j < N; j += kBlock) {
-        const long long ce = (long long)C->dep_cnt[0][j], ci = (long long)C->dep_cnt[1][j];
-        C->ccount[0][j] = ce;
-        C->ccount[1][j] = ci;
-        C->chi[j] = implicit ? C->sp[0].chi_coef * (double)ce + C->sp[1].chi_coef * (double)ci
-                             : 0.0;
+    __syncthreads();   // every deposit word has been read
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            C->dep_cnt[0][j] = 0; C->dep_cnt[1][j] = 0;
+            C->dep_w[0][j] = 0; C->dep_w[1][j] = 0;
+        }
     }
-    __syncthreads();
-    for (int j = tid; j < N; j += kBlock) {
-        C->dep_cnt[0][j] = 0; C->dep_cnt[1][j] = 0;
-        C->dep_w[0][j] = 0; C->dep_w[1][j] = 0;
-    }
-    if (tid == 0) S[0] = 0.0;
-    __syncthreads();
-    for (int k = 1 + tid; k < N; k += kBlock) S[k] *= dx;
-    __syncthreads();
-    block_scan(S, N, red);                          // S[j] = R_j
+    block_scan<double, NT>(S, N, red);             // S[j] = R_j
     double a = 0.0, b = 0.0;
-    for (int j = tid; j < N; j += kBlock) {
-        const double kap = kEps0 * (1.0 + C->chi[j]);
-        a += S[j] / kap;
-        b += 1.0 / kap;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            const double kap = kEps0 * (1.0 + X[j]);
+            a += S[j] / kap;
+            b += 1.0 / kap;
+        }
     }
-    a = block_sum(a, red);
-    b = block_sum(b, red);
+    a = block_sum<double, NT>(a, red);
+    b = block_sum<double, NT>(b, red);
     double V = 0.0;
-    if (!periodic) V = C->rf_volts * sin(C->rf_omega * ((double)next_step * C->dt));
+    if (!periodic) {
+        // V0 sin(2 pi f t) through the phase in cycles reduced to [0, 1)
+        const double cyc = C->rf_freq * ((double)next_step * C->dt);
+        V = C->rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
+    }
     const double D0 = (V / dx - a) / b;
     double we = 0.0;
-    for (int j = tid; j < N; j += kBlock) {
-        const double kap = kEps0 * (1.0 + C->chi[j]);
-        const double E = (D0 + S[j]) / kap;
-        C->E[j] = E;
-        C->ehat[0][j] = (float)(C->sp[0].accel * E);
-        C->ehat[1][j] = (float)(C->sp[1].accel * E);
-        we += 0.5 * kEps0 * E * E * dx;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            const double E = (D0 + S[j]) / (kEps0 * (1.0 + X[j]));
+            X[j] = E;   // X now holds E
+            C->E[j] = E;
+            C->ehat[0][j] = (float)(C->sp[0].accel * E);
+            C->ehat[1][j] = (float)(C->sp[1].accel * E);
+            we += 0.5 * kEps0 * E * E * dx;
+        }
     }
     __syncthreads();
-    for (int j = tid; j < N; j += kBlock) S[j] = C->E[j];
-    we = block_sum(we, red);
-    block_scan(S, N, red);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) S[j] = X[j];
+    }
+    we = block_sum<double, NT>(we, red);
+    block_scan<double, NT>(S, N, red);
     const double phi0 = periodic ? 0.0 : V;
     if (tid == 0) C->phi[0] = phi0;
-    for (int j = tid; j < N; j += kBlock) C->phi[j + 1] = phi0 - dx * S[j];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) C->phi[j + 1] = phi0 - dx * S[j];
+    }
     if (tid == 0) {
         st->WE = we;
         if (!isfinite(we)) st->flags |= 1;
@@ -108,71 +143,120 @@ __device__ void solve_case(Case* C, State* st, long long next_step, bool sample_
 }
 
 // ---------------------------------------------------------------------------
-// Ledger: the finalizing workgroup reduces the per-workgroup partials of its
-// case in a fixed order and appends one row.
+// Ledger: the workgroup reduces the partials of the case's workgroups (fixed
+// order: a strided per-thread sum, then a tree), then one thread writes the
+// row and folds the appended children into the occupied slots.
 // ---------------------------------------------------------------------------
-__device__ void finish_ledger(Case* C, State* st, const Partial* parts, double* red)
+template <int NT>
+__device__ __forceinline__ void reduce_partials(const Params& P, int fb, int nb, double* sd, long long* su)
 {
-    const int tid = threadIdx.x;
-    const int nb = C->n_blocks, fb = C->first_block;
-    constexpr int kD = 10, kI = 20;
-    __shared__ double sd[kD];
-    __shared__ long long si[kI];
-    for (int f = 0; f < kD; ++f) {
-        double v = 0.0;
-        for (int b = tid; b < nb; b += kBlock) v += (&parts[fb + b].work[0])[f];
-        v = block_sum(v, red);
-        if (tid == 0) sd[f] = v;
+    __shared__ double wd[NT / 64][PD_N];
+    __shared__ unsigned wu[NT / 64][PU_N];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        double d[PD_N];
+#pragma unroll
+        for (int f = 0; f < PD_N; ++f) d[f] = 0.0;
+        for (int b = tid; b < nb; b += NT)
+#pragma unroll
+            for (int f = 0; f < PD_N; ++f) d[f] += P.pd[(size_t)f * P.stride + fb + b];
+#pragma unroll
+        for (int f = 0; f < PD_N; ++f) {
+            const double v = wave_sum(d[f]);
+            if (lane == 0) wd[wave][f] = v;
+        }
     }
-    for (int f = 0; f < kI; ++f) {
-        long long v = 0;
-        for (int b = tid; b < nb; b += kBlock) v += (&parts[fb + b].abs_n[0][0])[f];
-        v = block_sum(v, (long long*)red);
-        if (tid == 0) si[f] = v;
+    {
+        // per-step counts of one case fit in 32 bits
+        unsigned u[PU_N];
+#pragma unroll
+        for (int f = 0; f < PU_N; ++f) u[f] = 0u;
+        for (int b = tid; b < nb; b += NT)
+#pragma unroll
+            for (int f = 0; f < PU_N; ++f) u[f] += P.pu[(size_t)f * P.stride + fb + b];
+#pragma unroll
+        for (int f = 0; f < PU_N; ++f) {
+            const unsigned v = wave_sum(u[f]);
+            if (lane == 0) wu[wave][f] = v;
+        }
     }
     __syncthreads();
-    if (tid != 0) return;
-    // field order of Partial: work[2], coll_dK[2], absK[2][2], v2sum[2]; then
-    // abs_n[2][2], n_coll[2][4], n_cand[2], n_created[2], n_over[2], n_lost[2]
-    pic_ledger L;
-    L.step = st->step;
-    L.WE = st->WE;
-    for (int s = 0; s < 2; ++s) {
-        const double ku = C->sp[s].kin_unit;
-        L.K_before[s] = st->K[s];
-        L.work[s] = sd[0 + s] * ku;
-        L.coll_dK[s] = sd[2 + s] * ku;
-        L.absorbed_K[s][0] = sd[4 + 2 * s] * ku;
-        L.absorbed_K[s][1] = sd[5 + 2 * s] * ku;
-        L.K_after[s] = L.K_before[s] + L.work[s] - L.absorbed_K[s][0] - L.absorbed_K[s][1] +
-                       L.coll_dK[s];
-        st->K[s] = L.K_after[s];
-        L.absorbed_n[s][0] = si[0 + 2 * s];
-        L.absorbed_n[s][1] = si[1 + 2 * s];
-        for (int k = 0; k < 4; ++k) L.n_coll[s][k] = si[4 + 4 * s + k];
-        L.n_candidates[s] = si[12 + s];
-        L.n_created[s] = si[14 + s];
-        L.n_over_table[s] = si[16 + s];
-        L.n_lost[s] = si[18 + s];
-        st->n_live[s] += (int32_t)(L.n_created[s] - L.absorbed_n[s][0] - L.absorbed_n[s][1]);
-        st->lost_total[s] += L.n_lost[s];
-        const long long ns = (long long)st->n_slots[s] + st->n_child[s];
-        const long long cap = C->sp[s].capacity;
-        st->n_slots[s] = (int32_t)(ns < cap ? ns : cap);
-        if (ns > cap || L.n_lost[s] > 0) st->flags |= 2;
-        st->n_child[s] = 0;
+    if (tid < PD_N) {
+        double v = 0.0;
+        for (int k = 0; k < NT / 64; ++k) v += wd[k][tid];
+        sd[tid] = v;
+    } else if (tid < PD_N + PU_N) {
+        unsigned long long v = 0;
+        for (int k = 0; k < NT / 64; ++k) v += wu[k][tid - PD_N];
+        su[tid - PD_N] = (long long)v;
     }
-    if (!isfinite(L.K_after[0]) || !isfinite(L.K_after[1])) st->flags |= 1;
-    pic_ledger* H = (pic_ledger*)C->history;
-    H[0] = L;
-    if (C->history_len > 0) H[1 + (st->history_n % C->history_len)] = L;
-    st->history_n += 1;
+    __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Shared-memory layout of k_step: ehat[N] float | dep[N] u64 | (DIAG) heat[N]
-// float | eedf[kEedfBins] u32.  The finalizer reuses it as N+1 doubles.
-// ---------------------------------------------------------------------------
+// Called by every thread of the workgroup.  Thread 0 reads the case's state
+// in one batch (no load waits behind a store), builds the row in LDS and
+// writes the state back; the row is then copied out by many threads.
+__device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* sd, const long long* si)
+{
+    __shared__ pic_ledger row;
+    __shared__ int ring;
+    if (threadIdx.x == 0) {
+        const State s0 = *st;
+        const double ku0 = C->sp[0].kin_unit, ku1 = C->sp[1].kin_unit;
+        const long long cap0 = C->sp[0].capacity, cap1 = C->sp[1].capacity;
+        const int hl = C->history_len;
+        State s1 = s0;
+        row.step = s0.step;
+        row.WE = s0.WE;
+        bool finite = true;
+        for (int s = 0; s < 2; ++s) {
+            const double ku = s == 0 ? ku0 : ku1;
+            const long long cap = s == 0 ? cap0 : cap1;
+            const double kb = s0.K[s];
+            const double wk = sd[PD_WORK + s] * ku, cd = sd[PD_COLL + s] * ku;
+            const double a0 = sd[PD_ABSK + 2 * s] * ku, a1 = sd[PD_ABSK + 2 * s + 1] * ku;
+            const double ka = kb + wk - a0 - a1 + cd;
+            row.K_before[s] = kb;
+            row.work[s] = wk;
+            row.coll_dK[s] = cd;
+            row.absorbed_K[s][0] = a0;
+            row.absorbed_K[s][1] = a1;
+            row.K_after[s] = ka;
+            s1.K[s] = ka;
+            finite = finite && isfinite(ka);
+            row.absorbed_n[s][0] = si[PU_ABS + 2 * s];
+            row.absorbed_n[s][1] = si[PU_ABS + 2 * s + 1];
+            for (int k = 0; k < 4; ++k) row.n_coll[s][k] = si[PU_COLL + 4 * s + k];
+            row.n_candidates[s] = si[PU_CAND + s];
+            row.n_created[s] = si[PU_CREATED + s];
+            row.n_over_table[s] = si[PU_OVER + s];
+            row.n_lost[s] = si[PU_LOST + s];
+            s1.n_live[s] += (int32_t)(si[PU_CREATED + s] - si[PU_ABS + 2 * s] -
+                                      si[PU_ABS + 2 * s + 1]);
+            s1.lost_total[s] += si[PU_LOST + s];
+            const long long ns = (long long)s0.n_slots[s] + s0.n_child[s];
+            s1.n_slots[s] = (int32_t)(ns < cap ? ns : cap);
+            if (ns > cap || si[PU_LOST + s] > 0) s1.flags |= 2;
+            s1.n_child[s] = 0;
+        }
+        if (!finite) s1.flags |= 1;
+        s1.history_n = s0.history_n + 1;
+        *st = s1;
+        ring = hl > 0 ? 1 + (int)(s0.history_n % hl) : -1;
+    }
+    __syncthreads();
+    constexpr int kW = (int)(sizeof(pic_ledger) / 8);
+    const long long* src = (const long long*)&row;
+    long long* h = (long long*)C->history;
+    for (int k = threadIdx.x; k < kW; k += blockDim.x) {
+        h[k] = src[k];
+        if (ring > 0) h[(size_t)ring * kW + k] = src[k];
+    }
+}
+
+// Shared-memory layout of k_step: ehat[N] float | dep[N] u64 | (DIAG: heat[N]
+// float | eedf[kEedfBins] u32) | candidate queues.  The finalizer reuses it as
+// N+1 doubles.
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct BlockAcc {
@@ -343,6 +427,45 @@ __device__ __forceinline__ void write_particle(const Species& S, long long slot,
 }
 
 // ---------------------------------------------------------------------------
+// Deposit of one particle per lane into the privatised LDS grid (Eq. (2)).
+// When every depositing lane of the wavefront lands in the same cell (the
+// common case for cell-sorted ions) the weights are summed across the
+// wavefront first and one LDS atomic is issued instead of 64 colliding ones.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want, int c, float o,
+                                             int& lo, int& hi)
+{
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    const int cl = __shfl(c, leader, 64);
+    if (__ballot(want && c != cl) == 0ull) {
+        unsigned w = want ? __float2uint_rn(o * 16777216.0f) : 0u;
+        w = wave_sum(w);   // at most 64 * 2^24 = 2^30
+        if (lane == leader) {
+            atomicAdd(&dep[cl], ((unsigned long long)__popcll(m) << 40) + (unsigned long long)w);
+            range_note(lo, hi, cl);
+        }
+    } else if (want) {
+        atomicAdd(&dep[c], packw(o));
+        range_note(lo, hi, c);
+    }
+}
+
+// Per-wavefront queue of collision candidates in LDS (structure of arrays).
+
+struct WaveQueue {
+    int* idx;     // particle slot
+    int* c1;      // cell of x_{n+1}
+    float* o1;    // offset of x_{n+1}
+    float* vn;    // v_{n+1/2} (x component) before the collision
+    float* abn;   // abar_n (implicit)
+};
+
+__host__ __device__ inline size_t queue_lds_bytes() { return (size_t)kWaves * kQCap * 5 * 4; }
+
+// ---------------------------------------------------------------------------
 // k_step: one step of every case in this launch.  Workgroup = a contiguous
 // chunk of one species of one case.  Per particle (explicit, leap-frog):
 //   a = ehat[cell] (EC, Eq. (3)) or CIC of the nodal field (MC);
@@ -351,20 +474,22 @@ __device__ __forceinline__ void write_particle(const Species& S, long long slot,
 // Per particle (implicit, D1, beta = 1/2; stored x~, v~, abar):
 //   a = ehat[cell of x~];  x = x~ + a/2;  v = v~ + a/2;  abar = (abar + a)/2;
 //   absorb; MCC; predict v~' = v + abar/2, x~' = x + v~'; absorb; deposit x~'.
-// The deposit goes to a privatised LDS copy of the grid (one int64 per cell
-// packs count and summed weight) and is flushed over the cell range the
-// workgroup touched.  The last workgroup of a case closes the ledger and
-// solves the field of the next step.
+//
+// The streaming loop keeps kILP particles per thread in flight and decides
+// candidacy (u0 < P_null, an integer compare on the Philox word).  Candidates
+// go to a per-wavefront LDS queue (ballot + prefix); whenever 64 are queued
+// the wavefront processes them with every lane busy.  The deposit goes to a
+// privatised LDS grid (one int64 per cell packs count and summed weight) and
+// is flushed over the cell range the workgroup touched.  The last workgroup
+// of a case closes the ledger and solves the field of the next step.
 // ---------------------------------------------------------------------------
 template <int SCHEME, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_step(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockAcc acc;
-    __shared__ double red[kWaves];
-    __shared__ int s_last;
     constexpr bool kImp = SCHEME == 1;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gblk = P.mode + (int)blockIdx.x;
     const Work w = P.work[gblk];
     Case* C = P.cases + w.c;
@@ -377,11 +502,25 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const bool coll = C->collisions != 0 && S.n_proc > 0;
     const uint32_t k0 = C->key0, k1 = C->key1;
 
+    const size_t o_dep = align16(4 * (size_t)N);
+    const size_t o_heat = o_dep + align16(8 * (size_t)N);
+    const size_t o_eedf = o_heat + align16(4 * (size_t)N);
+    const size_t o_q = DIAG ? o_eedf + align16(4 * (size_t)kEedfBins) : o_heat;
     float* eh = (float*)smem;
-    unsigned long long* dep = (unsigned long long*)(smem + align16(4 * (size_t)N));
-    float* heat = (float*)(smem + align16(4 * (size_t)N) + align16(8 * (size_t)N));
-    unsigned* eedf = (unsigned*)(smem + 2 * align16(4 * (size_t)N) + align16(8 * (size_t)N));
+    unsigned long long* dep = (unsigned long long*)(smem + o_dep);
+    float* heat = (float*)(smem + o_heat);
+    unsigned* eedf = (unsigned*)(smem + o_eedf);
+    WaveQueue q;
+    {
+        int* qb = (int*)(smem + o_q) + (size_t)wave * kQCap * 5;
+        q.idx = qb;
+        q.c1 = qb + kQCap;
+        q.o1 = (float*)(qb + 2 * kQCap);
+        q.vn = (float*)(qb + 3 * kQCap);
+        q.abn = (float*)(qb + 4 * kQCap);
+    }
 
+#pragma unroll 8
     for (int j = tid; j < N; j += kBlock) {
         eh[j] = C->ehat[s][j];
         dep[j] = 0ull;
@@ -424,130 +563,88 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     double work = 0.0, cdk = 0.0;
     unsigned cand = 0u;
     int lo = kNoCell, hi = -1;
+    int qh = 0, qn = 0;   // wavefront-uniform queue head and length
 
-    for (int base = start; base < end; base += kBlock) {
-        const int i = base + tid;
-        const bool in = i < end;
-        int c = in ? cellp[i] : -1;
-        bool live = c >= 0;
-        float o = 0.0f, v = 0.0f, ab = 0.0f, a = 0.0f;
-        if (live) {
-            o = offp[i];
-            v = vxp[i];
-            if (kImp) ab = abp[i];
-            a = mc ? gather_mc(eh, N, periodic, c, o) : eh[c];
-        }
-        // push: vn is v_{n+1/2}; (c2, o2) the position the step ends at
-        float vn, ab_n = 0.0f, vold;
-        int c1 = c;
-        float o1 = o;
-        if (kImp) {
-            vold = v - 0.5f * ab;
-            vn = v + 0.5f * a;
-            ab_n = 0.5f * (ab + a);
-            o1 = o + 0.5f * a;
-        } else {
-            vold = v;
-            vn = v + a;
-            o1 = o + vn;
-        }
-        if (live) {
-            const float dk = (vn - vold) * (vn + vold);
-            work += (double)dk;
-            if (DIAG) {
-                atomicAdd(&heat[c], dk);
-                range_note(lo, hi, c);
-            }
-            renorm(c1, o1);
-        }
-        float vy = 0.0f, vz = 0.0f;
-        bool have_yz = false, dirty = false;
-        // boundary at x_{n+1}
-        if (live) {
-            if (periodic) {
-                c1 %= N;
-                if (c1 < 0) c1 += N;
-            } else if (c1 < 0 || c1 >= N) {
-                vy = vyp[i];
-                vz = vzp[i];
-                const int e = c1 < 0 ? 0 : 1;
-                atomicAdd(&acc.absK[s][e], (double)(vn * vn + vy * vy + vz * vz));
-                atomicAdd(&acc.abs_n[s][e], 1u);
-                cellp[i] = -1;
-                live = false;
-            }
-        }
+    auto absorb = [&](int i, int e, float vxh, float vy, float vz) {
+        atomicAdd(&acc.absK[s][e], (double)(vxh * vxh + vy * vy + vz * vz));
+        atomicAdd(&acc.abs_n[s][e], 1u);
+        cellp[i] = -1;
+    };
+    auto eedf_note = [&](float vx, float vy, float vz) {
+        const float fb = (vx * vx + vy * vy + vz * vz) * S.eps_unit * S.eedf_scale;
+        const int bin = fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
+        atomicAdd(&eedf[bin], 1u);
+    };
+
+    // Process the m (<= 64) oldest queued candidates, one per lane.  The
+    // queue is a ring of kQCap entries: qh is its head, qn its length.
+    auto drain = [&](int m) {
+        __syncwarp();
+        const bool act = lane < m;
+        int i = 0, c1 = 0;
+        float o1 = 0.0f, vn = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
+        uint64_t id = 0;
         int kind = -1;
         Child ch;
-        uint64_t id = 0;
-        if (live && coll) {
+        if (act) {
+            int e = qh + lane;
+            if (e >= kQCap) e -= kQCap;
+            i = q.idx[e];
+            c1 = q.c1[e];
+            o1 = q.o1[e];
+            vn = q.vn[e];
+            abn = q.abn[e];
             id = idp[i];
+            vy = vyp[i];
+            vz = vzp[i];
             const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
                                     (uint32_t)s << 28, k0, k1);
-            if ((r0.x >> 9) < S.cand_thr) {
-                ++cand;
-                vy = vyp[i];
-                vz = vzp[i];
-                have_yz = true;
-                const float v2b = vn * vn + vy * vy + vz * vz;
-                bool over = false;
-                kind = s == 0 ? collide_electron(S, r0, id, step32, k0, k1, vn, vy, vz, over, ch)
-                              : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
-                if (over) atomicAdd(&acc.n_over, 1u);
-                if (kind >= 0) {
-                    dirty = true;
-                    atomicAdd(&acc.n_coll[kind], 1u);
-                    cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
-                }
-            }
-        }
-        if (DIAG && s == 0 && live) {
-            if (!have_yz) {
-                vy = vyp[i];
-                vz = vzp[i];
-            }
-            const float eps = (vn * vn + vy * vy + vz * vz) * S.eps_unit;
-            const float fb = eps * S.eedf_scale;   // NaN or negative -> bin 0
-            const int bin = fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
-            atomicAdd(&eedf[bin], 1u);
-        }
-        // predicted position (implicit) or final position (explicit)
-        int c2 = c1;
-        float o2 = o1, vst = vn;
-        if (kImp && live) {
-            vst = vn + 0.5f * ab_n;
-            o2 = o1 + vst;
-            renorm(c2, o2);
-            if (periodic) {
-                c2 %= N;
-                if (c2 < 0) c2 += N;
-            } else if (c2 < 0 || c2 >= N) {
-                if (!have_yz) {
-                    vy = vyp[i];
-                    vz = vzp[i];
-                }
-                const int e = c2 < 0 ? 0 : 1;
-                atomicAdd(&acc.absK[s][e], (double)(vn * vn + vy * vy + vz * vz));
-                atomicAdd(&acc.abs_n[s][e], 1u);
-                cellp[i] = -1;
-                live = false;
-            }
-        }
-        if (live) {
-            atomicAdd(&dep[c2], packw(o2));
-            range_note(lo, hi, c2);
-            cellp[i] = c2;
-            offp[i] = o2;
-            vxp[i] = vst;
-            if (kImp) abp[i] = ab_n;
-            if (dirty) {
+            ++cand;
+            const float v2b = vn * vn + vy * vy + vz * vz;
+            bool over = false;
+            kind = s == 0 ? collide_electron(S, r0, id, step32, k0, k1, vn, vy, vz, over, ch)
+                          : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
+            if (over) atomicAdd(&acc.n_over, 1u);
+            if (kind >= 0) {
+                atomicAdd(&acc.n_coll[kind], 1u);
+                cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
                 vyp[i] = vy;
                 vzp[i] = vz;
             }
+            if (DIAG && s == 0) eedf_note(vn, vy, vz);
         }
+        // implicit: predict from the post-collision velocity, absorb, deposit
+        bool dep_ok = false;
+        int c2 = c1;
+        float o2 = o1;
+        if (act) {
+            if (kImp) {
+                const float vst = vn + 0.5f * abn;
+                o2 = o1 + vst;
+                renorm(c2, o2);
+                bool gone = false;
+                if (periodic) {
+                    c2 %= N;
+                    if (c2 < 0) c2 += N;
+                } else if (c2 < 0 || c2 >= N) {
+                    absorb(i, c2 < 0 ? 0 : 1, vn, vy, vz);
+                    gone = true;
+                }
+                if (!gone) {
+                    cellp[i] = c2;
+                    offp[i] = o2;
+                    vxp[i] = vst;
+                    abp[i] = abn;
+                    dep_ok = true;
+                }
+            } else {
+                vxp[i] = vn;
+            }
+        }
+        if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
         // ionization children: electron and ion at the parent's x_{n+1};
         // implicit children are predicted from there with abar = 0
-        const bool ion_ev = kind == PIC_IONIZATION && s == 0;
+        const bool ion_ev = act && kind == PIC_IONIZATION && s == 0;
         if (__ballot(ion_ev)) {
             bool want_e = false, want_i = false;
             int ce = c1, ci = c1;
@@ -586,15 +683,16 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             }
             const long long se = reserve_slot(want_e, &st->n_child[0], ns0, C->sp[0].capacity);
             const long long si = reserve_slot(want_i, &st->n_child[1], ns1, C->sp[1].capacity);
+            bool dep_e = false;
             if (want_e) {
                 if (se >= 0) {
                     write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide, kImp);
-                    atomicAdd(&dep[ce], packw(oe));
-                    range_note(lo, hi, ce);
+                    dep_e = true;
                 } else {
                     atomicAdd(&acc.n_lost[0], 1u);
                 }
             }
+            deposit_wave(dep, dep_e, ce, oe, lo, hi);
             if (want_i) {
                 if (si >= 0) {
                     write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi, kImp);
@@ -605,6 +703,130 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
             }
         }
+        __syncwarp();
+    };
+
+    for (int base = start;;) {
+      const bool stream = base < end;
+      if (stream) {
+        int c[kILP];
+        float o[kILP], v[kILP], ab[kILP];
+        uint64_t idv[kILP];
+#pragma unroll
+        for (int k = 0; k < kILP; ++k) {
+            const int i = base + k * kBlock + tid;
+            c[k] = i < end ? cellp[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kILP; ++k) {
+            const int i = base + k * kBlock + tid;
+            o[k] = v[k] = ab[k] = 0.0f;
+            idv[k] = 0;
+            if (c[k] >= 0) {
+                o[k] = offp[i];
+                v[k] = vxp[i];
+                if (kImp) ab[k] = abp[i];
+                if (coll) idv[k] = idp[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kILP; ++k) {
+            const int i = base + k * kBlock + tid;
+            int cc = c[k];
+            bool live = cc >= 0;
+            float a = 0.0f;
+            if (live) a = mc ? gather_mc(eh, N, periodic, cc, o[k]) : eh[cc];
+            float vn, vold, abn = 0.0f, o1;
+            if (kImp) {
+                vold = v[k] - 0.5f * ab[k];
+                vn = v[k] + 0.5f * a;
+                abn = 0.5f * (ab[k] + a);
+                o1 = o[k] + 0.5f * a;
+            } else {
+                vold = v[k];
+                vn = v[k] + a;
+                o1 = o[k] + vn;
+            }
+            int c1 = cc;
+            if (live) {
+                const float dk = (vn - vold) * (vn + vold);
+                work += (double)dk;
+                if (DIAG) {
+                    atomicAdd(&heat[cc], dk);
+                    range_note(lo, hi, cc);
+                }
+                renorm(c1, o1);
+                if (periodic) {
+                    c1 %= N;
+                    if (c1 < 0) c1 += N;
+                } else if (c1 < 0 || c1 >= N) {
+                    absorb(i, c1 < 0 ? 0 : 1, vn, vyp[i], vzp[i]);
+                    live = false;
+                }
+            }
+            bool isc = false;
+            if (live && coll) {
+                const uint4 r0 = philox((uint32_t)idv[k], (uint32_t)(idv[k] >> 32), step32,
+                                        (uint32_t)s << 28, k0, k1);
+                isc = (r0.x >> 9) < S.cand_thr;
+            }
+            // non-candidates finish here; explicit candidates keep their position
+            int c2 = c1;
+            float o2 = o1, vst = vn;
+            bool dep_now = false;
+            if (live && !isc) {
+                if (kImp) {
+                    vst = vn + 0.5f * abn;
+                    o2 = o1 + vst;
+                    renorm(c2, o2);
+                    if (periodic) {
+                        c2 %= N;
+                        if (c2 < 0) c2 += N;
+                    } else if (c2 < 0 || c2 >= N) {
+                        absorb(i, c2 < 0 ? 0 : 1, vn, vyp[i], vzp[i]);
+                        live = false;
+                    }
+                }
+                if (live) {
+                    cellp[i] = c2;
+                    offp[i] = o2;
+                    vxp[i] = vst;
+                    if (kImp) abp[i] = abn;
+                    dep_now = true;
+                    if (DIAG && s == 0) eedf_note(vn, vyp[i], vzp[i]);
+                }
+            } else if (live && !kImp) {
+                cellp[i] = c1;
+                offp[i] = o1;
+                dep_now = true;
+            }
+            deposit_wave(dep, dep_now, c2, o2, lo, hi);
+            // queue the candidates of this wavefront
+            const bool enq = live && isc;
+            const unsigned long long qm = __ballot(enq);
+            if (enq) {
+                int slot = qh + qn + __popcll(qm & ((1ull << lane) - 1ull));
+                if (slot >= kQCap) slot -= kQCap;
+                q.idx[slot] = i;
+                q.c1[slot] = c1;
+                q.o1[slot] = o1;
+                q.vn[slot] = vn;
+                q.abn[slot] = abn;
+            }
+            qn += __popcll(qm);
+        }
+        base += kBlock * kILP;
+      }
+        // drain full batches of 64, and the remainder once the chunk is done
+        const bool tail = base >= end;
+        while (qn >= 64 || (tail && qn > 0)) {
+            const int m = qn < 64 ? qn : 64;
+            drain(m);
+            qh += m;
+            if (qh >= kQCap) qh -= kQCap;
+            qn -= m;
+        }
+        if (tail) break;
     }
 
     // flush the privatised deposit over the touched cell range
@@ -630,54 +852,75 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             for (int j = tid; j < kEedfBins; j += kBlock)
                 if (eedf[j]) atomicAdd(&C->eedf_acc[j], (unsigned long long)eedf[j]);
     }
-    // workgroup partial of the ledger
-    work = block_sum(work, red);
-    cdk = block_sum(cdk, red);
-    const unsigned ncand = block_sum(cand, (unsigned*)red);
+    // workgroup partial of the ledger (plain stores, reduced by k_finalize)
+    __shared__ double wsum[kWaves][3];
+    work = wave_sum(work);
+    cdk = wave_sum(cdk);
+    const unsigned ncw = wave_sum(cand);
+    if (lane == 0) {
+        wsum[wave][0] = work;
+        wsum[wave][1] = cdk;
+        wsum[wave][2] = (double)ncw;
+    }
+    __syncthreads();
     if (tid == 0) {
-        Partial& pp = P.partials[gblk];
+        double wk = 0.0, cd = 0.0, nc = 0.0;
+        for (int k = 0; k < kWaves; ++k) {
+            wk += wsum[k][0];
+            cd += wsum[k][1];
+            nc += wsum[k][2];
+        }
         const int o = 1 - s;
-        pp.work[s] = work;
-        pp.work[o] = 0.0;
-        pp.coll_dK[s] = cdk;
-        pp.coll_dK[o] = s == 0 ? acc.other_dK : 0.0;
+        const size_t S_ = (size_t)P.stride;
+        double* pd = P.pd + gblk;
+        unsigned* pu = P.pu + gblk;
+        pd[(PD_WORK + s) * S_] = wk;
+        pd[(PD_WORK + o) * S_] = 0.0;
+        pd[(PD_COLL + s) * S_] = cd;
+        pd[(PD_COLL + o) * S_] = s == 0 ? acc.other_dK : 0.0;
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
-                pp.absK[a][b] = acc.absK[a][b];
-                pp.abs_n[a][b] = acc.abs_n[a][b];
+                pd[(PD_ABSK + 2 * a + b) * S_] = acc.absK[a][b];
+                pu[(PU_ABS + 2 * a + b) * S_] = acc.abs_n[a][b];
             }
-        pp.v2sum[0] = pp.v2sum[1] = 0.0;
+        pd[(PD_V2 + 0) * S_] = 0.0;
+        pd[(PD_V2 + 1) * S_] = 0.0;
         for (int k = 0; k < 4; ++k) {
-            pp.n_coll[s][k] = acc.n_coll[k];
-            pp.n_coll[o][k] = 0;
+            pu[(PU_COLL + 4 * s + k) * S_] = acc.n_coll[k];
+            pu[(PU_COLL + 4 * o + k) * S_] = 0u;
         }
-        pp.n_cand[s] = ncand;
-        pp.n_cand[o] = 0;
-        pp.n_created[0] = acc.n_created[0];
-        pp.n_created[1] = acc.n_created[1];
-        pp.n_over[s] = acc.n_over;
-        pp.n_over[o] = 0;
-        pp.n_lost[0] = acc.n_lost[0];
-        pp.n_lost[1] = acc.n_lost[1];
+        pu[(PU_CAND + s) * S_] = (unsigned)nc;
+        pu[(PU_CAND + o) * S_] = 0u;
+        pu[(PU_CREATED + 0) * S_] = acc.n_created[0];
+        pu[(PU_CREATED + 1) * S_] = acc.n_created[1];
+        pu[(PU_OVER + s) * S_] = acc.n_over;
+        pu[(PU_OVER + o) * S_] = 0u;
+        pu[(PU_LOST + 0) * S_] = acc.n_lost[0];
+        pu[(PU_LOST + 1) * S_] = acc.n_lost[1];
     }
-    // the last workgroup of the case finalises the step
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(&st->done, 1u);
-        s_last = (prev + 1u == (unsigned)C->n_blocks);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    finish_ledger(C, st, P.partials, red);
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize: one workgroup per case after the particle pass.  Closes the
+// ledger of the step and solves the FP64 field of the next one.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kFinBlock / 64];
+    __shared__ double sd[PD_N];
+    __shared__ long long si[PU_N];
+    Case* C = P.cases + blockIdx.x;
+    State* st = P.state + blockIdx.x;
+    reduce_partials<kFinBlock>(P, C->first_block, C->n_blocks, sd, si);
+    finish_ledger(C, st, sd, si);
     __syncthreads();
     const long long next = st->step + 1;
-    solve_case(C, st, next + (kImp ? 1 : 0), DIAG, (double*)smem, red);
-    if (tid == 0) {
-        if (DIAG) st->eedf_samples += 1;
+    solve_case<kFinBlock>(C, st, next + (C->scheme == 1 ? 1 : 0), sample != 0, (double*)smem,
+                          red);
+    if (threadIdx.x == 0) {
+        if (sample) st->eedf_samples += 1;
         st->step = next;
-        st->done = 0u;
     }
 }
 
@@ -729,6 +972,27 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
     }
 }
 
+// LDS counter increment for the valid lanes of a wavefront.  Returns, for
+// each valid lane, the value a plain atomicAdd of 1 would have returned (its
+// slot).  When all valid lanes hit one cell (cell-sorted particles) a single
+// atomic serves the wavefront.
+__device__ __forceinline__ unsigned wave_count_add(unsigned* h, int c, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(valid);
+    if (m == 0ull) return 0u;
+    const int leader = __ffsll((long long)m) - 1;
+    const int key = __shfl(c, leader, 64);
+    if (__ballot(valid && c != key) == 0ull) {
+        // every valid lane hits one cell: one atomic for the wavefront
+        unsigned base = 0u;
+        if (lane == leader) base = atomicAdd(&h[key], (unsigned)__popcll(m));
+        base = __shfl(base, leader, 64);
+        return base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+    }
+    return valid ? atomicAdd(&h[c], 1u) : 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Compaction: drop absorbed slots and sort every species by cell (a stable
 // counting sort across workgroups; the order inside one cell is arbitrary).
@@ -756,12 +1020,11 @@ __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* his
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk, end = min(n, start + chunk);
     int lo = kNoCell, hi = -1;
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-        const int c = S.cell[i];
-        if (c >= 0) {
-            atomicAdd(&lh[c], 1u);
-            range_note(lo, hi, c);
-        }
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int c = i < end ? S.cell[i] : -1;
+        wave_count_add(lh, c, c >= 0);
+        if (c >= 0) range_note(lo, hi, c);
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
@@ -822,12 +1085,11 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk, end = min(n, start + chunk);
     int lo = kNoCell, hi = -1;
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-        const int c = S.cell[i];
-        if (c >= 0) {
-            atomicAdd(&lh[c], 1u);
-            range_note(lo, hi, c);
-        }
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int c = i < end ? S.cell[i] : -1;
+        wave_count_add(lh, c, c >= 0);
+        if (c >= 0) range_note(lo, hi, c);
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
@@ -841,10 +1103,12 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     }
     __syncthreads();
     double v2 = 0.0;
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-        const int c = S.cell[i];
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int c = i < end ? S.cell[i] : -1;
+        const unsigned r = wave_count_add(lh, c, c >= 0);
         if (c < 0) continue;
-        const unsigned d = lb[c] + atomicAdd(&lh[c], 1u);
+        const unsigned d = lb[c] + r;
         const float vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
         S.cell2[d] = c;
         S.off2[d] = S.off[i];
@@ -861,39 +1125,35 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
         v2 += (double)(vh * vh + vy * vy + vz * vz);
     }
     v2 = block_sum(v2, red);
-    if (threadIdx.x == 0) P.partials[blockIdx.x].v2sum[w.s] = v2;
+    if (threadIdx.x == 0) {
+        P.pd[(size_t)(PD_V2 + w.s) * P.stride + blockIdx.x] = v2;
+        P.pd[(size_t)(PD_V2 + 1 - w.s) * P.stride + blockIdx.x] = 0.0;
+    }
 }
 
 // one workgroup per case: swap buffers, set counts and the exact kinetic energy
-__global__ __launch_bounds__(kBlock) void k_compact_finish(Params P)
+__global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
 {
-    __shared__ double red[kWaves];
+    __shared__ double sd[PD_N];
+    __shared__ long long si[PU_N];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    const int nb = C->n_blocks, fb = C->first_block;
+    reduce_partials<kFinBlock>(P, C->first_block, C->n_blocks, sd, si);
+    if (threadIdx.x != 0) return;
     for (int s = 0; s < 2; ++s) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kBlock) {
-            const Work w = P.work[fb + b];
-            if (w.s == s) v += P.partials[fb + b].v2sum[s];
-        }
-        v = block_sum(v, red);
-        if (threadIdx.x == 0) {
-            Species& S = C->sp[s];
-            st->K[s] = v * S.kin_unit;
-            st->sortK[s] = st->K[s];
-            const int live = (int)st->sort_live[s];
-            st->n_slots[s] = live;
-            st->n_live[s] = live;
-            int32_t* t0 = S.cell; S.cell = S.cell2; S.cell2 = t0;
-            float* t1 = S.off; S.off = S.off2; S.off2 = t1;
-            t1 = S.vx; S.vx = S.vx2; S.vx2 = t1;
-            t1 = S.vy; S.vy = S.vy2; S.vy2 = t1;
-            t1 = S.vz; S.vz = S.vz2; S.vz2 = t1;
-            uint64_t* t2 = S.id; S.id = S.id2; S.id2 = t2;
-            t1 = S.abar; S.abar = S.abar2; S.abar2 = t1;
-        }
-        __syncthreads();
+        Species& S = C->sp[s];
+        st->K[s] = sd[PD_V2 + s] * S.kin_unit;
+        st->sortK[s] = st->K[s];
+        const int live = (int)st->sort_live[s];
+        st->n_slots[s] = live;
+        st->n_live[s] = live;
+        int32_t* t0 = S.cell; S.cell = S.cell2; S.cell2 = t0;
+        float* t1 = S.off; S.off = S.off2; S.off2 = t1;
+        t1 = S.vx; S.vx = S.vx2; S.vx2 = t1;
+        t1 = S.vy; S.vy = S.vy2; S.vy2 = t1;
+        t1 = S.vz; S.vz = S.vz2; S.vz2 = t1;
+        uint64_t* t2 = S.id; S.id = S.id2; S.id2 = t2;
+        t1 = S.abar; S.abar = S.abar2; S.abar2 = t1;
     }
 }
 
@@ -939,13 +1199,13 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_solve(Params P)
+__global__ __launch_bounds__(kFinBlock) void k_solve(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kWaves];
+    __shared__ double red[kFinBlock / 64];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    solve_case(C, st, st->step + (C->scheme == 1 ? 1 : 0), false, (double*)smem, red);
+    solve_case<kFinBlock>(C, st, st->step + (C->scheme == 1 ? 1 : 0), false, (double*)smem, red);
 }
 
 }  // namespace pic

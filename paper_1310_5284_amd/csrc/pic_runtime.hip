@@ -27,6 +27,7 @@ __global__ void k_compact_scatter(Params P, uint32_t* cursor_all, const int64_t*
 __global__ void k_compact_finish(Params P);
 __global__ void k_deposit(Params P);
 __global__ void k_solve(Params P);
+__global__ void k_finalize(Params P, int sample);
 }  // namespace pic
 
 using namespace pic;
@@ -65,7 +66,8 @@ struct pic_ctx {
     Case* d_cases = nullptr;
     State* d_state = nullptr;
     Work* d_work = nullptr;
-    Partial* d_partials = nullptr;
+    double* d_pd = nullptr;        // workgroup partials (field-major)
+    unsigned* d_pu = nullptr;
     uint32_t* d_hist = nullptr;
     uint32_t* d_cursor = nullptr;
     int64_t* d_hist_off = nullptr;
@@ -132,11 +134,14 @@ int dalloc(pic_ctx* c, std::vector<void*>& list, T** p, size_t n)
 
 size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Dynamic LDS of k_step: ehat[N] float | dep[N] u64 | (DIAG: heat[N] float |
+// eedf[kEedfBins] u32) | per-wavefront candidate queues.
 size_t step_lds(int N, bool diag)
 {
     size_t b = a16(4 * (size_t)N) + a16(8 * (size_t)N);
-    if (diag) b += a16(4 * (size_t)N) + 4 * (size_t)kEedfBins;
-    return std::max(b, 8 * ((size_t)N + 1) + 16);
+    if (diag) b += a16(4 * (size_t)N) + a16(4 * (size_t)kEedfBins);
+    b += (size_t)kWaves * kQCap * 5 * 4;
+    return b;
 }
 
 // Null-collision bound: n_g max over table intervals of
@@ -196,14 +201,18 @@ int build_work(pic_ctx* c)
 int upload_work(pic_ctx* c)
 {
     if (c->d_work) (void)hipFree(c->d_work);
-    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_pd) (void)hipFree(c->d_pd);
+    if (c->d_pu) (void)hipFree(c->d_pu);
     c->d_work = nullptr;
-    c->d_partials = nullptr;
-    HIPCHK(c, hipMalloc(&c->d_work, sizeof(Work) * c->work.size()));
-    HIPCHK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(Work) * c->work.size(),
-                        hipMemcpyHostToDevice));
-    HIPCHK(c, hipMalloc(&c->d_partials, sizeof(Partial) * c->work.size()));
-    HIPCHK(c, hipMemset(c->d_partials, 0, sizeof(Partial) * c->work.size()));
+    c->d_pd = nullptr;
+    c->d_pu = nullptr;
+    const size_t nb = c->work.size();
+    HIPCHK(c, hipMalloc(&c->d_work, sizeof(Work) * nb));
+    HIPCHK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(Work) * nb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&c->d_pd, sizeof(double) * PD_N * nb));
+    HIPCHK(c, hipMemset(c->d_pd, 0, sizeof(double) * PD_N * nb));
+    HIPCHK(c, hipMalloc(&c->d_pu, sizeof(unsigned) * PU_N * nb));
+    HIPCHK(c, hipMemset(c->d_pu, 0, sizeof(unsigned) * PU_N * nb));
     return PIC_OK;
 }
 
@@ -213,7 +222,9 @@ Params params(pic_ctx* c, int mode)
     p.cases = c->d_cases;
     p.state = c->d_state;
     p.work = c->d_work;
-    p.partials = c->d_partials;
+    p.pd = c->d_pd;
+    p.pu = c->d_pu;
+    p.stride = (int32_t)c->work.size();
     p.n_cases = c->n_cases;
     p.mode = mode;
     return p;
@@ -229,7 +240,7 @@ int compaction(pic_ctx* c)
                        c->d_hist, c->d_cursor, (const int64_t*)c->d_hist_off);
     hipLaunchKernelGGL(k_compact_scatter, dim3(c->n_blocks), dim3(kBlock), l2, c->stream, p,
                        c->d_cursor, (const int64_t*)c->d_hist_off);
-    hipLaunchKernelGGL(k_compact_finish, dim3(c->n_cases), dim3(kBlock), 0, c->stream, p);
+    hipLaunchKernelGGL(k_compact_finish, dim3(c->n_cases), dim3(kFinBlock), 0, c->stream, p);
     HIPCHK(c, hipGetLastError());
     c->since_sort = 0;
     return PIC_OK;
@@ -243,7 +254,8 @@ int set_lds_limits(pic_ctx* c, size_t need)
     const void* ks[] = {(const void*)k_step<0, false>, (const void*)k_step<0, true>,
                         (const void*)k_step<1, false>, (const void*)k_step<1, true>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
-                        (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve};
+                        (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve,
+                        (const void*)k_finalize};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v);
         if (e != hipSuccess) {
@@ -352,6 +364,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         C.dt = dt;
         C.rf_volts = g.rf_volts;
         C.rf_omega = 6.283185307179586476925286766559 * g.rf_freq_hz;
+        C.rf_freq = g.rf_freq_hz;
         C.background_rho = g.background_rho;
         C.key0 = (uint32_t)g.seed;
         C.key1 = (uint32_t)(g.seed >> 32);
@@ -551,8 +564,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         Params p = params(c, 0);
         hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock), 8 * (size_t)c->maxN,
                            c->stream, p);
-        hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kBlock), 8 * ((size_t)c->maxN + 1) + 16,
-                           c->stream, p);
+        hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock),
+                           16 * ((size_t)c->maxN + 1) + 16, c->stream, p);
         INITCHK(hipGetLastError());
         INITCHK(hipStreamSynchronize(c->stream));
     }
@@ -571,7 +584,8 @@ void destroy_ctx(pic_ctx* c)
         for (void* p : h.allocs) (void)hipFree(p);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->d_work) (void)hipFree(c->d_work);
-    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_pd) (void)hipFree(c->d_pd);
+    if (c->d_pu) (void)hipFree(c->d_pu);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -621,6 +635,8 @@ int run_steps(pic_ctx* c, int64_t n, int which)
                 c->ev_used += 2;
             }
         }
+        hipLaunchKernelGGL(k_finalize, dim3(c->n_cases), dim3(kFinBlock),
+                           16 * ((size_t)c->maxN + 1) + 16, c->stream, params(c, 0), diag ? 1 : 0);
         HIPCHK(c, hipGetLastError());
         c->steps_taken++;
         if (++c->since_sort >= c->sort_every)
