@@ -10,6 +10,23 @@
 
 namespace pic {
 
+// Pointers into device memory in the global address space: loads and stores
+// through them compile to global (not flat) instructions, which do not tie up
+// the LDS counter and keep independent loads in flight together.
+#define PIC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ PIC_GLOBAL T* gp(T* p)
+{
+    return (PIC_GLOBAL T*)p;
+}
+
+// relaxed device-scope atomic add through a global pointer
+template <class T>
+__device__ __forceinline__ T gatomic_add(PIC_GLOBAL T* p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with the round keys bumped by the Weyl constants.
@@ -78,6 +95,19 @@ __device__ __forceinline__ T wave_sum(T v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Total of a uint32 over the 64 lanes, through DPP row shifts and row
+// broadcasts (no LDS traffic).  Must be called with every lane active.
+__device__ __forceinline__ unsigned wave_total_u32(unsigned v)
+{
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false); // row_bcast:15
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Sum over a workgroup of NT threads; every thread gets the result.  red

@@ -154,4 +154,25 @@ constexpr int kFinBlock = 1024;   // threads of the per-case finalizing workgrou
 constexpr int kILP = 4;           // particles in flight per thread in k_step
 constexpr int kQCap = 64 * (kILP + 1);   // candidate-queue entries per wavefront
 
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Shared-memory layout of k_step for a case of N cells:
+//   field[N+1] float  (EC: ehat of the cells; MC: nodal field)
+//   dep[N] u64        (privatised deposit, count << 40 | summed weight)
+//   DIAG: heat[N] float, eedf[kEedfBins] u32
+//   candidate queues: per wavefront kQCap slots and vn (+ abar, implicit)
+struct StepLds {
+    size_t dep, heat, eedf, queue, total;
+};
+__host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool implicit)
+{
+    StepLds L;
+    L.dep = align16(4 * ((size_t)N + 1));
+    L.heat = L.dep + align16(8 * (size_t)N);
+    L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
+    L.queue = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
+    L.total = L.queue + (size_t)kWaves * kQCap * 4 * (implicit ? 3 : 2);
+    return L;
+}
+
 }  // namespace pic

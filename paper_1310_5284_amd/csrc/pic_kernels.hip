@@ -254,11 +254,7 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
     }
 }
 
-// Shared-memory layout of k_step: ehat[N] float | dep[N] u64 | (DIAG: heat[N]
-// float | eedf[kEedfBins] u32) | candidate queues.  The finalizer reuses it as
-// N+1 doubles.
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-
+// Per-workgroup accumulators of the rare events (LDS).
 struct BlockAcc {
     double absK[2][2];
     double other_dK;          // kinetic energy of ion children (electron blocks)
@@ -270,20 +266,27 @@ struct BlockAcc {
     int cmin, cmax;
 };
 
-// MC gather: CIC of the nodal field E_g = (E_{g-1/2} + E_{g+1/2}) / 2
-__device__ __forceinline__ float gather_mc(const float* eh, int N, bool periodic, int c, float o)
+// Momentum-conserving gather: linear interpolation of the nodal field (held
+// in LDS, N+1 nodes) at offset o of cell c.
+__device__ __forceinline__ float gather_mc(const float* en, int c, float o)
 {
-    auto node = [&](int g) -> float {
-        if (periodic) {
-            const int gl = g == 0 ? N - 1 : g - 1;
-            const int gr = g == N ? 0 : g;
-            return 0.5f * (eh[gl] + eh[gr]);
-        }
-        if (g == 0) return eh[0];
-        if (g == N) return eh[N - 1];
-        return 0.5f * (eh[g - 1] + eh[g]);
-    };
-    return (1.0f - o) * node(c) + o * node(c + 1);
+    return (1.0f - o) * en[c] + o * en[c + 1];
+}
+
+// Nodal field of node g from the cell fields of one species: the mean of the
+// two adjacent cells; the electrodes take the field of their own cell, a
+// periodic grid wraps.
+__device__ __forceinline__ float nodal_field(const PIC_GLOBAL float* eh, int N, bool periodic,
+                                             int g)
+{
+    if (periodic) {
+        const int gl = g == 0 ? N - 1 : g - 1;
+        const int gr = g == N ? 0 : g;
+        return 0.5f * (eh[gl] + eh[gr]);
+    }
+    if (g == 0) return eh[0];
+    if (g == N) return eh[N - 1];
+    return 0.5f * (eh[g - 1] + eh[g]);
 }
 
 __device__ __forceinline__ unsigned long long packw(float o)
@@ -293,7 +296,9 @@ __device__ __forceinline__ unsigned long long packw(float o)
 
 // ---------------------------------------------------------------------------
 // Collision of one candidate (null-collision MCC, Vahedi & Surendra 1995).
-// Returns the process kind or -2 (null).  Velocities in cells/step.
+// Returns the process kind or -2 (null).  Velocities in cells/step.  S is the
+// workgroup's register copy of the species constants; only constant indices
+// go into its per-process arrays.
 // ---------------------------------------------------------------------------
 struct Child {
     float vx, vy, vz;
@@ -313,22 +318,26 @@ __device__ __forceinline__ int collide_electron(const Species& S, uint4 r0, uint
     const float tc = fminf(fmaxf(t, 0.0f), S.t_max);
     const int k = min((int)tc, (int)S.t_max - 1);
     const float f = tc - (float)k;
-    const float4 A = S.tab_e[k], B = S.tab_e[k + 1];
-    float sg[4] = {fmaf(f, B.x - A.x, A.x), fmaf(f, B.y - A.y, A.y), fmaf(f, B.z - A.z, A.z),
-                   fmaf(f, B.w - A.w, A.w)};
+    const PIC_GLOBAL float* tab = gp((const float*)S.tab_e) + 4 * k;
+    float sg[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sg[p] = fmaf(f, tab[4 + p] - tab[p], tab[p]);
     const float u1 = u01(r0.y);
-    int slot = -1;
+    int kind = -2;
+    float thr = 0.0f;
     float cum = 0.0f;
 #pragma unroll
     for (int p = 0; p < kMaxProc; ++p) {
-        if (p < S.n_proc && slot < 0) {
+        if (p < S.n_proc && kind == -2) {
             const float sp = v2 > S.thr_v2[p] ? sg[p] : 0.0f;
             cum += sp * vm;
-            if (u1 < cum) slot = p;
+            if (u1 < cum) {
+                kind = S.kind[p];
+                thr = S.thr_v2[p];
+            }
         }
     }
-    if (slot < 0) return -2;
-    const int kind = S.kind[slot];
+    if (kind == -2) return -2;
     float dx, dy, dz;
     iso_dir(u01(r0.z), u01(r0.w), dx, dy, dz);
     if (kind == PIC_ELASTIC) {
@@ -336,13 +345,13 @@ __device__ __forceinline__ int collide_electron(const Species& S, uint4 r0, uint
         const float sp = sqrtf(v2 * (1.0f - S.recoil2 * (1.0f - cchi)));
         vx = sp * dx; vy = sp * dy; vz = sp * dz;
     } else if (kind == PIC_EXCITATION) {
-        const float sp = sqrtf(fmaxf(v2 - S.thr_v2[slot], 0.0f));
+        const float sp = sqrtf(fmaxf(v2 - thr, 0.0f));
         vx = sp * dx; vy = sp * dy; vz = sp * dz;
     } else if (kind == PIC_IONIZATION) {
         const uint4 r1 = philox((uint32_t)id, (uint32_t)(id >> 32), step, 1u, k0, k1);
         const uint4 r3 = philox((uint32_t)id, (uint32_t)(id >> 32), step, 3u, k0, k1);
         const float B = S.opal_B;
-        const float avail = fmaxf(v2 - S.thr_v2[slot], 0.0f) * S.eps_unit;   // eV
+        const float avail = fmaxf(v2 - thr, 0.0f) * S.eps_unit;   // eV
         const float eej = B * tanf(u01(r1.x) * atanf(avail / (2.0f * B)));
         const float esc = fmaxf(avail - eej, 0.0f);
         const float s1 = sqrtf(esc / S.eps_unit);
@@ -377,7 +386,8 @@ __device__ __forceinline__ int collide_ion(const Species& S, uint4 r0, uint64_t 
     const float tc = fminf(fmaxf(t, 0.0f), S.t_max);
     const int k = min((int)tc, (int)S.t_max - 1);
     const float f = tc - (float)k;
-    const float a = S.tab_i[k], b = S.tab_i[k + 1];
+    const PIC_GLOBAL float* tab = gp(S.tab_i);
+    const float a = tab[k], b = tab[k + 1];
     const float sg = g2 > S.thr_v2[0] ? fmaf(f, b - a, a) : 0.0f;
     if (u01(r0.y) < sg * sqrtf(g2)) {
         vx = wx; vy = wy; vz = wz;
@@ -390,15 +400,10 @@ __device__ __forceinline__ int collide_ion(const Species& S, uint4 r0, uint64_t 
 // Children of an ionization: one electron and one ion per event, appended
 // after the occupied slots (one atomic per wavefront and species).
 // ---------------------------------------------------------------------------
-struct ChildSink {
-    Case* C;
-    State* st;
-    int n_slots0, n_slots1;
-};
-
-// Reserve slots for the lanes with want = true; returns the slot or -1.
-__device__ __forceinline__ long long reserve_slot(bool want, int32_t* counter, int base_slots,
-                                                  long long cap)
+// Reserve slots for the lanes with want = true; returns the slot, -1 when
+// not wanted, -2 when the species is full.
+__device__ __forceinline__ long long reserve_slot(bool want, PIC_GLOBAL int32_t* counter,
+                                                  int base_slots, long long cap)
 {
     const unsigned long long m = __ballot(want);
     if (m == 0) return -1;
@@ -406,7 +411,7 @@ __device__ __forceinline__ long long reserve_slot(bool want, int32_t* counter, i
     const int leader = __ffsll((long long)m) - 1;
     const int rank = __popcll(m & ((1ull << lane) - 1ull));
     int b = 0;
-    if (lane == leader) b = atomicAdd(counter, __popcll(m));
+    if (lane == leader) b = gatomic_add(counter, (int32_t)__popcll(m));
     b = __shfl(b, leader, 64);
     if (!want) return -1;
     const long long slot = (long long)base_slots + b + rank;
@@ -417,13 +422,13 @@ __device__ __forceinline__ void write_particle(const Species& S, long long slot,
                                                float vx, float vy, float vz, uint64_t id,
                                                bool implicit)
 {
-    S.cell[slot] = c;
-    S.off[slot] = o;
-    S.vx[slot] = vx;
-    S.vy[slot] = vy;
-    S.vz[slot] = vz;
-    S.id[slot] = id;
-    if (implicit) S.abar[slot] = 0.0f;
+    gp(S.cell)[slot] = c;
+    gp(S.off)[slot] = o;
+    gp(S.vx)[slot] = vx;
+    gp(S.vy)[slot] = vy;
+    gp(S.vz)[slot] = vz;
+    gp(S.id)[slot] = id;
+    if (implicit) gp(S.abar)[slot] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -431,6 +436,7 @@ __device__ __forceinline__ void write_particle(const Species& S, long long slot,
 // When every depositing lane of the wavefront lands in the same cell (the
 // common case for cell-sorted ions) the weights are summed across the
 // wavefront first and one LDS atomic is issued instead of 64 colliding ones.
+// Called with every lane of the wavefront active.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want, int c, float o,
                                              int& lo, int& hi)
@@ -439,10 +445,10 @@ __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want,
     if (m == 0ull) return;
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((long long)m) - 1;
-    const int cl = __shfl(c, leader, 64);
+    const int cl = __builtin_amdgcn_readlane(c, leader);
     if (__ballot(want && c != cl) == 0ull) {
-        unsigned w = want ? __float2uint_rn(o * 16777216.0f) : 0u;
-        w = wave_sum(w);   // at most 64 * 2^24 = 2^30
+        // at most 64 * 2^24 = 2^30
+        const unsigned w = wave_total_u32(want ? __float2uint_rn(o * 16777216.0f) : 0u);
         if (lane == leader) {
             atomicAdd(&dep[cl], ((unsigned long long)__popcll(m) << 40) + (unsigned long long)w);
             range_note(lo, hi, cl);
@@ -453,35 +459,25 @@ __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want,
     }
 }
 
-// Per-wavefront queue of collision candidates in LDS (structure of arrays).
-
-struct WaveQueue {
-    int* idx;     // particle slot
-    int* c1;      // cell of x_{n+1}
-    float* o1;    // offset of x_{n+1}
-    float* vn;    // v_{n+1/2} (x component) before the collision
-    float* abn;   // abar_n (implicit)
-};
-
-__host__ __device__ inline size_t queue_lds_bytes() { return (size_t)kWaves * kQCap * 5 * 4; }
-
 // ---------------------------------------------------------------------------
 // k_step: one step of every case in this launch.  Workgroup = a contiguous
 // chunk of one species of one case.  Per particle (explicit, leap-frog):
-//   a = ehat[cell] (EC, Eq. (3)) or CIC of the nodal field (MC);
+//   a = ehat[cell] (EC, Eq. (3)) or the interpolated nodal field (MC);
 //   v += a;  x += v;  absorb at the electrodes or wrap;
 //   null-collision MCC with Philox(id, step);  deposit (Eq. (2)).
 // Per particle (implicit, D1, beta = 1/2; stored x~, v~, abar):
 //   a = ehat[cell of x~];  x = x~ + a/2;  v = v~ + a/2;  abar = (abar + a)/2;
 //   absorb; MCC; predict v~' = v + abar/2, x~' = x + v~'; absorb; deposit x~'.
 //
-// The streaming loop keeps kILP particles per thread in flight and decides
-// candidacy (u0 < P_null, an integer compare on the Philox word).  Candidates
-// go to a per-wavefront LDS queue (ballot + prefix); whenever 64 are queued
-// the wavefront processes them with every lane busy.  The deposit goes to a
+// The streaming loop issues the loads of kILP particles per thread together
+// (indices past the chunk are clamped to its last slot and treated as dead)
+// and decides candidacy (u0 < P_null, an integer compare on the Philox word).
+// A candidate's x_{n+1} goes to memory and its slot and v_{n+1/2} to a
+// per-wavefront LDS ring (ballot + prefix); whenever 64 are queued the
+// wavefront collides them with every lane busy.  The deposit goes to a
 // privatised LDS grid (one int64 per cell packs count and summed weight) and
-// is flushed over the cell range the workgroup touched.  The last workgroup
-// of a case closes the ledger and solves the field of the next step.
+// is flushed over the cell range the workgroup touched.  k_finalize then
+// closes the ledger and solves the field of the next step.
 // ---------------------------------------------------------------------------
 template <int SCHEME, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_step(Params P)
@@ -496,33 +492,33 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     State* st = P.state + w.c;
     const int N = C->n_cells;
     const int s = w.s;
-    const Species& S = C->sp[s];
+    // register copy: stores to the particle arrays cannot alias it
+    const Species S = C->sp[s];
     const bool periodic = C->bc == 1;
     const bool mc = C->gather == 1;
     const bool coll = C->collisions != 0 && S.n_proc > 0;
     const uint32_t k0 = C->key0, k1 = C->key1;
 
-    const size_t o_dep = align16(4 * (size_t)N);
-    const size_t o_heat = o_dep + align16(8 * (size_t)N);
-    const size_t o_eedf = o_heat + align16(4 * (size_t)N);
-    const size_t o_q = DIAG ? o_eedf + align16(4 * (size_t)kEedfBins) : o_heat;
+    const StepLds L = step_lds_layout(N, DIAG, kImp);
     float* eh = (float*)smem;
-    unsigned long long* dep = (unsigned long long*)(smem + o_dep);
-    float* heat = (float*)(smem + o_heat);
-    unsigned* eedf = (unsigned*)(smem + o_eedf);
-    WaveQueue q;
-    {
-        int* qb = (int*)(smem + o_q) + (size_t)wave * kQCap * 5;
-        q.idx = qb;
-        q.c1 = qb + kQCap;
-        q.o1 = (float*)(qb + 2 * kQCap);
-        q.vn = (float*)(qb + 3 * kQCap);
-        q.abn = (float*)(qb + 4 * kQCap);
-    }
+    unsigned long long* dep = (unsigned long long*)(smem + L.dep);
+    float* heat = (float*)(smem + L.heat);
+    unsigned* eedf = (unsigned*)(smem + L.eedf);
+    int* q_idx = (int*)(smem + L.queue) + (size_t)wave * kQCap * (kImp ? 3 : 2);
+    float* q_vn = (float*)(q_idx + kQCap);
+    float* q_ab = (float*)(q_idx + 2 * kQCap);   // implicit only
 
+    {
+        const PIC_GLOBAL float* ehg = gp(C->ehat[s]);
+        if (mc) {
+            for (int g = tid; g <= N; g += kBlock) eh[g] = nodal_field(ehg, N, periodic, g);
+        } else {
+#pragma unroll 8
+            for (int j = tid; j < N; j += kBlock) eh[j] = ehg[j];
+        }
+    }
 #pragma unroll 8
     for (int j = tid; j < N; j += kBlock) {
-        eh[j] = C->ehat[s][j];
         dep[j] = 0ull;
         if (DIAG) heat[j] = 0.0f;
     }
@@ -552,13 +548,15 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const int start = w.b * chunk;
     const int end = min(n, start + chunk);
 
-    int32_t* __restrict__ cellp = S.cell;
-    float* __restrict__ offp = S.off;
-    float* __restrict__ vxp = S.vx;
-    float* __restrict__ vyp = S.vy;
-    float* __restrict__ vzp = S.vz;
-    const uint64_t* __restrict__ idp = S.id;
-    float* __restrict__ abp = S.abar;
+    PIC_GLOBAL int32_t* __restrict__ cellp = gp(S.cell);
+    PIC_GLOBAL float* __restrict__ offp = gp(S.off);
+    PIC_GLOBAL float* __restrict__ vxp = gp(S.vx);
+    PIC_GLOBAL float* __restrict__ vyp = gp(S.vy);
+    PIC_GLOBAL float* __restrict__ vzp = gp(S.vz);
+    const PIC_GLOBAL uint64_t* __restrict__ idp = gp((const uint64_t*)S.id);
+    PIC_GLOBAL float* __restrict__ abp = gp(S.abar);
+    const uint32_t cand_thr = S.cand_thr;
+    const float eedf_k = S.eps_unit * S.eedf_scale;
 
     double work = 0.0, cdk = 0.0;
     unsigned cand = 0u;
@@ -571,13 +569,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         cellp[i] = -1;
     };
     auto eedf_note = [&](float vx, float vy, float vz) {
-        const float fb = (vx * vx + vy * vy + vz * vz) * S.eps_unit * S.eedf_scale;
+        const float fb = (vx * vx + vy * vy + vz * vz) * eedf_k;
         const int bin = fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
         atomicAdd(&eedf[bin], 1u);
     };
 
-    // Process the m (<= 64) oldest queued candidates, one per lane.  The
-    // queue is a ring of kQCap entries: qh is its head, qn its length.
+    // Collide the m (<= 64) oldest queued candidates, one per lane.  The
+    // queue is a ring of kQCap entries: qh is its head, qn its length.  The
+    // candidate's x_{n+1} was stored in its slot by the streaming pass.
     auto drain = [&](int m) {
         __syncwarp();
         const bool act = lane < m;
@@ -589,11 +588,11 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         if (act) {
             int e = qh + lane;
             if (e >= kQCap) e -= kQCap;
-            i = q.idx[e];
-            c1 = q.c1[e];
-            o1 = q.o1[e];
-            vn = q.vn[e];
-            abn = q.abn[e];
+            i = q_idx[e];
+            vn = q_vn[e];
+            if (kImp) abn = q_ab[e];
+            c1 = cellp[i];
+            o1 = offp[i];
             id = idp[i];
             vy = vyp[i];
             vz = vzp[i];
@@ -681,8 +680,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     }
                 }
             }
-            const long long se = reserve_slot(want_e, &st->n_child[0], ns0, C->sp[0].capacity);
-            const long long si = reserve_slot(want_i, &st->n_child[1], ns1, C->sp[1].capacity);
+            const long long se = reserve_slot(want_e, gp(&st->n_child[0]), ns0, C->sp[0].capacity);
+            const long long si = reserve_slot(want_i, gp(&st->n_child[1]), ns1, C->sp[1].capacity);
             bool dep_e = false;
             if (want_e) {
                 if (se >= 0) {
@@ -696,8 +695,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             if (want_i) {
                 if (si >= 0) {
                     write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi, kImp);
-                    atomicAdd(&C->dep_cnt[1][ci], 1ull);
-                    atomicAdd(&C->dep_w[1][ci], packw(oi) & kWMask);
+                    gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
+                    gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
                 } else {
                     atomicAdd(&acc.n_lost[1], 1u);
                 }
@@ -707,35 +706,29 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     };
 
     for (int base = start;;) {
-      const bool stream = base < end;
-      if (stream) {
+      if (base < end) {
+        // the loads of the batch are issued together; indices past the chunk
+        // are clamped to its last slot (and treated as dead below)
         int c[kILP];
         float o[kILP], v[kILP], ab[kILP];
         uint64_t idv[kILP];
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
-            const int i = base + k * kBlock + tid;
-            c[k] = i < end ? cellp[i] : -1;
+            const int j = min(base + k * kBlock + tid, end - 1);
+            c[k] = cellp[j];
+            o[k] = offp[j];
+            v[k] = vxp[j];
+            ab[k] = kImp ? abp[j] : 0.0f;
+            idv[k] = coll ? idp[j] : 0ull;
         }
+        float wk = 0.0f;
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
             const int i = base + k * kBlock + tid;
-            o[k] = v[k] = ab[k] = 0.0f;
-            idv[k] = 0;
-            if (c[k] >= 0) {
-                o[k] = offp[i];
-                v[k] = vxp[i];
-                if (kImp) ab[k] = abp[i];
-                if (coll) idv[k] = idp[i];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kILP; ++k) {
-            const int i = base + k * kBlock + tid;
-            int cc = c[k];
+            const int cc = i < end ? c[k] : -1;
             bool live = cc >= 0;
             float a = 0.0f;
-            if (live) a = mc ? gather_mc(eh, N, periodic, cc, o[k]) : eh[cc];
+            if (live) a = mc ? gather_mc(eh, cc, o[k]) : eh[cc];
             float vn, vold, abn = 0.0f, o1;
             if (kImp) {
                 vold = v[k] - 0.5f * ab[k];
@@ -750,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             int c1 = cc;
             if (live) {
                 const float dk = (vn - vold) * (vn + vold);
-                work += (double)dk;
+                wk += dk;
                 if (DIAG) {
                     atomicAdd(&heat[cc], dk);
                     range_note(lo, hi, cc);
@@ -768,9 +761,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             if (live && coll) {
                 const uint4 r0 = philox((uint32_t)idv[k], (uint32_t)(idv[k] >> 32), step32,
                                         (uint32_t)s << 28, k0, k1);
-                isc = (r0.x >> 9) < S.cand_thr;
+                isc = (r0.x >> 9) < cand_thr;
             }
-            // non-candidates finish here; explicit candidates keep their position
+            // non-candidates finish here; candidates store x_{n+1} (final
+            // for the explicit scheme, which deposits it now)
             int c2 = c1;
             float o2 = o1, vst = vn;
             bool dep_now = false;
@@ -795,10 +789,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     dep_now = true;
                     if (DIAG && s == 0) eedf_note(vn, vyp[i], vzp[i]);
                 }
-            } else if (live && !kImp) {
+            } else if (live) {
                 cellp[i] = c1;
                 offp[i] = o1;
-                dep_now = true;
+                dep_now = !kImp;
             }
             deposit_wave(dep, dep_now, c2, o2, lo, hi);
             // queue the candidates of this wavefront
@@ -807,14 +801,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             if (enq) {
                 int slot = qh + qn + __popcll(qm & ((1ull << lane) - 1ull));
                 if (slot >= kQCap) slot -= kQCap;
-                q.idx[slot] = i;
-                q.c1[slot] = c1;
-                q.o1[slot] = o1;
-                q.vn[slot] = vn;
-                q.abn[slot] = abn;
+                q_idx[slot] = i;
+                q_vn[slot] = vn;
+                if (kImp) q_ab[slot] = abn;
             }
             qn += __popcll(qm);
         }
+        work += (double)wk;
         base += kBlock * kILP;
       }
         // drain full batches of 64, and the remainder once the chunk is done
@@ -836,21 +829,23 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     }
     __syncthreads();
     {
+        PIC_GLOBAL unsigned long long* gcnt = gp(C->dep_cnt[s]);
+        PIC_GLOBAL unsigned long long* gw = gp(C->dep_w[s]);
         const int cl = acc.cmin, chh = acc.cmax;
         for (int j = cl + tid; chh >= 0 && j <= chh; j += kBlock) {
             const unsigned long long p = dep[j];
             if (p) {
-                atomicAdd(&C->dep_cnt[s][j], p >> 40);
-                atomicAdd(&C->dep_w[s][j], p & kWMask);
+                gatomic_add(&gcnt[j], p >> 40);
+                gatomic_add(&gw[j], p & kWMask);
             }
             if (DIAG) {
                 const float h = heat[j];
-                if (h != 0.0f) atomicAdd(&C->heat_acc[s][j], (double)h * S.kin_unit);
+                if (h != 0.0f) gatomic_add(gp(&C->heat_acc[s][j]), (double)h * S.kin_unit);
             }
         }
         if (DIAG && s == 0)
             for (int j = tid; j < kEedfBins; j += kBlock)
-                if (eedf[j]) atomicAdd(&C->eedf_acc[j], (unsigned long long)eedf[j]);
+                if (eedf[j]) gatomic_add(gp(&C->eedf_acc[j]), (unsigned long long)eedf[j]);
     }
     // workgroup partial of the ledger (plain stores, reduced by k_finalize)
     __shared__ double wsum[kWaves][3];

@@ -136,12 +136,9 @@ size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Dynamic LDS of k_step: ehat[N] float | dep[N] u64 | (DIAG: heat[N] float |
 // eedf[kEedfBins] u32) | per-wavefront candidate queues.
-size_t step_lds(int N, bool diag)
+size_t step_lds(int N, bool diag, bool implicit)
 {
-    size_t b = a16(4 * (size_t)N) + a16(8 * (size_t)N);
-    if (diag) b += a16(4 * (size_t)N) + a16(4 * (size_t)kEedfBins);
-    b += (size_t)kWaves * kQCap * 5 * 4;
-    return b;
+    return step_lds_layout(N, diag, implicit).total;
 }
 
 // Null-collision bound: n_g max over table intervals of
@@ -514,7 +511,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         h.hist_off[1] = hist_total + N;
         hist_total += 2 * (size_t)N;
     }
-    if (set_lds_limits(c, std::max(step_lds(c->maxN, true), 8 * (size_t)c->maxN)))
+    if (set_lds_limits(c, std::max(step_lds(c->maxN, true, true), 8 * (size_t)c->maxN)))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
@@ -624,7 +621,7 @@ int run_steps(pic_ctx* c, int64_t n, int which)
         for (int g = 0; g < 2; ++g) {
             if (!c->grp_cnt[g]) continue;
             Params p = params(c, c->grp_off[g]);
-            const size_t lds = step_lds(c->grp_maxN[g], diag);
+            const size_t lds = step_lds(c->grp_maxN[g], diag, g == 1);
             auto kern = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
                                : (diag ? k_step<1, true> : k_step<1, false>);
             const bool rec = c->timing && c->ev_used + 2 <= (int)c->ev.size();
