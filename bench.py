@@ -91,6 +91,10 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--fp64-steps", type=int, default=20,
+                    help="steps of the plain FP64 GPU form timed for comparison (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run the streaming copy kernel of BYTES and print its rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -98,6 +102,13 @@ def main():
         sys.exit(2)
 
     import paper_1310_5284_amd as P
+
+    if args.copy_calibration:
+        ms = P.copy_calibration(args.copy_calibration, reps=10)
+        print(json.dumps(dict(calibration="copy", bytes_read=args.copy_calibration,
+                              bytes_written=args.copy_calibration, ms_per_copy=ms,
+                              GBps=2 * args.copy_calibration / (ms * 1e-3) / 1e9)), flush=True)
+        return
 
     log(f"[bench] building inputs: {args.workload} scale {args.scale}")
     wls = make_workload(args.workload, args.scale)
@@ -162,6 +173,20 @@ def main():
                            particles=int(particles), tile=tile, sort_every=sort_every,
                            scheme="implicit" if implicit else "explicit"),
                roofline=roof)
+    if args.fp64_steps > 0 and not implicit:
+        # the plain FP64 GPU form of the same method, from the same state
+        log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
+        ctx.fp64_init()
+        ctx.fp64_step(2)
+        n64 = live()
+        t0 = time.perf_counter()
+        ctx.fp64_step(args.fp64_steps)
+        t1 = time.perf_counter()
+        v64 = n64 * args.fp64_steps / (t1 - t0)
+        out["fp64_gpu_form"] = dict(value=v64, unit="particle-steps/s",
+                                    ms_per_step=(t1 - t0) * 1e3 / args.fp64_steps,
+                                    steps=args.fp64_steps)
+        out["speedup_vs_fp64_form"] = value / v64
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)

@@ -234,6 +234,14 @@ int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int
                              double* xi, double* vx, double* vy, double* vz, uint64_t* id,
                              int64_t* n_out);
 
+/* Measurement helper, independent of any context: allocates two device
+ * buffers of `bytes` (a multiple of 16), copies one into the other `reps`
+ * times with a plain streaming kernel on the null stream, frees them and
+ * returns the mean milliseconds per copy.  Its FETCH_SIZE / WRITE_SIZE
+ * counter readings calibrate the HBM traffic figures of the other kernels.
+ * Errors: PIC_E_INVAL (bad sizes), PIC_E_NOMEM, PIC_E_DEVICE. */
+int pic_copy_calibration(int64_t bytes, int32_t reps, double* ms_per_copy);
+
 void pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);
 /* Timing of the most recent pic_step* call: milliseconds of device time

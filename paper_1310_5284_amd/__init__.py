@@ -113,6 +113,7 @@ def lib():
         L.pic_fp64_reference_step.argtypes = [_P, C.c_int64]
         L.pic_fp64_reference_state.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D,
                                                _D, C.POINTER(C.c_uint64), _I64]
+        L.pic_copy_calibration.argtypes = [C.c_int64, C.c_int32, _D]
         L.pic_destroy.argtypes = [_P]
         L.pic_destroy.restype = None
         L.pic_last_error.argtypes = [_P]
@@ -120,6 +121,15 @@ def lib():
         L.pic_last_timing.argtypes = [_P, _D, _I64]
         _lib = L
     return _lib
+
+
+def copy_calibration(nbytes, reps=10):
+    """Milliseconds per copy of `nbytes` by the library's streaming copy kernel."""
+    ms = C.c_double()
+    rc = lib().pic_copy_calibration(int(nbytes), int(reps), C.byref(ms))
+    if rc != 0:
+        raise PicError(rc, "pic_copy_calibration")
+    return ms.value
 
 
 class PicError(RuntimeError):
@@ -293,6 +303,29 @@ class PicContext:
             n = int(d.n_particles[s])
             out.append({k: v[:n].copy() for k, v in arrs[s].items()})
         return dict(species=out, vel_unit=d.vel_unit, acc_unit=d.acc_unit, step=d.step)
+
+    # ---- plain FP64 GPU form of the same explicit method ----------------
+    def fp64_init(self):
+        """Copy the current state into the plain FP64 form (explicit cases)."""
+        self._check(lib().pic_fp64_reference_init(self._h), "pic_fp64_reference_init")
+
+    def fp64_step(self, n=1):
+        self._check(lib().pic_fp64_reference_step(self._h, n), "pic_fp64_reference_step")
+
+    def fp64_state(self, case=0, species=0, cap=None):
+        """Live particles of the FP64 form: xi (cells), v (cells/step), id."""
+        if cap is None:
+            cap = int(self.counts(case)["n_slots"][species]) * 2 + 1024
+        a = {k: np.zeros(cap) for k in ("xi", "vx", "vy", "vz")}
+        ids = np.zeros(cap, np.uint64)
+        n = C.c_int64()
+        self._check(lib().pic_fp64_reference_state(
+            self._h, case, species, cap, *(a[k].ctypes.data_as(_D) for k in ("xi", "vx", "vy", "vz")),
+            ids.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n)), "pic_fp64_reference_state")
+        k = n.value
+        out = {key: v[:k].copy() for key, v in a.items()}
+        out["id"] = ids[:k].copy()
+        return out
 
     def density(self, case=0):
         N = self.n_cells[case]

@@ -20,6 +20,18 @@ __device__ __forceinline__ PIC_GLOBAL T* gp(T* p)
     return (PIC_GLOBAL T*)p;
 }
 
+// Workgroup barrier that orders LDS only: it waits for the wavefront's LDS
+// operations but not for its outstanding global stores (which only later
+// kernels read), so a barrier after a burst of stores does not stall on
+// their acknowledgements.  Global data shared inside a workgroup must not be
+// handed over through it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // relaxed device-scope atomic add through a global pointer
 template <class T>
 __device__ __forceinline__ T gatomic_add(PIC_GLOBAL T* p, T v)
@@ -117,9 +129,9 @@ __device__ __forceinline__ T block_sum(T v, T* red)
 {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
+    lds_barrier();
     if (lane == 0) red[wave] = v;
-    __syncthreads();
+    lds_barrier();
     T r = 0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) r += red[w];
@@ -141,16 +153,16 @@ __device__ void block_scan(T* a, int n, T* red)
         const T t = __shfl_up(inc, o, 64);
         if (lane >= o) inc += t;
     }
-    __syncthreads();
+    lds_barrier();
     if (lane == 63) red[wave] = inc;
-    __syncthreads();
+    lds_barrier();
     T run = inc - loc;
     for (int w = 0; w < wave; ++w) run += red[w];
     for (int i = lo; i < hi; ++i) {
         run += a[i];
         a[i] = run;
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // "no cell touched" marker of the range trackers; far from INT_MAX so that

@@ -102,13 +102,14 @@ struct State {
     int32_t n_live[2];
     int32_t flags;           // bit 0: non-finite field, bit 1: capacity
     double K[2];             // kinetic energy at the current half step (J/m^2)
-    double WE;               // field energy of the solve the next step uses
+    double WE[2];            // field energy of the field of step k, in slot k & 1
     long long dens_samples;
     long long eedf_samples;
     long long history_n;
     long long lost_total[2];
     long long sort_live[2];  // live counts found by the last compaction
     double sortK[2];         // exact kinetic energy found by the last compaction
+    long long ledger_step;   // step whose ledger row is closed next
 };
 
 struct Work {

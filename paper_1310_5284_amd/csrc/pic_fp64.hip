@@ -344,6 +344,7 @@ extern "C" int pic__ctx_case_info(pic_ctx* ctx, int32_t case_id, pic_case_config
 extern "C" int pic__ctx_table(pic_ctx* ctx, int32_t s, int32_t p, int32_t* n,
                               const double** sigma);
 extern "C" void** pic__ctx_fp64_slot(pic_ctx* ctx);
+extern "C" int pic__ctx_species_consts(pic_ctx* ctx, int32_t k, int32_t s, double* out12);
 
 extern "C" void pic__fp64_free(pic_ctx* ctx)
 {
@@ -436,20 +437,22 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
             S.capacity = cap[s];
             S.accel = F.accel;
             S.qw_dx = F.qw_dx;
-            S.eps_unit = F.eps_unit;
-            S.t_scale = F.t_scale;
-            S.t_off = F.t_off;
-            S.t_max = F.t_max;
+            double c64[12];
+            if (pic__ctx_species_consts(ctx, k, s, c64)) return PIC_E_STATE;
+            S.eps_unit = c64[0];
+            S.opal_B = c64[1];
+            S.recoil2 = c64[2];
+            S.vth_neutral = c64[3];
+            S.vth_newion = c64[4];
+            S.t_scale = c64[5];
+            S.t_off = c64[6];
+            S.t_max = c64[7];
             for (int p = 0; p < kMaxProc; ++p) {
-                S.thr_v2[p] = F.thr_v2[p];
+                S.thr_v2[p] = c64[8 + p];
                 S.kind[p] = F.kind[p];
             }
             S.n_proc = F.n_proc;
             S.cand_thr = F.cand_thr;
-            S.vth_neutral = F.vth_neutral;
-            S.vth_newion = F.vth_newion;
-            S.recoil2 = F.recoil2;
-            S.opal_B = F.opal_B;
             // float64 tables from the context's copy of the input cross sections
             if (S.n_proc > 0) {
                 const int n = (int)F.t_max + 1;

@@ -31,59 +31,82 @@ namespace pic {
 constexpr double kEps0 = 8.8541878128e-12;
 
 template <int NT>
-__device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step, bool sample_density,
-                           double* S, double* red)
+__device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step,
+                                           long long field_step, bool sample_density, double* S,
+                                           double* red)
 {
     constexpr int kPer = (PIC_MAX_CELLS + 1 + NT - 1) / NT;   // nodes per thread
-    const int N = C->n_cells, tid = threadIdx.x;
-    const bool periodic = C->bc == 1;
-    const bool implicit = C->scheme == 1;
-    const double dx = C->dx;
+    // register copy of the case: the stores below cannot alias it, so none
+    // of its pointers is reloaded after a store
+    const Case Cc = *C;
+    const int N = Cc.n_cells, tid = threadIdx.x;
+    const bool periodic = Cc.bc == 1;
+    const bool implicit = Cc.scheme == 1;
+    const double dx = Cc.dx;
     // X: chi_{j+1/2} of the cells (LDS, after the N+1 values of S)
     double* X = S + N + 1;
-    // node g = tid + k NT: counts and weights of cells g and g-1 (the loads of
-    // one node are issued together)
-#pragma unroll 1
-    for (int k = 0; k < kPer; ++k) {
-        const int g = tid + k * NT;
-        if (g > N) break;
-        const int gg = (periodic && g == N) ? 0 : g;
-        const int gl = gg > 0 ? gg - 1 : (periodic ? N - 1 : -1);
-        long long cn[2], wr[2], wl[2];
+    // node g = tid + k NT needs the counts and weights of cells g and g-1
+    const PIC_GLOBAL unsigned long long* dc[2] = {gp((const unsigned long long*)Cc.dep_cnt[0]),
+                                                  gp((const unsigned long long*)Cc.dep_cnt[1])};
+    const PIC_GLOBAL unsigned long long* dw[2] = {gp((const unsigned long long*)Cc.dep_w[0]),
+                                                  gp((const unsigned long long*)Cc.dep_w[1])};
+    // Nodes in batches of kB per thread; inside a batch every load is issued
+    // before any result is used (unconditional loads from clamped indices,
+    // selected afterwards, so that none waits behind a branch).
+    constexpr int kB = 3;
+    const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
+    const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
+    const double rho_bg = Cc.background_rho;
+    for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
+        long long cn[kB][2], wr[kB][2], wl[kB][2];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            cn[s] = gg < N ? (long long)C->dep_cnt[s][gg] : 0;
-            wr[s] = gg < N ? (long long)C->dep_w[s][gg] : 0;
-            wl[s] = gl >= 0 ? (long long)C->dep_w[s][gl] : 0;
-        }
-        double rho = C->background_rho;
+        for (int k = 0; k < kB; ++k) {
+            const int g = tid + (k0 + k) * NT;
+            const int gg = (periodic && g == N) ? 0 : g;
+            const int gl = gg > 0 ? gg - 1 : (periodic ? N - 1 : -1);
+            const bool in = g <= N;
+            const bool hr = in && gg < N, hl = in && gl >= 0;
+            const int ir = min(gg, N - 1), il = max(min(gl, N - 1), 0);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const long long q = cn[s] * (1ll << kFixBits) - wr[s] + wl[s];
-            C->qfix[s][g] = q;
-            if (sample_density) atomicAdd(&C->dens_acc[s][g], (unsigned long long)q);
-            rho += (double)q * (C->sp[s].qw_dx / kFixScale);
+            for (int s = 0; s < 2; ++s) {
+                const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
+                const long long l = (long long)dw[s][il];
+                cn[k][s] = hr ? c : 0;
+                wr[k][s] = hr ? r : 0;
+                wl[k][s] = hl ? l : 0;
+            }
         }
-        C->rho[g] = rho;
-        // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
-        S[g] = g == 0 ? 0.0 : rho * dx;
-        if (g < N) {
-            C->ccount[0][g] = cn[0];
-            C->ccount[1][g] = cn[1];
-            const double chi = implicit ? C->sp[0].chi_coef * (double)cn[0] +
-                                              C->sp[1].chi_coef * (double)cn[1]
-                                        : 0.0;
-            X[g] = chi;
-            C->chi[g] = chi;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int g = tid + (k0 + k) * NT;
+            if (g > N) continue;
+            double rho = rho_bg;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const long long q = cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
+                gp(Cc.qfix[s])[g] = q;
+                if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
+                rho += (double)q * (s == 0 ? qs0 : qs1);
+            }
+            gp(Cc.rho)[g] = rho;
+            // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
+            S[g] = g == 0 ? 0.0 : rho * dx;
+            if (g < N) {
+                gp(Cc.ccount[0])[g] = cn[k][0];
+                gp(Cc.ccount[1])[g] = cn[k][1];
+                const double chi = implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
+                X[g] = chi;
+                gp(Cc.chi)[g] = chi;
+            }
         }
     }
-    __syncthreads();   // every deposit word has been read
+    lds_barrier();   // every deposit word has been read
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
         if (j < N) {
-            C->dep_cnt[0][j] = 0; C->dep_cnt[1][j] = 0;
-            C->dep_w[0][j] = 0; C->dep_w[1][j] = 0;
+            gp(Cc.dep_cnt[0])[j] = 0; gp(Cc.dep_cnt[1])[j] = 0;
+            gp(Cc.dep_w[0])[j] = 0; gp(Cc.dep_w[1])[j] = 0;
         }
     }
     block_scan<double, NT>(S, N, red);             // S[j] = R_j
@@ -102,8 +125,8 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     double V = 0.0;
     if (!periodic) {
         // V0 sin(2 pi f t) through the phase in cycles reduced to [0, 1)
-        const double cyc = C->rf_freq * ((double)next_step * C->dt);
-        V = C->rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
+        const double cyc = Cc.rf_freq * ((double)next_step * Cc.dt);
+        V = Cc.rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
     }
     const double D0 = (V / dx - a) / b;
     double we = 0.0;
@@ -113,13 +136,13 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         if (j < N) {
             const double E = (D0 + S[j]) / (kEps0 * (1.0 + X[j]));
             X[j] = E;   // X now holds E
-            C->E[j] = E;
-            C->ehat[0][j] = (float)(C->sp[0].accel * E);
-            C->ehat[1][j] = (float)(C->sp[1].accel * E);
+            gp(Cc.E)[j] = E;
+            gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
+            gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
             we += 0.5 * kEps0 * E * E * dx;
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
@@ -128,18 +151,18 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     we = block_sum<double, NT>(we, red);
     block_scan<double, NT>(S, N, red);
     const double phi0 = periodic ? 0.0 : V;
-    if (tid == 0) C->phi[0] = phi0;
+    if (tid == 0) gp(Cc.phi)[0] = phi0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
-        if (j < N) C->phi[j + 1] = phi0 - dx * S[j];
+        if (j < N) gp(Cc.phi)[j + 1] = phi0 - dx * S[j];
     }
     if (tid == 0) {
-        st->WE = we;
-        if (!isfinite(we)) st->flags |= 1;
+        st->WE[field_step & 1] = we;
+        if (!isfinite(we)) atomicOr(&st->flags, 1);
         if (sample_density) st->dens_samples += 1;
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // ---------------------------------------------------------------------------
@@ -148,49 +171,48 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
 // row and folds the appended children into the occupied slots.
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ __forceinline__ void reduce_partials(const Params& P, int fb, int nb, double* sd, long long* su)
+__device__ __forceinline__ void reduce_partials(const double* pd_, const unsigned* pu_, int stride,
+                                                int fb, int nb, double* sd, long long* su)
 {
-    __shared__ double wd[NT / 64][PD_N];
-    __shared__ unsigned wu[NT / 64][PU_N];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    {
-        double d[PD_N];
+    // wavefront w sums the fields w, w + NT/64, ...: every lane strides over
+    // the workgroup partials with kU loads in flight, then a wavefront tree
+    constexpr int kU = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const PIC_GLOBAL double* pd = gp(pd_);
+    const PIC_GLOBAL unsigned* pu = gp(pu_);
+    for (int f = wave; f < PD_N + PU_N; f += NT / 64) {
+        if (f < PD_N) {
+            const PIC_GLOBAL double* row = pd + (size_t)f * stride + fb;
+            double a[kU];
 #pragma unroll
-        for (int f = 0; f < PD_N; ++f) d[f] = 0.0;
-        for (int b = tid; b < nb; b += NT)
+            for (int u = 0; u < kU; ++u) a[u] = 0.0;
+            // unconditional loads from clamped indices keep all kU in flight
+            for (int b = lane; b < nb; b += 64 * kU)
 #pragma unroll
-            for (int f = 0; f < PD_N; ++f) d[f] += P.pd[(size_t)f * P.stride + fb + b];
+                for (int u = 0; u < kU; ++u) {
+                    const double x = row[min(b + 64 * u, nb - 1)];
+                    a[u] += b + 64 * u < nb ? x : 0.0;
+                }
+            double v = 0.0;
 #pragma unroll
-        for (int f = 0; f < PD_N; ++f) {
-            const double v = wave_sum(d[f]);
-            if (lane == 0) wd[wave][f] = v;
+            for (int u = 0; u < kU; ++u) v += a[u];
+            v = wave_sum(v);
+            if (lane == 0) sd[f] = v;
+        } else {
+            // per-step counts of one case fit in 32 bits
+            const PIC_GLOBAL unsigned* row = pu + (size_t)(f - PD_N) * stride + fb;
+            unsigned a = 0u;
+            for (int b = lane; b < nb; b += 64 * kU)
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const unsigned x = row[min(b + 64 * u, nb - 1)];
+                    a += b + 64 * u < nb ? x : 0u;
+                }
+            a = wave_sum(a);
+            if (lane == 0) su[f - PD_N] = (long long)a;
         }
     }
-    {
-        // per-step counts of one case fit in 32 bits
-        unsigned u[PU_N];
-#pragma unroll
-        for (int f = 0; f < PU_N; ++f) u[f] = 0u;
-        for (int b = tid; b < nb; b += NT)
-#pragma unroll
-            for (int f = 0; f < PU_N; ++f) u[f] += P.pu[(size_t)f * P.stride + fb + b];
-#pragma unroll
-        for (int f = 0; f < PU_N; ++f) {
-            const unsigned v = wave_sum(u[f]);
-            if (lane == 0) wu[wave][f] = v;
-        }
-    }
-    __syncthreads();
-    if (tid < PD_N) {
-        double v = 0.0;
-        for (int k = 0; k < NT / 64; ++k) v += wd[k][tid];
-        sd[tid] = v;
-    } else if (tid < PD_N + PU_N) {
-        unsigned long long v = 0;
-        for (int k = 0; k < NT / 64; ++k) v += wu[k][tid - PD_N];
-        su[tid - PD_N] = (long long)v;
-    }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Called by every thread of the workgroup.  Thread 0 reads the case's state
@@ -201,18 +223,27 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
     __shared__ pic_ledger row;
     __shared__ int ring;
     if (threadIdx.x == 0) {
-        const State s0 = *st;
+        // fields of the state owned by the ledger (the field solve of the
+        // same finalizer runs concurrently and owns step, WE[] and samples)
+        const long long lstep = st->ledger_step;
+        const double we = st->WE[lstep & 1];
+        const double K0[2] = {st->K[0], st->K[1]};
+        const int32_t slots[2] = {st->n_slots[0], st->n_slots[1]};
+        const int32_t child[2] = {st->n_child[0], st->n_child[1]};
+        const int32_t live[2] = {st->n_live[0], st->n_live[1]};
+        const long long lost[2] = {st->lost_total[0], st->lost_total[1]};
+        const long long hn = st->history_n;
         const double ku0 = C->sp[0].kin_unit, ku1 = C->sp[1].kin_unit;
         const long long cap0 = C->sp[0].capacity, cap1 = C->sp[1].capacity;
         const int hl = C->history_len;
-        State s1 = s0;
-        row.step = s0.step;
-        row.WE = s0.WE;
+        row.step = lstep;
+        row.WE = we;
         bool finite = true;
+        int flags = 0;
         for (int s = 0; s < 2; ++s) {
             const double ku = s == 0 ? ku0 : ku1;
             const long long cap = s == 0 ? cap0 : cap1;
-            const double kb = s0.K[s];
+            const double kb = K0[s];
             const double wk = sd[PD_WORK + s] * ku, cd = sd[PD_COLL + s] * ku;
             const double a0 = sd[PD_ABSK + 2 * s] * ku, a1 = sd[PD_ABSK + 2 * s + 1] * ku;
             const double ka = kb + wk - a0 - a1 + cd;
@@ -222,7 +253,7 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
             row.absorbed_K[s][0] = a0;
             row.absorbed_K[s][1] = a1;
             row.K_after[s] = ka;
-            s1.K[s] = ka;
+            st->K[s] = ka;
             finite = finite && isfinite(ka);
             row.absorbed_n[s][0] = si[PU_ABS + 2 * s];
             row.absorbed_n[s][1] = si[PU_ABS + 2 * s + 1];
@@ -231,20 +262,21 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
             row.n_created[s] = si[PU_CREATED + s];
             row.n_over_table[s] = si[PU_OVER + s];
             row.n_lost[s] = si[PU_LOST + s];
-            s1.n_live[s] += (int32_t)(si[PU_CREATED + s] - si[PU_ABS + 2 * s] -
-                                      si[PU_ABS + 2 * s + 1]);
-            s1.lost_total[s] += si[PU_LOST + s];
-            const long long ns = (long long)s0.n_slots[s] + s0.n_child[s];
-            s1.n_slots[s] = (int32_t)(ns < cap ? ns : cap);
-            if (ns > cap || si[PU_LOST + s] > 0) s1.flags |= 2;
-            s1.n_child[s] = 0;
+            st->n_live[s] = live[s] + (int32_t)(si[PU_CREATED + s] - si[PU_ABS + 2 * s] -
+                                                si[PU_ABS + 2 * s + 1]);
+            st->lost_total[s] = lost[s] + si[PU_LOST + s];
+            const long long ns = (long long)slots[s] + child[s];
+            st->n_slots[s] = (int32_t)(ns < cap ? ns : cap);
+            if (ns > cap || si[PU_LOST + s] > 0) flags |= 2;
+            st->n_child[s] = 0;
         }
-        if (!finite) s1.flags |= 1;
-        s1.history_n = s0.history_n + 1;
-        *st = s1;
-        ring = hl > 0 ? 1 + (int)(s0.history_n % hl) : -1;
+        if (!finite) flags |= 1;
+        if (flags) atomicOr(&st->flags, flags);
+        st->history_n = hn + 1;
+        st->ledger_step = lstep + 1;
+        ring = hl > 0 ? 1 + (int)(hn % hl) : -1;
     }
-    __syncthreads();
+    lds_barrier();
     constexpr int kW = (int)(sizeof(pic_ledger) / 8);
     const long long* src = (const long long*)&row;
     long long* h = (long long*)C->history;
@@ -538,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         acc.cmin = kNoCell;
         acc.cmax = -1;
     }
-    __syncthreads();
+    lds_barrier();
 
     const uint32_t step32 = (uint32_t)st->step;
     const int n = st->n_slots[s];
@@ -827,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         atomicMin(&acc.cmin, lo);
         atomicMax(&acc.cmax, hi);
     }
-    __syncthreads();
+    lds_barrier();
     {
         PIC_GLOBAL unsigned long long* gcnt = gp(C->dep_cnt[s]);
         PIC_GLOBAL unsigned long long* gw = gp(C->dep_w[s]);
@@ -857,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         wsum[wave][1] = cdk;
         wsum[wave][2] = (double)ncw;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) {
         double wk = 0.0, cd = 0.0, nc = 0.0;
         for (int k = 0; k < kWaves; ++k) {
@@ -896,8 +928,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
 }
 
 // ---------------------------------------------------------------------------
-// k_finalize: one workgroup per case after the particle pass.  Closes the
-// ledger of the step and solves the FP64 field of the next one.
+// k_finalize: two workgroups per case after the particle pass, running side
+// by side: the odd one closes the ledger of the step (reduction of the
+// workgroup partials), the even one solves the FP64 field of the next step.
+// They write disjoint fields of the case state (flags through atomics).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
 {
@@ -905,14 +939,21 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
     __shared__ double red[kFinBlock / 64];
     __shared__ double sd[PD_N];
     __shared__ long long si[PU_N];
-    Case* C = P.cases + blockIdx.x;
-    State* st = P.state + blockIdx.x;
-    reduce_partials<kFinBlock>(P, C->first_block, C->n_blocks, sd, si);
-    finish_ledger(C, st, sd, si);
-    __syncthreads();
-    const long long next = st->step + 1;
-    solve_case<kFinBlock>(C, st, next + (C->scheme == 1 ? 1 : 0), sample != 0, (double*)smem,
-                          red);
+    Case* C = P.cases + (blockIdx.x >> 1);
+    State* st = P.state + (blockIdx.x >> 1);
+    if (blockIdx.x & 1) {
+        // ledger of the step just taken
+        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+        finish_ledger(C, st, sd, si);
+        return;
+    }
+    // field of the next step (thread 0 alone reads and writes st->step)
+    __shared__ long long s_step;
+    if (threadIdx.x == 0) s_step = st->step;
+    lds_barrier();
+    const long long next = s_step + 1;
+    solve_case<kFinBlock>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
+                          (double*)smem, red);
     if (threadIdx.x == 0) {
         if (sample) st->eedf_samples += 1;
         st->step = next;
@@ -989,9 +1030,22 @@ __device__ __forceinline__ unsigned wave_count_add(unsigned* h, int c, bool vali
 }
 
 // ---------------------------------------------------------------------------
-// Compaction: drop absorbed slots and sort every species by cell (a stable
-// counting sort across workgroups; the order inside one cell is arbitrary).
+// Compaction: drop absorbed slots and sort every species by bucket with a
+// counting sort across workgroups (the order inside one bucket is
+// arbitrary).  Ions are sorted by cell; electrons, which cross many cells
+// between sorts, by buckets of 2^kElecBucketShift cells, so that every
+// workgroup writes its particles in a few long runs (the writes of a run
+// complete cache lines while they are resident instead of trickling out as
+// partial lines).
 // ---------------------------------------------------------------------------
+constexpr int kElecBucketShift = 4;
+
+__device__ __forceinline__ int bucket_shift(int s) { return s == 0 ? kElecBucketShift : 0; }
+__device__ __forceinline__ int n_buckets(int N, int s)
+{
+    return (N + (1 << bucket_shift(s)) - 1) >> bucket_shift(s);
+}
+
 __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* hist_all,
                                                          const int64_t* hist_off)
 {
@@ -1000,16 +1054,17 @@ __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* his
     const Work w = P.work[blockIdx.x];
     Case* C = P.cases + w.c;
     State* st = P.state + w.c;
-    const Species& S = C->sp[w.s];
-    const int N = C->n_cells;
-    uint32_t* hist = hist_all + hist_off[2 * w.c + w.s];
+    const int sh = bucket_shift(w.s);
+    const int NB = n_buckets(C->n_cells, w.s);
+    const PIC_GLOBAL int32_t* __restrict__ cellp = gp((const int32_t*)C->sp[w.s].cell);
+    PIC_GLOBAL uint32_t* hist = gp(hist_all + hist_off[2 * w.c + w.s]);
     unsigned* lh = (unsigned*)smem;
-    for (int j = threadIdx.x; j < N; j += kBlock) lh[j] = 0u;
+    for (int j = threadIdx.x; j < NB; j += kBlock) lh[j] = 0u;
     if (threadIdx.x == 0) {
         s_lo = kNoCell;
         s_hi = -1;
     }
-    __syncthreads();
+    lds_barrier();
     const int n = st->n_slots[w.s];
     int chunk = (n + w.nb - 1) / w.nb;
     chunk = (chunk + 63) & ~63;
@@ -1017,17 +1072,18 @@ __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* his
     int lo = kNoCell, hi = -1;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
-        const int c = i < end ? S.cell[i] : -1;
-        wave_count_add(lh, c, c >= 0);
-        if (c >= 0) range_note(lo, hi, c);
+        const int c = i < end ? cellp[i] : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        wave_count_add(lh, b, b >= 0);
+        if (b >= 0) range_note(lo, hi, b);
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
         atomicMax(&s_hi, hi);
     }
-    __syncthreads();
+    lds_barrier();
     for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock)
-        if (lh[j]) atomicAdd(&hist[j], lh[j]);
+        if (lh[j]) gatomic_add(&hist[j], lh[j]);
 }
 
 // one workgroup per (case, species): exclusive scan of the histogram
@@ -1040,18 +1096,18 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(Params P, uint32_t* his
     const int c = blockIdx.x >> 1, s = blockIdx.x & 1;
     Case* C = P.cases + c;
     State* st = P.state + c;
-    const int N = C->n_cells;
-    uint32_t* hist = hist_all + hist_off[2 * c + s];
-    uint32_t* cur = cursor_all + hist_off[2 * c + s];
+    const int NB = n_buckets(C->n_cells, s);
+    PIC_GLOBAL uint32_t* hist = gp(hist_all + hist_off[2 * c + s]);
+    PIC_GLOBAL uint32_t* cur = gp(cursor_all + hist_off[2 * c + s]);
     unsigned* a = (unsigned*)smem;
-    for (int j = threadIdx.x; j < N; j += kBlock) {
+    for (int j = threadIdx.x; j < NB; j += kBlock) {
         a[j] = hist[j];
         hist[j] = 0u;
     }
-    __syncthreads();
-    block_scan(a, N, red);
-    for (int j = threadIdx.x; j < N; j += kBlock) cur[j] = j > 0 ? a[j - 1] : 0u;
-    if (threadIdx.x == 0) st->sort_live[s] = N > 0 ? a[N - 1] : 0;
+    lds_barrier();
+    block_scan(a, NB, red);
+    for (int j = threadIdx.x; j < NB; j += kBlock) cur[j] = j > 0 ? a[j - 1] : 0u;
+    if (threadIdx.x == 0) st->sort_live[s] = NB > 0 ? a[NB - 1] : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* cursor_all,
@@ -1063,58 +1119,79 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     const Work w = P.work[blockIdx.x];
     Case* C = P.cases + w.c;
     State* st = P.state + w.c;
-    const Species& S = C->sp[w.s];
-    const int N = C->n_cells;
+    const Species S = C->sp[w.s];
+    const int sh = bucket_shift(w.s);
+    const int NB = n_buckets(C->n_cells, w.s);
     const bool imp = C->scheme == 1;
-    uint32_t* cur = cursor_all + hist_off[2 * w.c + w.s];
+    PIC_GLOBAL uint32_t* cur = gp(cursor_all + hist_off[2 * w.c + w.s]);
     unsigned* lh = (unsigned*)smem;
-    unsigned* lb = lh + N;
-    for (int j = threadIdx.x; j < N; j += kBlock) lh[j] = 0u;
+    unsigned* lb = lh + NB;
+    for (int j = threadIdx.x; j < NB; j += kBlock) lh[j] = 0u;
     if (threadIdx.x == 0) {
         s_lo = kNoCell;
         s_hi = -1;
     }
-    __syncthreads();
+    lds_barrier();
     const int n = st->n_slots[w.s];
     int chunk = (n + w.nb - 1) / w.nb;
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk, end = min(n, start + chunk);
+    const PIC_GLOBAL int32_t* __restrict__ cellp = gp((const int32_t*)S.cell);
     int lo = kNoCell, hi = -1;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
-        const int c = i < end ? S.cell[i] : -1;
-        wave_count_add(lh, c, c >= 0);
-        if (c >= 0) range_note(lo, hi, c);
+        const int c = i < end ? cellp[i] : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        wave_count_add(lh, b, b >= 0);
+        if (b >= 0) range_note(lo, hi, b);
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
         atomicMax(&s_hi, hi);
     }
-    __syncthreads();
+    lds_barrier();
+    // one run per touched bucket
     for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock) {
         const unsigned k = lh[j];
-        if (k) lb[j] = atomicAdd(&cur[j], k);
+        if (k) lb[j] = gatomic_add(&cur[j], k);
         lh[j] = 0u;
     }
-    __syncthreads();
+    lds_barrier();
+    const PIC_GLOBAL float* __restrict__ offp = gp((const float*)S.off);
+    const PIC_GLOBAL float* __restrict__ vxp = gp((const float*)S.vx);
+    const PIC_GLOBAL float* __restrict__ vyp = gp((const float*)S.vy);
+    const PIC_GLOBAL float* __restrict__ vzp = gp((const float*)S.vz);
+    const PIC_GLOBAL uint64_t* __restrict__ idp = gp((const uint64_t*)S.id);
+    const PIC_GLOBAL float* __restrict__ abp = gp((const float*)S.abar);
+    PIC_GLOBAL int32_t* __restrict__ cell2 = gp(S.cell2);
+    PIC_GLOBAL float* __restrict__ off2 = gp(S.off2);
+    PIC_GLOBAL float* __restrict__ vx2 = gp(S.vx2);
+    PIC_GLOBAL float* __restrict__ vy2 = gp(S.vy2);
+    PIC_GLOBAL float* __restrict__ vz2 = gp(S.vz2);
+    PIC_GLOBAL uint64_t* __restrict__ id2 = gp(S.id2);
+    PIC_GLOBAL float* __restrict__ ab2 = gp(S.abar2);
     double v2 = 0.0;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
-        const int c = i < end ? S.cell[i] : -1;
-        const unsigned r = wave_count_add(lh, c, c >= 0);
+        const int j = min(i, end - 1);
+        const int c0 = cellp[j];
+        const float o = offp[j], vx = vxp[j], vy = vyp[j], vz = vzp[j];
+        const uint64_t id = idp[j];
+        const float ab = imp ? abp[j] : 0.0f;
+        const int c = i < end ? c0 : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        const unsigned r = wave_count_add(lh, b, b >= 0);
         if (c < 0) continue;
-        const unsigned d = lb[c] + r;
-        const float vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
-        S.cell2[d] = c;
-        S.off2[d] = S.off[i];
-        S.vx2[d] = vx;
-        S.vy2[d] = vy;
-        S.vz2[d] = vz;
-        S.id2[d] = S.id[i];
+        const unsigned d = lb[b] + r;
+        cell2[d] = c;
+        off2[d] = o;
+        vx2[d] = vx;
+        vy2[d] = vy;
+        vz2[d] = vz;
+        id2[d] = id;
         float vh = vx;
         if (imp) {
-            const float ab = S.abar[i];
-            S.abar2[d] = ab;
+            ab2[d] = ab;
             vh = vx - 0.5f * ab;   // v_{n-1/2} from the stored prediction
         }
         v2 += (double)(vh * vh + vy * vy + vz * vz);
@@ -1133,7 +1210,7 @@ __global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
     __shared__ long long si[PU_N];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    reduce_partials<kFinBlock>(P, C->first_block, C->n_blocks, sd, si);
+    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
     if (threadIdx.x != 0) return;
     for (int s = 0; s < 2; ++s) {
         Species& S = C->sp[s];
@@ -1168,7 +1245,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         s_lo = kNoCell;
         s_hi = -1;
     }
-    __syncthreads();
+    lds_barrier();
     const int n = st->n_slots[w.s];
     int chunk = (n + w.nb - 1) / w.nb;
     chunk = (chunk + 63) & ~63;
@@ -1184,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         atomicMin(&s_lo, lo);
         atomicMax(&s_hi, hi);
     }
-    __syncthreads();
+    lds_barrier();
     for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock) {
         const unsigned long long p = dep[j];
         if (p) {
@@ -1200,7 +1277,8 @@ __global__ __launch_bounds__(kFinBlock) void k_solve(Params P)
     __shared__ double red[kFinBlock / 64];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    solve_case<kFinBlock>(C, st, st->step + (C->scheme == 1 ? 1 : 0), false, (double*)smem, red);
+    solve_case<kFinBlock>(C, st, st->step + (C->scheme == 1 ? 1 : 0), st->step, false,
+                          (double*)smem, red);
 }
 
 }  // namespace pic

@@ -46,6 +46,10 @@ struct HostCase {
     int64_t cap[2];
     int64_t n0[2];
     double vscale;          // (m/s) -> cells/step
+    // float64 values of the per-species collision constants that the float
+    // path stores as float32 (for the plain FP64 form): eps_unit, opal_B,
+    // recoil2, vth_neutral, vth_newion, t_scale, t_off, t_max, thr_v2[4]
+    double c64[2][12];
     size_t hist_off[2];
     // device allocations owned by the case
     std::vector<void*> allocs;
@@ -187,6 +191,7 @@ int build_work(pic_ctx* c)
                 for (int b = 0; b < nb; ++b) c->work.push_back(Work{k, s, b, nb});
             }
             C.n_blocks = (int)c->work.size() - C.first_block;
+
             c->grp_maxN[g] = std::max(c->grp_maxN[g], (int)h.cfg.n_cells);
         }
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
@@ -210,6 +215,7 @@ int upload_work(pic_ctx* c)
     HIPCHK(c, hipMemset(c->d_pd, 0, sizeof(double) * PD_N * nb));
     HIPCHK(c, hipMalloc(&c->d_pu, sizeof(unsigned) * PU_N * nb));
     HIPCHK(c, hipMemset(c->d_pu, 0, sizeof(unsigned) * PU_N * nb));
+
     return PIC_OK;
 }
 
@@ -224,6 +230,7 @@ Params params(pic_ctx* c, int mode)
     p.stride = (int32_t)c->work.size();
     p.n_cases = c->n_cases;
     p.mode = mode;
+
     return p;
 }
 
@@ -407,6 +414,13 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             S.vth_neutral = (float)(std::sqrt(KB * g.gas_temp_K / (g.gas_mass_kg > 0 ? g.gas_mass_kg : 1.0)) * dt / dx);
             S.vth_newion = (float)(std::sqrt(KB * g.gas_temp_K / species[2 * k + 1].m_kg) * dt / dx);
             S.eedf_scale = 2.0f;   // 0.5 eV bins
+            double* c64 = h.c64[s];
+            c64[0] = eps_unit;
+            c64[1] = g.opal_B_eV;
+            c64[2] = 2.0 * species[2 * k].m_kg / (g.gas_mass_kg > 0 ? g.gas_mass_kg : 1.0);
+            c64[3] = std::sqrt(KB * g.gas_temp_K / (g.gas_mass_kg > 0 ? g.gas_mass_kg : 1.0)) * dt / dx;
+            c64[4] = std::sqrt(KB * g.gas_temp_K / species[2 * k + 1].m_kg) * dt / dx;
+            for (int p = 5; p < 12; ++p) c64[p] = p >= 8 ? -1.0 : 0.0;
             for (int p = 0; p < kMaxProc; ++p) {
                 S.kind[p] = -1;
                 S.thr_v2[p] = -1.0f;
@@ -423,11 +437,16 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                 S.t_scale = (float)(eps_unit / a->de_eV);
                 S.t_off = (float)(-a->e0_eV / a->de_eV);
                 S.t_max = (float)(a->n - 1);
+                c64[5] = eps_unit / a->de_eV;
+                c64[6] = -a->e0_eV / a->de_eV;
+                c64[7] = (double)(a->n - 1);
                 for (int p = 0; p < S.n_proc; ++p) {
                     S.kind[p] = proc[s][p]->kind;
                     S.thr_v2[p] = proc[s][p]->threshold_eV > 0
                                       ? (float)(proc[s][p]->threshold_eV / eps_unit)
                                       : -1.0f;
+                    c64[8 + p] = proc[s][p]->threshold_eV > 0 ? proc[s][p]->threshold_eV / eps_unit
+                                                              : -1.0;
                 }
                 if (s == 0) {
                     std::vector<float> t(4 * (size_t)a->n, 0.0f);
@@ -536,6 +555,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         std::memset(st.data(), 0, sizeof(State) * n_cases);
         for (int k = 0; k < n_cases; ++k) {
             st[k].step = cases[k].start_step;
+            st[k].ledger_step = cases[k].start_step;
             for (int s = 0; s < 2; ++s) {
                 st[k].n_slots[s] = (int32_t)species[2 * k + s].n;
                 st[k].n_live[s] = (int32_t)species[2 * k + s].n;
@@ -632,7 +652,7 @@ int run_steps(pic_ctx* c, int64_t n, int which)
                 c->ev_used += 2;
             }
         }
-        hipLaunchKernelGGL(k_finalize, dim3(c->n_cases), dim3(kFinBlock),
+        hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock),
                            16 * ((size_t)c->maxN + 1) + 16, c->stream, params(c, 0), diag ? 1 : 0);
         HIPCHK(c, hipGetLastError());
         c->steps_taken++;
@@ -866,6 +886,13 @@ extern "C" int pic__ctx_case_info(pic_ctx* ctx, int32_t k, pic_case_config* cfg,
         scale[s] = ctx->hc[k].scale[s];
         cap[s] = ctx->hc[k].cap[s];
     }
+    return PIC_OK;
+}
+
+extern "C" int pic__ctx_species_consts(pic_ctx* ctx, int32_t k, int32_t s, double* out12)
+{
+    if (!ctx || k < 0 || k >= ctx->n_cases || s < 0 || s > 1) return PIC_E_INVAL;
+    for (int i = 0; i < 12; ++i) out12[i] = ctx->hc[k].c64[s][i];
     return PIC_OK;
 }
 
