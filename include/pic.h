@@ -96,7 +96,8 @@ typedef struct {
 typedef struct {
     double q_C, m_kg, weight;
     int64_t n;              /* particles given                                  */
-    int64_t capacity;       /* slots reserved (>= n); ionization appends        */
+    int64_t capacity;       /* slots reserved (>= n, < 2^29 - 1024); ionization
+                               appends children after the occupied slots       */
     const int32_t* cell;
     const float* off;
     const float* vx;

@@ -70,6 +70,10 @@ class Ledger(C.Structure):
         }
 
 
+# null-collision waiting-time word: count (17 bits) | capped flag
+WAIT_MAX = 0x1FFFF
+WAIT_CAPPED = 0x20000
+
 _lib = None
 _D = C.POINTER(C.c_double)
 _U64 = C.POINTER(C.c_uint64)
@@ -98,7 +102,7 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_species.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
-                                      C.c_double, C.c_int64, _D, _D, _D, _D, _D, _U64]
+                                      C.c_double, C.c_int64, _D, _D, _D, _D, _D, _U64, _U32]
         L.orc_add_process.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double,
                                       C.c_double, C.c_double, C.c_int32, _D]
         L.orc_prepare.argtypes = [C.c_void_p]
@@ -110,7 +114,9 @@ def lib():
         L.orc_count.restype = C.c_int64
         L.orc_step_index.argtypes = [C.c_void_p]
         L.orc_step_index.restype = C.c_int64
-        L.orc_get_species.argtypes = [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D, _U64]
+        L.orc_get_species.argtypes = [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D, _U64, _U32]
+        L.orc_mcc_wait_step.argtypes = [C.c_void_p, C.c_int32, C.c_uint64, C.c_int64, _U32]
+        L.orc_mcc_wait_step.restype = C.c_int
         L.orc_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, _D, _D, _D]
         L.orc_get_ledger.argtypes = [C.c_void_p, C.POINTER(Ledger)]
         L.orc_get_heating.argtypes = [C.c_void_p, _D, _D]
@@ -217,9 +223,12 @@ class Sim:
             ab = None if ab is None else _f64(ab)
             ids = np.ascontiguousarray(sp["id"], dtype=np.uint64)
             vx, vy, vz = _f64(sp["vx"]), _f64(sp["vy"]), _f64(sp["vz"])
+            wt = sp.get("wait")
+            wt = None if wt is None else np.ascontiguousarray(wt, dtype=np.uint32)
             rc = lib().orc_set_species(self._h, k, sp["q"], sp["m"], sp["w"], n, _dp(xi),
                                        _dp(vx), _dp(vy), _dp(vz), _dp(ab),
-                                       ids.ctypes.data_as(_U64))
+                                       ids.ctypes.data_as(_U64),
+                                       None if wt is None else wt.ctypes.data_as(_U32))
             if rc:
                 raise ValueError("bad species")
         self.q = [sp["q"] for sp in species]
@@ -268,9 +277,12 @@ class Sim:
         n = self.count(sp)
         out = {k: np.zeros(n) for k in ("xi", "vx", "vy", "vz", "abar")}
         ids = np.zeros(n, dtype=np.uint64)
+        wt = np.zeros(n, dtype=np.uint32)
         lib().orc_get_species(self._h, sp, _dp(out["xi"]), _dp(out["vx"]), _dp(out["vy"]),
-                              _dp(out["vz"]), _dp(out["abar"]), ids.ctypes.data_as(_U64))
+                              _dp(out["vz"]), _dp(out["abar"]), ids.ctypes.data_as(_U64),
+                              wt.ctypes.data_as(_U32))
         out["id"] = ids
+        out["wait"] = wt
         return out
 
     def fields(self) -> dict:
@@ -290,6 +302,12 @@ class Sim:
         he, hi = np.zeros(self.N), np.zeros(self.N)
         lib().orc_get_heating(self._h, _dp(he), _dp(hi))
         return he, hi
+
+    def wait_step(self, sp: int, pid: int, step: int, wait: int):
+        """One step of the candidacy rule: (is_candidate, new wait word)."""
+        w = C.c_uint32(int(wait))
+        r = lib().orc_mcc_wait_step(self._h, sp, pid, step, C.byref(w))
+        return bool(r), int(w.value)
 
     def collide_one(self, sp: int, pid: int, step: int, v):
         v = _f64(v).copy()

@@ -44,6 +44,8 @@ typedef struct {
     int64_t n, cap;
     double *xi, *vx, *vy, *vz, *abar;
     uint64_t* id;
+    uint32_t* wait;      /* null-collision waiting time (see orc_mcc_wait_step) */
+    int32_t wait_given;  /* waits supplied by the caller (else drawn by prepare) */
 } species_t;
 
 struct orc_sim {
@@ -55,6 +57,7 @@ struct orc_sim {
     proc_t proc[MAX_PROC];
     double numax[2];
     double pnull[2];
+    double inv_log1mp[2];  /* 1 / ln(1 - P_null) */
     /* fields of the most recent solve */
     double *rho, *phi, *E, *chi, *Q[2], *cnt[2];
     double* heat[2];
@@ -268,6 +271,7 @@ void orc_destroy(orc_sim* s)
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
         free(p->xi); free(p->vx); free(p->vy); free(p->vz); free(p->abar); free(p->id);
+        free(p->wait);
         free(s->Q[k]); free(s->cnt[k]); free(s->heat[k]);
     }
     for (int k = 0; k < s->n_proc; ++k) free(s->proc[k].sigma);
@@ -286,12 +290,13 @@ static void species_reserve(species_t* p, int64_t need)
     p->vz = (double*)realloc(p->vz, sizeof(double) * (size_t)cap);
     p->abar = (double*)realloc(p->abar, sizeof(double) * (size_t)cap);
     p->id = (uint64_t*)realloc(p->id, sizeof(uint64_t) * (size_t)cap);
+    p->wait = (uint32_t*)realloc(p->wait, sizeof(uint32_t) * (size_t)cap);
     p->cap = cap;
 }
 
 int orc_set_species(orc_sim* s, int32_t k, double q, double m, double w, int64_t n,
                     const double* xi, const double* vx, const double* vy, const double* vz,
-                    const double* abar, const uint64_t* id)
+                    const double* abar, const uint64_t* id, const uint32_t* wait)
 {
     if (k < 0 || k > 1 || n < 0 || m <= 0.0) return -1;
     species_t* p = &s->sp[k];
@@ -305,7 +310,9 @@ int orc_set_species(orc_sim* s, int32_t k, double q, double m, double w, int64_t
         p->vz[i] = vz[i];
         p->abar[i] = abar ? abar[i] : 0.0;
         p->id[i] = id[i];
+        p->wait[i] = wait ? wait[i] : 0u;
     }
+    p->wait_given = wait != NULL;
     return 0;
 }
 
@@ -339,6 +346,64 @@ static int beyond_table(const orc_sim* s, int32_t sp, double eps)
         if (s->proc[k].sp == sp)
             return eps > s->proc[k].e0 + (double)(s->proc[k].n - 1) * s->proc[k].de;
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Null-collision candidacy (Vahedi & Surendra 1995): in every step every   */
+/* particle is a candidate independently with probability P_null.  The      */
+/* Bernoulli sequence is realised by geometric waiting times: a particle    */
+/* carries the number of non-candidate steps left before its next           */
+/* candidacy, W ~ Geo0(P_null), P(W = k) = (1 - P_null)^k P_null, drawn by  */
+/* inversion W = floor(ln u / ln(1 - P_null)) from a uniform u of the       */
+/* particle's Philox stream.  Stored word: count (17 bits) | capped << 17;  */
+/* a draw above the count range is stored as the largest count with the     */
+/* capped flag, and when such a wait runs out the step's trial is drawn     */
+/* afresh (the geometric law is memoryless, so the sequence of trials stays */
+/* Bernoulli).                                                              */
+/* ------------------------------------------------------------------------ */
+static double geo0(const orc_sim* s, int32_t sp, double u)
+{
+    if (s->pnull[sp] >= 1.0) return 0.0;
+    return floor(log(u) * s->inv_log1mp[sp]);
+}
+
+static uint32_t wait_encode(double W)
+{
+    if (W > (double)ORC_WAIT_MAX) return ORC_WAIT_MAX | ORC_WAIT_CAPPED;
+    return (uint32_t)W;
+}
+
+/* first trial of a particle at step `step`: draw 4 of its stream */
+static uint32_t initial_wait(const orc_sim* s, int32_t sp, uint64_t id, int64_t step)
+{
+    double u[4];
+    draw4(s, sp, id, step, 4, u);
+    return wait_encode(geo0(s, sp, u[0]));
+}
+
+int orc_mcc_wait_step(const orc_sim* s, int32_t sp, uint64_t id, int64_t step, uint32_t* wait)
+{
+    uint32_t w = *wait;
+    uint32_t cnt = w & ORC_WAIT_MAX;
+    if (cnt > 0) {
+        *wait = (cnt - 1) | (w & ORC_WAIT_CAPPED);
+        return 0;
+    }
+    if (w & ORC_WAIT_CAPPED) {
+        /* a capped wait ran out: this step's trial is still open */
+        double u[4];
+        draw4(s, sp, id, step, 4, u);
+        double W = geo0(s, sp, u[0]);
+        if (W >= 1.0) {
+            *wait = wait_encode(W - 1.0);
+            return 0;
+        }
+    }
+    /* candidate: the next waiting time comes from u0 of draw 0 */
+    double u[4];
+    draw4(s, sp, id, step, 0, u);
+    *wait = wait_encode(geo0(s, sp, u[0]));
+    return 1;
 }
 
 /* Null-collision frequency (Vahedi & Surendra, Comput. Phys. Commun. 87 (1995)
@@ -377,6 +442,14 @@ int orc_prepare(orc_sim* s)
         }
         s->numax[sp] = s->c.gas_density_m3 * best;
         s->pnull[sp] = 1.0 - exp(-s->numax[sp] * s->c.dt_s);
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        double p = s->pnull[sp];
+        s->inv_log1mp[sp] = (p > 0.0 && p < 1.0) ? 1.0 / log1p(-p) : 0.0;
+        /* particles loaded without waits take their first trial at step0 */
+        species_t* q = &s->sp[sp];
+        if (!q->wait_given)
+            for (int64_t i = 0; i < q->n; ++i) q->wait[i] = initial_wait(s, sp, q->id[i], s->step);
     }
     return 0;
 }
@@ -452,16 +525,18 @@ static void remove_particle(species_t* p, int64_t i)
     int64_t last = p->n - 1;
     p->xi[i] = p->xi[last]; p->vx[i] = p->vx[last]; p->vy[i] = p->vy[last];
     p->vz[i] = p->vz[last]; p->abar[i] = p->abar[last]; p->id[i] = p->id[last];
+    p->wait[i] = p->wait[last];
     p->n = last;
 }
 
 static void append_particle(species_t* p, double xi, double vx, double vy, double vz,
-                            double abar, uint64_t id)
+                            double abar, uint64_t id, uint32_t wait)
 {
     species_reserve(p, p->n + 1);
     int64_t i = p->n++;
     p->xi[i] = xi; p->vx[i] = vx; p->vy[i] = vy; p->vz[i] = vz; p->abar[i] = abar;
     p->id[i] = id;
+    p->wait[i] = wait;
 }
 
 /* Boundary rule.  Dirichlet: absorbed at the electrode it crossed
@@ -510,7 +585,6 @@ int orc_collide_one(orc_sim* s, int32_t sp, uint64_t id, int64_t step, double* v
 {
     double u[4];
     draw4(s, sp, id, step, 0, u);
-    if (!(u[0] < s->pnull[sp])) return -1;
     const species_t* me = &s->sp[sp];
     double ng = s->c.gas_density_m3;
     double vth_gas = sqrt(KB_J * s->c.gas_temp_K / s->c.gas_mass_kg);
@@ -594,15 +668,16 @@ int orc_collide_one(orc_sim* s, int32_t sp, uint64_t id, int64_t step, double* v
 static void mcc_species(orc_sim* s, int32_t sp, int64_t n0, int64_t step)
 {
     species_t* p = &s->sp[sp];
+    if (!(s->pnull[sp] > 0.0)) return;
     for (int64_t i = 0; i < n0; ++i) {
+        if (!orc_mcc_wait_step(s, sp, p->id[i], step, &p->wait[i])) continue;
+        s->led.n_candidates[sp]++;
         double v[3] = {p->vx[i], p->vy[i], p->vz[i]};
         double ve[3], vi[3];
         int over = 0;
         double k0 = kin(p, v[0], v[1], v[2]);
         int r = orc_collide_one(s, sp, p->id[i], step, v, ve, vi, &over);
         if (over) s->led.n_over_table[sp]++;
-        if (r == -1) continue;
-        s->led.n_candidates[sp]++;
         if (r < 0) continue;
         s->led.n_coll[sp][r]++;
         p->vx[i] = v[0]; p->vy[i] = v[1]; p->vz[i] = v[2];
@@ -611,8 +686,10 @@ static void mcc_species(orc_sim* s, int32_t sp, int64_t n0, int64_t step)
             uint64_t ide = child_id(s, p->id[i], step, 0);
             uint64_t idi = child_id(s, p->id[i], step, 1);
             double x = p->xi[i];
-            append_particle(&s->sp[0], x, ve[0], ve[1], ve[2], 0.0, ide);
-            append_particle(&s->sp[1], x, vi[0], vi[1], vi[2], 0.0, idi);
+            append_particle(&s->sp[0], x, ve[0], ve[1], ve[2], 0.0, ide,
+                            initial_wait(s, 0, ide, step));
+            append_particle(&s->sp[1], x, vi[0], vi[1], vi[2], 0.0, idi,
+                            initial_wait(s, 1, idi, step));
             s->led.coll_dK[0] += kin(&s->sp[0], ve[0], ve[1], ve[2]);
             s->led.coll_dK[1] += kin(&s->sp[1], vi[0], vi[1], vi[2]);
             s->led.n_created[0]++;
@@ -807,7 +884,7 @@ int64_t orc_count(const orc_sim* s, int32_t sp) { return s->sp[sp].n; }
 int64_t orc_step_index(const orc_sim* s) { return s->step; }
 
 void orc_get_species(const orc_sim* s, int32_t sp, double* xi, double* vx, double* vy,
-                     double* vz, double* abar, uint64_t* id)
+                     double* vz, double* abar, uint64_t* id, uint32_t* wait)
 {
     const species_t* p = &s->sp[sp];
     for (int64_t i = 0; i < p->n; ++i) {
@@ -817,6 +894,7 @@ void orc_get_species(const orc_sim* s, int32_t sp, double* xi, double* vx, doubl
         if (vz) vz[i] = p->vz[i];
         if (abar) abar[i] = p->abar[i];
         if (id) id[i] = p->id[i];
+        if (wait) wait[i] = p->wait[i];
     }
 }
 

@@ -32,6 +32,31 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A pointer known to be the same in every lane, moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+// Load / store at a 32-bit byte offset from a global base held in scalar
+// registers: one address form (scalar base + vector offset) instead of 64-bit
+// vector address arithmetic per access.  Arrays addressed this way stay below
+// 4 GiB.
+template <class T>
+__device__ __forceinline__ T ldg(const PIC_GLOBAL T* base, uint32_t byte_off)
+{
+    return *(const PIC_GLOBAL T*)((const PIC_GLOBAL char*)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void stg(PIC_GLOBAL T* base, uint32_t byte_off, T v)
+{
+    *(PIC_GLOBAL T*)((PIC_GLOBAL char*)base + byte_off) = v;
+}
+
 // relaxed device-scope atomic add through a global pointer
 template <class T>
 __device__ __forceinline__ T gatomic_add(PIC_GLOBAL T* p, T v)

@@ -524,11 +524,27 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     State* st = P.state + w.c;
     const int N = C->n_cells;
     const int s = w.s;
-    // register copy: stores to the particle arrays cannot alias it
-    const Species S = C->sp[s];
+    // particle arrays (addressed by 32-bit byte offsets from a scalar base)
+    // and the constants of the streaming pass, read before any store
+    PIC_GLOBAL int32_t* __restrict__ cellp = gp(uniform_ptr(C->sp[s].cell));
+    PIC_GLOBAL float* __restrict__ offp = gp(uniform_ptr(C->sp[s].off));
+    PIC_GLOBAL float* __restrict__ vxp = gp(uniform_ptr(C->sp[s].vx));
+    PIC_GLOBAL float* __restrict__ vyp = gp(uniform_ptr(C->sp[s].vy));
+    PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
+    const PIC_GLOBAL uint64_t* __restrict__ idp = gp(uniform_ptr((const uint64_t*)C->sp[s].id));
+    PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
+    const uint32_t cand_thr = C->sp[s].cand_thr;
+    const float eedf_k = C->sp[s].eps_unit * C->sp[s].eedf_scale;
+    const double kin_unit = C->sp[s].kin_unit;
+    const int n_proc = C->sp[s].n_proc;
+    // The collision constants go to LDS (the drain reads them there: no
+    // register pressure, and stores to the particle arrays cannot alias them).
+    __shared__ Species S;
+    for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
+        ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
     const bool periodic = C->bc == 1;
     const bool mc = C->gather == 1;
-    const bool coll = C->collisions != 0 && S.n_proc > 0;
+    const bool coll = C->collisions != 0 && n_proc > 0;
     const uint32_t k0 = C->key0, k1 = C->key1;
 
     const StepLds L = step_lds_layout(N, DIAG, kImp);
@@ -580,15 +596,6 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const int start = w.b * chunk;
     const int end = min(n, start + chunk);
 
-    PIC_GLOBAL int32_t* __restrict__ cellp = gp(S.cell);
-    PIC_GLOBAL float* __restrict__ offp = gp(S.off);
-    PIC_GLOBAL float* __restrict__ vxp = gp(S.vx);
-    PIC_GLOBAL float* __restrict__ vyp = gp(S.vy);
-    PIC_GLOBAL float* __restrict__ vzp = gp(S.vz);
-    const PIC_GLOBAL uint64_t* __restrict__ idp = gp((const uint64_t*)S.id);
-    PIC_GLOBAL float* __restrict__ abp = gp(S.abar);
-    const uint32_t cand_thr = S.cand_thr;
-    const float eedf_k = S.eps_unit * S.eedf_scale;
 
     double work = 0.0, cdk = 0.0;
     unsigned cand = 0u;
@@ -598,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     auto absorb = [&](int i, int e, float vxh, float vy, float vz) {
         atomicAdd(&acc.absK[s][e], (double)(vxh * vxh + vy * vy + vz * vz));
         atomicAdd(&acc.abs_n[s][e], 1u);
-        cellp[i] = -1;
+        stg(cellp, (uint32_t)i << 2, -1);
     };
     auto eedf_note = [&](float vx, float vy, float vz) {
         const float fb = (vx * vx + vy * vy + vz * vz) * eedf_k;
@@ -623,11 +630,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             i = q_idx[e];
             vn = q_vn[e];
             if (kImp) abn = q_ab[e];
-            c1 = cellp[i];
-            o1 = offp[i];
-            id = idp[i];
-            vy = vyp[i];
-            vz = vzp[i];
+            const uint32_t i4 = (uint32_t)i << 2;
+            c1 = ldg(cellp, i4);
+            o1 = ldg(offp, i4);
+            id = ldg(idp, i4 << 1);
+            vy = ldg(vyp, i4);
+            vz = ldg(vzp, i4);
             const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
                                     (uint32_t)s << 28, k0, k1);
             ++cand;
@@ -639,8 +647,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             if (kind >= 0) {
                 atomicAdd(&acc.n_coll[kind], 1u);
                 cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
-                vyp[i] = vy;
-                vzp[i] = vz;
+                stg(vyp, (uint32_t)i << 2, vy);
+                stg(vzp, (uint32_t)i << 2, vz);
             }
             if (DIAG && s == 0) eedf_note(vn, vy, vz);
         }
@@ -662,14 +670,15 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     gone = true;
                 }
                 if (!gone) {
-                    cellp[i] = c2;
-                    offp[i] = o2;
-                    vxp[i] = vst;
-                    abp[i] = abn;
+                    const uint32_t i4 = (uint32_t)i << 2;
+                    stg(cellp, i4, c2);
+                    stg(offp, i4, o2);
+                    stg(vxp, i4, vst);
+                    stg(abp, i4, abn);
                     dep_ok = true;
                 }
             } else {
-                vxp[i] = vn;
+                stg(vxp, (uint32_t)i << 2, vn);
             }
         }
         if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
@@ -746,17 +755,27 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         uint64_t idv[kILP];
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
-            const int j = min(base + k * kBlock + tid, end - 1);
-            c[k] = cellp[j];
-            o[k] = offp[j];
-            v[k] = vxp[j];
-            ab[k] = kImp ? abp[j] : 0.0f;
-            idv[k] = coll ? idp[j] : 0ull;
+            const uint32_t j4 = (uint32_t)min(base + k * kBlock + tid, end - 1) << 2;
+            c[k] = ldg(cellp, j4);
+            o[k] = ldg(offp, j4);
+            v[k] = ldg(vxp, j4);
+            ab[k] = kImp ? ldg(abp, j4) : 0.0f;
+        }
+        // ids only where collisions are drawn (a uniform branch around the
+        // whole batch, so the loads above stay in flight together)
+        if (coll) {
+#pragma unroll
+            for (int k = 0; k < kILP; ++k)
+                idv[k] = ldg(idp, (uint32_t)min(base + k * kBlock + tid, end - 1) << 3);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kILP; ++k) idv[k] = 0ull;
         }
         float wk = 0.0f;
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
             const int i = base + k * kBlock + tid;
+            const uint32_t i4 = (uint32_t)i << 2;
             const int cc = i < end ? c[k] : -1;
             bool live = cc >= 0;
             float a = 0.0f;
@@ -785,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     c1 %= N;
                     if (c1 < 0) c1 += N;
                 } else if (c1 < 0 || c1 >= N) {
-                    absorb(i, c1 < 0 ? 0 : 1, vn, vyp[i], vzp[i]);
+                    absorb(i, c1 < 0 ? 0 : 1, vn, ldg(vyp, i4), ldg(vzp, i4));
                     live = false;
                 }
             }
@@ -809,21 +828,21 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                         c2 %= N;
                         if (c2 < 0) c2 += N;
                     } else if (c2 < 0 || c2 >= N) {
-                        absorb(i, c2 < 0 ? 0 : 1, vn, vyp[i], vzp[i]);
+                        absorb(i, c2 < 0 ? 0 : 1, vn, ldg(vyp, i4), ldg(vzp, i4));
                         live = false;
                     }
                 }
                 if (live) {
-                    cellp[i] = c2;
-                    offp[i] = o2;
-                    vxp[i] = vst;
-                    if (kImp) abp[i] = abn;
+                    stg(cellp, i4, c2);
+                    stg(offp, i4, o2);
+                    stg(vxp, i4, vst);
+                    if (kImp) stg(abp, i4, abn);
                     dep_now = true;
-                    if (DIAG && s == 0) eedf_note(vn, vyp[i], vzp[i]);
+                    if (DIAG && s == 0) eedf_note(vn, ldg(vyp, i4), ldg(vzp, i4));
                 }
             } else if (live) {
-                cellp[i] = c1;
-                offp[i] = o1;
+                stg(cellp, i4, c1);
+                stg(offp, i4, o1);
                 dep_now = !kImp;
             }
             deposit_wave(dep, dep_now, c2, o2, lo, hi);
@@ -872,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             }
             if (DIAG) {
                 const float h = heat[j];
-                if (h != 0.0f) gatomic_add(gp(&C->heat_acc[s][j]), (double)h * S.kin_unit);
+                if (h != 0.0f) gatomic_add(gp(&C->heat_acc[s][j]), (double)h * kin_unit);
             }
         }
         if (DIAG && s == 0)

@@ -34,22 +34,88 @@ def sigma_tab(procs, kind, eps):
 
 @pytest.mark.parametrize("eps", [8.0, 30.0, 120.0])
 def test_process_fractions_match_null_collision_law(orc, eps):
+    # a candidate undergoes process k with probability n_g sigma_k(eps) v / nu_max
     sim, case, procs = beam_sim(orc)
     numax = sim.numax(0)
-    dt, ng = case["dt_s"], case["gas_density_m3"]
+    ng = case["gas_density_m3"]
     v = speed_of(eps, W.M_E)
-    pnull = 1 - math.exp(-numax * dt)
-    n = 60000
-    counts = {k: 0 for k in (-1, -2, 0, 1, 2)}
+    n = 30000
+    counts = {k: 0 for k in (-2, 0, 1, 2)}
     for pid in range(n):
         r = sim.collide_one(0, pid, 17, [v, 0.0, 0.0])[0]
         counts[r] += 1
     for kind in (W.ELASTIC, W.EXCITATION, W.IONIZATION):
-        p = ng * sigma_tab(procs, kind, eps) * v / numax * pnull
+        p = ng * sigma_tab(procs, kind, eps) * v / numax
         sd = math.sqrt(n * p * (1 - p)) + 1e-9
         assert abs(counts[kind] - n * p) <= 5 * sd + 1, (kind, counts[kind], n * p)
-    pc = pnull
-    assert abs((n - counts[-1]) - n * pc) <= 5 * math.sqrt(n * pc * (1 - pc))
+
+
+def _pnull(sim, case, sp):
+    return 1 - math.exp(-sim.numax(sp) * case["dt_s"])
+
+
+def test_waiting_times_are_geometric(orc):
+    # the initial wait W of a particle loaded at step0 is Geo0(P_null):
+    # P(W = k) = (1 - p)^k p; checked on the first few k and the mean
+    sim, case, procs = beam_sim(orc, p_mtorr=10.0)
+    p = _pnull(sim, case, 0)
+    assert 0.05 < p < 0.5
+    n = 40000
+    ws = []
+    for pid in range(n):
+        cand, w = sim.wait_step(0, pid, 7, orc.WAIT_CAPPED)   # open trial -> fresh draw
+        ws.append(-1 if cand else w + 1)    # -1: candidate now (W = 0)
+    ws = np.array(ws)
+    for k in range(4):
+        pk = (1 - p) ** k * p
+        cnt = int((ws == k).sum()) if k > 0 else int((ws == -1).sum())
+        assert abs(cnt - n * pk) <= 5 * math.sqrt(n * pk * (1 - pk)), (k, cnt, n * pk)
+    W = np.where(ws < 0, 0, ws)
+    assert abs(W.mean() - (1 - p) / p) <= 5 * math.sqrt((1 - p) / p ** 2 / n)
+
+
+def test_candidacy_is_bernoulli_per_step(orc):
+    # driving the rule over many steps: rate P_null, no correlation between
+    # consecutive steps (memoryless), gaps between candidacies geometric
+    sim, case, procs = beam_sim(orc, p_mtorr=10.0)
+    p = _pnull(sim, case, 0)
+    n, T = 3000, 40
+    c = np.zeros((n, T), bool)
+    for pid in range(n):
+        w = int(orc.WAIT_CAPPED)
+        for t in range(T):
+            c[pid, t], w = sim.wait_step(0, pid, 100 + t, w)
+    rate = c.mean()
+    N = n * T
+    assert abs(rate - p) <= 5 * math.sqrt(p * (1 - p) / N)
+    both = (c[:, 1:] & c[:, :-1]).mean()
+    assert abs(both - p * p) <= 5 * math.sqrt(p * p * (1 - p * p) / (n * (T - 1))) + 1e-4
+    # every step is decided by the stream of that step alone: the same
+    # particle run twice gives the same sequence
+    w = int(orc.WAIT_CAPPED)
+    seq = []
+    for t in range(T):
+        cand, w = sim.wait_step(0, 5, 100 + t, w)
+        seq.append(cand)
+    assert np.array_equal(np.array(seq), c[5])
+
+
+def test_capped_wait_counts_down_then_redraws(orc):
+    sim, case, procs = beam_sim(orc, p_mtorr=10.0)
+    cand, w = sim.wait_step(0, 3, 10, orc.WAIT_CAPPED | 2)
+    assert not cand and w == (orc.WAIT_CAPPED | 1)
+    cand, w = sim.wait_step(0, 3, 11, w)
+    assert not cand and w == orc.WAIT_CAPPED
+    # the open trial is Bernoulli(P_null) (the wait law is memoryless)
+    p = _pnull(sim, case, 0)
+    n = 20000
+    hits = sum(sim.wait_step(0, pid, 12, orc.WAIT_CAPPED)[0] for pid in range(n))
+    assert abs(hits - n * p) <= 5 * math.sqrt(n * p * (1 - p))
+    # a plain count decrements and never draws
+    assert sim.wait_step(0, 3, 12, 5) == (False, 4)
+    assert sim.wait_step(0, 3, 12, 1) == (False, 0)
+    cand, w = sim.wait_step(0, 3, 12, 0)
+    assert cand and w <= orc.WAIT_MAX
 
 
 def test_numax_bounds_every_table_interval(orc):
@@ -134,16 +200,15 @@ def test_charge_exchange_probability_and_neutral_velocity(orc):
     numax = sim.numax(1)
     dt, ng = case["dt_s"], case["gas_density_m3"]
     assert numax == pytest.approx(ng * 5e-19 * speed_of(2.0, W.M_AR), rel=1e-12)
-    pnull = 1 - math.exp(-numax * dt)
     # ion at rest: relative speed is the neutral speed, mean sqrt(8kT/(pi M))
     gbar = math.sqrt(8 * KB * 300.0 / (math.pi * W.M_AR))
-    n = 100000
+    n = 40000
     hits = []
     for pid in range(n):
         r, v1, ve, vi, over = sim.collide_one(1, pid, 5, [0.0, 0.0, 0.0])
         if r == W.CHARGE_EXCHANGE:
             hits.append(v1)
-    p = pnull * ng * 5e-19 * gbar / numax
+    p = ng * 5e-19 * gbar / numax
     sd = math.sqrt(n * p * (1 - p))
     assert abs(len(hits) - n * p) < 5 * sd
     # after CX the ion carries the neutral's velocity, drawn with probability
@@ -161,10 +226,7 @@ def test_over_table_energies_are_flagged(orc):
     sim, case, procs = beam_sim(orc, p_mtorr=5000.0)
     v = speed_of(1500.0, W.M_E)
     flagged = 0
-    cand = 0
-    for pid in range(2000):
+    for pid in range(500):
         r, v1, ve, vi, over = sim.collide_one(0, pid, 1, [v, 0, 0])
-        if r != -1:
-            cand += 1
-            flagged += over
-    assert cand > 0 and flagged == cand
+        flagged += over
+    assert flagged == 500
