@@ -88,11 +88,25 @@ typedef struct {
 
 #define PIC_MAX_CELLS 4096
 
+/* Null-collision waiting time of a particle (Vahedi & Surendra 1995, the
+ * MCC of Sec. III): in every step every particle is a candidate with
+ * probability P_null, independently; the library realises this Bernoulli
+ * process by waiting times W ~ Geo0(P_null) = floor(ln u / ln(1 - P_null))
+ * drawn from the particle's Philox stream, the number of non-candidate steps
+ * before the next candidacy.  Word: count (bits 0..16) | PIC_WAIT_CAPPED for
+ * a draw beyond the count range (when it runs out the step's trial is drawn
+ * afresh). */
+#define PIC_WAIT_MAX 0x1FFFFu
+#define PIC_WAIT_CAPPED 0x20000u
+
 /* One species of one case.  q_C, m_kg per physical particle; weight =
  * physical particles per macro-particle per m^2 of electrode area.
  * Positions: cell in [0, N), off in [0, 1).  Velocities in m/s unless
  * PIC_FLAG_INTERNAL_UNITS.  id: unique per species (the random stream of a
- * particle is keyed by (id, step)).  abar may be NULL (zero). */
+ * particle is keyed by (id, step)).  abar may be NULL (zero).  mcc_wait may
+ * be NULL: every particle then draws its wait for a first trial at the start
+ * step; a state exported by pic_diagnostics carries them for an exact
+ * resume. */
 typedef struct {
     double q_C, m_kg, weight;
     int64_t n;              /* particles given                                  */
@@ -105,6 +119,7 @@ typedef struct {
     const float* vz;
     const uint64_t* id;
     const float* abar;
+    const uint32_t* mcc_wait;   /* waiting-time words (< 2^18) or NULL           */
 } pic_species_init;
 
 /* Cross-section table of one process on the uniform energy grid
@@ -181,6 +196,7 @@ typedef struct {
     float* vz[2];
     uint64_t* id[2];
     float* abar[2];
+    uint32_t* mcc_wait[2];      /* null-collision waiting-time words            */
     /* PIC_DIAG_DENSITY: mean over sampled steps of the node density (m^-3) */
     double* density[2];         /* [N+1]                                        */
     int64_t density_samples;

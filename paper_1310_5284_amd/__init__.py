@@ -43,10 +43,16 @@ class CaseConfig(C.Structure):
                 ("opal_B_eV", C.c_double), ("seed", C.c_uint64)]
 
 
+# null-collision waiting-time word: count (17 bits) | capped flag
+WAIT_MAX = 0x1FFFF
+WAIT_CAPPED = 0x20000
+
+
 class SpeciesInit(C.Structure):
     _fields_ = [("q_C", C.c_double), ("m_kg", C.c_double), ("weight", C.c_double),
                 ("n", C.c_int64), ("capacity", C.c_int64), ("cell", _P), ("off", _P),
-                ("vx", _P), ("vy", _P), ("vz", _P), ("id", _P), ("abar", _P)]
+                ("vx", _P), ("vy", _P), ("vz", _P), ("id", _P), ("abar", _P),
+                ("mcc_wait", _P)]
 
 
 class Xsec(C.Structure):
@@ -85,6 +91,7 @@ class Diag(C.Structure):
                 ("history_cap", C.c_int64), ("history_n", C.c_int64),
                 ("state_cap", C.c_int64 * 2), ("cell", _P * 2), ("off", _P * 2), ("vx", _P * 2),
                 ("vy", _P * 2), ("vz", _P * 2), ("id", _P * 2), ("abar", _P * 2),
+                ("mcc_wait", _P * 2),
                 ("density", _P * 2), ("density_samples", C.c_int64), ("heating", _P * 2),
                 ("eedf_bins", C.c_int32), ("eedf_bin_eV", C.c_double), ("eedf", _P),
                 ("eedf_samples", C.c_int64)]
@@ -177,13 +184,16 @@ class PicContext:
                     arrs[key] = np.ascontiguousarray(sp[key], dtype=dt)
                 ab = sp.get("abar")
                 arrs["abar"] = None if ab is None else np.ascontiguousarray(ab, dtype=np.float32)
+                wt = sp.get("mcc_wait")
+                arrs["mcc_wait"] = None if wt is None else np.ascontiguousarray(wt, dtype=np.uint32)
                 self._keep.append(arrs)
                 nn = arrs["cell"].size
                 sps[2 * k + s] = SpeciesInit(
                     q_C=sp["q"], m_kg=sp["m"], weight=sp["w"], n=nn,
                     capacity=max(int(sp.get("capacity", nn)), nn), cell=_ptr(arrs["cell"]),
                     off=_ptr(arrs["off"]), vx=_ptr(arrs["vx"]), vy=_ptr(arrs["vy"]),
-                    vz=_ptr(arrs["vz"]), id=_ptr(arrs["id"]), abar=_ptr(arrs["abar"]))
+                    vz=_ptr(arrs["vz"]), id=_ptr(arrs["id"]), abar=_ptr(arrs["abar"]),
+                    mcc_wait=_ptr(arrs["mcc_wait"]))
         procs = processes if processes is not None else workloads[0].get("processes", [])
         xs = (Xsec * max(len(procs), 1))()
         for i, p in enumerate(procs):
@@ -292,10 +302,10 @@ class PicContext:
             a = dict(cell=np.zeros(n, np.int32), off=np.zeros(n, np.float32),
                      vx=np.zeros(n, np.float32), vy=np.zeros(n, np.float32),
                      vz=np.zeros(n, np.float32), id=np.zeros(n, np.uint64),
-                     abar=np.zeros(n, np.float32))
+                     abar=np.zeros(n, np.float32), mcc_wait=np.zeros(n, np.uint32))
             arrs.append(a)
             d.state_cap[s] = n
-            for k in ("cell", "off", "vx", "vy", "vz", "id", "abar"):
+            for k in ("cell", "off", "vx", "vy", "vz", "id", "abar", "mcc_wait"):
                 getattr(d, k)[s] = a[k].ctypes.data
         self._diag(case, DIAG_STATE, d)
         out = []

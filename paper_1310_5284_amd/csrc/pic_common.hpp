@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pic.h"
 #include "pic_device.hpp"
 
 namespace pic {
@@ -121,6 +122,32 @@ __device__ __forceinline__ uint64_t child_id(uint64_t parent, uint32_t step, uin
     const uint4 r = philox((uint32_t)parent, (uint32_t)(parent >> 32), step,
                            (sp_child << 28) | 0x0FFFFFFu, k0, k1);
     return ((uint64_t)r.x | ((uint64_t)r.y << 32)) | (1ull << 63);
+}
+
+// ---------------------------------------------------------------------------
+// Particle cell word: bit 31 set (negative) for an empty slot, else the cell
+// index in bits 0..12 and the null-collision waiting-time word (count in 17
+// bits | capped flag, PIC_WAIT_*) in bits 13..30.
+// ---------------------------------------------------------------------------
+constexpr int kCellBits = 13;
+constexpr int32_t kCellMask = (1 << kCellBits) - 1;
+
+__device__ __forceinline__ int32_t pack_cell(int c, uint32_t wait)
+{
+    return c | (int32_t)(wait << kCellBits);
+}
+__device__ __forceinline__ int cell_of(int32_t word) { return word >= 0 ? (word & kCellMask) : -1; }
+__device__ __forceinline__ uint32_t wait_of(int32_t word) { return (uint32_t)word >> kCellBits; }
+
+// Waiting time W ~ Geo0(P_null) by inversion, W = floor(ln u / ln(1 - P_null)),
+// in float64 (inv = 1 / ln(1 - P_null); 0 when P_null >= 1, giving W = 0).
+__device__ __forceinline__ double geo0(uint32_t r, double inv)
+{
+    return floor(log((double)u01(r)) * inv);
+}
+__device__ __forceinline__ uint32_t wait_encode(double W)
+{
+    return W > (double)PIC_WAIT_MAX ? (PIC_WAIT_MAX | PIC_WAIT_CAPPED) : (uint32_t)W;
 }
 
 // ---------------------------------------------------------------------------

@@ -61,6 +61,7 @@ struct Species {
     const float* tab_i;  // ion table (charge exchange), sigma * sig_scale
     float eedf_scale;    // EEDF bins per eV
     int32_t pad;
+    double inv_log1mp;   // 1 / ln(1 - P_null) (geometric waiting times)
 };
 
 // Everything a kernel needs to know about one case.

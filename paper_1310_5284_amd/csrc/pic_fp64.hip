@@ -24,6 +24,7 @@ struct Species64 {
     double* vz;
     uint64_t* id;
     int32_t* alive;
+    uint32_t* wait;     // null-collision waiting-time words
     int64_t capacity;
     double accel;       // cells/step^2 per (V/m)
     double qw_dx;
@@ -32,6 +33,7 @@ struct Species64 {
     int32_t kind[kMaxProc];
     int32_t n_proc;
     uint32_t cand_thr;
+    double inv_log1mp;  // 1 / ln(1 - P_null)
     double vth_neutral, vth_newion, recoil2, opal_B;
     const double* tab;  // electrons [n][4], ions [n]: sigma * n_g (dx/dt) / nu_max
 };
@@ -170,8 +172,15 @@ __device__ __forceinline__ void box_muller64(double ua, double ub, double& n1, d
     n2 = r * sp;
 }
 
+__device__ __forceinline__ uint32_t geo_wait64(uint32_t r, double inv)
+{
+    const double W = floor(log(u01d(r)) * inv);
+    return W > (double)PIC_WAIT_MAX ? (PIC_WAIT_MAX | PIC_WAIT_CAPPED) : (uint32_t)W;
+}
+
 __device__ __forceinline__ void append64(Case64* C, State64* st, int s, double x, double vx,
-                                         double vy, double vz, uint64_t id)
+                                         double vy, double vz, uint64_t id, uint32_t step,
+                                         uint32_t k0, uint32_t k1)
 {
     const Species64& S = C->sp[s];
     const int slot = atomicAdd(&st->n_next[s], 1);
@@ -186,6 +195,10 @@ __device__ __forceinline__ void append64(Case64* C, State64* st, int s, double x
     S.vz[slot] = vz;
     S.id[slot] = id;
     S.alive[slot] = 1;
+    // first trial of the child at the next step: draw 4 of its stream
+    const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step, ((uint32_t)s << 28) | 4u,
+                            k0, k1);
+    S.wait[slot] = geo_wait64(r4.x, S.inv_log1mp);
 }
 
 __global__ __launch_bounds__(kBlock) void k64_push(Params64 P)
@@ -231,9 +244,31 @@ __global__ __launch_bounds__(kBlock) void k64_push(Params64 P)
         S.xi[i] = x;
         if (C->collisions && S.n_proc > 0) {
             const uint64_t id = S.id[i];
-            const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
-                                    (uint32_t)s << 28, k0, k1);
-            if ((r0.x >> 9) < S.cand_thr) {
+            // null-collision candidacy by waiting time (count, capped flag)
+            const uint32_t w = S.wait[i];
+            const uint32_t cnt = w & PIC_WAIT_MAX;
+            bool cand = false;
+            if (cnt > 0) {
+                S.wait[i] = (cnt - 1) | (w & PIC_WAIT_CAPPED);
+            } else {
+                cand = true;
+                if (w & PIC_WAIT_CAPPED) {
+                    const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                            ((uint32_t)s << 28) | 4u, k0, k1);
+                    const double W = floor(log(u01d(r4.x)) * S.inv_log1mp);
+                    if (W >= 1.0) {
+                        cand = false;
+                        const double Wm = W - 1.0;
+                        S.wait[i] = Wm > (double)PIC_WAIT_MAX ? (PIC_WAIT_MAX | PIC_WAIT_CAPPED)
+                                                              : (uint32_t)Wm;
+                    }
+                }
+            }
+            const uint4 r0 = cand ? philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                           (uint32_t)s << 28, k0, k1)
+                                  : make_uint4(0, 0, 0, 0);
+            if (cand) S.wait[i] = geo_wait64(r0.x, S.inv_log1mp);
+            if (cand) {
                 double vy = S.vy[i], vz = S.vz[i];
                 const double u1 = u01d(r0.y);
                 if (s == 0) {
@@ -278,8 +313,10 @@ __global__ __launch_bounds__(kBlock) void k64_push(Params64 P)
                             box_muller64(u01d(r3.x), u01d(r3.y), n1, n2);
                             box_muller64(u01d(r3.z), u01d(r3.w), n3, n4);
                             const double vt = C->sp[0].vth_newion;
-                            append64(C, st, 0, x, s2 * ex, s2 * ey, s2 * ez, child_id(id, step32, 0u, k0, k1));
-                            append64(C, st, 1, x, vt * n1, vt * n2, vt * n3, child_id(id, step32, 1u, k0, k1));
+                            append64(C, st, 0, x, s2 * ex, s2 * ey, s2 * ez,
+                                     child_id(id, step32, 0u, k0, k1), step32, k0, k1);
+                            append64(C, st, 1, x, vt * n1, vt * n2, vt * n3,
+                                     child_id(id, step32, 1u, k0, k1), step32, k0, k1);
                         }
                         S.vy[i] = vy;
                         S.vz[i] = vz;
@@ -419,16 +456,18 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
         std::vector<int32_t> cell[2];
         std::vector<float> off[2], vx[2], vy[2], vz[2], ab[2];
         std::vector<uint64_t> idv[2];
+        std::vector<uint32_t> wtv[2];
         pic_diag e;
         std::memset(&e, 0, sizeof(e));
         for (int s = 0; s < 2; ++s) {
             const size_t n = (size_t)d.n_slots[s];
             cell[s].resize(n); off[s].resize(n); vx[s].resize(n); vy[s].resize(n);
-            vz[s].resize(n); ab[s].resize(n); idv[s].resize(n);
+            vz[s].resize(n); ab[s].resize(n); idv[s].resize(n); wtv[s].resize(n);
             e.state_cap[s] = (int64_t)n;
             e.cell[s] = cell[s].data(); e.off[s] = off[s].data(); e.vx[s] = vx[s].data();
             e.vy[s] = vy[s].data(); e.vz[s] = vz[s].data(); e.id[s] = idv[s].data();
             e.abar[s] = ab[s].data();
+            e.mcc_wait[s] = wtv[s].data();
         }
         if (pic_diagnostics(ctx, k, PIC_DIAG_STATE, &e)) return PIC_E_STATE;
         for (int s = 0; s < 2; ++s) {
@@ -453,6 +492,7 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
             }
             S.n_proc = F.n_proc;
             S.cand_thr = F.cand_thr;
+            S.inv_log1mp = F.inv_log1mp;
             // float64 tables from the context's copy of the input cross sections
             if (S.n_proc > 0) {
                 const int n = (int)F.t_max + 1;
@@ -472,7 +512,8 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
             }
             const size_t c = (size_t)cap[s];
             if (alloc64(r, &S.xi, c) || alloc64(r, &S.vx, c) || alloc64(r, &S.vy, c) ||
-                alloc64(r, &S.vz, c) || alloc64(r, &S.id, c) || alloc64(r, &S.alive, c))
+                alloc64(r, &S.vz, c) || alloc64(r, &S.id, c) || alloc64(r, &S.alive, c) ||
+                alloc64(r, &S.wait, c))
                 return PIC_E_NOMEM;
             const int64_t live = e.n_particles[s];
             std::vector<double> xd(live), vxd(live), vyd(live), vzd(live);
@@ -489,7 +530,8 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
                     hipMemcpy(S.vy, vyd.data(), 8 * live, hipMemcpyHostToDevice) ||
                     hipMemcpy(S.vz, vzd.data(), 8 * live, hipMemcpyHostToDevice) ||
                     hipMemcpy(S.id, idv[s].data(), 8 * live, hipMemcpyHostToDevice) ||
-                    hipMemcpy(S.alive, al.data(), 4 * live, hipMemcpyHostToDevice))
+                    hipMemcpy(S.alive, al.data(), 4 * live, hipMemcpyHostToDevice) ||
+                    hipMemcpy(S.wait, wtv[s].data(), 4 * live, hipMemcpyHostToDevice))
                     return PIC_E_DEVICE;
             }
             st[k].n_next[s] = (int32_t)live;

@@ -452,9 +452,9 @@ __device__ __forceinline__ long long reserve_slot(bool want, PIC_GLOBAL int32_t*
 
 __device__ __forceinline__ void write_particle(const Species& S, long long slot, int c, float o,
                                                float vx, float vy, float vz, uint64_t id,
-                                               bool implicit)
+                                               uint32_t wait, bool implicit)
 {
-    gp(S.cell)[slot] = c;
+    gp(S.cell)[slot] = pack_cell(c, wait);
     gp(S.off)[slot] = o;
     gp(S.vx)[slot] = vx;
     gp(S.vy)[slot] = vy;
@@ -533,7 +533,6 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
     const PIC_GLOBAL uint64_t* __restrict__ idp = gp(uniform_ptr((const uint64_t*)C->sp[s].id));
     PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
-    const uint32_t cand_thr = C->sp[s].cand_thr;
     const float eedf_k = C->sp[s].eps_unit * C->sp[s].eedf_scale;
     const double kin_unit = C->sp[s].kin_unit;
     const int n_proc = C->sp[s].n_proc;
@@ -622,6 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         int i = 0, c1 = 0;
         float o1 = 0.0f, vn = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
         uint64_t id = 0;
+        uint32_t nw = 0u;   // the particle's next waiting-time word
         int kind = -1;
         Child ch;
         if (act) {
@@ -631,19 +631,34 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             vn = q_vn[e];
             if (kImp) abn = q_ab[e];
             const uint32_t i4 = (uint32_t)i << 2;
-            c1 = ldg(cellp, i4);
+            const int32_t w1 = ldg(cellp, i4);
+            c1 = cell_of(w1);
             o1 = ldg(offp, i4);
             id = ldg(idp, i4 << 1);
             vy = ldg(vyp, i4);
             vz = ldg(vzp, i4);
-            const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
-                                    (uint32_t)s << 28, k0, k1);
-            ++cand;
             const float v2b = vn * vn + vy * vy + vz * vz;
-            bool over = false;
-            kind = s == 0 ? collide_electron(S, r0, id, step32, k0, k1, vn, vy, vz, over, ch)
-                          : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
-            if (over) atomicAdd(&acc.n_over, 1u);
+            bool is_cand = true;
+            if (wait_of(w1) & PIC_WAIT_CAPPED) {
+                // a capped wait ran out: the trial of this step is drawn afresh
+                const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                        ((uint32_t)s << 28) | 4u, k0, k1);
+                const double W = geo0(r4.x, S.inv_log1mp);
+                if (W >= 1.0) {
+                    is_cand = false;
+                    nw = wait_encode(W - 1.0);
+                }
+            }
+            if (is_cand) {
+                const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                        (uint32_t)s << 28, k0, k1);
+                ++cand;
+                nw = wait_encode(geo0(r0.x, S.inv_log1mp));
+                bool over = false;
+                kind = s == 0 ? collide_electron(S, r0, id, step32, k0, k1, vn, vy, vz, over, ch)
+                              : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
+                if (over) atomicAdd(&acc.n_over, 1u);
+            }
             if (kind >= 0) {
                 atomicAdd(&acc.n_coll[kind], 1u);
                 cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
@@ -671,14 +686,16 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
                 if (!gone) {
                     const uint32_t i4 = (uint32_t)i << 2;
-                    stg(cellp, i4, c2);
+                    stg(cellp, i4, pack_cell(c2, nw));
                     stg(offp, i4, o2);
                     stg(vxp, i4, vst);
                     stg(abp, i4, abn);
                     dep_ok = true;
                 }
             } else {
-                stg(vxp, (uint32_t)i << 2, vn);
+                const uint32_t i4 = (uint32_t)i << 2;
+                stg(vxp, i4, vn);
+                stg(cellp, i4, pack_cell(c1, nw));
             }
         }
         if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
@@ -726,7 +743,11 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             bool dep_e = false;
             if (want_e) {
                 if (se >= 0) {
-                    write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide, kImp);
+                    // first trial of a child at the next step: draw 4 of its stream
+                    const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
+                                            4u, k0, k1);
+                    write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
+                                   wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
                     dep_e = true;
                 } else {
                     atomicAdd(&acc.n_lost[0], 1u);
@@ -735,7 +756,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             deposit_wave(dep, dep_e, ce, oe, lo, hi);
             if (want_i) {
                 if (si >= 0) {
-                    write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi, kImp);
+                    const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
+                                            (1u << 28) | 4u, k0, k1);
+                    write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
+                                   wait_encode(geo0(r4.x, C->sp[1].inv_log1mp)), kImp);
                     gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
                     gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
                 } else {
@@ -750,9 +774,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
       if (base < end) {
         // the loads of the batch are issued together; indices past the chunk
         // are clamped to its last slot (and treated as dead below)
-        int c[kILP];
+        int32_t c[kILP];   // cell words
         float o[kILP], v[kILP], ab[kILP];
-        uint64_t idv[kILP];
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
             const uint32_t j4 = (uint32_t)min(base + k * kBlock + tid, end - 1) << 2;
@@ -761,22 +784,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             v[k] = ldg(vxp, j4);
             ab[k] = kImp ? ldg(abp, j4) : 0.0f;
         }
-        // ids only where collisions are drawn (a uniform branch around the
-        // whole batch, so the loads above stay in flight together)
-        if (coll) {
-#pragma unroll
-            for (int k = 0; k < kILP; ++k)
-                idv[k] = ldg(idp, (uint32_t)min(base + k * kBlock + tid, end - 1) << 3);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kILP; ++k) idv[k] = 0ull;
-        }
         float wk = 0.0f;
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
             const int i = base + k * kBlock + tid;
             const uint32_t i4 = (uint32_t)i << 2;
-            const int cc = i < end ? c[k] : -1;
+            const int cc = i < end ? cell_of(c[k]) : -1;
+            uint32_t wt = wait_of(c[k]);
             bool live = cc >= 0;
             float a = 0.0f;
             if (live) a = mc ? gather_mc(eh, cc, o[k]) : eh[cc];
@@ -808,11 +822,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     live = false;
                 }
             }
+            // null-collision candidacy by waiting time: a count above zero is
+            // a non-candidate step; at zero the particle is a candidate (or, for
+            // a capped wait, its trial is still open: decided in the drain)
             bool isc = false;
             if (live && coll) {
-                const uint4 r0 = philox((uint32_t)idv[k], (uint32_t)(idv[k] >> 32), step32,
-                                        (uint32_t)s << 28, k0, k1);
-                isc = (r0.x >> 9) < cand_thr;
+                const uint32_t cnt = wt & PIC_WAIT_MAX;
+                if (cnt > 0) wt = (cnt - 1) | (wt & PIC_WAIT_CAPPED);
+                else isc = true;
             }
             // non-candidates finish here; candidates store x_{n+1} (final
             // for the explicit scheme, which deposits it now)
@@ -833,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     }
                 }
                 if (live) {
-                    stg(cellp, i4, c2);
+                    stg(cellp, i4, pack_cell(c2, wt));
                     stg(offp, i4, o2);
                     stg(vxp, i4, vst);
                     if (kImp) stg(abp, i4, abn);
@@ -841,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     if (DIAG && s == 0) eedf_note(vn, ldg(vyp, i4), ldg(vzp, i4));
                 }
             } else if (live) {
-                stg(cellp, i4, c1);
+                stg(cellp, i4, pack_cell(c1, wt));
                 stg(offp, i4, o1);
                 dep_now = !kImp;
             }
@@ -1003,27 +1020,41 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
     const double vs = w.s == 0 ? vscale0 : vscale1;
     const bool convert = P.mode & 1;
     const bool startup = (P.mode & 2) && C->scheme == 1;
+    // waits drawn for a first trial at the start step (species loaded
+    // without them, collisions on)
+    const bool draw = ((P.mode >> (3 + w.s)) & 1) && C->collisions && S.n_proc > 0;
+    const uint32_t step32 = (uint32_t)st->step;
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
         if (convert) {
             S.vx[i] = (float)((double)S.vx[i] * vs);
             S.vy[i] = (float)((double)S.vy[i] * vs);
             S.vz[i] = (float)((double)S.vz[i] * vs);
         }
+        const int32_t word = S.cell[i];
+        if (word < 0) continue;
+        int c = cell_of(word);
+        uint32_t wt = wait_of(word);
+        if (draw) {
+            const uint64_t id = S.id[i];
+            const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                    ((uint32_t)w.s << 28) | 4u, C->key0, C->key1);
+            wt = wait_encode(geo0(r4.x, S.inv_log1mp));
+        }
+        float o = S.off[i];
         if (startup) {
             S.abar[i] = 0.0f;
-            int c = S.cell[i];
-            if (c < 0) continue;
-            float o = S.off[i] + S.vx[i];
+            o += S.vx[i];
             renorm(c, o);
             if (C->bc == 1) {
                 c %= N;
                 if (c < 0) c += N;
             } else if (c < 0 || c >= N) {
-                c = -1;
+                S.cell[i] = -1;
+                continue;
             }
-            S.cell[i] = c;
             S.off[i] = o;
         }
+        S.cell[i] = pack_cell(c, wt);
     }
 }
 
@@ -1091,7 +1122,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* his
     int lo = kNoCell, hi = -1;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
-        const int c = i < end ? cellp[i] : -1;
+        const int c = i < end ? cell_of(cellp[i]) : -1;
         const int b = c >= 0 ? c >> sh : -1;
         wave_count_add(lh, b, b >= 0);
         if (b >= 0) range_note(lo, hi, b);
@@ -1159,7 +1190,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     int lo = kNoCell, hi = -1;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
-        const int c = i < end ? cellp[i] : -1;
+        const int c = i < end ? cell_of(cellp[i]) : -1;
         const int b = c >= 0 ? c >> sh : -1;
         wave_count_add(lh, b, b >= 0);
         if (b >= 0) range_note(lo, hi, b);
@@ -1193,16 +1224,16 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         const int j = min(i, end - 1);
-        const int c0 = cellp[j];
+        const int32_t w0 = cellp[j];
         const float o = offp[j], vx = vxp[j], vy = vyp[j], vz = vzp[j];
         const uint64_t id = idp[j];
         const float ab = imp ? abp[j] : 0.0f;
-        const int c = i < end ? c0 : -1;
+        const int c = i < end ? cell_of(w0) : -1;
         const int b = c >= 0 ? c >> sh : -1;
         const unsigned r = wave_count_add(lh, b, b >= 0);
         if (c < 0) continue;
         const unsigned d = lb[b] + r;
-        cell2[d] = c;
+        cell2[d] = w0;
         off2[d] = o;
         vx2[d] = vx;
         vy2[d] = vy;
@@ -1271,7 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     const int start = w.b * chunk, end = min(n, start + chunk);
     int lo = kNoCell, hi = -1;
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-        const int c = S.cell[i];
+        const int c = cell_of(S.cell[i]);
         if (c < 0) continue;
         atomicAdd(&dep[c], packw(S.off[i]));
         range_note(lo, hi, c);

@@ -36,6 +36,7 @@ namespace {
 
 constexpr double QE = 1.602176634e-19;
 constexpr double EPS0 = 8.8541878128e-12;
+constexpr int kCellWordBits = 13;   // cell index bits of the device cell word
 constexpr double KB = 1.380649e-23;
 constexpr double ME_LIMIT = 1e-27;  // species lighter than this are "electron-like"
 
@@ -432,6 +433,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                 const double numax = nu_max(proc[s], g.gas_density_m3, m);
                 const double pnull = 1.0 - std::exp(-numax * dt);
                 S.cand_thr = numax > 0 ? candidate_threshold(pnull) : 0u;
+                S.inv_log1mp = (pnull > 0.0 && pnull < 1.0) ? 1.0 / std::log1p(-pnull) : 0.0;
                 const double scale = numax > 0 ? g.gas_density_m3 * (dx / dt) / numax : 0.0;
                 h.scale[s] = scale;
                 S.t_scale = (float)(eps_unit / a->de_eV);
@@ -504,6 +506,20 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                                 k, s, i);
                         return bail(PIC_E_INVAL);
                     }
+                // the device cell word carries the null-collision waiting time
+                if (sp.mcc_wait) {
+                    std::vector<uint32_t> ww(n);
+                    INITCHK(hipMemcpy(ww.data(), sp.mcc_wait, 4 * n, hipMemcpyDefault));
+                    for (size_t i = 0; i < n; ++i) {
+                        if (ww[i] > (PIC_WAIT_MAX | PIC_WAIT_CAPPED)) {
+                            fprintf(stderr, "pic_init: case %d species %d particle %zu: bad wait\n",
+                                    k, s, i);
+                            return bail(PIC_E_INVAL);
+                        }
+                        cc[i] |= (int32_t)(ww[i] << kCellWordBits);
+                    }
+                    INITCHK(hipMemcpy(S.cell, cc.data(), 4 * n, hipMemcpyHostToDevice));
+                }
             }
         }
         // grids
@@ -566,10 +582,15 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
     }
     // ---- set-up on the device: units, D1 start-up, sort, deposit, solve ----
     {
-        int mode = (flags & PIC_FLAG_INTERNAL_UNITS) ? 0 : 3;
+        // mode bits: 1 unit conversion, 2 D1 start-up (both only for inputs in
+        // physical units; an internal-units state is already predicted), 8 << s
+        // draw the waits of species s (loaded without them)
+        const int base_mode = (flags & PIC_FLAG_INTERNAL_UNITS) ? 0 : 3;
         // one kernel per case scale: vscale differs per case, so pass per launch
         for (int k = 0; k < n_cases; ++k) {
-            if (mode == 0) break;
+            int mode = base_mode;
+            for (int s = 0; s < 2; ++s)
+                if (!species[2 * k + s].mcc_wait) mode |= 8 << s;
             // restrict the launch to this case's workgroups
             Params p = params(c, mode);
             p.work = c->d_work + c->cases_h[k].first_block;
@@ -806,10 +827,14 @@ extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic
                 HIPCHK(ctx, hipMemcpy(ab.data(), S.abar, 4 * ns, hipMemcpyDeviceToHost));
                 HIPCHK(ctx, hipMemcpy(id.data(), S.id, 8 * ns, hipMemcpyDeviceToHost));
             }
+            std::vector<uint32_t> wt(ns);
             size_t k = 0;
             for (size_t i = 0; i < ns; ++i) {
                 if (cell[i] < 0) continue;
-                cell[k] = cell[i]; off[k] = off[i]; vx[k] = vx[i]; vy[k] = vy[i];
+                const int32_t word = cell[i];
+                cell[k] = word & ((1 << kCellWordBits) - 1);
+                wt[k] = (uint32_t)word >> kCellWordBits;
+                off[k] = off[i]; vx[k] = vx[i]; vy[k] = vy[i];
                 vz[k] = vz[i]; ab[k] = ab[i]; id[k] = id[i];
                 ++k;
             }
@@ -826,6 +851,8 @@ extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic
             if (out->vz[s]) HIPCHK(ctx, hipMemcpy(out->vz[s], vz.data(), 4 * k, hipMemcpyDefault));
             if (out->id[s]) HIPCHK(ctx, hipMemcpy(out->id[s], id.data(), 8 * k, hipMemcpyDefault));
             if (out->abar[s]) HIPCHK(ctx, hipMemcpy(out->abar[s], ab.data(), 4 * k, hipMemcpyDefault));
+            if (out->mcc_wait[s])
+                HIPCHK(ctx, hipMemcpy(out->mcc_wait[s], wt.data(), 4 * k, hipMemcpyDefault));
         }
         if (rc) return fail(ctx, rc, "state buffers too small");
     }

@@ -41,7 +41,8 @@ def to_oracle_species(st, wl):
                         xi=sp["cell"].astype(np.float64) + sp["off"].astype(np.float64),
                         vx=sp["vx"].astype(np.float64) * vu, vy=sp["vy"].astype(np.float64) * vu,
                         vz=sp["vz"].astype(np.float64) * vu,
-                        abar=sp["abar"].astype(np.float64) * au, id=sp["id"]))
+                        abar=sp["abar"].astype(np.float64) * au, id=sp["id"],
+                        wait=sp["mcc_wait"]))
     return out
 
 
@@ -96,6 +97,11 @@ def compare_particles(g, o, N, periodic, vrms):
     # either side (only collisions change vy, vz)
     vy_changed = (np.abs(vg[1] - vo[1]) > VEL_TOL * scale)
     dec = (bad_v | bad_x) & vy_changed
+    # the next waiting time of a candidate is an integer drawn in float64
+    # (floor of ln u / ln(1 - P_null)) on both sides: equal unless the quotient
+    # lies within rounding of an integer
+    if "wait" in g and "wait" in o:
+        dec |= g["wait"][ig] != o["wait"][io]
     mism += int(dec.sum())
     ok = ~dec
     err = dict(pos=float(relx[ok].max(initial=0.0)),

@@ -35,16 +35,19 @@ def test_struct_layouts_match_binding(tmp_path):
     import paper_1310_5284_amd as P
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pic.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %u %u\\n",'
                     'sizeof(pic_case_config),sizeof(pic_species_init),sizeof(pic_xsec),'
                     'sizeof(pic_ledger),sizeof(pic_diag),offsetof(pic_diag,ledger),'
-                    'offsetof(pic_diag,eedf_samples));return 0;}\n')
+                    'offsetof(pic_diag,eedf_samples),offsetof(pic_diag,mcc_wait),'
+                    'offsetof(pic_species_init,mcc_wait),PIC_WAIT_MAX,PIC_WAIT_CAPPED);'
+                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(P.CaseConfig), C.sizeof(P.SpeciesInit), C.sizeof(P.Xsec),
             C.sizeof(P.Ledger), C.sizeof(P.Diag), P.Diag.ledger.offset,
-            P.Diag.eedf_samples.offset]
+            P.Diag.eedf_samples.offset, P.Diag.mcc_wait.offset, P.SpeciesInit.mcc_wait.offset,
+            P.WAIT_MAX, P.WAIT_CAPPED]
     assert got == want
 
 
