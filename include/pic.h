@@ -265,6 +265,9 @@ const char* pic_last_error(const pic_ctx* ctx);
  * spent in the particle kernel (HIP events on the context's stream) and the
  * number of particle-kernel launches it made. */
 int pic_last_timing(const pic_ctx* ctx, double* particle_kernel_ms, int64_t* launches);
+/* The same for the collision kernel that follows each particle pass (the
+ * null-collision MCC of the candidates the pass listed). */
+int pic_last_timing_collide(const pic_ctx* ctx, double* collide_kernel_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

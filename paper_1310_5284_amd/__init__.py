@@ -126,6 +126,7 @@ def lib():
         L.pic_last_error.argtypes = [_P]
         L.pic_last_error.restype = C.c_char_p
         L.pic_last_timing.argtypes = [_P, _D, _I64]
+        L.pic_last_timing_collide.argtypes = [_P, _D, _I64]
         _lib = L
     return _lib
 
@@ -248,9 +249,17 @@ class PicContext:
         self._diag(0, 0, Diag())
 
     def last_timing(self):
+        """(ms, launches) of the particle pass kernel over the last step call."""
         ms = C.c_double()
         k = C.c_int64()
         lib().pic_last_timing(self._h, C.byref(ms), C.byref(k))
+        return ms.value, k.value
+
+    def last_timing_collide(self):
+        """(ms, launches) of the collision kernel over the last step call."""
+        ms = C.c_double()
+        k = C.c_int64()
+        lib().pic_last_timing_collide(self._h, C.byref(ms), C.byref(k))
         return ms.value, k.value
 
     # ------------------------------------------------------------------

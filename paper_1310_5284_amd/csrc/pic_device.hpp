@@ -62,6 +62,16 @@ struct Species {
     float eedf_scale;    // EEDF bins per eV
     int32_t pad;
     double inv_log1mp;   // 1 / ln(1 - P_null) (geometric waiting times)
+    // collision candidates of the running step, listed by k_step in the
+    // region of each workgroup's chunk: slot, v_{n+1/2}, abar_n (implicit)
+    int32_t* cq_idx;
+    float* cq_vn;
+    float* cq_ab;
+    // electrons: upper bounds of sum_k n_g sigma_k v / nu_max (the scaled
+    // table times the speed) over bins of bound_k table intervals
+    const float* cbound;
+    int32_t bound_k;
+    int32_t pad2;
 };
 
 // Everything a kernel needs to know about one case.
@@ -73,6 +83,8 @@ struct Case {
     int32_t collisions;
     int32_t first_block;  // this case's first workgroup in the work table
     int32_t n_blocks;
+    int32_t first_crow;   // this case's first k_collide partial row
+    int32_t n_crows;
     int32_t history_len;
     double dx, dt;
     double rf_volts, rf_omega, rf_freq;
@@ -120,6 +132,15 @@ struct Work {
     int32_t nb;  // workgroups of (case, species)
 };
 
+// A k_collide workgroup: round `round` (kBlock candidates) of the candidates
+// listed by k_step workgroup `step_blk`; the last round takes the rest.
+struct CollideWork {
+    int32_t step_blk;
+    int32_t round;
+    int32_t rounds;
+    int32_t row;      // its ledger partial row
+};
+
 // Ledger partial sums of one workgroup, stored field-major: field f of
 // workgroup b lives at pd[f * stride + b] (doubles) or pu[f * stride + b]
 // (counters), so that a reduction over workgroups reads contiguous memory.
@@ -150,11 +171,13 @@ struct Params {
     int32_t stride;      // workgroups in the work table
     int32_t n_cases;
     int32_t mode;        // kernel-specific
+    int32_t* cand_n;     // candidates listed by each workgroup of the work table
+    const CollideWork* cwork;   // k_collide work table
 };
 
+constexpr int kBoundBins = 256;   // bins of the null-collision bound table
 constexpr int kFinBlock = 1024;   // threads of the per-case finalizing workgroup
 constexpr int kILP = 4;           // particles in flight per thread in k_step
-constexpr int kQCap = 64 * (kILP + 1);   // candidate-queue entries per wavefront
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -162,19 +185,24 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 //   field[N+1] float  (EC: ehat of the cells; MC: nodal field)
 //   dep[N] u64        (privatised deposit, count << 40 | summed weight)
 //   DIAG: heat[N] float, eedf[kEedfBins] u32
-//   candidate queues: per wavefront kQCap slots and vn (+ abar, implicit)
 struct StepLds {
-    size_t dep, heat, eedf, queue, total;
+    size_t dep, heat, eedf, total;
 };
-__host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool implicit)
+__host__ __device__ inline StepLds step_lds_layout(int N, bool diag)
 {
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
     L.heat = L.dep + align16(8 * (size_t)N);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
-    L.queue = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
-    L.total = L.queue + (size_t)kWaves * kQCap * 4 * (implicit ? 3 : 2);
+    L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;
+}
+
+// Shared-memory layout of k_collide: dep[N] u64 (predicted positions of the
+// implicit candidates) | eedf[kEedfBins] u32
+__host__ __device__ inline size_t collide_lds_bytes(int N)
+{
+    return align16(8 * (size_t)N) + align16(4 * (size_t)kEedfBins);
 }
 
 }  // namespace pic

@@ -172,7 +172,8 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigned* pu_, int stride,
-                                                int fb, int nb, double* sd, long long* su)
+                                                int fb, int nb, int fb2, int nb2, double* sd,
+                                                long long* su)
 {
     // wavefront w sums the fields w, w + NT/64, ...: every lane strides over
     // the workgroup partials with kU loads in flight, then a wavefront tree
@@ -182,17 +183,21 @@ __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigne
     const PIC_GLOBAL unsigned* pu = gp(pu_);
     for (int f = wave; f < PD_N + PU_N; f += NT / 64) {
         if (f < PD_N) {
-            const PIC_GLOBAL double* row = pd + (size_t)f * stride + fb;
             double a[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) a[u] = 0.0;
-            // unconditional loads from clamped indices keep all kU in flight
-            for (int b = lane; b < nb; b += 64 * kU)
+            // two row ranges (k_step rows, k_collide rows); unconditional
+            // loads from clamped indices keep all kU in flight
+            for (int r = 0; r < 2; ++r) {
+                const int n_r = r == 0 ? nb : nb2;
+                const PIC_GLOBAL double* row = pd + (size_t)f * stride + (r == 0 ? fb : fb2);
+                for (int b = lane; b < n_r; b += 64 * kU)
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const double x = row[min(b + 64 * u, nb - 1)];
-                    a[u] += b + 64 * u < nb ? x : 0.0;
-                }
+                    for (int u = 0; u < kU; ++u) {
+                        const double x = row[min(b + 64 * u, n_r - 1)];
+                        a[u] += b + 64 * u < n_r ? x : 0.0;
+                    }
+            }
             double v = 0.0;
 #pragma unroll
             for (int u = 0; u < kU; ++u) v += a[u];
@@ -200,14 +205,18 @@ __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigne
             if (lane == 0) sd[f] = v;
         } else {
             // per-step counts of one case fit in 32 bits
-            const PIC_GLOBAL unsigned* row = pu + (size_t)(f - PD_N) * stride + fb;
             unsigned a = 0u;
-            for (int b = lane; b < nb; b += 64 * kU)
+            for (int r = 0; r < 2; ++r) {
+                const int n_r = r == 0 ? nb : nb2;
+                const PIC_GLOBAL unsigned* row =
+                    pu + (size_t)(f - PD_N) * stride + (r == 0 ? fb : fb2);
+                for (int b = lane; b < n_r; b += 64 * kU)
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const unsigned x = row[min(b + 64 * u, nb - 1)];
-                    a += b + 64 * u < nb ? x : 0u;
-                }
+                    for (int u = 0; u < kU; ++u) {
+                        const unsigned x = row[min(b + 64 * u, n_r - 1)];
+                        a += b + 64 * u < n_r ? x : 0u;
+                    }
+            }
             a = wave_sum(a);
             if (lane == 0) su[f - PD_N] = (long long)a;
         }
@@ -338,10 +347,10 @@ struct Child {
     uint64_t ide, idi;
 };
 
-__device__ __forceinline__ int collide_electron(const Species& S, uint4 r0, uint64_t id,
-                                                uint32_t step, uint32_t k0, uint32_t k1,
-                                                float& vx, float& vy, float& vz, bool& over,
-                                                Child& ch)
+__device__ __forceinline__ int collide_electron(const Species& S, const float* bound, uint4 r0,
+                                                uint64_t id, uint32_t step, uint32_t k0,
+                                                uint32_t k1, float& vx, float& vy, float& vz,
+                                                bool& over, Child& ch)
 {
     const float v2 = vx * vx + vy * vy + vz * vz;
     const float vm = sqrtf(v2);
@@ -349,6 +358,9 @@ __device__ __forceinline__ int collide_electron(const Species& S, uint4 r0, uint
     over = t > S.t_max;
     const float tc = fminf(fmaxf(t, 0.0f), S.t_max);
     const int k = min((int)tc, (int)S.t_max - 1);
+    // a u1 above the bound of the energy bin is a null collision for certain:
+    // decided without the table (the full comparison below would agree)
+    if (!over && u01(r0.y) >= bound[min(k / S.bound_k, kBoundBins - 1)]) return -2;
     const float f = tc - (float)k;
     const PIC_GLOBAL float* tab = gp((const float*)S.tab_e) + 4 * k;
     float sg[4];
@@ -492,30 +504,31 @@ __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want,
 }
 
 // ---------------------------------------------------------------------------
-// k_step: one step of every case in this launch.  Workgroup = a contiguous
-// chunk of one species of one case.  Per particle (explicit, leap-frog):
+// k_step: the particle pass of one step of every case in this launch.
+// Workgroup = a contiguous chunk of one species of one case.  Per particle
+// (explicit, leap-frog):
 //   a = ehat[cell] (EC, Eq. (3)) or the interpolated nodal field (MC);
-//   v += a;  x += v;  absorb at the electrodes or wrap;
-//   null-collision MCC with Philox(id, step);  deposit (Eq. (2)).
+//   v += a;  x += v;  absorb at the electrodes or wrap;  deposit (Eq. (2));
+//   null-collision candidacy by the particle's waiting time.
 // Per particle (implicit, D1, beta = 1/2; stored x~, v~, abar):
 //   a = ehat[cell of x~];  x = x~ + a/2;  v = v~ + a/2;  abar = (abar + a)/2;
-//   absorb; MCC; predict v~' = v + abar/2, x~' = x + v~'; absorb; deposit x~'.
+//   absorb; candidacy; non-candidates predict v~' = v + abar/2,
+//   x~' = x + v~', absorb and deposit x~'.
 //
 // The streaming loop issues the loads of kILP particles per thread together
-// (indices past the chunk are clamped to its last slot and treated as dead)
-// and decides candidacy (u0 < P_null, an integer compare on the Philox word).
-// A candidate's x_{n+1} goes to memory and its slot and v_{n+1/2} to a
-// per-wavefront LDS ring (ballot + prefix); whenever 64 are queued the
-// wavefront collides them with every lane busy.  The deposit goes to a
-// privatised LDS grid (one int64 per cell packs count and summed weight) and
-// is flushed over the cell range the workgroup touched.  k_finalize then
-// closes the ledger and solves the field of the next step.
+// (indices past the chunk are clamped to its last slot and treated as dead).
+// Candidates store x_{n+1} and are listed (slot, v_{n+1/2}, abar_n) in the
+// region of the workgroup's chunk for k_collide (ballot + one LDS atomic per
+// wavefront).  The deposit goes to a privatised LDS grid (one int64 per cell
+// packs count and summed weight), flushed over the cell range the workgroup
+// touched.  The workgroup's ledger partial is a row of plain stores.
 // ---------------------------------------------------------------------------
 template <int SCHEME, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_step(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockAcc acc;
+    __shared__ int s_ncand;
     constexpr bool kImp = SCHEME == 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gblk = P.mode + (int)blockIdx.x;
@@ -525,36 +538,27 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const int N = C->n_cells;
     const int s = w.s;
     // particle arrays (addressed by 32-bit byte offsets from a scalar base)
-    // and the constants of the streaming pass, read before any store
+    // and the constants of the pass, read before any store
     PIC_GLOBAL int32_t* __restrict__ cellp = gp(uniform_ptr(C->sp[s].cell));
     PIC_GLOBAL float* __restrict__ offp = gp(uniform_ptr(C->sp[s].off));
     PIC_GLOBAL float* __restrict__ vxp = gp(uniform_ptr(C->sp[s].vx));
     PIC_GLOBAL float* __restrict__ vyp = gp(uniform_ptr(C->sp[s].vy));
     PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
-    const PIC_GLOBAL uint64_t* __restrict__ idp = gp(uniform_ptr((const uint64_t*)C->sp[s].id));
     PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
+    PIC_GLOBAL int32_t* __restrict__ cq_idx = gp(uniform_ptr(C->sp[s].cq_idx));
+    PIC_GLOBAL float* __restrict__ cq_vn = gp(uniform_ptr(C->sp[s].cq_vn));
+    PIC_GLOBAL float* __restrict__ cq_ab = gp(uniform_ptr(C->sp[s].cq_ab));
     const float eedf_k = C->sp[s].eps_unit * C->sp[s].eedf_scale;
     const double kin_unit = C->sp[s].kin_unit;
-    const int n_proc = C->sp[s].n_proc;
-    // The collision constants go to LDS (the drain reads them there: no
-    // register pressure, and stores to the particle arrays cannot alias them).
-    __shared__ Species S;
-    for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
-        ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
     const bool periodic = C->bc == 1;
     const bool mc = C->gather == 1;
-    const bool coll = C->collisions != 0 && n_proc > 0;
-    const uint32_t k0 = C->key0, k1 = C->key1;
+    const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
-    const StepLds L = step_lds_layout(N, DIAG, kImp);
+    const StepLds L = step_lds_layout(N, DIAG);
     float* eh = (float*)smem;
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
     float* heat = (float*)(smem + L.heat);
     unsigned* eedf = (unsigned*)(smem + L.eedf);
-    int* q_idx = (int*)(smem + L.queue) + (size_t)wave * kQCap * (kImp ? 3 : 2);
-    float* q_vn = (float*)(q_idx + kQCap);
-    float* q_ab = (float*)(q_idx + 2 * kQCap);   // implicit only
-
     {
         const PIC_GLOBAL float* ehg = gp(C->ehat[s]);
         if (mc) {
@@ -577,201 +581,28 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 acc.absK[a][b] = 0.0;
                 acc.abs_n[a][b] = 0u;
             }
-        acc.other_dK = 0.0;
-        for (int k = 0; k < 4; ++k) acc.n_coll[k] = 0u;
-        acc.n_created[0] = acc.n_created[1] = 0u;
-        acc.n_over = 0u;
-        acc.n_lost[0] = acc.n_lost[1] = 0u;
         acc.cmin = kNoCell;
         acc.cmax = -1;
+        s_ncand = 0;
     }
     lds_barrier();
 
-    const uint32_t step32 = (uint32_t)st->step;
     const int n = st->n_slots[s];
-    const int ns0 = st->n_slots[0], ns1 = st->n_slots[1];
     int chunk = (n + w.nb - 1) / w.nb;
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk;
     const int end = min(n, start + chunk);
 
-
-    double work = 0.0, cdk = 0.0;
-    unsigned cand = 0u;
+    double work = 0.0;
     int lo = kNoCell, hi = -1;
-    int qh = 0, qn = 0;   // wavefront-uniform queue head and length
 
     auto absorb = [&](int i, int e, float vxh, float vy, float vz) {
         atomicAdd(&acc.absK[s][e], (double)(vxh * vxh + vy * vy + vz * vz));
         atomicAdd(&acc.abs_n[s][e], 1u);
         stg(cellp, (uint32_t)i << 2, -1);
     };
-    auto eedf_note = [&](float vx, float vy, float vz) {
-        const float fb = (vx * vx + vy * vy + vz * vz) * eedf_k;
-        const int bin = fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
-        atomicAdd(&eedf[bin], 1u);
-    };
 
-    // Collide the m (<= 64) oldest queued candidates, one per lane.  The
-    // queue is a ring of kQCap entries: qh is its head, qn its length.  The
-    // candidate's x_{n+1} was stored in its slot by the streaming pass.
-    auto drain = [&](int m) {
-        __syncwarp();
-        const bool act = lane < m;
-        int i = 0, c1 = 0;
-        float o1 = 0.0f, vn = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
-        uint64_t id = 0;
-        uint32_t nw = 0u;   // the particle's next waiting-time word
-        int kind = -1;
-        Child ch;
-        if (act) {
-            int e = qh + lane;
-            if (e >= kQCap) e -= kQCap;
-            i = q_idx[e];
-            vn = q_vn[e];
-            if (kImp) abn = q_ab[e];
-            const uint32_t i4 = (uint32_t)i << 2;
-            const int32_t w1 = ldg(cellp, i4);
-            c1 = cell_of(w1);
-            o1 = ldg(offp, i4);
-            id = ldg(idp, i4 << 1);
-            vy = ldg(vyp, i4);
-            vz = ldg(vzp, i4);
-            const float v2b = vn * vn + vy * vy + vz * vz;
-            bool is_cand = true;
-            if (wait_of(w1) & PIC_WAIT_CAPPED) {
-                // a capped wait ran out: the trial of this step is drawn afresh
-                const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
-                                        ((uint32_t)s << 28) | 4u, k0, k1);
-                const double W = geo0(r4.x, S.inv_log1mp);
-                if (W >= 1.0) {
-                    is_cand = false;
-                    nw = wait_encode(W - 1.0);
-                }
-            }
-            if (is_cand) {
-                const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
-                                        (uint32_t)s << 28, k0, k1);
-                ++cand;
-                nw = wait_encode(geo0(r0.x, S.inv_log1mp));
-                bool over = false;
-                kind = s == 0 ? collide_electron(S, r0, id, step32, k0, k1, vn, vy, vz, over, ch)
-                              : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
-                if (over) atomicAdd(&acc.n_over, 1u);
-            }
-            if (kind >= 0) {
-                atomicAdd(&acc.n_coll[kind], 1u);
-                cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
-                stg(vyp, (uint32_t)i << 2, vy);
-                stg(vzp, (uint32_t)i << 2, vz);
-            }
-            if (DIAG && s == 0) eedf_note(vn, vy, vz);
-        }
-        // implicit: predict from the post-collision velocity, absorb, deposit
-        bool dep_ok = false;
-        int c2 = c1;
-        float o2 = o1;
-        if (act) {
-            if (kImp) {
-                const float vst = vn + 0.5f * abn;
-                o2 = o1 + vst;
-                renorm(c2, o2);
-                bool gone = false;
-                if (periodic) {
-                    c2 %= N;
-                    if (c2 < 0) c2 += N;
-                } else if (c2 < 0 || c2 >= N) {
-                    absorb(i, c2 < 0 ? 0 : 1, vn, vy, vz);
-                    gone = true;
-                }
-                if (!gone) {
-                    const uint32_t i4 = (uint32_t)i << 2;
-                    stg(cellp, i4, pack_cell(c2, nw));
-                    stg(offp, i4, o2);
-                    stg(vxp, i4, vst);
-                    stg(abp, i4, abn);
-                    dep_ok = true;
-                }
-            } else {
-                const uint32_t i4 = (uint32_t)i << 2;
-                stg(vxp, i4, vn);
-                stg(cellp, i4, pack_cell(c1, nw));
-            }
-        }
-        if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
-        // ionization children: electron and ion at the parent's x_{n+1};
-        // implicit children are predicted from there with abar = 0
-        const bool ion_ev = act && kind == PIC_IONIZATION && s == 0;
-        if (__ballot(ion_ev)) {
-            bool want_e = false, want_i = false;
-            int ce = c1, ci = c1;
-            float oe = o1, oi = o1;
-            if (ion_ev) {
-                const float ke = ch.vx * ch.vx + ch.vy * ch.vy + ch.vz * ch.vz;
-                const float ki = ch.ix * ch.ix + ch.iy * ch.iy + ch.iz * ch.iz;
-                cdk += (double)ke;
-                atomicAdd(&acc.other_dK, (double)ki);
-                atomicAdd(&acc.n_created[0], 1u);
-                atomicAdd(&acc.n_created[1], 1u);
-                want_e = want_i = true;
-                if (kImp) {
-                    oe = o1 + ch.vx;
-                    renorm(ce, oe);
-                    oi = o1 + ch.ix;
-                    renorm(ci, oi);
-                    if (periodic) {
-                        ce %= N; if (ce < 0) ce += N;
-                        ci %= N; if (ci < 0) ci += N;
-                    } else {
-                        if (ce < 0 || ce >= N) {
-                            want_e = false;
-                            const int e = ce < 0 ? 0 : 1;
-                            atomicAdd(&acc.absK[0][e], (double)ke);
-                            atomicAdd(&acc.abs_n[0][e], 1u);
-                        }
-                        if (ci < 0 || ci >= N) {
-                            want_i = false;
-                            const int e = ci < 0 ? 0 : 1;
-                            atomicAdd(&acc.absK[1][e], (double)ki);
-                            atomicAdd(&acc.abs_n[1][e], 1u);
-                        }
-                    }
-                }
-            }
-            const long long se = reserve_slot(want_e, gp(&st->n_child[0]), ns0, C->sp[0].capacity);
-            const long long si = reserve_slot(want_i, gp(&st->n_child[1]), ns1, C->sp[1].capacity);
-            bool dep_e = false;
-            if (want_e) {
-                if (se >= 0) {
-                    // first trial of a child at the next step: draw 4 of its stream
-                    const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
-                                            4u, k0, k1);
-                    write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
-                                   wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
-                    dep_e = true;
-                } else {
-                    atomicAdd(&acc.n_lost[0], 1u);
-                }
-            }
-            deposit_wave(dep, dep_e, ce, oe, lo, hi);
-            if (want_i) {
-                if (si >= 0) {
-                    const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
-                                            (1u << 28) | 4u, k0, k1);
-                    write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
-                                   wait_encode(geo0(r4.x, C->sp[1].inv_log1mp)), kImp);
-                    gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
-                    gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
-                } else {
-                    atomicAdd(&acc.n_lost[1], 1u);
-                }
-            }
-        }
-        __syncwarp();
-    };
-
-    for (int base = start;;) {
-      if (base < end) {
+    for (int base = start; base < end; base += kBlock * kILP) {
         // the loads of the batch are issued together; indices past the chunk
         // are clamped to its last slot (and treated as dead below)
         int32_t c[kILP];   // cell words
@@ -784,6 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             v[k] = ldg(vxp, j4);
             ab[k] = kImp ? ldg(abp, j4) : 0.0f;
         }
+
         float wk = 0.0f;
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
@@ -823,8 +655,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
             }
             // null-collision candidacy by waiting time: a count above zero is
-            // a non-candidate step; at zero the particle is a candidate (or, for
-            // a capped wait, its trial is still open: decided in the drain)
+            // a non-candidate step; at zero the particle is a candidate (or,
+            // for a capped wait, its trial is still open: decided by k_collide)
             bool isc = false;
             if (live && coll) {
                 const uint32_t cnt = wt & PIC_WAIT_MAX;
@@ -855,7 +687,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     stg(vxp, i4, vst);
                     if (kImp) stg(abp, i4, abn);
                     dep_now = true;
-                    if (DIAG && s == 0) eedf_note(vn, ldg(vyp, i4), ldg(vzp, i4));
+                    if (DIAG && s == 0) {
+                        const float ey = ldg(vyp, i4), ez = ldg(vzp, i4);
+                        const float fb = (vn * vn + ey * ey + ez * ez) * eedf_k;
+                        const int bin =
+                            fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
+                        atomicAdd(&eedf[bin], 1u);
+                    }
                 }
             } else if (live) {
                 stg(cellp, i4, pack_cell(c1, wt));
@@ -863,31 +701,23 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 dep_now = !kImp;
             }
             deposit_wave(dep, dep_now, c2, o2, lo, hi);
-            // queue the candidates of this wavefront
+            // list the candidates of this wavefront in the workgroup's region
             const bool enq = live && isc;
             const unsigned long long qm = __ballot(enq);
-            if (enq) {
-                int slot = qh + qn + __popcll(qm & ((1ull << lane) - 1ull));
-                if (slot >= kQCap) slot -= kQCap;
-                q_idx[slot] = i;
-                q_vn[slot] = vn;
-                if (kImp) q_ab[slot] = abn;
+            if (qm) {
+                int b0 = 0;
+                if (lane == 0) b0 = atomicAdd(&s_ncand, (int)__popcll(qm));
+                b0 = __builtin_amdgcn_readfirstlane(b0);
+                if (enq) {
+                    const int e = start + b0 + (int)__popcll(qm & ((1ull << lane) - 1ull));
+                    const uint32_t e4 = (uint32_t)e << 2;
+                    stg(cq_idx, e4, i);
+                    stg(cq_vn, e4, vn);
+                    if (kImp) stg(cq_ab, e4, abn);
+                }
             }
-            qn += __popcll(qm);
         }
         work += (double)wk;
-        base += kBlock * kILP;
-      }
-        // drain full batches of 64, and the remainder once the chunk is done
-        const bool tail = base >= end;
-        while (qn >= 64 || (tail && qn > 0)) {
-            const int m = qn < 64 ? qn : 64;
-            drain(m);
-            qh += m;
-            if (qh >= kQCap) qh -= kQCap;
-            qn -= m;
-        }
-        if (tail) break;
     }
 
     // flush the privatised deposit over the touched cell range
@@ -915,30 +745,329 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             for (int j = tid; j < kEedfBins; j += kBlock)
                 if (eedf[j]) gatomic_add(gp(&C->eedf_acc[j]), (unsigned long long)eedf[j]);
     }
-    // workgroup partial of the ledger (plain stores, reduced by k_finalize)
-    __shared__ double wsum[kWaves][3];
+    // workgroup partial of the ledger (plain stores; k_collide adds the
+    // collision terms of the same workgroup, k_finalize reduces)
+    __shared__ double wsum[kWaves];
     work = wave_sum(work);
-    cdk = wave_sum(cdk);
-    const unsigned ncw = wave_sum(cand);
-    if (lane == 0) {
-        wsum[wave][0] = work;
-        wsum[wave][1] = cdk;
-        wsum[wave][2] = (double)ncw;
-    }
+    if (lane == 0) wsum[wave] = work;
     lds_barrier();
     if (tid == 0) {
-        double wk = 0.0, cd = 0.0, nc = 0.0;
-        for (int k = 0; k < kWaves; ++k) {
-            wk += wsum[k][0];
-            cd += wsum[k][1];
-            nc += wsum[k][2];
-        }
+        double wk = 0.0;
+        for (int k = 0; k < kWaves; ++k) wk += wsum[k];
         const int o = 1 - s;
         const size_t S_ = (size_t)P.stride;
         double* pd = P.pd + gblk;
         unsigned* pu = P.pu + gblk;
         pd[(PD_WORK + s) * S_] = wk;
         pd[(PD_WORK + o) * S_] = 0.0;
+        pd[(PD_COLL + 0) * S_] = 0.0;
+        pd[(PD_COLL + 1) * S_] = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                pd[(PD_ABSK + 2 * a + b) * S_] = acc.absK[a][b];
+                pu[(PU_ABS + 2 * a + b) * S_] = acc.abs_n[a][b];
+            }
+        pd[(PD_V2 + 0) * S_] = 0.0;
+        pd[(PD_V2 + 1) * S_] = 0.0;
+        for (int f = PU_COLL; f < PU_N; ++f) pu[f * S_] = 0u;
+        P.cand_n[gblk] = s_ncand;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_collide: the null-collision MCC (Vahedi & Surendra 1995) of the
+// candidates that k_step listed, one workgroup per k_step workgroup, one
+// candidate per thread.  A candidate whose capped wait ran out first draws
+// its trial; a candidate draws its next waiting time, the process (u1 of
+// draw 0 against the cumulative n_g sigma_k v / nu_max) and the scattering;
+// ionizations append an electron and an ion.  Implicit candidates then
+// predict, are absorbed or deposit (privatised LDS grid).  The collision
+// terms of the ledger are added to the row of the same workgroup.
+// ---------------------------------------------------------------------------
+template <int SCHEME, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_collide(Params P)
+{
+    const CollideWork cw = P.cwork[P.mode + (int)blockIdx.x];
+    const int gblk = cw.step_blk;
+    const int ncand = P.cand_n[gblk];
+    const size_t S_ = (size_t)P.stride;
+    if (cw.round * kBlock >= ncand) {
+        // nothing in this round: the row of the workgroup holds zeros
+        if (threadIdx.x < PD_N) P.pd[threadIdx.x * S_ + cw.row] = 0.0;
+        else if (threadIdx.x < PD_N + PU_N) P.pu[(threadIdx.x - PD_N) * S_ + cw.row] = 0u;
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ BlockAcc acc;
+    __shared__ Species S;
+    constexpr bool kImp = SCHEME == 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Work w = P.work[gblk];
+    Case* C = P.cases + w.c;
+    State* st = P.state + w.c;
+    const int N = C->n_cells;
+    const int s = w.s;
+    PIC_GLOBAL int32_t* __restrict__ cellp = gp(uniform_ptr(C->sp[s].cell));
+    PIC_GLOBAL float* __restrict__ offp = gp(uniform_ptr(C->sp[s].off));
+    PIC_GLOBAL float* __restrict__ vxp = gp(uniform_ptr(C->sp[s].vx));
+    PIC_GLOBAL float* __restrict__ vyp = gp(uniform_ptr(C->sp[s].vy));
+    PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
+    const PIC_GLOBAL uint64_t* __restrict__ idp = gp(uniform_ptr((const uint64_t*)C->sp[s].id));
+    PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
+    const PIC_GLOBAL int32_t* __restrict__ cq_idx =
+        gp(uniform_ptr((const int32_t*)C->sp[s].cq_idx));
+    const PIC_GLOBAL float* __restrict__ cq_vn = gp(uniform_ptr((const float*)C->sp[s].cq_vn));
+    const PIC_GLOBAL float* __restrict__ cq_ab = gp(uniform_ptr((const float*)C->sp[s].cq_ab));
+    const double inv_ion = C->sp[1].inv_log1mp;
+    const long long cap0 = C->sp[0].capacity, cap1 = C->sp[1].capacity;
+    // collision constants in LDS (stores to the particle arrays cannot alias them)
+    for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
+        ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
+    const bool periodic = C->bc == 1;
+    const uint32_t k0 = C->key0, k1 = C->key1;
+    unsigned long long* dep = (unsigned long long*)smem;
+    unsigned* eedf = (unsigned*)(smem + align16(8 * (size_t)N));
+    __shared__ float lbound[kBoundBins];
+    if (s == 0 && C->sp[0].n_proc > 0)
+        for (int j = tid; j < kBoundBins; j += kBlock) lbound[j] = C->sp[0].cbound[j];
+    if (kImp)
+        for (int j = tid; j < N; j += kBlock) dep[j] = 0ull;
+    if (DIAG)
+        for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
+    if (tid == 0) {
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                acc.absK[a][b] = 0.0;
+                acc.abs_n[a][b] = 0u;
+            }
+        acc.other_dK = 0.0;
+        for (int k = 0; k < 4; ++k) acc.n_coll[k] = 0u;
+        acc.n_created[0] = acc.n_created[1] = 0u;
+        acc.n_over = 0u;
+        acc.n_lost[0] = acc.n_lost[1] = 0u;
+        acc.cmin = kNoCell;
+        acc.cmax = -1;
+    }
+    lds_barrier();
+
+    const uint32_t step32 = (uint32_t)st->step;
+    const int ns0 = st->n_slots[0], ns1 = st->n_slots[1];
+    const int n = st->n_slots[s];
+    int chunk = (n + w.nb - 1) / w.nb;
+    chunk = (chunk + 63) & ~63;
+    const int region = w.b * chunk;   // the candidate list of this workgroup
+    const float eedf_k = S.eps_unit * S.eedf_scale;
+
+    double cdk = 0.0;
+    unsigned cand = 0u;
+    int lo = kNoCell, hi = -1;
+
+    auto absorb = [&](int i, int e, float vxh, float vy, float vz) {
+        atomicAdd(&acc.absK[s][e], (double)(vxh * vxh + vy * vy + vz * vz));
+        atomicAdd(&acc.abs_n[s][e], 1u);
+        stg(cellp, (uint32_t)i << 2, -1);
+    };
+
+    // this round, and for the last round all candidates beyond the estimate
+    const int e_step = cw.round == cw.rounds - 1 ? kBlock : ncand;
+    for (int e0 = cw.round * kBlock; e0 < ncand; e0 += e_step) {
+        const int e = e0 + tid;
+        const bool act = e < ncand;
+        int i = 0, c1 = 0;
+        float o1 = 0.0f, vn = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
+        uint64_t id = 0;
+        uint32_t nw = 0u;   // the particle's next waiting-time word
+        int kind = -1;
+        Child ch;
+        if (act) {
+            const uint32_t q4 = (uint32_t)(region + e) << 2;
+            i = ldg(cq_idx, q4);
+            vn = ldg(cq_vn, q4);
+            if (kImp) abn = ldg(cq_ab, q4);
+            const uint32_t i4 = (uint32_t)i << 2;
+            const int32_t w1 = ldg(cellp, i4);
+            o1 = ldg(offp, i4);
+            id = ldg(idp, i4 << 1);
+            vy = ldg(vyp, i4);
+            vz = ldg(vzp, i4);
+            c1 = cell_of(w1);
+            const float v2b = vn * vn + vy * vy + vz * vz;
+            bool is_cand = true;
+            if (wait_of(w1) & PIC_WAIT_CAPPED) {
+                // a capped wait ran out: the trial of this step is drawn afresh
+                const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                        ((uint32_t)s << 28) | 4u, k0, k1);
+                const double W = geo0(r4.x, S.inv_log1mp);
+                if (W >= 1.0) {
+                    is_cand = false;
+                    nw = wait_encode(W - 1.0);
+                }
+            }
+            if (is_cand) {
+                const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                        (uint32_t)s << 28, k0, k1);
+                ++cand;
+                nw = wait_encode(geo0(r0.x, S.inv_log1mp));
+                bool over = false;
+                kind = s == 0 ? collide_electron(S, lbound, r0, id, step32, k0, k1, vn, vy, vz,
+                                                 over, ch)
+                              : collide_ion(S, r0, id, step32, k0, k1, vn, vy, vz, over);
+                if (over) atomicAdd(&acc.n_over, 1u);
+            }
+            if (kind >= 0) {
+                atomicAdd(&acc.n_coll[kind], 1u);
+                cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
+                stg(vyp, i4, vy);
+                stg(vzp, i4, vz);
+            }
+            if (DIAG && s == 0) {
+                const float fb = (vn * vn + vy * vy + vz * vz) * eedf_k;
+                const int bin = fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
+                atomicAdd(&eedf[bin], 1u);
+            }
+        }
+        // implicit: predict from the post-collision velocity, absorb, deposit
+        bool dep_ok = false;
+        int c2 = c1;
+        float o2 = o1;
+        if (act) {
+            const uint32_t i4 = (uint32_t)i << 2;
+            if (kImp) {
+                const float vst = vn + 0.5f * abn;
+                o2 = o1 + vst;
+                renorm(c2, o2);
+                bool gone = false;
+                if (periodic) {
+                    c2 %= N;
+                    if (c2 < 0) c2 += N;
+                } else if (c2 < 0 || c2 >= N) {
+                    absorb(i, c2 < 0 ? 0 : 1, vn, vy, vz);
+                    gone = true;
+                }
+                if (!gone) {
+                    stg(cellp, i4, pack_cell(c2, nw));
+                    stg(offp, i4, o2);
+                    stg(vxp, i4, vst);
+                    stg(abp, i4, abn);
+                    dep_ok = true;
+                }
+            } else {
+                stg(vxp, i4, vn);
+                stg(cellp, i4, pack_cell(c1, nw));
+            }
+        }
+        if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
+        // ionization children: electron and ion at the parent's x_{n+1};
+        // implicit children are predicted from there with abar = 0; their
+        // deposits are rare and go straight to the case grids
+        const bool ion_ev = act && kind == PIC_IONIZATION && s == 0;
+        if (__ballot(ion_ev)) {
+            bool want_e = false, want_i = false;
+            int ce = c1, ci = c1;
+            float oe = o1, oi = o1;
+            if (ion_ev) {
+                const float ke = ch.vx * ch.vx + ch.vy * ch.vy + ch.vz * ch.vz;
+                const float ki = ch.ix * ch.ix + ch.iy * ch.iy + ch.iz * ch.iz;
+                cdk += (double)ke;
+                atomicAdd(&acc.other_dK, (double)ki);
+                atomicAdd(&acc.n_created[0], 1u);
+                atomicAdd(&acc.n_created[1], 1u);
+                want_e = want_i = true;
+                if (kImp) {
+                    oe = o1 + ch.vx;
+                    renorm(ce, oe);
+                    oi = o1 + ch.ix;
+                    renorm(ci, oi);
+                    if (periodic) {
+                        ce %= N; if (ce < 0) ce += N;
+                        ci %= N; if (ci < 0) ci += N;
+                    } else {
+                        if (ce < 0 || ce >= N) {
+                            want_e = false;
+                            const int eo = ce < 0 ? 0 : 1;
+                            atomicAdd(&acc.absK[0][eo], (double)ke);
+                            atomicAdd(&acc.abs_n[0][eo], 1u);
+                        }
+                        if (ci < 0 || ci >= N) {
+                            want_i = false;
+                            const int eo = ci < 0 ? 0 : 1;
+                            atomicAdd(&acc.absK[1][eo], (double)ki);
+                            atomicAdd(&acc.abs_n[1][eo], 1u);
+                        }
+                    }
+                }
+            }
+            const long long se = reserve_slot(want_e, gp(&st->n_child[0]), ns0, cap0);
+            const long long si = reserve_slot(want_i, gp(&st->n_child[1]), ns1, cap1);
+            if (want_e) {
+                if (se >= 0) {
+                    // first trial of a child at the next step: draw 4 of its stream
+                    const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
+                                            4u, k0, k1);
+                    write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
+                                   wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
+                    gatomic_add(gp(&C->dep_cnt[0][ce]), 1ull);
+                    gatomic_add(gp(&C->dep_w[0][ce]), packw(oe) & kWMask);
+                } else {
+                    atomicAdd(&acc.n_lost[0], 1u);
+                }
+            }
+            if (want_i) {
+                if (si >= 0) {
+                    const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
+                                            (1u << 28) | 4u, k0, k1);
+                    write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
+                                   wait_encode(geo0(r4.x, inv_ion)), kImp);
+                    gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
+                    gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
+                } else {
+                    atomicAdd(&acc.n_lost[1], 1u);
+                }
+            }
+        }
+    }
+
+    // flush the deposit of the implicit candidates and the EEDF counts
+    if (kImp && hi >= 0) {
+        atomicMin(&acc.cmin, lo);
+        atomicMax(&acc.cmax, hi);
+    }
+    lds_barrier();
+    if (kImp) {
+        PIC_GLOBAL unsigned long long* gcnt = gp(C->dep_cnt[s]);
+        PIC_GLOBAL unsigned long long* gw = gp(C->dep_w[s]);
+        const int cl = acc.cmin, chh = acc.cmax;
+        for (int j = cl + tid; chh >= 0 && j <= chh; j += kBlock) {
+            const unsigned long long p = dep[j];
+            if (p) {
+                gatomic_add(&gcnt[j], p >> 40);
+                gatomic_add(&gw[j], p & kWMask);
+            }
+        }
+    }
+    if (DIAG && s == 0)
+        for (int j = tid; j < kEedfBins; j += kBlock)
+            if (eedf[j]) gatomic_add(gp(&C->eedf_acc[j]), (unsigned long long)eedf[j]);
+    // collision terms added to the workgroup's ledger row
+    __shared__ double wsum[kWaves][2];
+    cdk = wave_sum(cdk);
+    const unsigned ncw = wave_sum(cand);
+    if (lane == 0) {
+        wsum[wave][0] = cdk;
+        wsum[wave][1] = (double)ncw;
+    }
+    lds_barrier();
+    if (tid == 0) {
+        double cd = 0.0, nc = 0.0;
+        for (int k = 0; k < kWaves; ++k) {
+            cd += wsum[k][0];
+            nc += wsum[k][1];
+        }
+        const int o = 1 - s;
+        double* pd = P.pd + cw.row;
+        unsigned* pu = P.pu + cw.row;
+        pd[(PD_WORK + 0) * S_] = 0.0;
+        pd[(PD_WORK + 1) * S_] = 0.0;
         pd[(PD_COLL + s) * S_] = cd;
         pd[(PD_COLL + o) * S_] = s == 0 ? acc.other_dK : 0.0;
         for (int a = 0; a < 2; ++a)
@@ -979,7 +1108,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
     State* st = P.state + (blockIdx.x >> 1);
     if (blockIdx.x & 1) {
         // ledger of the step just taken
-        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks,
+                                   C->first_crow, C->n_crows, sd, si);
         finish_ledger(C, st, sd, si);
         return;
     }
@@ -1000,6 +1130,10 @@ template __global__ void k_step<0, false>(Params);
 template __global__ void k_step<0, true>(Params);
 template __global__ void k_step<1, false>(Params);
 template __global__ void k_step<1, true>(Params);
+template __global__ void k_collide<0, false>(Params);
+template __global__ void k_collide<0, true>(Params);
+template __global__ void k_collide<1, false>(Params);
+template __global__ void k_collide<1, true>(Params);
 
 // ---------------------------------------------------------------------------
 // Set-up: velocities from m/s to cells/step (unless given in internal
@@ -1260,7 +1394,7 @@ __global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
     __shared__ long long si[PU_N];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, 0, 0, sd, si);
     if (threadIdx.x != 0) return;
     for (int s = 0; s < 2; ++s) {
         Species& S = C->sp[s];

@@ -19,6 +19,8 @@
 namespace pic {
 template <int SCHEME, bool DIAG>
 __global__ void k_step(Params P);
+template <int SCHEME, bool DIAG>
+__global__ void k_collide(Params P);
 __global__ void k_init_species(Params P, double vscale0, double vscale1);
 __global__ void k_compact_hist(Params P, uint32_t* hist_all, const int64_t* hist_off);
 __global__ void k_compact_scan(Params P, uint32_t* hist_all, uint32_t* cursor_all,
@@ -43,6 +45,7 @@ constexpr double ME_LIMIT = 1e-27;  // species lighter than this are "electron-l
 struct HostCase {
     pic_case_config cfg;
     double scale[2];        // n_g (dx/dt) / nu_max per species (collision tables)
+    double pnull[2] = {0.0, 0.0};   // null-collision candidate probability per step
     double q[2], m[2], w[2];
     int64_t cap[2];
     int64_t n0[2];
@@ -73,12 +76,16 @@ struct pic_ctx {
     Work* d_work = nullptr;
     double* d_pd = nullptr;        // workgroup partials (field-major)
     unsigned* d_pu = nullptr;
+    int32_t* d_cand_n = nullptr;    // candidates listed by each workgroup
     uint32_t* d_hist = nullptr;
     uint32_t* d_cursor = nullptr;
     int64_t* d_hist_off = nullptr;
     std::vector<Work> work;
     int n_blocks = 0;
     int grp_off[2] = {0, 0}, grp_cnt[2] = {0, 0};   // explicit, implicit workgroups
+    std::vector<CollideWork> cwork;                 // k_collide work table
+    int cgrp_off[2] = {0, 0}, cgrp_cnt[2] = {0, 0};
+    CollideWork* d_cwork = nullptr;
     int grp_maxN[2] = {0, 0};
     int maxN = 0;
     int tile = 8192;
@@ -90,6 +97,9 @@ struct pic_ctx {
     int ev_used = 0;
     double last_ms = 0.0;
     int64_t last_launches = 0;
+    double last_ms_coll = 0.0;
+    int64_t last_launches_coll = 0;
+    std::vector<int> ev_kind;      // 0: k_step, 1: k_collide
     bool timing = true;
     void* fp64 = nullptr;          // FP64 reference form (pic_fp64.hip)
     std::vector<void*> allocs;     // context-level allocations
@@ -139,11 +149,11 @@ int dalloc(pic_ctx* c, std::vector<void*>& list, T** p, size_t n)
 
 size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// Dynamic LDS of k_step: ehat[N] float | dep[N] u64 | (DIAG: heat[N] float |
+// Dynamic LDS of k_step: field[N+1] float | dep[N] u64 | (DIAG: heat[N] float |
 // eedf[kEedfBins] u32) | per-wavefront candidate queues.
-size_t step_lds(int N, bool diag, bool implicit)
+size_t step_lds(int N, bool diag)
 {
-    return step_lds_layout(N, diag, implicit).total;
+    return step_lds_layout(N, diag).total;
 }
 
 // Null-collision bound: n_g max over table intervals of
@@ -179,6 +189,7 @@ uint32_t candidate_threshold(double pnull)
 int build_work(pic_ctx* c)
 {
     c->work.clear();
+    c->cwork.clear();
     for (int g = 0; g < 2; ++g) {
         c->grp_off[g] = (int)c->work.size();
         c->grp_maxN[g] = 0;
@@ -198,6 +209,27 @@ int build_work(pic_ctx* c)
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
     }
     c->n_blocks = (int)c->work.size();
+    // k_collide: one workgroup per k_step workgroup that can list
+    // candidates (splitting a workgroup's list into several rounds adds more
+    // per-workgroup latency than it hides); partial rows follow the k_step
+    // rows.
+    for (int g = 0; g < 2; ++g) {
+        c->cgrp_off[g] = (int)c->cwork.size();
+        for (int k = 0; k < c->n_cases; ++k) {
+            HostCase& h = c->hc[k];
+            if (h.cfg.scheme != g) continue;
+            Case& C = c->cases_h[k];
+            C.first_crow = c->n_blocks + (int)c->cwork.size();
+            for (int b = C.first_block; b < C.first_block + C.n_blocks; ++b) {
+                const Work& w = c->work[b];
+                const double p = h.cfg.collisions ? h.pnull[w.s] : 0.0;
+                if (!(p > 0.0)) continue;
+                c->cwork.push_back(CollideWork{b, 0, 1, c->n_blocks + (int)c->cwork.size()});
+            }
+            C.n_crows = c->n_blocks + (int)c->cwork.size() - C.first_crow;
+        }
+        c->cgrp_cnt[g] = (int)c->cwork.size() - c->cgrp_off[g];
+    }
     return PIC_OK;
 }
 
@@ -206,16 +238,28 @@ int upload_work(pic_ctx* c)
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_pd) (void)hipFree(c->d_pd);
     if (c->d_pu) (void)hipFree(c->d_pu);
+    if (c->d_cand_n) (void)hipFree(c->d_cand_n);
+    if (c->d_cwork) (void)hipFree(c->d_cwork);
     c->d_work = nullptr;
     c->d_pd = nullptr;
     c->d_pu = nullptr;
+    c->d_cand_n = nullptr;
+    c->d_cwork = nullptr;
     const size_t nb = c->work.size();
+    const size_t ncw = c->cwork.size();
+    const size_t rows = nb + ncw;   // partial rows: k_step, then k_collide
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(Work) * nb));
     HIPCHK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(Work) * nb, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMalloc(&c->d_pd, sizeof(double) * PD_N * nb));
-    HIPCHK(c, hipMemset(c->d_pd, 0, sizeof(double) * PD_N * nb));
-    HIPCHK(c, hipMalloc(&c->d_pu, sizeof(unsigned) * PU_N * nb));
-    HIPCHK(c, hipMemset(c->d_pu, 0, sizeof(unsigned) * PU_N * nb));
+    HIPCHK(c, hipMalloc(&c->d_cwork, sizeof(CollideWork) * std::max<size_t>(ncw, 1)));
+    if (ncw)
+        HIPCHK(c, hipMemcpy(c->d_cwork, c->cwork.data(), sizeof(CollideWork) * ncw,
+                            hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&c->d_pd, sizeof(double) * PD_N * rows));
+    HIPCHK(c, hipMemset(c->d_pd, 0, sizeof(double) * PD_N * rows));
+    HIPCHK(c, hipMalloc(&c->d_pu, sizeof(unsigned) * PU_N * rows));
+    HIPCHK(c, hipMemset(c->d_pu, 0, sizeof(unsigned) * PU_N * rows));
+    HIPCHK(c, hipMalloc(&c->d_cand_n, sizeof(int32_t) * nb));
+    HIPCHK(c, hipMemset(c->d_cand_n, 0, sizeof(int32_t) * nb));
 
     return PIC_OK;
 }
@@ -228,9 +272,11 @@ Params params(pic_ctx* c, int mode)
     p.work = c->d_work;
     p.pd = c->d_pd;
     p.pu = c->d_pu;
-    p.stride = (int32_t)c->work.size();
+    p.stride = (int32_t)(c->work.size() + c->cwork.size());
     p.n_cases = c->n_cases;
     p.mode = mode;
+    p.cand_n = c->d_cand_n;
+    p.cwork = c->d_cwork;
 
     return p;
 }
@@ -258,6 +304,8 @@ int set_lds_limits(pic_ctx* c, size_t need)
     const int v = (int)need;
     const void* ks[] = {(const void*)k_step<0, false>, (const void*)k_step<0, true>,
                         (const void*)k_step<1, false>, (const void*)k_step<1, true>,
+                        (const void*)k_collide<0, false>, (const void*)k_collide<0, true>,
+                        (const void*)k_collide<1, false>, (const void*)k_collide<1, true>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
                         (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve,
                         (const void*)k_finalize};
@@ -436,6 +484,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                 S.inv_log1mp = (pnull > 0.0 && pnull < 1.0) ? 1.0 / std::log1p(-pnull) : 0.0;
                 const double scale = numax > 0 ? g.gas_density_m3 * (dx / dt) / numax : 0.0;
                 h.scale[s] = scale;
+                h.pnull[s] = pnull;
                 S.t_scale = (float)(eps_unit / a->de_eV);
                 S.t_off = (float)(-a->e0_eV / a->de_eV);
                 S.t_max = (float)(a->n - 1);
@@ -459,6 +508,35 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                     if (dalloc(c, h.allocs, &d, (size_t)a->n)) return bail(PIC_E_NOMEM);
                     INITCHK(hipMemcpy(d, t.data(), t.size() * 4, hipMemcpyHostToDevice));
                     S.tab_e = d;
+                    // Bound table: for the intervals k in [b K, (b+1) K) the
+                    // cumulative sum the kernel compares u1 with is at most
+                    // sum_p max sigma_p over the points b K .. (b+1) K times the
+                    // largest speed of the bin (a 1e-5 margin covers float
+                    // rounding); u1 above it is a null collision for certain.
+                    const int K = std::max(1, (a->n - 1 + kBoundBins - 1) / kBoundBins);
+                    std::vector<float> bnd(kBoundBins, 0.0f);
+                    for (int b = 0; b < kBoundBins; ++b) {
+                        const int k_lo = b * K;
+                        if (k_lo > a->n - 1) {
+                            bnd[b] = bnd[b > 0 ? b - 1 : 0];
+                            continue;
+                        }
+                        const int k_hi = std::min((b + 1) * K, a->n - 1);
+                        double sum = 0.0;
+                        for (int p = 0; p < S.n_proc; ++p) {
+                            float mx = 0.0f;
+                            for (int k2 = k_lo; k2 <= k_hi; ++k2) mx = std::max(mx, t[4 * k2 + p]);
+                            sum += mx;
+                        }
+                        const double t_hi = (double)k_hi + 1.0;   // slack of one interval
+                        const double v2 = std::max(0.0, (t_hi - c64[6]) / c64[5]);
+                        bnd[b] = (float)(sum * std::sqrt(v2) * (1.0 + 1e-5));
+                    }
+                    float* db = nullptr;
+                    if (dalloc(c, h.allocs, &db, (size_t)kBoundBins)) return bail(PIC_E_NOMEM);
+                    INITCHK(hipMemcpy(db, bnd.data(), 4 * (size_t)kBoundBins, hipMemcpyHostToDevice));
+                    S.cbound = db;
+                    S.bound_k = K;
                 } else {
                     std::vector<float> t((size_t)a->n);
                     for (int32_t i = 0; i < a->n; ++i) t[i] = (float)(proc[s][0]->sigma_m2[i] * scale);
@@ -485,6 +563,9 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             rc |= dalloc(c, h.allocs, &S.vz2, cap);
             rc |= dalloc(c, h.allocs, &S.id2, cap);
             rc |= dalloc(c, h.allocs, &S.abar2, cap);
+            rc |= dalloc(c, h.allocs, &S.cq_idx, cap);
+            rc |= dalloc(c, h.allocs, &S.cq_vn, cap);
+            rc |= dalloc(c, h.allocs, &S.cq_ab, cap);
             if (rc) return bail(PIC_E_NOMEM);
             if (sp.n > 0) {
                 const size_t n = (size_t)sp.n;
@@ -546,7 +627,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         h.hist_off[1] = hist_total + N;
         hist_total += 2 * (size_t)N;
     }
-    if (set_lds_limits(c, std::max(step_lds(c->maxN, true, true), 8 * (size_t)c->maxN)))
+    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true), collide_lds_bytes(c->maxN)),
+                                   8 * (size_t)c->maxN)))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
@@ -624,6 +706,8 @@ void destroy_ctx(pic_ctx* c)
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_pd) (void)hipFree(c->d_pd);
     if (c->d_pu) (void)hipFree(c->d_pu);
+    if (c->d_cand_n) (void)hipFree(c->d_cand_n);
+    if (c->d_cwork) (void)hipFree(c->d_cwork);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -649,7 +733,7 @@ int run_steps(pic_ctx* c, int64_t n, int which)
         if (which >= 0 && c->hc[k].cfg.scheme != which)
             return fail(c, PIC_E_INVAL, "a case of the context uses the other scheme");
     int needed = 0;
-    for (int g = 0; g < 2; ++g) needed += c->grp_cnt[g] ? 2 : 0;
+    for (int g = 0; g < 2; ++g) needed += c->grp_cnt[g] ? 4 : 0;
     needed *= (int)std::min<int64_t>(n, 1 << 20);
     while ((int)c->ev.size() < needed) {
         hipEvent_t e;
@@ -657,20 +741,32 @@ int run_steps(pic_ctx* c, int64_t n, int which)
         c->ev.push_back(e);
     }
     c->ev_used = 0;
+    c->ev_kind.clear();
     for (int64_t it = 0; it < n; ++it) {
         const bool diag = c->diag_every > 0 && (c->steps_taken % c->diag_every == 0);
         for (int g = 0; g < 2; ++g) {
             if (!c->grp_cnt[g]) continue;
             Params p = params(c, c->grp_off[g]);
-            const size_t lds = step_lds(c->grp_maxN[g], diag, g == 1);
-            auto kern = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
-                               : (diag ? k_step<1, true> : k_step<1, false>);
-            const bool rec = c->timing && c->ev_used + 2 <= (int)c->ev.size();
-            if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
-            hipLaunchKernelGGL(kern, dim3(c->grp_cnt[g]), dim3(kBlock), lds, c->stream, p);
-            if (rec) {
-                (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
-                c->ev_used += 2;
+            Params pc = params(c, c->cgrp_off[g]);
+            const int N = c->grp_maxN[g];
+            auto ks = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
+                             : (diag ? k_step<1, true> : k_step<1, false>);
+            auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
+                             : (diag ? k_collide<1, true> : k_collide<1, false>);
+            for (int kind = 0; kind < 2; ++kind) {
+                const bool rec = c->timing && c->ev_used + 2 <= (int)c->ev.size();
+                if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+                if (kind == 0)
+                    hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock), step_lds(N, diag),
+                                       c->stream, p);
+                else if (c->cgrp_cnt[g])
+                    hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
+                                       collide_lds_bytes(N), c->stream, pc);
+                if (rec) {
+                    (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+                    c->ev_used += 2;
+                    c->ev_kind.push_back(kind);
+                }
             }
         }
         hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock),
@@ -681,13 +777,18 @@ int run_steps(pic_ctx* c, int64_t n, int which)
             if (compaction(c)) return PIC_E_DEVICE;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms = 0.0;
+    double ms[2] = {0.0, 0.0};
+    int64_t launches[2] = {0, 0};
     for (int e = 0; e + 1 < c->ev_used; e += 2) {
         float t = 0.0f;
-        if (hipEventElapsedTime(&t, c->ev[e], c->ev[e + 1]) == hipSuccess) ms += t;
+        const int kind = c->ev_kind[e / 2];
+        if (hipEventElapsedTime(&t, c->ev[e], c->ev[e + 1]) == hipSuccess) ms[kind] += t;
+        launches[kind]++;
     }
-    c->last_ms = ms;
-    c->last_launches = c->ev_used / 2;
+    c->last_ms = ms[0];
+    c->last_launches = launches[0];
+    c->last_ms_coll = ms[1];
+    c->last_launches_coll = launches[1];
     return check_flags(c);
 }
 
@@ -716,6 +817,14 @@ extern "C" int pic_last_timing(const pic_ctx* ctx, double* ms, int64_t* launches
     if (!ctx) return PIC_E_INVAL;
     if (ms) *ms = ctx->last_ms;
     if (launches) *launches = ctx->last_launches;
+    return PIC_OK;
+}
+
+extern "C" int pic_last_timing_collide(const pic_ctx* ctx, double* ms, int64_t* launches)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ms) *ms = ctx->last_ms_coll;
+    if (launches) *launches = ctx->last_launches_coll;
     return PIC_OK;
 }
 
