@@ -22,11 +22,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per particle-step of the explicit pass: read cell, off,
-# vx, vy, vz (4 B each) and id (8 B); write cell, off, vx (4 B each)
-ALG_BYTES_EXPLICIT = 40
-# implicit pass also reads and writes abar (4 B each)
-ALG_BYTES_IMPLICIT = 48
+# Algorithmic bytes of the particle pass (k_step) per particle-step: read the
+# cell word, offset and vx, write them back (4 B each); the implicit pass also
+# reads and writes abar.  Per listed collision candidate: slot and v (8 B; the
+# implicit list also carries abar, 4 B).
+PASS_BYTES = {0: 24, 1: 32}
+LIST_BYTES = {0: 8, 1: 12}
+# Algorithmic bytes of the collision kernel (k_collide) per candidate: the
+# list entry, the cell word, offset, id, vy, vz of the slot (24 B) and the
+# velocity and cell word written back (8 B).
+COLLIDE_BYTES = {0: 40, 1: 52}
 
 
 def log(*a):
@@ -44,6 +49,36 @@ def make_workload(name, scale):
     if name == "sweep64":
         return W.c5(np_scale=scale)
     raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pic_kernels.hip", "pic_common.hpp", "pic_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1310_5284_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    the summary is for another workload or the kernel sources changed since."""
+    name = kernel.split("<")[0]
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return int(float(kv["bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05):
@@ -87,7 +122,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="ccp2048_explicit")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="particles per workgroup (default 16384)")
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -114,7 +149,7 @@ def main():
     wls = make_workload(args.workload, args.scale)
     log("[bench] pic_init")
     ctx = P.PicContext(wls)
-    tile = args.tile or 8192
+    tile = args.tile or 16384
     sort_every = args.sort_every or 64
     ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
     implicit = all(w["case"]["scheme"] == 1 for w in wls)
@@ -138,29 +173,33 @@ def main():
     ctx.sync()
     t1 = time.perf_counter()
     kern_ms, launches = ctx.last_timing()
+    coll_ms, coll_launches = ctx.last_timing_collide()
     n_after = live()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     particles = 0.5 * (n_before + n_after)
     value = particles * args.steps / (t1 - t0)
 
-    bpp = ALG_BYTES_IMPLICIT if implicit else ALG_BYTES_EXPLICIT
+    # candidates of the last step (ledger), as the per-step count
+    sch = 1 if implicit else 0
+    cands = sum(int(sum(ctx.ledger(k)["n_candidates"])) for k in range(len(wls)))
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     launches_per_step = launches / args.steps
-    alg_bytes = bpp * particles / launches_per_step
+    alg_bytes = (PASS_BYTES[sch] * particles + LIST_BYTES[sch] * cands) / launches_per_step
     achieved = alg_bytes / avg_launch_s / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
-                kernel="k_step<%d,false>" % (1 if implicit else 0),
+                kernel="k_step<%d,false>" % sch,
                 avg_launch_ms=round(avg_launch_s * 1e3, 4),
-                alg_bytes_per_particle_step=bpp)
-    tprof = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tprof):
-        try:
-            t = json.load(open(tprof))
-            if t.get("workload") == args.workload and t.get("kernel") == roof["kernel"]:
-                roof["traffic"] = t.get("bytes_per_launch")
-        except Exception:
-            pass
+                alg_bytes_per_launch=int(alg_bytes),
+                alg_bytes_rule="%d B per particle + %d B per listed candidate"
+                               % (PASS_BYTES[sch], LIST_BYTES[sch]))
+    coll_avg_s = coll_ms / 1e3 / max(coll_launches, 1)
+    coll_bytes = COLLIDE_BYTES[sch] * cands / max(coll_launches / args.steps, 1e-9)
+    collide = dict(kernel="k_collide<%d,false>" % sch, avg_launch_ms=round(coll_avg_s * 1e3, 4),
+                   candidates_per_step=cands,
+                   achieved_GBps=round(coll_bytes / max(coll_avg_s, 1e-12) / 1e9, 1),
+                   alg_bytes_rule="%d B per candidate" % COLLIDE_BYTES[sch])
+    roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
 
     out = dict(metric="particle-steps/sec (push+deposit+MCC) vs plain FP64 GPU form at "
                       "matched EEDF",
@@ -172,7 +211,7 @@ def main():
                            cells=[w["case"]["n_cells"] for w in wls][:4],
                            particles=int(particles), tile=tile, sort_every=sort_every,
                            scheme="implicit" if implicit else "explicit"),
-               roofline=roof)
+               roofline=roof, collide=collide)
     if args.fp64_steps > 0 and not implicit:
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
