@@ -58,6 +58,20 @@ __device__ __forceinline__ void stg(PIC_GLOBAL T* base, uint32_t byte_off, T v)
     *(PIC_GLOBAL T*)((PIC_GLOBAL char*)base + byte_off) = v;
 }
 
+// The collision record of a particle: id (x, y), vy (z), vz (w).
+__device__ __forceinline__ uint64_t rec_id(u32x4 r) { return (uint64_t)r.x | ((uint64_t)r.y << 32); }
+__device__ __forceinline__ float rec_vy(u32x4 r) { return __uint_as_float(r.z); }
+__device__ __forceinline__ float rec_vz(u32x4 r) { return __uint_as_float(r.w); }
+__device__ __forceinline__ u32x4 make_rec(uint64_t id, float vy, float vz)
+{
+    u32x4 r;
+    r.x = (uint32_t)id;
+    r.y = (uint32_t)(id >> 32);
+    r.z = __float_as_uint(vy);
+    r.w = __float_as_uint(vz);
+    return r;
+}
+
 // relaxed device-scope atomic add through a global pointer
 template <class T>
 __device__ __forceinline__ T gatomic_add(PIC_GLOBAL T* p, T v)

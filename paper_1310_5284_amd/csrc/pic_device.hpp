@@ -23,21 +23,26 @@ constexpr int kMaxProc = 4;                 // electron processes per table row
 constexpr int kEedfBins = 256;
 constexpr int kMaxTile = 32767;             // keeps packed LDS counts < 2^16
 
+// 16- and 8-byte vectors of uint32 (native vector types: loadable through
+// global address-space pointers)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 // One species of one case.  Particle pointers are swapped by the compaction.
+// The streaming pass touches cell, off, vx (and abar); the collision inputs
+// that only candidates need (id, vy, vz) form one 16-byte record per
+// particle (x, y: id low and high words; z, w: vy and vz bits), so that a
+// candidate touches one cache line instead of three.
 struct Species {
     int32_t* cell;
     float* off;
     float* vx;
-    float* vy;
-    float* vz;
-    uint64_t* id;
+    u32x4* rec;
     float* abar;
     int32_t* cell2;
     float* off2;
     float* vx2;
-    float* vy2;
-    float* vz2;
-    uint64_t* id2;
+    u32x4* rec2;
     float* abar2;
     int64_t capacity;
     double accel;        // cells/step^2 per (V/m): (q/m) dt^2 / dx
@@ -67,6 +72,8 @@ struct Species {
     int32_t* cq_idx;
     float* cq_vn;
     float* cq_ab;
+    int32_t* cq_w;       // cell word of x_{n+1} (cell, waiting time)
+    float* cq_o;         // offset of x_{n+1} (implicit)
     // electrons: upper bounds of sum_k n_g sigma_k v / nu_max (the scaled
     // table times the speed) over bins of bound_k table intervals
     const float* cbound;

@@ -469,9 +469,7 @@ __device__ __forceinline__ void write_particle(const Species& S, long long slot,
     gp(S.cell)[slot] = pack_cell(c, wait);
     gp(S.off)[slot] = o;
     gp(S.vx)[slot] = vx;
-    gp(S.vy)[slot] = vy;
-    gp(S.vz)[slot] = vz;
-    gp(S.id)[slot] = id;
+    gp(S.rec)[slot] = make_rec(id, vy, vz);
     if (implicit) gp(S.abar)[slot] = 0.0f;
 }
 
@@ -542,12 +540,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     PIC_GLOBAL int32_t* __restrict__ cellp = gp(uniform_ptr(C->sp[s].cell));
     PIC_GLOBAL float* __restrict__ offp = gp(uniform_ptr(C->sp[s].off));
     PIC_GLOBAL float* __restrict__ vxp = gp(uniform_ptr(C->sp[s].vx));
-    PIC_GLOBAL float* __restrict__ vyp = gp(uniform_ptr(C->sp[s].vy));
-    PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
+    const PIC_GLOBAL u32x4* __restrict__ recp = gp(uniform_ptr((const u32x4*)C->sp[s].rec));
     PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
     PIC_GLOBAL int32_t* __restrict__ cq_idx = gp(uniform_ptr(C->sp[s].cq_idx));
     PIC_GLOBAL float* __restrict__ cq_vn = gp(uniform_ptr(C->sp[s].cq_vn));
     PIC_GLOBAL float* __restrict__ cq_ab = gp(uniform_ptr(C->sp[s].cq_ab));
+    PIC_GLOBAL int32_t* __restrict__ cq_w = gp(uniform_ptr(C->sp[s].cq_w));
+    PIC_GLOBAL float* __restrict__ cq_o = gp(uniform_ptr(C->sp[s].cq_o));
     const float eedf_k = C->sp[s].eps_unit * C->sp[s].eedf_scale;
     const double kin_unit = C->sp[s].kin_unit;
     const bool periodic = C->bc == 1;
@@ -650,7 +649,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     c1 %= N;
                     if (c1 < 0) c1 += N;
                 } else if (c1 < 0 || c1 >= N) {
-                    absorb(i, c1 < 0 ? 0 : 1, vn, ldg(vyp, i4), ldg(vzp, i4));
+                    const u32x4 r = ldg(recp, i4 << 2);
+                    absorb(i, c1 < 0 ? 0 : 1, vn, rec_vy(r), rec_vz(r));
                     live = false;
                 }
             }
@@ -677,7 +677,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                         c2 %= N;
                         if (c2 < 0) c2 += N;
                     } else if (c2 < 0 || c2 >= N) {
-                        absorb(i, c2 < 0 ? 0 : 1, vn, ldg(vyp, i4), ldg(vzp, i4));
+                        const u32x4 r = ldg(recp, i4 << 2);
+                        absorb(i, c2 < 0 ? 0 : 1, vn, rec_vy(r), rec_vz(r));
                         live = false;
                     }
                 }
@@ -688,7 +689,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     if (kImp) stg(abp, i4, abn);
                     dep_now = true;
                     if (DIAG && s == 0) {
-                        const float ey = ldg(vyp, i4), ez = ldg(vzp, i4);
+                        const u32x4 r = ldg(recp, i4 << 2);
+                        const float ey = rec_vy(r), ez = rec_vz(r);
                         const float fb = (vn * vn + ey * ey + ez * ez) * eedf_k;
                         const int bin =
                             fb >= 1.0f ? min((int)fminf(fb, (float)kEedfBins), kEedfBins - 1) : 0;
@@ -713,7 +715,11 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     const uint32_t e4 = (uint32_t)e << 2;
                     stg(cq_idx, e4, i);
                     stg(cq_vn, e4, vn);
-                    if (kImp) stg(cq_ab, e4, abn);
+                    stg(cq_w, e4, pack_cell(c1, wt));
+                    if (kImp) {
+                        stg(cq_ab, e4, abn);
+                        stg(cq_o, e4, o1);
+                    }
                 }
             }
         }
@@ -810,10 +816,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     PIC_GLOBAL int32_t* __restrict__ cellp = gp(uniform_ptr(C->sp[s].cell));
     PIC_GLOBAL float* __restrict__ offp = gp(uniform_ptr(C->sp[s].off));
     PIC_GLOBAL float* __restrict__ vxp = gp(uniform_ptr(C->sp[s].vx));
-    PIC_GLOBAL float* __restrict__ vyp = gp(uniform_ptr(C->sp[s].vy));
-    PIC_GLOBAL float* __restrict__ vzp = gp(uniform_ptr(C->sp[s].vz));
-    const PIC_GLOBAL uint64_t* __restrict__ idp = gp(uniform_ptr((const uint64_t*)C->sp[s].id));
+    PIC_GLOBAL u32x4* __restrict__ recp = gp(uniform_ptr(C->sp[s].rec));
     PIC_GLOBAL float* __restrict__ abp = gp(uniform_ptr(C->sp[s].abar));
+    const PIC_GLOBAL int32_t* __restrict__ cq_w = gp(uniform_ptr((const int32_t*)C->sp[s].cq_w));
+    const PIC_GLOBAL float* __restrict__ cq_o = gp(uniform_ptr((const float*)C->sp[s].cq_o));
     const PIC_GLOBAL int32_t* __restrict__ cq_idx =
         gp(uniform_ptr((const int32_t*)C->sp[s].cq_idx));
     const PIC_GLOBAL float* __restrict__ cq_vn = gp(uniform_ptr((const float*)C->sp[s].cq_vn));
@@ -885,11 +891,13 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             vn = ldg(cq_vn, q4);
             if (kImp) abn = ldg(cq_ab, q4);
             const uint32_t i4 = (uint32_t)i << 2;
-            const int32_t w1 = ldg(cellp, i4);
-            o1 = ldg(offp, i4);
-            id = ldg(idp, i4 << 1);
-            vy = ldg(vyp, i4);
-            vz = ldg(vzp, i4);
+            // the list carries x_{n+1}; one 16-byte record holds id, vy, vz
+            const int32_t w1 = ldg(cq_w, q4);
+            if (kImp) o1 = ldg(cq_o, q4);
+            const u32x4 r = ldg((const PIC_GLOBAL u32x4*)recp, i4 << 2);
+            id = rec_id(r);
+            vy = rec_vy(r);
+            vz = rec_vz(r);
             c1 = cell_of(w1);
             const float v2b = vn * vn + vy * vy + vz * vz;
             bool is_cand = true;
@@ -917,8 +925,11 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             if (kind >= 0) {
                 atomicAdd(&acc.n_coll[kind], 1u);
                 cdk += (double)(vn * vn + vy * vy + vz * vz - v2b);
-                stg(vyp, i4, vy);
-                stg(vzp, i4, vz);
+                // vy, vz: the upper half of the record
+                u32x2 yz;
+                yz.x = __float_as_uint(vy);
+                yz.y = __float_as_uint(vz);
+                stg((PIC_GLOBAL u32x2*)recp, (i4 << 2) + 8u, yz);
             }
             if (DIAG && s == 0) {
                 const float fb = (vn * vn + vy * vy + vz * vz) * eedf_k;
@@ -962,6 +973,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         // deposits are rare and go straight to the case grids
         const bool ion_ev = act && kind == PIC_IONIZATION && s == 0;
         if (__ballot(ion_ev)) {
+            // explicit lists carry no offset: read it for the rare ionizations
+            if (!kImp && ion_ev) o1 = ldg(offp, (uint32_t)i << 2);
             bool want_e = false, want_i = false;
             int ce = c1, ci = c1;
             float oe = o1, oi = o1;
@@ -1161,15 +1174,16 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
         if (convert) {
             S.vx[i] = (float)((double)S.vx[i] * vs);
-            S.vy[i] = (float)((double)S.vy[i] * vs);
-            S.vz[i] = (float)((double)S.vz[i] * vs);
+            const u32x4 r = S.rec[i];
+            S.rec[i] = make_rec(rec_id(r), (float)((double)rec_vy(r) * vs),
+                                (float)((double)rec_vz(r) * vs));
         }
         const int32_t word = S.cell[i];
         if (word < 0) continue;
         int c = cell_of(word);
         uint32_t wt = wait_of(word);
         if (draw) {
-            const uint64_t id = S.id[i];
+            const uint64_t id = rec_id(S.rec[i]);
             const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
                                     ((uint32_t)w.s << 28) | 4u, C->key0, C->key1);
             wt = wait_encode(geo0(r4.x, S.inv_log1mp));
@@ -1343,24 +1357,21 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     lds_barrier();
     const PIC_GLOBAL float* __restrict__ offp = gp((const float*)S.off);
     const PIC_GLOBAL float* __restrict__ vxp = gp((const float*)S.vx);
-    const PIC_GLOBAL float* __restrict__ vyp = gp((const float*)S.vy);
-    const PIC_GLOBAL float* __restrict__ vzp = gp((const float*)S.vz);
-    const PIC_GLOBAL uint64_t* __restrict__ idp = gp((const uint64_t*)S.id);
+    const PIC_GLOBAL u32x4* __restrict__ recp = gp((const u32x4*)S.rec);
     const PIC_GLOBAL float* __restrict__ abp = gp((const float*)S.abar);
     PIC_GLOBAL int32_t* __restrict__ cell2 = gp(S.cell2);
     PIC_GLOBAL float* __restrict__ off2 = gp(S.off2);
     PIC_GLOBAL float* __restrict__ vx2 = gp(S.vx2);
-    PIC_GLOBAL float* __restrict__ vy2 = gp(S.vy2);
-    PIC_GLOBAL float* __restrict__ vz2 = gp(S.vz2);
-    PIC_GLOBAL uint64_t* __restrict__ id2 = gp(S.id2);
+    PIC_GLOBAL u32x4* __restrict__ rec2 = gp(S.rec2);
     PIC_GLOBAL float* __restrict__ ab2 = gp(S.abar2);
     double v2 = 0.0;
     for (int base = start; base < end; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         const int j = min(i, end - 1);
         const int32_t w0 = cellp[j];
-        const float o = offp[j], vx = vxp[j], vy = vyp[j], vz = vzp[j];
-        const uint64_t id = idp[j];
+        const float o = offp[j], vx = vxp[j];
+        const u32x4 rc = recp[j];
+        const float vy = rec_vy(rc), vz = rec_vz(rc);
         const float ab = imp ? abp[j] : 0.0f;
         const int c = i < end ? cell_of(w0) : -1;
         const int b = c >= 0 ? c >> sh : -1;
@@ -1370,9 +1381,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
         cell2[d] = w0;
         off2[d] = o;
         vx2[d] = vx;
-        vy2[d] = vy;
-        vz2[d] = vz;
-        id2[d] = id;
+        rec2[d] = rc;
         float vh = vx;
         if (imp) {
             ab2[d] = ab;
@@ -1406,9 +1415,7 @@ __global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
         int32_t* t0 = S.cell; S.cell = S.cell2; S.cell2 = t0;
         float* t1 = S.off; S.off = S.off2; S.off2 = t1;
         t1 = S.vx; S.vx = S.vx2; S.vx2 = t1;
-        t1 = S.vy; S.vy = S.vy2; S.vy2 = t1;
-        t1 = S.vz; S.vz = S.vz2; S.vz2 = t1;
-        uint64_t* t2 = S.id; S.id = S.id2; S.id2 = t2;
+        u32x4* t2 = S.rec; S.rec = S.rec2; S.rec2 = t2;
         t1 = S.abar; S.abar = S.abar2; S.abar2 = t1;
     }
 }

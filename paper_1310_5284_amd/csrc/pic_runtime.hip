@@ -552,29 +552,40 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             rc |= dalloc(c, h.allocs, &S.cell, cap);
             rc |= dalloc(c, h.allocs, &S.off, cap);
             rc |= dalloc(c, h.allocs, &S.vx, cap);
-            rc |= dalloc(c, h.allocs, &S.vy, cap);
-            rc |= dalloc(c, h.allocs, &S.vz, cap);
-            rc |= dalloc(c, h.allocs, &S.id, cap);
+            rc |= dalloc(c, h.allocs, &S.rec, cap);
             rc |= dalloc(c, h.allocs, &S.abar, cap);
             rc |= dalloc(c, h.allocs, &S.cell2, cap);
             rc |= dalloc(c, h.allocs, &S.off2, cap);
             rc |= dalloc(c, h.allocs, &S.vx2, cap);
-            rc |= dalloc(c, h.allocs, &S.vy2, cap);
-            rc |= dalloc(c, h.allocs, &S.vz2, cap);
-            rc |= dalloc(c, h.allocs, &S.id2, cap);
+            rc |= dalloc(c, h.allocs, &S.rec2, cap);
             rc |= dalloc(c, h.allocs, &S.abar2, cap);
             rc |= dalloc(c, h.allocs, &S.cq_idx, cap);
             rc |= dalloc(c, h.allocs, &S.cq_vn, cap);
             rc |= dalloc(c, h.allocs, &S.cq_ab, cap);
+            rc |= dalloc(c, h.allocs, &S.cq_w, cap);
+            rc |= dalloc(c, h.allocs, &S.cq_o, cap);
             if (rc) return bail(PIC_E_NOMEM);
             if (sp.n > 0) {
                 const size_t n = (size_t)sp.n;
                 INITCHK(hipMemcpy(S.cell, sp.cell, 4 * n, hipMemcpyDefault));
                 INITCHK(hipMemcpy(S.off, sp.off, 4 * n, hipMemcpyDefault));
                 INITCHK(hipMemcpy(S.vx, sp.vx, 4 * n, hipMemcpyDefault));
-                INITCHK(hipMemcpy(S.vy, sp.vy, 4 * n, hipMemcpyDefault));
-                INITCHK(hipMemcpy(S.vz, sp.vz, 4 * n, hipMemcpyDefault));
-                INITCHK(hipMemcpy(S.id, sp.id, 8 * n, hipMemcpyDefault));
+                {
+                    // id, vy, vz into the 16-byte records
+                    std::vector<float> yy(n), zz(n);
+                    std::vector<uint64_t> ii(n);
+                    INITCHK(hipMemcpy(yy.data(), sp.vy, 4 * n, hipMemcpyDefault));
+                    INITCHK(hipMemcpy(zz.data(), sp.vz, 4 * n, hipMemcpyDefault));
+                    INITCHK(hipMemcpy(ii.data(), sp.id, 8 * n, hipMemcpyDefault));
+                    std::vector<uint32_t> rr(4 * n);
+                    for (size_t i = 0; i < n; ++i) {
+                        rr[4 * i] = (uint32_t)ii[i];
+                        rr[4 * i + 1] = (uint32_t)(ii[i] >> 32);
+                        std::memcpy(&rr[4 * i + 2], &yy[i], 4);
+                        std::memcpy(&rr[4 * i + 3], &zz[i], 4);
+                    }
+                    INITCHK(hipMemcpy(S.rec, rr.data(), 16 * n, hipMemcpyHostToDevice));
+                }
                 if (sp.abar) INITCHK(hipMemcpy(S.abar, sp.abar, 4 * n, hipMemcpyDefault));
                 // positions must lie inside the gap / box
                 std::vector<int32_t> cc(n);
@@ -931,10 +942,15 @@ extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic
                 HIPCHK(ctx, hipMemcpy(cell.data(), S.cell, 4 * ns, hipMemcpyDeviceToHost));
                 HIPCHK(ctx, hipMemcpy(off.data(), S.off, 4 * ns, hipMemcpyDeviceToHost));
                 HIPCHK(ctx, hipMemcpy(vx.data(), S.vx, 4 * ns, hipMemcpyDeviceToHost));
-                HIPCHK(ctx, hipMemcpy(vy.data(), S.vy, 4 * ns, hipMemcpyDeviceToHost));
-                HIPCHK(ctx, hipMemcpy(vz.data(), S.vz, 4 * ns, hipMemcpyDeviceToHost));
+                std::vector<uint32_t> rr(4 * ns);
+                HIPCHK(ctx, hipMemcpy(rr.data(), S.rec, 16 * ns, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < ns; ++i) {
+                    std::memcpy(&vy[i], &rr[4 * i + 2], 4);
+                    std::memcpy(&vz[i], &rr[4 * i + 3], 4);
+                    id[i] = (uint64_t)rr[4 * i] | ((uint64_t)rr[4 * i + 1] << 32);
+                }
                 HIPCHK(ctx, hipMemcpy(ab.data(), S.abar, 4 * ns, hipMemcpyDeviceToHost));
-                HIPCHK(ctx, hipMemcpy(id.data(), S.id, 8 * ns, hipMemcpyDeviceToHost));
+
             }
             std::vector<uint32_t> wt(ns);
             size_t k = 0;
