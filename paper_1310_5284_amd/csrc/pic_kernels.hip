@@ -700,6 +700,9 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             } else if (live) {
                 stg(cellp, i4, pack_cell(c1, wt));
                 stg(offp, i4, o1);
+                // explicit: v_{n+1/2} stands unless k_collide finds a real
+                // collision (the store joins the coalesced stream)
+                if (!kImp) stg(vxp, i4, vn);
                 dep_now = !kImp;
             }
             deposit_wave(dep, dep_now, c2, o2, lo, hi);
@@ -963,7 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                     dep_ok = true;
                 }
             } else {
-                stg(vxp, i4, vn);
+                if (kind >= 0) stg(vxp, i4, vn);   // the pass stored v_{n+1/2}
                 stg(cellp, i4, pack_cell(c1, nw));
             }
         }
