@@ -230,3 +230,28 @@ def test_over_table_energies_are_flagged(orc):
         r, v1, ve, vi, over = sim.collide_one(0, pid, 1, [v, 0, 0])
         flagged += over
     assert flagged == 500
+
+
+def test_children_draw_geometric_first_waits(orc):
+    # ionization children take their first trial at the next step with a
+    # Geo0(P_null) wait of their own: mean (1 - p)/p over many children
+    sim, case, procs = beam_sim(orc, p_mtorr=50.0)
+    numax = sim.numax(0)
+    case = dict(case, dt_s=-math.log(1 - 0.3) / numax)      # P_null = 0.3
+    n = 20000
+    v80 = speed_of(80.0, W.M_E)
+    e = dict(q=-QE, m=W.M_E, w=1e9, xi=np.full(n, 32.5), vx=np.zeros(n), vy=np.zeros(n),
+             vz=np.full(n, v80), id=np.arange(n, dtype=np.uint64), abar=None)
+    i = dict(q=QE, m=W.M_AR, w=1e9, xi=np.zeros(0), vx=np.zeros(0), vy=np.zeros(0),
+             vz=np.zeros(0), id=np.zeros(0, dtype=np.uint64), abar=None)
+    sim = orc.Sim(dict(case, rf_volts=0.0), [e, i], procs)
+    p = 1 - math.exp(-sim.numax(0) * case["dt_s"])
+    assert abs(p - 0.3) < 1e-9
+    sim.step(1)
+    out = sim.species(0)
+    kids = out["wait"][out["id"] >= np.uint64(1 << 63)]
+    assert kids.size > 150
+    mean, sd = (1 - p) / p, math.sqrt(1 - p) / p
+    assert abs(kids.mean() - mean) <= 5 * sd / math.sqrt(kids.size), (kids.mean(), mean)
+    pz = (kids == 0).mean()
+    assert abs(pz - p) <= 5 * math.sqrt(p * (1 - p) / kids.size)
