@@ -24,14 +24,17 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes of the particle pass (k_step) per particle-step: read the
 # cell word, offset and vx, write them back (4 B each); the implicit pass also
-# reads and writes abar.  Per listed collision candidate: slot and v (8 B; the
-# implicit list also carries abar, 4 B).
+# reads and writes abar.  Per listed collision candidate: slot, v and the cell
+# word of x_{n+1} (12 B); the implicit list also carries abar and the offset.
 PASS_BYTES = {0: 24, 1: 32}
-LIST_BYTES = {0: 8, 1: 12}
-# Algorithmic bytes of the collision kernel (k_collide) per candidate: the
-# list entry, the cell word, offset, id, vy, vz of the slot (24 B) and the
-# velocity and cell word written back (8 B).
-COLLIDE_BYTES = {0: 40, 1: 52}
+LIST_BYTES = {0: 12, 1: 20}
+# Algorithmic bytes of the collision kernel (k_collide) per candidate: read the
+# list entry and the 16-byte record (id, vy, vz), write the cell word back
+# (explicit: 12 + 16 + 4; implicit: 20 + 16 + cell word, offset, vx, abar).
+# Per real collision the new velocity is written: vx, vy, vz explicit (the
+# implicit pass rewrites vx anyway, so vy, vz only).
+COLLIDE_BYTES = {0: 32, 1: 52}
+COLLISION_BYTES = {0: 12, 1: 8}
 
 
 def log(*a):
@@ -45,7 +48,11 @@ def make_workload(name, scale):
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":
-        return [W.c3()]
+        # omega_p dt = 2: at 5 the D1 discharge heats and ionizes without bound
+        wl = W.c3(wdt=2.0)
+        for sp in wl["species"]:
+            sp["capacity"] = 2 * sp["cell"].size
+        return [wl]
     if name == "sweep64":
         return W.c5(np_scale=scale)
     raise SystemExit(f"unknown workload {name}")
@@ -81,7 +88,7 @@ def measured_traffic(workload, kernel):
         return None
 
 
-def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05):
+def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge"):
     """The FP64 oracle (single thread) on a particle sample of the workload."""
     import numpy as np
 
@@ -111,7 +118,7 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05):
         steps += 1
     dt = time.perf_counter() - t0
     return dict(value=n_ps / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"{frac:g} of the particles of the same discharge (weights scaled "
+                sample=f"{frac:g} of the particles of {where} (weights scaled "
                        f"to keep the densities), {steps} steps, FP64, single thread")
 
 
@@ -124,6 +131,11 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--tile", type=int, default=0, help="particles per workgroup (default 16384)")
     ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="replay whole sort periods from a captured HIP graph")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="HIP events around the kernels of every n-th step (they cost "
+                         "about 4 us each)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=20,
@@ -152,11 +164,14 @@ def main():
     tile = args.tile or 16384
     sort_every = args.sort_every or 64
     ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
-    implicit = all(w["case"]["scheme"] == 1 for w in wls)
+    ctx.set_launch(graph=args.graph, timing_every=args.timing_every)
+    schemes = [int(w["case"]["scheme"]) for w in wls]
+    implicit = all(sc == 1 for sc in schemes)
+    groups = len(set(schemes))          # one k_step and one k_collide launch per group
     stepper = ctx.step
 
-    def live():
-        return sum(sum(ctx.counts(k)["n"]) for k in range(len(wls)))
+    def live_per_case():
+        return [sum(ctx.counts(k)["n"]) for k in range(len(wls))]
 
     log(f"[bench] warmup {args.warmup} steps")
     done = 0
@@ -165,40 +180,55 @@ def main():
         stepper(k)
         done += k
         log(f"[bench] warmup {done}/{args.warmup}")
-    n_before = live()
+    n_before = live_per_case()
     ctx.sync()
-    log(f"[bench] timing {args.steps} steps, {n_before} particles")
+    log(f"[bench] timing {args.steps} steps, {sum(n_before)} particles")
     t0 = time.perf_counter()
     stepper(args.steps)
     ctx.sync()
     t1 = time.perf_counter()
     kern_ms, launches = ctx.last_timing()
     coll_ms, coll_launches = ctx.last_timing_collide()
-    n_after = live()
+    n_after = live_per_case()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    particles = 0.5 * (n_before + n_after)
+    per_case = [0.5 * (a + b) for a, b in zip(n_before, n_after)]
+    particles = sum(per_case)
     value = particles * args.steps / (t1 - t0)
 
-    # candidates of the last step (ledger), as the per-step count
-    sch = 1 if implicit else 0
-    cands = sum(int(sum(ctx.ledger(k)["n_candidates"])) for k in range(len(wls)))
+    # algorithmic bytes of one step from the particles and the candidates and
+    # collisions of the last step (ledger); per launch = per step / groups
+    step_bytes = coll_step_bytes = 0.0
+    cands = real = 0
+    for k, w in enumerate(wls):
+        sc = schemes[k]
+        L = ctx.ledger(k)
+        ck, rk = int(sum(L["n_candidates"])), int(L["n_coll"].sum())
+        cands += ck
+        real += rk
+        step_bytes += PASS_BYTES[sc] * per_case[k] + LIST_BYTES[sc] * ck
+        coll_step_bytes += COLLIDE_BYTES[sc] * ck + COLLISION_BYTES[sc] * rk
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    launches_per_step = launches / args.steps
-    alg_bytes = (PASS_BYTES[sch] * particles + LIST_BYTES[sch] * cands) / launches_per_step
+    alg_bytes = step_bytes / groups
     achieved = alg_bytes / avg_launch_s / 1e9
+    kname = "k_step<%d,false>" % schemes[0] if groups == 1 else "k_step<0|1,false>"
+    rule = " and ".join("%s: %d B per particle + %d B per listed candidate"
+                        % (("explicit", "implicit")[sc], PASS_BYTES[sc], LIST_BYTES[sc])
+                        for sc in sorted(set(schemes)))
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
-                kernel="k_step<%d,false>" % sch,
-                avg_launch_ms=round(avg_launch_s * 1e3, 4),
-                alg_bytes_per_launch=int(alg_bytes),
-                alg_bytes_rule="%d B per particle + %d B per listed candidate"
-                               % (PASS_BYTES[sch], LIST_BYTES[sch]))
+                kernel=kname, avg_launch_ms=round(avg_launch_s * 1e3, 4),
+                timed_launches=launches, alg_bytes_per_launch=int(alg_bytes),
+                alg_bytes_rule=rule)
     coll_avg_s = coll_ms / 1e3 / max(coll_launches, 1)
-    coll_bytes = COLLIDE_BYTES[sch] * cands / max(coll_launches / args.steps, 1e-9)
-    collide = dict(kernel="k_collide<%d,false>" % sch, avg_launch_ms=round(coll_avg_s * 1e3, 4),
-                   candidates_per_step=cands,
+    coll_bytes = coll_step_bytes / groups
+    collide = dict(kernel=kname.replace("k_step", "k_collide"),
+                   avg_launch_ms=round(coll_avg_s * 1e3, 4),
+                   candidates_per_step=cands, collisions_per_step=real,
                    achieved_GBps=round(coll_bytes / max(coll_avg_s, 1e-12) / 1e9, 1),
-                   alg_bytes_rule="%d B per candidate" % COLLIDE_BYTES[sch])
+                   alg_bytes_rule=" and ".join(
+                       "%s: %d B per candidate + %d B per real collision"
+                       % (("explicit", "implicit")[sc], COLLIDE_BYTES[sc], COLLISION_BYTES[sc])
+                       for sc in sorted(set(schemes))))
     roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
 
     out = dict(metric="particle-steps/sec (push+deposit+MCC) vs plain FP64 GPU form at "
@@ -210,14 +240,16 @@ def main():
                config=dict(workload=args.workload, cases=len(wls),
                            cells=[w["case"]["n_cells"] for w in wls][:4],
                            particles=int(particles), tile=tile, sort_every=sort_every,
-                           scheme="implicit" if implicit else "explicit"),
+                           scheme=("explicit", "implicit", "mixed")[
+                               2 if groups == 2 else schemes[0]],
+                           graph=args.graph, timing_every=args.timing_every),
                roofline=roof, collide=collide)
-    if args.fp64_steps > 0 and not implicit:
+    if args.fp64_steps > 0 and all(sc == 0 for sc in schemes):
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
         ctx.fp64_init()
         ctx.fp64_step(2)
-        n64 = live()
+        n64 = sum(live_per_case())
         t0 = time.perf_counter()
         ctx.fp64_step(args.fp64_steps)
         t1 = time.perf_counter()
@@ -228,7 +260,9 @@ def main():
         out["speedup_vs_fp64_form"] = value / v64
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(
+            wls[0], args.cpu_seconds,
+            where="the same discharge" if len(wls) == 1 else "case 0 of the batch")
     ctx.close()
     print(json.dumps(out), flush=True)
 

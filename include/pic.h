@@ -213,7 +213,8 @@ typedef struct pic_ctx pic_ctx;
 
 /* Creates a context holding n_cases discharges.  species points to
  * 2*n_cases entries: [case][0 = electrons, 1 = ions].  hip_stream is a
- * hipStream_t (NULL = the default stream).  Validation: N range, dt > 0,
+ * hipStream_t that every launch goes to (NULL = a non-blocking stream that
+ * the context creates and destroys).  Validation: N range, dt > 0,
  * positions in range, ids present, tables consistent, capacity >= n, and for
  * explicit cases omega_p,max dt < 2 (Eq. (1)) unless PIC_FLAG_ALLOW_UNSTABLE.
  * On error *out is NULL and nothing is leaked. */
@@ -238,6 +239,24 @@ int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what_mask, pic_diag*
  * samples of density, heating and EEDF (0 = off).  tile: particles per
  * workgroup (multiple of 256, <= 32768; 0 = keep). */
 int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_every, int32_t tile);
+/* Launch mode and kernel timing.  In both modes all cases of a scheme share
+ * every launch.
+ * graph = 0: every kernel is launched from the host.
+ * graph = 1: one sort period (sort_every consecutive steps and the compaction
+ *   that ends it) is captured into a HIP graph on first use and replayed
+ *   whenever a call's remaining steps cover a whole period that starts at a
+ *   period boundary; the other steps are launched from the host.  Steps with
+ *   diagnostics samples (diag_every > 0), and periods longer than 1024 steps,
+ *   are always launched from the host.  The graph is captured again after
+ *   pic_set_schedule or pic_set_launch.  Requires a context stream other than
+ *   the null stream (else PIC_E_INVAL).  Results are identical in both modes.
+ * timing_every: HIP events bracket the particle and collision kernels of the
+ *   steps whose index within the sort period is a multiple of timing_every
+ *   (0 = no events; default 1).  Events recorded inside a replayed graph give
+ *   the durations of the call's last replay; pic_last_timing* report the sum
+ *   and count of the timed launches.
+ * Errors: PIC_E_INVAL (bad values), PIC_E_STATE (failed context). */
+int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every);
 /* Zero the density, heating and EEDF accumulators of every case. */
 int pic_reset_accumulators(pic_ctx* ctx);
 
@@ -262,8 +281,8 @@ int pic_copy_calibration(int64_t bytes, int32_t reps, double* ms_per_copy);
 void pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);
 /* Timing of the most recent pic_step* call: milliseconds of device time
- * spent in the particle kernel (HIP events on the context's stream) and the
- * number of particle-kernel launches it made. */
+ * spent in the timed launches of the particle kernel (HIP events on the
+ * context's stream, see pic_set_launch) and the number of launches timed. */
 int pic_last_timing(const pic_ctx* ctx, double* particle_kernel_ms, int64_t* launches);
 /* The same for the collision kernel that follows each particle pass (the
  * null-collision MCC of the candidates the pass listed). */

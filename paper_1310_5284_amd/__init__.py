@@ -115,6 +115,7 @@ def lib():
         L.pic_step.argtypes = [_P, C.c_int64]
         L.pic_diagnostics.argtypes = [_P, C.c_int32, C.c_uint32, C.POINTER(Diag)]
         L.pic_set_schedule.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
+        L.pic_set_launch.argtypes = [_P, C.c_int32, C.c_int32]
         L.pic_reset_accumulators.argtypes = [_P]
         L.pic_fp64_reference_init.argtypes = [_P]
         L.pic_fp64_reference_step.argtypes = [_P, C.c_int64]
@@ -240,6 +241,12 @@ class PicContext:
     def set_schedule(self, sort_every=64, diag_every=0, tile=0):
         self._check(lib().pic_set_schedule(self._h, sort_every, diag_every, tile),
                     "pic_set_schedule")
+
+    def set_launch(self, graph=0, timing_every=1):
+        """Host launches (graph=0) or replay of a captured sort period
+        (graph=1); HIP-event timing of every timing_every-th step."""
+        self._check(lib().pic_set_launch(self._h, int(graph), int(timing_every)),
+                    "pic_set_launch")
 
     def reset_accumulators(self):
         self._check(lib().pic_reset_accumulators(self._h), "pic_reset_accumulators")

@@ -347,6 +347,15 @@ struct Child {
     uint64_t ide, idi;
 };
 
+// An ionization queued by k_collide: the parent's slot, x_{n+1} (cell; the
+// offset for implicit lists) and the pair it creates.
+struct ChildEv {
+    int32_t parent, cell;
+    float off, pad;
+    Child ch;
+};
+constexpr int kChildQ = 128;   // queued ionizations per k_collide workgroup
+
 __device__ __forceinline__ int collide_electron(const Species& S, const float* bound, uint4 r0,
                                                 uint64_t id, uint32_t step, uint32_t k0,
                                                 uint32_t k1, float& vx, float& vy, float& vz,
@@ -789,7 +798,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
 // candidate per thread.  A candidate whose capped wait ran out first draws
 // its trial; a candidate draws its next waiting time, the process (u1 of
 // draw 0 against the cumulative n_g sigma_k v / nu_max) and the scattering;
-// ionizations append an electron and an ion.  Implicit candidates then
+// ionizations are queued in LDS and append their electron and ion after the
+// loop.  Implicit candidates then
 // predict, are absorbed or deposit (privatised LDS grid).  The collision
 // terms of the ledger are added to the row of the same workgroup.
 // ---------------------------------------------------------------------------
@@ -809,6 +819,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockAcc acc;
     __shared__ Species S;
+    __shared__ ChildEv cq[kChildQ];
+    __shared__ int q_n;
     constexpr bool kImp = SCHEME == 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Work w = P.work[gblk];
@@ -856,6 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         acc.n_lost[0] = acc.n_lost[1] = 0u;
         acc.cmin = kNoCell;
         acc.cmax = -1;
+        q_n = 0;
     }
     lds_barrier();
 
@@ -877,7 +890,78 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         stg(cellp, (uint32_t)i << 2, -1);
     };
 
+    // ionization children: electron and ion at the parent's x_{n+1};
+    // implicit children are predicted from there with abar = 0; their
+    // deposits are rare and go straight to the case grids.  Called by whole
+    // wavefronts; lanes with ion_ev set emit one pair each.
+    auto emit_children = [&](bool ion_ev, int c1, float o1, const Child& ch) {
+        bool want_e = false, want_i = false;
+        int ce = c1, ci = c1;
+        float oe = o1, oi = o1;
+        if (ion_ev) {
+            const float ke = ch.vx * ch.vx + ch.vy * ch.vy + ch.vz * ch.vz;
+            const float ki = ch.ix * ch.ix + ch.iy * ch.iy + ch.iz * ch.iz;
+            cdk += (double)ke;
+            atomicAdd(&acc.other_dK, (double)ki);
+            atomicAdd(&acc.n_created[0], 1u);
+            atomicAdd(&acc.n_created[1], 1u);
+            want_e = want_i = true;
+            if (kImp) {
+                oe = o1 + ch.vx;
+                renorm(ce, oe);
+                oi = o1 + ch.ix;
+                renorm(ci, oi);
+                if (periodic) {
+                    ce %= N; if (ce < 0) ce += N;
+                    ci %= N; if (ci < 0) ci += N;
+                } else {
+                    if (ce < 0 || ce >= N) {
+                        want_e = false;
+                        const int eo = ce < 0 ? 0 : 1;
+                        atomicAdd(&acc.absK[0][eo], (double)ke);
+                        atomicAdd(&acc.abs_n[0][eo], 1u);
+                    }
+                    if (ci < 0 || ci >= N) {
+                        want_i = false;
+                        const int eo = ci < 0 ? 0 : 1;
+                        atomicAdd(&acc.absK[1][eo], (double)ki);
+                        atomicAdd(&acc.abs_n[1][eo], 1u);
+                    }
+                }
+            }
+        }
+        const long long se = reserve_slot(want_e, gp(&st->n_child[0]), ns0, cap0);
+        const long long si = reserve_slot(want_i, gp(&st->n_child[1]), ns1, cap1);
+        if (want_e) {
+            if (se >= 0) {
+                // first trial of a child at the next step: draw 4 of its stream
+                const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
+                                        4u, k0, k1);
+                write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
+                               wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
+                gatomic_add(gp(&C->dep_cnt[0][ce]), 1ull);
+                gatomic_add(gp(&C->dep_w[0][ce]), packw(oe) & kWMask);
+            } else {
+                atomicAdd(&acc.n_lost[0], 1u);
+            }
+        }
+        if (want_i) {
+            if (si >= 0) {
+                const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
+                                        (1u << 28) | 4u, k0, k1);
+                write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
+                               wait_encode(geo0(r4.x, inv_ion)), kImp);
+                gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
+                gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
+            } else {
+                atomicAdd(&acc.n_lost[1], 1u);
+            }
+        }
+    };
+
     // this round, and for the last round all candidates beyond the estimate
+    // (loading several candidates per thread ahead of their processing
+    // measured slower: the loads are scattered, not latency-bound)
     const int e_step = cw.round == cw.rounds - 1 ? kBlock : ncand;
     for (int e0 = cw.round * kBlock; e0 < ncand; e0 += e_step) {
         const int e = e0 + tid;
@@ -971,76 +1055,48 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             }
         }
         if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
-        // ionization children: electron and ion at the parent's x_{n+1};
-        // implicit children are predicted from there with abar = 0; their
-        // deposits are rare and go straight to the case grids
+        // ionization children: queued in LDS and written after the loop, so
+        // that a workgroup pays the latency of the slot reservation once;
+        // events beyond the queue are handled here
         const bool ion_ev = act && kind == PIC_IONIZATION && s == 0;
-        if (__ballot(ion_ev)) {
-            // explicit lists carry no offset: read it for the rare ionizations
-            if (!kImp && ion_ev) o1 = ldg(offp, (uint32_t)i << 2);
-            bool want_e = false, want_i = false;
-            int ce = c1, ci = c1;
-            float oe = o1, oi = o1;
-            if (ion_ev) {
-                const float ke = ch.vx * ch.vx + ch.vy * ch.vy + ch.vz * ch.vz;
-                const float ki = ch.ix * ch.ix + ch.iy * ch.iy + ch.iz * ch.iz;
-                cdk += (double)ke;
-                atomicAdd(&acc.other_dK, (double)ki);
-                atomicAdd(&acc.n_created[0], 1u);
-                atomicAdd(&acc.n_created[1], 1u);
-                want_e = want_i = true;
-                if (kImp) {
-                    oe = o1 + ch.vx;
-                    renorm(ce, oe);
-                    oi = o1 + ch.ix;
-                    renorm(ci, oi);
-                    if (periodic) {
-                        ce %= N; if (ce < 0) ce += N;
-                        ci %= N; if (ci < 0) ci += N;
-                    } else {
-                        if (ce < 0 || ce >= N) {
-                            want_e = false;
-                            const int eo = ce < 0 ? 0 : 1;
-                            atomicAdd(&acc.absK[0][eo], (double)ke);
-                            atomicAdd(&acc.abs_n[0][eo], 1u);
-                        }
-                        if (ci < 0 || ci >= N) {
-                            want_i = false;
-                            const int eo = ci < 0 ? 0 : 1;
-                            atomicAdd(&acc.absK[1][eo], (double)ki);
-                            atomicAdd(&acc.abs_n[1][eo], 1u);
-                        }
-                    }
-                }
+        const unsigned long long im = __ballot(ion_ev);
+        if (im) {
+            const int leader = __ffsll((long long)im) - 1;
+            int qb = 0;
+            if (lane == leader) qb = atomicAdd(&q_n, (int)__popcll(im));
+            qb = __shfl(qb, leader, 64);
+            const int pos = qb + __popcll(im & ((1ull << lane) - 1ull));
+            const bool queued = ion_ev && pos < kChildQ;
+            if (queued) {
+                ChildEv& q = cq[pos];
+                q.parent = i;
+                q.cell = c1;
+                q.off = o1;
+                q.ch = ch;
             }
-            const long long se = reserve_slot(want_e, gp(&st->n_child[0]), ns0, cap0);
-            const long long si = reserve_slot(want_i, gp(&st->n_child[1]), ns1, cap1);
-            if (want_e) {
-                if (se >= 0) {
-                    // first trial of a child at the next step: draw 4 of its stream
-                    const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
-                                            4u, k0, k1);
-                    write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
-                                   wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
-                    gatomic_add(gp(&C->dep_cnt[0][ce]), 1ull);
-                    gatomic_add(gp(&C->dep_w[0][ce]), packw(oe) & kWMask);
-                } else {
-                    atomicAdd(&acc.n_lost[0], 1u);
-                }
-            }
-            if (want_i) {
-                if (si >= 0) {
-                    const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
-                                            (1u << 28) | 4u, k0, k1);
-                    write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
-                                   wait_encode(geo0(r4.x, inv_ion)), kImp);
-                    gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
-                    gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
-                } else {
-                    atomicAdd(&acc.n_lost[1], 1u);
-                }
+            const bool now = ion_ev && !queued;
+            if (__ballot(now)) {
+                // explicit lists carry no offset: read it for the rare ionizations
+                if (!kImp && now) o1 = ldg(offp, (uint32_t)i << 2);
+                emit_children(now, c1, o1, ch);
             }
         }
+    }
+    // the queued ionizations: one event per thread
+    lds_barrier();
+    {
+        const int nq = min(q_n, kChildQ);
+        const bool ev = tid < nq;
+        int c1 = 0;
+        float o1 = 0.0f;
+        Child ch{};
+        if (ev) {
+            const ChildEv& q = cq[tid];
+            c1 = q.cell;
+            o1 = kImp ? q.off : ldg(offp, (uint32_t)q.parent << 2);
+            ch = q.ch;
+        }
+        if (__ballot(ev)) emit_children(ev, c1, o1, ch);
     }
 
     // flush the deposit of the implicit candidates and the EEDF counts

@@ -61,6 +61,23 @@ struct HostCase {
 
 struct FP64Ref;  // plain FP64 GPU form (pic_fp64.hip)
 
+// Timing events around the particle and collision kernels: pairs (start,
+// stop) in launch order, with the kernel each pair brackets.
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;          // 0: k_step, 1: k_collide
+    int used = 0;
+};
+
+// One sort period (sort_every steps and the compaction after them) captured
+// into a HIP graph.  Its timing events are recorded by event nodes, so after
+// several replays they hold the last replay's times.
+struct PeriodGraph {
+    hipGraphExec_t exec = nullptr;
+    EventPool ev;
+    int period = 0;
+};
+
 }  // namespace
 
 struct pic_ctx {
@@ -93,14 +110,14 @@ struct pic_ctx {
     int diag_every = 0;
     int64_t since_sort = 0;
     int64_t steps_taken = 0;
-    std::vector<hipEvent_t> ev;
-    int ev_used = 0;
+    EventPool ev;                  // events of host-launched steps
     double last_ms = 0.0;
     int64_t last_launches = 0;
     double last_ms_coll = 0.0;
     int64_t last_launches_coll = 0;
-    std::vector<int> ev_kind;      // 0: k_step, 1: k_collide
-    bool timing = true;
+    int timing_every = 1;          // steps between timed steps (0: none)
+    bool use_graph = false;
+    PeriodGraph graph;             // one sort period, captured on first use
     void* fp64 = nullptr;          // FP64 reference form (pic_fp64.hip)
     std::vector<void*> allocs;     // context-level allocations
     std::vector<std::vector<double>> sigma[2];   // float64 copy of the input tables
@@ -321,6 +338,7 @@ int set_lds_limits(pic_ctx* c, size_t need)
 }
 
 void destroy_ctx(pic_ctx* c);
+void drop_graph(pic_ctx* c);
 
 }  // namespace
 
@@ -719,7 +737,9 @@ void destroy_ctx(pic_ctx* c)
     if (c->d_pu) (void)hipFree(c->d_pu);
     if (c->d_cand_n) (void)hipFree(c->d_cand_n);
     if (c->d_cwork) (void)hipFree(c->d_cwork);
-    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    drop_graph(c);
+    for (hipEvent_t e : c->ev.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->graph.ev.ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -736,6 +756,125 @@ int check_flags(pic_ctx* c)
     return rc;
 }
 
+// Longest sort period captured into one graph (a graph holds 3-5 nodes per step).
+constexpr int kMaxGraphPeriod = 1024;
+
+// Make sure the pool holds at least `pairs` event pairs.
+int reserve_events(pic_ctx* c, EventPool& pool, int pairs)
+{
+    while ((int)pool.ev.size() < 2 * pairs) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        pool.ev.push_back(e);
+    }
+    return PIC_OK;
+}
+
+// The launches of one step on the context's stream: per scheme group the
+// particle pass and the collision kernel, then the finalizer of every case;
+// the compaction follows when the sort period ends.  With `pool`, HIP events
+// bracket the particle and collision kernels (as event nodes under capture).
+int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
+{
+    auto record = [&](hipEvent_t e) {
+        return capturing ? hipEventRecordWithFlags(e, c->stream, hipEventRecordExternal)
+                         : hipEventRecord(e, c->stream);
+    };
+    for (int g = 0; g < 2; ++g) {
+        if (!c->grp_cnt[g]) continue;
+        Params p = params(c, c->grp_off[g]);
+        Params pc = params(c, c->cgrp_off[g]);
+        const int N = c->grp_maxN[g];
+        auto ks = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
+                         : (diag ? k_step<1, true> : k_step<1, false>);
+        auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
+                         : (diag ? k_collide<1, true> : k_collide<1, false>);
+        for (int kind = 0; kind < 2; ++kind) {
+            if (kind == 1 && !c->cgrp_cnt[g]) continue;
+            const bool rec = pool && pool->used + 2 <= (int)pool->ev.size();
+            if (rec) HIPCHK(c, record(pool->ev[pool->used]));
+            if (kind == 0)
+                hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock), step_lds(N, diag),
+                                   c->stream, p);
+            else
+                hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
+                                   collide_lds_bytes(N), c->stream, pc);
+            if (rec) {
+                HIPCHK(c, record(pool->ev[pool->used + 1]));
+                pool->used += 2;
+                pool->kind.push_back(kind);
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock),
+                       16 * ((size_t)c->maxN + 1) + 16, c->stream, params(c, 0), diag ? 1 : 0);
+    HIPCHK(c, hipGetLastError());
+    if (++c->since_sort >= c->sort_every)
+        if (compaction(c)) return PIC_E_DEVICE;
+    return PIC_OK;
+}
+
+bool timed_step(const pic_ctx* c, int64_t step)
+{
+    return c->timing_every > 0 && step % c->timing_every == 0;
+}
+
+void drop_graph(pic_ctx* c)
+{
+    if (c->graph.exec) {
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->graph.exec);
+    }
+    c->graph.exec = nullptr;
+    c->graph.period = 0;
+}
+
+// Capture one sort period, starting at a period boundary, into c->graph.
+int capture_period(pic_ctx* c)
+{
+    drop_graph(c);
+    int timed = 0;
+    for (int j = 0; j < c->sort_every; ++j) timed += timed_step(c, j) ? 1 : 0;
+    if (reserve_events(c, c->graph.ev, 4 * timed)) return PIC_E_DEVICE;
+    c->graph.ev.used = 0;
+    c->graph.ev.kind.clear();
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = PIC_OK;
+    const int64_t since0 = c->since_sort;
+    for (int j = 0; j < c->sort_every && rc == PIC_OK; ++j)
+        rc = enqueue_step(c, false, timed_step(c, j) ? &c->graph.ev : nullptr, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->since_sort = since0;
+    if (rc != PIC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, PIC_E_DEVICE, std::string("hipStreamEndCapture: ") +
+                                             hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&c->graph.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        c->graph.exec = nullptr;
+        return fail(c, PIC_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    c->graph.period = c->sort_every;
+    return PIC_OK;
+}
+
+// Sum the elapsed times of the pool's event pairs by kernel kind.
+void add_times(const EventPool& pool, double ms[2], int64_t launches[2])
+{
+    for (int e = 0; e + 1 < pool.used; e += 2) {
+        float t = 0.0f;
+        const int kind = pool.kind[e / 2];
+        if (hipEventElapsedTime(&t, pool.ev[e], pool.ev[e + 1]) == hipSuccess) {
+            ms[kind] += t;
+            launches[kind]++;
+        }
+    }
+}
+
 int run_steps(pic_ctx* c, int64_t n, int which)
 {
     if (c->failed) return fail(c, PIC_E_STATE, "context failed earlier: " + c->err);
@@ -743,59 +882,38 @@ int run_steps(pic_ctx* c, int64_t n, int which)
     for (int k = 0; k < c->n_cases; ++k)
         if (which >= 0 && c->hc[k].cfg.scheme != which)
             return fail(c, PIC_E_INVAL, "a case of the context uses the other scheme");
-    int needed = 0;
-    for (int g = 0; g < 2; ++g) needed += c->grp_cnt[g] ? 4 : 0;
-    needed *= (int)std::min<int64_t>(n, 1 << 20);
-    while ((int)c->ev.size() < needed) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->ev.push_back(e);
-    }
-    c->ev_used = 0;
-    c->ev_kind.clear();
-    for (int64_t it = 0; it < n; ++it) {
-        const bool diag = c->diag_every > 0 && (c->steps_taken % c->diag_every == 0);
-        for (int g = 0; g < 2; ++g) {
-            if (!c->grp_cnt[g]) continue;
-            Params p = params(c, c->grp_off[g]);
-            Params pc = params(c, c->cgrp_off[g]);
-            const int N = c->grp_maxN[g];
-            auto ks = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
-                             : (diag ? k_step<1, true> : k_step<1, false>);
-            auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
-                             : (diag ? k_collide<1, true> : k_collide<1, false>);
-            for (int kind = 0; kind < 2; ++kind) {
-                const bool rec = c->timing && c->ev_used + 2 <= (int)c->ev.size();
-                if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
-                if (kind == 0)
-                    hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock), step_lds(N, diag),
-                                       c->stream, p);
-                else if (c->cgrp_cnt[g])
-                    hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
-                                       collide_lds_bytes(N), c->stream, pc);
-                if (rec) {
-                    (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
-                    c->ev_used += 2;
-                    c->ev_kind.push_back(kind);
-                }
-            }
+    const bool graphs = c->use_graph && c->diag_every == 0 && c->sort_every <= kMaxGraphPeriod;
+    // host-launched steps: at most one partial period at each end when graphs are used
+    int64_t host_steps = graphs ? std::min<int64_t>(n, 2 * (int64_t)c->sort_every) : n;
+    int64_t timed = 0;
+    if (c->timing_every > 0) timed = host_steps / c->timing_every + 1;
+    // up to two timed kernels per scheme group and step
+    if (reserve_events(c, c->ev, (int)std::min<int64_t>(4 * timed, 1 << 20))) return PIC_E_DEVICE;
+    c->ev.used = 0;
+    c->ev.kind.clear();
+    int64_t replays = 0;
+    for (int64_t it = 0; it < n;) {
+        if (graphs && c->since_sort == 0 && n - it >= c->sort_every) {
+            if (c->graph.period != c->sort_every || !c->graph.exec)
+                if (capture_period(c)) return PIC_E_DEVICE;
+            HIPCHK(c, hipGraphLaunch(c->graph.exec, c->stream));
+            c->steps_taken += c->sort_every;
+            it += c->sort_every;
+            ++replays;
+            continue;
         }
-        hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock),
-                           16 * ((size_t)c->maxN + 1) + 16, c->stream, params(c, 0), diag ? 1 : 0);
-        HIPCHK(c, hipGetLastError());
+        const bool diag = c->diag_every > 0 && (c->steps_taken % c->diag_every == 0);
+        // the step index within the period decides timing, as in a captured period
+        if (enqueue_step(c, diag, timed_step(c, c->since_sort) ? &c->ev : nullptr, false))
+            return PIC_E_DEVICE;
         c->steps_taken++;
-        if (++c->since_sort >= c->sort_every)
-            if (compaction(c)) return PIC_E_DEVICE;
+        ++it;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double ms[2] = {0.0, 0.0};
     int64_t launches[2] = {0, 0};
-    for (int e = 0; e + 1 < c->ev_used; e += 2) {
-        float t = 0.0f;
-        const int kind = c->ev_kind[e / 2];
-        if (hipEventElapsedTime(&t, c->ev[e], c->ev[e + 1]) == hipSuccess) ms[kind] += t;
-        launches[kind]++;
-    }
+    add_times(c->ev, ms, launches);
+    if (replays > 0) add_times(c->graph.ev, ms, launches);
     c->last_ms = ms[0];
     c->last_launches = launches[0];
     c->last_ms_coll = ms[1];
@@ -845,6 +963,7 @@ extern "C" int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_e
     if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
     if (sort_every < 1 || diag_every < 0 || tile < 0 || (tile > 0 && (tile % kBlock || tile > kMaxTile + 1)))
         return fail(ctx, PIC_E_INVAL, "bad schedule");
+    drop_graph(ctx);   // the captured period holds the old schedule's launches
     ctx->sort_every = sort_every;
     ctx->diag_every = diag_every;
     if (tile > 0 && tile != ctx->tile) {
@@ -858,6 +977,20 @@ extern "C" int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_e
         HIPCHK(ctx, hipMemcpy(ctx->d_cases, ctx->cases_h.data(), sizeof(Case) * ctx->n_cases,
                               hipMemcpyHostToDevice));
     }
+    return PIC_OK;
+}
+
+extern "C" int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
+    if ((graph != 0 && graph != 1) || timing_every < 0)
+        return fail(ctx, PIC_E_INVAL, "bad launch mode");
+    if (graph && !ctx->stream)
+        return fail(ctx, PIC_E_INVAL, "graph replay needs a stream other than the null stream");
+    drop_graph(ctx);
+    ctx->use_graph = graph == 1;
+    ctx->timing_every = timing_every;
     return PIC_OK;
 }
 

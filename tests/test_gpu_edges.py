@@ -160,3 +160,38 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(P().PicError) as ei:
         ctx.step_implicit(1)                  # explicit case
     assert ei.value.code == P().PIC_E_INVAL
+
+
+@pytest.mark.parametrize("timing_every", [0, 1, 3])
+def test_graph_replay_equals_host_launches(timing_every):
+    # a mixed batch (explicit + implicit case) stepped with every kernel
+    # launched from the host, and again with whole sort periods replayed from
+    # a captured graph; calls that start and end inside a period mix both
+    wls = [W.c1(collisions=1, np_per_species=6144, scheme=0),
+           W.c1(collisions=1, np_per_species=4096, scheme=1)]
+    outs = []
+    for graph in (0, 1):
+        ctx = P().PicContext(wls)
+        ctx.set_schedule(sort_every=7, diag_every=0, tile=1024)
+        ctx.set_launch(graph=graph, timing_every=timing_every)
+        for n in (3, 25, 2, 30):
+            ctx.step(n)
+            ms, launches = ctx.last_timing()
+            assert (launches > 0) == (timing_every > 0)
+            assert ms >= 0.0
+        outs.append([(sorted_state(ctx, k), ctx.fields(k)) for k in range(2)])
+        ctx.close()
+    for (s1, f1), (s2, f2) in zip(*outs):
+        for a, b in zip(s1, s2):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
+        for k in ("rho", "phi", "E"):
+            assert np.array_equal(f1[k], f2[k]), k
+
+
+def test_launch_mode_rejects_bad_values():
+    ctx = ctx_for(W.c1(collisions=0, np_per_species=1024))
+    for g, t in ((2, 1), (-1, 1), (0, -1)):
+        with pytest.raises(P().PicError):
+            ctx.set_launch(graph=g, timing_every=t)
+    ctx.close()

@@ -51,3 +51,36 @@ def test_ccp256_implicit_teacher_forced(wdt, steps):
     rep = teacher_forced(ctx, wl, steps)
     print(rep)
     assert_report(rep)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_ionizing_beam_teacher_forced(scheme):
+    # 100 eV isotropic electrons in dense gas: every electron is a candidate
+    # in every step and about 5 % of them ionize, i.e. more ionizations per
+    # collision workgroup than its LDS queue holds, so both the queued and
+    # the immediate child paths run
+    wl = W.c1(collisions=1, np_per_species=8192 + 33, scheme=scheme)
+    wl["case"]["gas_density_m3"] = W.gas_density(1000.0)
+    e = wl["species"][0]
+    n = e["cell"].size
+    rng = np.random.Generator(np.random.PCG64(0xBEA))
+    v = math.sqrt(2.0 * 100.0 * 1.602176634e-19 / 9.1093837015e-31)
+    mu = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * math.pi, n)
+    sn = np.sqrt(1.0 - mu * mu)
+    e["vx"] = (v * mu).astype(np.float32)
+    e["vy"] = (v * sn * np.cos(ph)).astype(np.float32)
+    e["vz"] = (v * sn * np.sin(ph)).astype(np.float32)
+    for sp in wl["species"]:
+        sp["capacity"] = 3 * sp["cell"].size // 2
+    tile = 8192
+    n_wg = -(-wl["species"][0]["capacity"] // tile)   # electron workgroups
+    probe = ctx_for(wl, tile=tile)
+    probe.step(1)
+    n_ion = int(probe.ledger()["n_coll"][0][2])
+    probe.close()
+    assert n_ion > 128 * n_wg, (n_ion, n_wg)   # so one workgroup holds > 128
+    ctx = ctx_for(wl, tile=tile)
+    rep = teacher_forced(ctx, wl, 8)
+    print(n_ion, rep)
+    assert_report(rep)
