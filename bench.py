@@ -230,6 +230,7 @@ def main():
                        % (("explicit", "implicit")[sc], COLLIDE_BYTES[sc], COLLISION_BYTES[sc])
                        for sc in sorted(set(schemes))))
     roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+    collide["traffic"] = measured_traffic(args.workload, collide["kernel"])
 
     out = dict(metric="particle-steps/sec (push+deposit+MCC) vs plain FP64 GPU form at "
                       "matched EEDF",
