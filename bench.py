@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--tile", type=int, default=0, help="particles per workgroup (default 16384)")
     ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=32, metavar="STEPS",
+                    help="steps per autotuning trial of tile and sort period (0: off; "
+                         "off when --tile or --sort-every is given)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="replay whole sort periods from a captured HIP graph")
     ap.add_argument("--timing-every", type=int, default=8,
@@ -164,6 +167,15 @@ def main():
     tile = args.tile or 16384
     sort_every = args.sort_every or 64
     ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+    tuned = None
+    if args.autotune and not (args.tile or args.sort_every):
+        # the autotuner's trials are real steps before the warm-up
+        tile, sort_every, ms = ctx.autotune(steps_per_trial=args.autotune)
+        tiles, sorts = (1024, 2048, 4096, 8192, 16384, 32512), (16, 32, 64, 128)
+        tuned = dict(steps_per_trial=args.autotune,
+                     tile_ms_per_step={str(t): round(m, 4) for t, m in zip(tiles, ms[:6])},
+                     sort_ms_per_step={str(t): round(m, 4) for t, m in zip(sorts, ms[6:])})
+        log(f"[bench] autotune: tile {tile}, sort every {sort_every}")
     ctx.set_launch(graph=args.graph, timing_every=args.timing_every)
     schemes = [int(w["case"]["scheme"]) for w in wls]
     implicit = all(sc == 1 for sc in schemes)
@@ -245,6 +257,8 @@ def main():
                                2 if groups == 2 else schemes[0]],
                            graph=args.graph, timing_every=args.timing_every),
                roofline=roof, collide=collide)
+    if tuned:
+        out["autotune"] = tuned
     if args.fp64_steps > 0 and all(sc == 0 for sc in schemes):
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")

@@ -257,6 +257,24 @@ int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_every, int32
  *   and count of the timed launches.
  * Errors: PIC_E_INVAL (bad values), PIC_E_STATE (failed context). */
 int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every);
+/* Autotuner of the launch schedule.  Runs real steps of the context (they
+ * advance every case exactly as pic_step does, diagnostics cadence
+ * included): first `steps_per_trial` steps at each tile of
+ * tiles[0..n_tiles) at the current sort period, then whole sort periods
+ * (at least steps_per_trial steps, from a period boundary) at each period of
+ * sorts[0..n_sorts) with the fastest tile.  Each trial is timed by two HIP
+ * events around its launches on the context's stream and follows two
+ * untimed steps at the new tile.  The fastest tile and period are applied
+ * (pic_set_schedule) and returned in tile_out / sort_out (may be NULL).
+ * ms_out (NULL or n_tiles + n_sorts entries, resp. of the defaults) receives
+ * the device milliseconds per step of every trial.
+ * tiles == NULL: {1024, 2048, 4096, 8192, 16384, 32512}; sorts == NULL:
+ * {16, 32, 64, 128} (the counts are then ignored).  Tiles must be positive
+ * multiples of 256 up to 32512, periods positive.
+ * Errors: PIC_E_INVAL (bad candidates), those of pic_step. */
+int pic_autotune(pic_ctx* ctx, const int32_t* tiles, int32_t n_tiles, const int32_t* sorts,
+                 int32_t n_sorts, int32_t steps_per_trial, int32_t* tile_out,
+                 int32_t* sort_out, double* ms_out);
 /* Zero the density, heating and EEDF accumulators of every case. */
 int pic_reset_accumulators(pic_ctx* ctx);
 

@@ -116,6 +116,9 @@ def lib():
         L.pic_diagnostics.argtypes = [_P, C.c_int32, C.c_uint32, C.POINTER(Diag)]
         L.pic_set_schedule.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
         L.pic_set_launch.argtypes = [_P, C.c_int32, C.c_int32]
+        L.pic_autotune.argtypes = [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
+                                   C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), _D]
         L.pic_reset_accumulators.argtypes = [_P]
         L.pic_fp64_reference_init.argtypes = [_P]
         L.pic_fp64_reference_step.argtypes = [_P, C.c_int64]
@@ -247,6 +250,20 @@ class PicContext:
         (graph=1); HIP-event timing of every timing_every-th step."""
         self._check(lib().pic_set_launch(self._h, int(graph), int(timing_every)),
                     "pic_set_launch")
+
+    def autotune(self, tiles=None, sorts=None, steps_per_trial=32):
+        """Pick the fastest tile and sort period by timing real steps
+        (pic_autotune); returns (tile, sort_every, ms per step of each trial)."""
+        def arr(v):
+            return (None, 0) if v is None else ((C.c_int32 * len(v))(*v), len(v))
+        t, nt = arr(tiles)
+        so, ns = arr(sorts)
+        n_ms = (nt if tiles is not None else 6) + (ns if sorts is not None else 4)
+        ms = (C.c_double * n_ms)()
+        tile, sort = C.c_int32(0), C.c_int32(0)
+        self._check(lib().pic_autotune(self._h, t, nt, so, ns, int(steps_per_trial),
+                                       C.byref(tile), C.byref(sort), ms), "pic_autotune")
+        return tile.value, sort.value, list(ms)
 
     def reset_accumulators(self):
         self._check(lib().pic_reset_accumulators(self._h), "pic_reset_accumulators")

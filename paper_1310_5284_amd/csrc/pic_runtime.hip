@@ -875,7 +875,9 @@ void add_times(const EventPool& pool, double ms[2], int64_t launches[2])
     }
 }
 
-int run_steps(pic_ctx* c, int64_t n, int which)
+// Advance n steps.  With `bracket`, events bracket the whole enqueued
+// sequence on the stream (used to time autotuning trials).
+int run_steps(pic_ctx* c, int64_t n, int which, hipEvent_t* bracket = nullptr)
 {
     if (c->failed) return fail(c, PIC_E_STATE, "context failed earlier: " + c->err);
     if (n < 0) return fail(c, PIC_E_INVAL, "negative step count");
@@ -892,6 +894,7 @@ int run_steps(pic_ctx* c, int64_t n, int which)
     c->ev.used = 0;
     c->ev.kind.clear();
     int64_t replays = 0;
+    if (bracket) HIPCHK(c, hipEventRecord(bracket[0], c->stream));
     for (int64_t it = 0; it < n;) {
         if (graphs && c->since_sort == 0 && n - it >= c->sort_every) {
             if (c->graph.period != c->sort_every || !c->graph.exec)
@@ -909,6 +912,7 @@ int run_steps(pic_ctx* c, int64_t n, int which)
         c->steps_taken++;
         ++it;
     }
+    if (bracket) HIPCHK(c, hipEventRecord(bracket[1], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double ms[2] = {0.0, 0.0};
     int64_t launches[2] = {0, 0};
@@ -991,6 +995,100 @@ extern "C" int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every)
     drop_graph(ctx);
     ctx->use_graph = graph == 1;
     ctx->timing_every = timing_every;
+    return PIC_OK;
+}
+
+namespace {
+
+// Device milliseconds per step of `steps` real steps at the current schedule,
+// after `warm` untimed steps.
+int timed_trial(pic_ctx* c, int warm, int64_t steps, hipEvent_t* ev, double* ms_per_step)
+{
+    if (warm > 0) {
+        const int r = run_steps(c, warm, -1);
+        if (r) return r;
+    }
+    const int rc = run_steps(c, steps, -1, ev);
+    if (rc) return rc;
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *ms_per_step = (double)ms / (double)steps;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" int pic_autotune(pic_ctx* ctx, const int32_t* tiles, int32_t n_tiles,
+                            const int32_t* sorts, int32_t n_sorts, int32_t steps_per_trial,
+                            int32_t* tile_out, int32_t* sort_out, double* ms_out)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
+    static const int32_t kTiles[] = {1024, 2048, 4096, 8192, 16384, 32512};
+    static const int32_t kSorts[] = {16, 32, 64, 128};
+    if (!tiles) {
+        tiles = kTiles;
+        n_tiles = (int32_t)(sizeof(kTiles) / sizeof(kTiles[0]));
+    }
+    if (!sorts) {
+        sorts = kSorts;
+        n_sorts = (int32_t)(sizeof(kSorts) / sizeof(kSorts[0]));
+    }
+    if (n_tiles < 1 || n_sorts < 1 || steps_per_trial < 1)
+        return fail(ctx, PIC_E_INVAL, "autotune: empty candidate list or no steps");
+    for (int j = 0; j < n_tiles; ++j)
+        if (tiles[j] <= 0 || tiles[j] % kBlock || tiles[j] > kMaxTile)
+            return fail(ctx, PIC_E_INVAL, "autotune: bad tile candidate");
+    for (int j = 0; j < n_sorts; ++j)
+        if (sorts[j] < 1) return fail(ctx, PIC_E_INVAL, "autotune: bad sort candidate");
+    const int diag = ctx->diag_every;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    HIPCHK(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(ctx, PIC_E_DEVICE, "autotune: hipEventCreate");
+    }
+    int rc = PIC_OK;
+    int best_tile = ctx->tile, best_sort = ctx->sort_every;
+    double best = 1e300;
+    // tiles at the current sort period; each trial starts after two steps
+    // at the new tile
+    for (int j = 0; j < n_tiles && rc == PIC_OK; ++j) {
+        double t = 0.0;
+        rc = pic_set_schedule(ctx, ctx->sort_every, diag, tiles[j]);
+        if (rc == PIC_OK) rc = timed_trial(ctx, 2, steps_per_trial, ev, &t);
+        if (rc == PIC_OK) {
+            if (ms_out) ms_out[j] = t;
+            if (t < best) {
+                best = t;
+                best_tile = tiles[j];
+            }
+        }
+    }
+    // sort periods at the best tile: whole periods, from a period boundary
+    best = 1e300;
+    for (int j = 0; j < n_sorts && rc == PIC_OK; ++j) {
+        double t = 0.0;
+        rc = pic_set_schedule(ctx, sorts[j], diag, best_tile);
+        if (rc != PIC_OK) break;
+        const int64_t to_boundary = (sorts[j] - ctx->since_sort % sorts[j]) % sorts[j];
+        const int64_t periods = (steps_per_trial + sorts[j] - 1) / sorts[j];
+        rc = timed_trial(ctx, (int)to_boundary, periods * sorts[j], ev, &t);
+        if (rc == PIC_OK) {
+            if (ms_out) ms_out[n_tiles + j] = t;
+            if (t < best) {
+                best = t;
+                best_sort = sorts[j];
+            }
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc != PIC_OK) return rc;
+    rc = pic_set_schedule(ctx, best_sort, diag, best_tile);
+    if (rc != PIC_OK) return rc;
+    if (tile_out) *tile_out = best_tile;
+    if (sort_out) *sort_out = best_sort;
     return PIC_OK;
 }
 

@@ -195,3 +195,29 @@ def test_launch_mode_rejects_bad_values():
         with pytest.raises(P().PicError):
             ctx.set_launch(graph=g, timing_every=t)
     ctx.close()
+
+
+def test_autotune_picks_a_candidate_and_steps_like_pic_step():
+    wl = W.c1(collisions=1, np_per_species=8192 + 5)
+    ctx = ctx_for(wl, tile=1024, sort_every=16)
+    ctx.step(3)
+    tile, sort, ms = ctx.autotune(tiles=[256, 1024, 4096], sorts=[5, 16], steps_per_trial=6)
+    assert tile in (256, 1024, 4096) and sort in (5, 16)
+    assert len(ms) == 5 and all(m > 0.0 for m in ms)
+    assert ms[[256, 1024, 4096].index(tile)] == min(ms[:3])
+    assert ms[3 + [5, 16].index(sort)] == min(ms[3:])
+    ctx.step(4)
+    n = ctx.state()["step"] - wl["case"].get("step0", 0)
+    # the same number of plain steps at another schedule gives the same state
+    ref = ctx_for(wl, tile=2048, sort_every=7)
+    ref.step(n)
+    for a, b in zip(sorted_state(ctx), sorted_state(ref)):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    fa, fb = ctx.fields(), ref.fields()
+    for k in ("rho", "phi", "E"):
+        assert np.array_equal(fa[k], fb[k]), k
+    with pytest.raises(P().PicError):
+        ctx.autotune(tiles=[300], sorts=[8], steps_per_trial=2)
+    ctx.close()
+    ref.close()
