@@ -610,19 +610,35 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         stg(cellp, (uint32_t)i << 2, -1);
     };
 
+    // The loads of a batch (kILP particles per thread) are issued together,
+    // one batch ahead of its processing, so that a wavefront keeps loads in
+    // flight while it computes.  Indices past the chunk are clamped to its
+    // last slot (and treated as dead below); the batch after the last one
+    // reloads that slot and is discarded.
+    int32_t cn[kILP];   // cell words of the next batch
+    float on[kILP], vnx[kILP], abx[kILP];
+    auto load_batch = [&](int b0) {
+#pragma unroll
+        for (int k = 0; k < kILP; ++k) {
+            const uint32_t j4 = (uint32_t)min(b0 + k * kBlock + tid, end - 1) << 2;
+            cn[k] = ldg(cellp, j4);
+            on[k] = ldg(offp, j4);
+            vnx[k] = ldg(vxp, j4);
+            abx[k] = kImp ? ldg(abp, j4) : 0.0f;
+        }
+    };
+    if (start < end) load_batch(start);
     for (int base = start; base < end; base += kBlock * kILP) {
-        // the loads of the batch are issued together; indices past the chunk
-        // are clamped to its last slot (and treated as dead below)
         int32_t c[kILP];   // cell words
         float o[kILP], v[kILP], ab[kILP];
 #pragma unroll
         for (int k = 0; k < kILP; ++k) {
-            const uint32_t j4 = (uint32_t)min(base + k * kBlock + tid, end - 1) << 2;
-            c[k] = ldg(cellp, j4);
-            o[k] = ldg(offp, j4);
-            v[k] = ldg(vxp, j4);
-            ab[k] = kImp ? ldg(abp, j4) : 0.0f;
+            c[k] = cn[k];
+            o[k] = on[k];
+            v[k] = vnx[k];
+            ab[k] = abx[k];
         }
+        load_batch(base + kBlock * kILP);
 
         float wk = 0.0f;
 #pragma unroll
