@@ -90,8 +90,6 @@ struct Case {
     int32_t collisions;
     int32_t first_block;  // this case's first workgroup in the work table
     int32_t n_blocks;
-    int32_t first_crow;   // this case's first k_collide partial row
-    int32_t n_crows;
     int32_t history_len;
     double dx, dt;
     double rf_volts, rf_omega, rf_freq;
@@ -139,13 +137,14 @@ struct Work {
     int32_t nb;  // workgroups of (case, species)
 };
 
-// A k_collide workgroup: round `round` (kBlock candidates) of the candidates
-// listed by k_step workgroup `step_blk`; the last round takes the rest.
+// A k_collide workgroup: round `round` of `rounds` over the candidates listed
+// by k_step workgroup `step_blk` (the rounds take its blocks of kBlock
+// candidates in turn).
 struct CollideWork {
     int32_t step_blk;
     int32_t round;
     int32_t rounds;
-    int32_t row;      // its ledger partial row
+    int32_t pad;
 };
 
 // Ledger partial sums of one workgroup, stored field-major: field f of

@@ -172,8 +172,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigned* pu_, int stride,
-                                                int fb, int nb, int fb2, int nb2, double* sd,
-                                                long long* su)
+                                                int fb, int nb, double* sd, long long* su)
 {
     // wavefront w sums the fields w, w + NT/64, ...: every lane strides over
     // the workgroup partials with kU loads in flight, then a wavefront tree
@@ -186,18 +185,14 @@ __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigne
             double a[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) a[u] = 0.0;
-            // two row ranges (k_step rows, k_collide rows); unconditional
-            // loads from clamped indices keep all kU in flight
-            for (int r = 0; r < 2; ++r) {
-                const int n_r = r == 0 ? nb : nb2;
-                const PIC_GLOBAL double* row = pd + (size_t)f * stride + (r == 0 ? fb : fb2);
-                for (int b = lane; b < n_r; b += 64 * kU)
+            // unconditional loads from clamped indices keep all kU in flight
+            const PIC_GLOBAL double* row = pd + (size_t)f * stride + fb;
+            for (int b = lane; b < nb; b += 64 * kU)
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const double x = row[min(b + 64 * u, n_r - 1)];
-                        a[u] += b + 64 * u < n_r ? x : 0.0;
-                    }
-            }
+                for (int u = 0; u < kU; ++u) {
+                    const double x = row[min(b + 64 * u, nb - 1)];
+                    a[u] += b + 64 * u < nb ? x : 0.0;
+                }
             double v = 0.0;
 #pragma unroll
             for (int u = 0; u < kU; ++u) v += a[u];
@@ -206,17 +201,13 @@ __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigne
         } else {
             // per-step counts of one case fit in 32 bits
             unsigned a = 0u;
-            for (int r = 0; r < 2; ++r) {
-                const int n_r = r == 0 ? nb : nb2;
-                const PIC_GLOBAL unsigned* row =
-                    pu + (size_t)(f - PD_N) * stride + (r == 0 ? fb : fb2);
-                for (int b = lane; b < n_r; b += 64 * kU)
+            const PIC_GLOBAL unsigned* row = pu + (size_t)(f - PD_N) * stride + fb;
+            for (int b = lane; b < nb; b += 64 * kU)
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const unsigned x = row[min(b + 64 * u, n_r - 1)];
-                        a += b + 64 * u < n_r ? x : 0u;
-                    }
-            }
+                for (int u = 0; u < kU; ++u) {
+                    const unsigned x = row[min(b + 64 * u, nb - 1)];
+                    a += b + 64 * u < nb ? x : 0u;
+                }
             a = wave_sum(a);
             if (lane == 0) su[f - PD_N] = (long long)a;
         }
@@ -785,26 +776,23 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     work = wave_sum(work);
     if (lane == 0) wsum[wave] = work;
     lds_barrier();
-    if (tid == 0) {
-        double wk = 0.0;
-        for (int k = 0; k < kWaves; ++k) wk += wsum[k];
-        const int o = 1 - s;
+    // one field per thread
+    if (tid < PD_N + PU_N) {
         const size_t S_ = (size_t)P.stride;
-        double* pd = P.pd + gblk;
-        unsigned* pu = P.pu + gblk;
-        pd[(PD_WORK + s) * S_] = wk;
-        pd[(PD_WORK + o) * S_] = 0.0;
-        pd[(PD_COLL + 0) * S_] = 0.0;
-        pd[(PD_COLL + 1) * S_] = 0.0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                pd[(PD_ABSK + 2 * a + b) * S_] = acc.absK[a][b];
-                pu[(PU_ABS + 2 * a + b) * S_] = acc.abs_n[a][b];
-            }
-        pd[(PD_V2 + 0) * S_] = 0.0;
-        pd[(PD_V2 + 1) * S_] = 0.0;
-        for (int f = PU_COLL; f < PU_N; ++f) pu[f * S_] = 0u;
-        P.cand_n[gblk] = s_ncand;
+        if (tid < PD_N) {
+            double x = 0.0;
+            if (tid == PD_WORK + s)
+                for (int k = 0; k < kWaves; ++k) x += wsum[k];
+            else if (tid >= PD_ABSK && tid < PD_ABSK + 4)
+                x = acc.absK[(tid - PD_ABSK) >> 1][(tid - PD_ABSK) & 1];
+            P.pd[(size_t)tid * S_ + gblk] = x;
+        } else {
+            const int f = tid - PD_N;
+            const unsigned x = f >= PU_ABS && f < PU_ABS + 4
+                                   ? acc.abs_n[(f - PU_ABS) >> 1][(f - PU_ABS) & 1] : 0u;
+            P.pu[(size_t)f * S_ + gblk] = x;
+        }
+        if (tid == 0) P.cand_n[gblk] = s_ncand;
     }
 }
 
@@ -825,13 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     const CollideWork cw = P.cwork[P.mode + (int)blockIdx.x];
     const int gblk = cw.step_blk;
     const int ncand = P.cand_n[gblk];
-    const size_t S_ = (size_t)P.stride;
-    if (cw.round * kBlock >= ncand) {
-        // nothing in this round: the row of the workgroup holds zeros
-        if (threadIdx.x < PD_N) P.pd[threadIdx.x * S_ + cw.row] = 0.0;
-        else if (threadIdx.x < PD_N + PU_N) P.pu[(threadIdx.x - PD_N) * S_ + cw.row] = 0u;
-        return;
-    }
+    if (cw.round * kBlock >= ncand) return;   // nothing in this round
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockAcc acc;
     __shared__ Species S;
@@ -975,11 +957,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         }
     };
 
-    // this round, and for the last round all candidates beyond the estimate
+    // the rounds of a list take its blocks of kBlock candidates in turn
     // (loading several candidates per thread ahead of their processing
     // measured slower: the loads are scattered, not latency-bound)
-    const int e_step = cw.round == cw.rounds - 1 ? kBlock : ncand;
-    for (int e0 = cw.round * kBlock; e0 < ncand; e0 += e_step) {
+    for (int e0 = cw.round * kBlock; e0 < ncand; e0 += cw.rounds * kBlock) {
         const int e = e0 + tid;
         const bool act = e < ncand;
         int i = 0, c1 = 0;
@@ -1145,38 +1126,41 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         wsum[wave][1] = (double)ncw;
     }
     lds_barrier();
-    if (tid == 0) {
-        double cd = 0.0, nc = 0.0;
-        for (int k = 0; k < kWaves; ++k) {
-            cd += wsum[k][0];
-            nc += wsum[k][1];
-        }
+    // added to the row of the k_step workgroup whose list this is (its
+    // collision fields start at zero; several rounds add in any order), one
+    // field per thread
+    if (tid < PD_N + PU_N) {
         const int o = 1 - s;
-        double* pd = P.pd + cw.row;
-        unsigned* pu = P.pu + cw.row;
-        pd[(PD_WORK + 0) * S_] = 0.0;
-        pd[(PD_WORK + 1) * S_] = 0.0;
-        pd[(PD_COLL + s) * S_] = cd;
-        pd[(PD_COLL + o) * S_] = s == 0 ? acc.other_dK : 0.0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                pd[(PD_ABSK + 2 * a + b) * S_] = acc.absK[a][b];
-                pu[(PU_ABS + 2 * a + b) * S_] = acc.abs_n[a][b];
+        const size_t S_ = (size_t)P.stride;
+        if (tid < PD_N) {
+            double x = 0.0;
+            if (tid == PD_COLL + s)
+                for (int k = 0; k < kWaves; ++k) x += wsum[k][0];
+            else if (tid == PD_COLL + o && s == 0)
+                x = acc.other_dK;
+            else if (tid >= PD_ABSK && tid < PD_ABSK + 4)
+                x = acc.absK[(tid - PD_ABSK) >> 1][(tid - PD_ABSK) & 1];
+            if (x != 0.0) gatomic_add(gp(P.pd + (size_t)tid * S_ + gblk), x);
+        } else {
+            const int f = tid - PD_N;
+            unsigned x = 0u;
+            if (f >= PU_ABS && f < PU_ABS + 4) {
+                x = acc.abs_n[(f - PU_ABS) >> 1][(f - PU_ABS) & 1];
+            } else if (f >= PU_COLL + 4 * s && f < PU_COLL + 4 * s + 4) {
+                x = acc.n_coll[f - PU_COLL - 4 * s];
+            } else if (f == PU_CAND + s) {
+                double nc = 0.0;
+                for (int k = 0; k < kWaves; ++k) nc += wsum[k][1];
+                x = (unsigned)nc;
+            } else if (f == PU_CREATED + 0 || f == PU_CREATED + 1) {
+                x = acc.n_created[f - PU_CREATED];
+            } else if (f == PU_OVER + s) {
+                x = acc.n_over;
+            } else if (f == PU_LOST + 0 || f == PU_LOST + 1) {
+                x = acc.n_lost[f - PU_LOST];
             }
-        pd[(PD_V2 + 0) * S_] = 0.0;
-        pd[(PD_V2 + 1) * S_] = 0.0;
-        for (int k = 0; k < 4; ++k) {
-            pu[(PU_COLL + 4 * s + k) * S_] = acc.n_coll[k];
-            pu[(PU_COLL + 4 * o + k) * S_] = 0u;
+            if (x != 0u) gatomic_add(gp(P.pu + (size_t)f * S_ + gblk), x);
         }
-        pu[(PU_CAND + s) * S_] = (unsigned)nc;
-        pu[(PU_CAND + o) * S_] = 0u;
-        pu[(PU_CREATED + 0) * S_] = acc.n_created[0];
-        pu[(PU_CREATED + 1) * S_] = acc.n_created[1];
-        pu[(PU_OVER + s) * S_] = acc.n_over;
-        pu[(PU_OVER + o) * S_] = 0u;
-        pu[(PU_LOST + 0) * S_] = acc.n_lost[0];
-        pu[(PU_LOST + 1) * S_] = acc.n_lost[1];
     }
 }
 
@@ -1196,8 +1180,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
     State* st = P.state + (blockIdx.x >> 1);
     if (blockIdx.x & 1) {
         // ledger of the step just taken
-        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks,
-                                   C->first_crow, C->n_crows, sd, si);
+        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
         finish_ledger(C, st, sd, si);
         return;
     }
@@ -1478,7 +1461,7 @@ __global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
     __shared__ long long si[PU_N];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, 0, 0, sd, si);
+    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
     if (threadIdx.x != 0) return;
     for (int s = 0; s < 2; ++s) {
         Species& S = C->sp[s];

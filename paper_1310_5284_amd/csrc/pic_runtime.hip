@@ -203,6 +203,10 @@ uint32_t candidate_threshold(double pnull)
     return (uint32_t)c;
 }
 
+// k_collide rounds: candidates per thread aimed at, and the most rounds
+constexpr double kCandPerThread = 8.0;
+constexpr int kMaxRounds = 32;
+
 int build_work(pic_ctx* c)
 {
     c->work.clear();
@@ -226,24 +230,26 @@ int build_work(pic_ctx* c)
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
     }
     c->n_blocks = (int)c->work.size();
-    // k_collide: one workgroup per k_step workgroup that can list
-    // candidates (splitting a workgroup's list into several rounds adds more
-    // per-workgroup latency than it hides); partial rows follow the k_step
-    // rows.
+    // k_collide: for every k_step workgroup that can list candidates, as
+    // many workgroups (rounds) as its expected list needs at about
+    // kCandPerThread candidates per thread; they add their collision terms
+    // to the ledger row of that k_step workgroup
     for (int g = 0; g < 2; ++g) {
         c->cgrp_off[g] = (int)c->cwork.size();
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
             Case& C = c->cases_h[k];
-            C.first_crow = c->n_blocks + (int)c->cwork.size();
             for (int b = C.first_block; b < C.first_block + C.n_blocks; ++b) {
                 const Work& w = c->work[b];
                 const double p = h.cfg.collisions ? h.pnull[w.s] : 0.0;
                 if (!(p > 0.0)) continue;
-                c->cwork.push_back(CollideWork{b, 0, 1, c->n_blocks + (int)c->cwork.size()});
+                const double per_wg = (double)std::min<int64_t>(c->tile, h.cap[w.s]);
+                const int rounds = (int)std::min<double>(
+                    kMaxRounds, std::max(1.0, std::ceil(p * per_wg / (kBlock * kCandPerThread))));
+                for (int r = 0; r < rounds; ++r)
+                    c->cwork.push_back(CollideWork{b, r, rounds, 0});
             }
-            C.n_crows = c->n_blocks + (int)c->cwork.size() - C.first_crow;
         }
         c->cgrp_cnt[g] = (int)c->cwork.size() - c->cgrp_off[g];
     }
@@ -264,7 +270,7 @@ int upload_work(pic_ctx* c)
     c->d_cwork = nullptr;
     const size_t nb = c->work.size();
     const size_t ncw = c->cwork.size();
-    const size_t rows = nb + ncw;   // partial rows: k_step, then k_collide
+    const size_t rows = nb;   // ledger partial rows: one per k_step workgroup
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(Work) * nb));
     HIPCHK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(Work) * nb, hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&c->d_cwork, sizeof(CollideWork) * std::max<size_t>(ncw, 1)));
@@ -289,7 +295,7 @@ Params params(pic_ctx* c, int mode)
     p.work = c->d_work;
     p.pd = c->d_pd;
     p.pu = c->d_pu;
-    p.stride = (int32_t)(c->work.size() + c->cwork.size());
+    p.stride = (int32_t)c->work.size();
     p.n_cases = c->n_cases;
     p.mode = mode;
     p.cand_n = c->d_cand_n;
