@@ -219,9 +219,11 @@ def main():
         real += rk
         step_bytes += PASS_BYTES[sc] * per_case[k] + LIST_BYTES[sc] * ck
         coll_step_bytes += COLLIDE_BYTES[sc] * ck + COLLISION_BYTES[sc] * rk
+    if launches == 0:
+        log("[bench] no timed launch in the timed steps (see --timing-every)")
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     alg_bytes = step_bytes / groups
-    achieved = alg_bytes / avg_launch_s / 1e9
+    achieved = alg_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     kname = "k_step<%d,false>" % schemes[0] if groups == 1 else "k_step<0|1,false>"
     rule = " and ".join("%s: %d B per particle + %d B per listed candidate"
                         % (("explicit", "implicit")[sc], PASS_BYTES[sc], LIST_BYTES[sc])
