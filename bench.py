@@ -35,6 +35,9 @@ LIST_BYTES = {0: 12, 1: 20}
 # implicit pass rewrites vx anyway, so vy, vz only).
 COLLIDE_BYTES = {0: 32, 1: 52}
 COLLISION_BYTES = {0: 12, 1: 8}
+# Bytes per particle-step of a plain streaming form of the method that reads
+# every particle's whole state each step (the whole-step comparison figure).
+STREAM_BYTES = {0: 40, 1: 48}
 
 
 def log(*a):
@@ -125,8 +128,9 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge")
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
+    # about 2000 steps (autotuning trials included) before the timed window
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--workload", default="ccp2048_explicit")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--tile", type=int, default=0, help="particles per workgroup (default 16384)")
@@ -244,6 +248,15 @@ def main():
                        % (("explicit", "implicit")[sc], COLLIDE_BYTES[sc], COLLISION_BYTES[sc])
                        for sc in sorted(set(schemes))))
     roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+    if roof["traffic"] and avg_launch_s > 0:
+        roof["traffic_GBps"] = round(roof["traffic"] / avg_launch_s / 1e9, 1)
+    # the whole step priced at the bytes a plain streaming form of the method
+    # moves per particle-step (explicit: read cell, off, vx, vy, vz, id and
+    # write cell, off, vx = 40 B; implicit: + abar read and written = 48 B)
+    plain = sum(STREAM_BYTES[sc] * per_case[k] for k, sc in enumerate(schemes)) / particles
+    roof["step_equivalent"] = dict(bytes_per_particle_step=round(plain, 2),
+                                   GBps=round(value * plain / 1e9, 1),
+                                   frac=round(value * plain / 1e9 / PEAK_HBM_GBS, 4))
     collide["traffic"] = measured_traffic(args.workload, collide["kernel"])
 
     out = dict(metric="particle-steps/sec (push+deposit+MCC) vs plain FP64 GPU form at "
