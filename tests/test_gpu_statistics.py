@@ -6,7 +6,8 @@ Float32 particle state against float64 makes the two microstates drift apart
 (the motion is chaotic), so they are compared through statistics over the
 last 4 periods: the time-averaged node densities, the electron energy
 distribution and the power absorbed from the field (the field work summed
-over cells and species), each to 2 %.  The GPU side also exercises the
+over cells and species), each to 2 %; the energy history (kinetic and total
+energy at the end of every period) follows the oracle's to 2 %.  The GPU side also exercises the
 diagnostics accumulators (density, heating, EEDF sampled every step); the
 oracle side samples its particle state after every step of the window."""
 import numpy as np
@@ -30,7 +31,7 @@ def test_ccp64_ten_periods_statistics_match_oracle():
     dx = wl["case"]["gap_m"] / N
     t0, tw = 6 * PERIOD, 4 * PERIOD
 
-    ctx = P.PicContext([wl])
+    ctx = P.PicContext([wl], history_steps=t0 + tw)
     ctx.set_schedule(sort_every=64, diag_every=0, tile=2048)
     ctx.step(t0)
     ctx.reset_accumulators()
@@ -39,17 +40,28 @@ def test_ccp64_ten_periods_statistics_match_oracle():
     dens_g, n_samples = ctx.density()
     heat_g = ctx.heating()
     eedf_g, bin_eV, e_samples = ctx.eedf()
+    hist = {h["step"]: h for h in ctx.history(cap=t0 + tw)}
     ctx.close()
     assert n_samples == tw and e_samples == tw
 
     case, sps, procs = W.to_oracle(wl)
     sim = oracle.Sim(case, sps, procs)
-    sim.step(t0)
+    energy = []      # (step, kinetic, total) of the oracle at period ends
+
+    def note_energy():
+        L = sim.ledger()
+        energy.append((sim.step_index - 1, L["K_after"].sum(), L["K_after"].sum() + L["WE"]))
+
+    for _ in range(t0 // PERIOD):
+        sim.step(PERIOD)
+        note_energy()
     h0 = sim.heating()
     dens_o = [np.zeros(N + 1), np.zeros(N + 1)]
     eedf_o = np.zeros(eedf_g.size)
-    for _ in range(tw):
+    for it in range(tw):
         sim.step(1)
+        if (it + 1) % PERIOD == 0:
+            note_energy()
         for s in range(2):
             sp = sim.species(s)
             dens_o[s] += oracle.deposit_linear(N, sp["xi"]) * sim.w[s]
@@ -78,8 +90,52 @@ def test_ccp64_ten_periods_statistics_match_oracle():
     assert l1 < TOL
     assert abs(mg - mo) / mo < TOL
 
+    for step, k_o, tot_o in energy:
+        g = hist[step]
+        k_g, tot_g = g["K_after"].sum(), g["K_after"].sum() + g["WE"]
+        print(f"step {step}: kinetic {k_g:.5e} / {k_o:.5e}, total {tot_g:.5e} / {tot_o:.5e}")
+        assert abs(k_g - k_o) / k_o < TOL
+        assert abs(tot_g - tot_o) / tot_o < TOL
+
     pg_abs = sum(h.sum() for h in heat_g)
     po_abs = sum((h1[s] - h0[s]).sum() for s in range(2))
     err = abs(pg_abs - po_abs) / abs(po_abs)
     print(f"absorbed energy over the window: {pg_abs:.5e} / {po_abs:.5e} J/m^2 ({err:.4f})")
     assert err < TOL
+
+
+def test_mixed_path_eedf_matches_fp64_gpu_form():
+    # the throughput comparison is made at matched physics: the float32 /
+    # int64 path and the plain FP64 GPU form of the same method, run from the
+    # same 64-cell discharge (131k particles per species) for 10 periods,
+    # give the same electron energy distribution over the last 4
+    import paper_1310_5284_amd as P
+    wl = W.c1(collisions=1, np_per_species=131072)
+    t0, tw, every = 6 * PERIOD, 4 * PERIOD, 4
+    ctx = P.PicContext([wl])
+    ctx.set_schedule(sort_every=64, diag_every=0, tile=4096)
+    ctx.fp64_init()
+    ctx.step(t0)
+    ctx.reset_accumulators()
+    ctx.set_schedule(sort_every=64, diag_every=every, tile=4096)
+    ctx.step(tw)
+    eedf_g, bin_eV, samples = ctx.eedf()
+    assert samples == tw // every
+    vu = ctx.state()["vel_unit"]
+    ctx.fp64_step(t0)
+    eedf_f = np.zeros(eedf_g.size)
+    for _ in range(tw // every):
+        ctx.fp64_step(every)
+        sp = ctx.fp64_state(0, 0)
+        eps = 0.5 * ME * vu * vu * (sp["vx"] ** 2 + sp["vy"] ** 2 + sp["vz"] ** 2) / E
+        b = np.minimum(np.floor(eps / bin_eV).astype(np.int64), eedf_g.size - 1)
+        eedf_f += np.bincount(b, minlength=eedf_g.size)
+    ctx.close()
+    pg = eedf_g.reshape(-1, 2).sum(1) / eedf_g.sum()
+    pf = eedf_f.reshape(-1, 2).sum(1) / eedf_f.sum()
+    l1 = np.abs(pg - pf).sum()
+    c = (np.arange(pg.size) + 0.5) * 2 * bin_eV
+    mg, mf = (pg * c).sum(), (pf * c).sum()
+    print(f"EEDF mixed vs FP64 form: L1 {l1:.4f}, mean energy {mg:.4f} / {mf:.4f} eV")
+    assert l1 < TOL
+    assert abs(mg - mf) / mf < TOL
