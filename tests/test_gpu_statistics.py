@@ -139,3 +139,56 @@ def test_mixed_path_eedf_matches_fp64_gpu_form():
     print(f"EEDF mixed vs FP64 form: L1 {l1:.4f}, mean energy {mg:.4f} / {mf:.4f} eV")
     assert l1 < TOL
     assert abs(mg - mf) / mf < TOL
+
+
+def gpu_thermal(ratio, gather, wdt, T=40.0, n_cells=32, ppc=64, seed=7):
+    """Total energy history of the periodic thermal plasma on the GPU path:
+    (max relative error, heating rate per 1/omega_p, energies)."""
+    import paper_1310_5284_amd as P
+    wl = W.c2(ratio=ratio, gather=gather, ppc=ppc, n_cells=n_cells, wdt=wdt, seed=seed)
+    ctx = P.PicContext([wl])
+    ctx.set_schedule(sort_every=64, diag_every=0, tile=1024)
+    nsteps = int(round(T / wdt))
+    tot = []
+    for _ in range(nsteps):
+        ctx.step(1)
+        L = ctx.ledger()
+        # kinetic energy at integer time n: mean of the two half steps
+        tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+    ctx.close()
+    tot = np.array(tot)
+    err = np.abs(tot - tot[0]).max() / tot[0]
+    rate = np.polyfit(np.arange(nsteps) * wdt, tot / tot[0], 1)[0]
+    return err, rate, tot
+
+
+def test_grid_heating_mc_heats_ec_does_not_on_gpu():
+    # the paper's central comparison on the float32 / int64 path, at
+    # dx = 20 lambda_D: the momentum-conserving scheme heats at a rate that
+    # does not shrink with dt, the energy-conserving one does not heat; the
+    # same run in the oracle heats at the same rate
+    r = [gpu_thermal(20.0, 1, w) for w in (0.2, 0.1)]
+    rate_mc = [x[1] for x in r]
+    rate_ec = gpu_thermal(20.0, 0, 0.1)[1]
+    wl = W.c2(ratio=20.0, gather=1, ppc=64, n_cells=32, wdt=0.2, seed=7)
+    case, sps, procs = W.to_oracle(wl)
+    sim = oracle.Sim(case, sps, procs)
+    tot = []
+    for _ in range(200):
+        sim.step(1)
+        L = sim.ledger()
+        tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+    tot = np.array(tot)
+    rate_orc = np.polyfit(np.arange(200) * 0.2, tot / tot[0], 1)[0]
+    print(f"MC heating rate {rate_mc} (oracle {rate_orc:.4g}), EC {rate_ec:.3g}")
+    assert rate_mc[0] > 1e-3 and rate_mc[1] > 1e-3
+    assert 0.7 < rate_mc[0] / rate_mc[1] < 1.4
+    assert abs(rate_ec) < 0.05 * rate_mc[1]
+    assert 0.7 < rate_mc[0] / rate_orc < 1.4
+
+
+def test_ec_energy_error_shrinks_like_dt_squared_on_gpu():
+    # dx = 5 lambda_D: the EC energy error is the leap-frog time error
+    errs = [gpu_thermal(5.0, 0, w)[0] for w in (0.2, 0.1)]
+    print("EC energy error", errs)
+    assert 3.0 <= errs[0] / errs[1] <= 5.5, errs
