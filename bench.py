@@ -125,6 +125,49 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge")
                        f"to keep the densities), {steps} steps, FP64, single thread")
 
 
+def drift_table(P, steps):
+    """Total-energy drift of the periodic thermal plasma (512 cells, 1000
+    electrons per cell on a fixed neutralising background) on the GPU path,
+    EC and MC gathers, dx / lambda_D = 0.5, 5, 20 at omega_p dt = 0.2, and at
+    dx = 5 lambda_D also omega_p dt = 0.1 and 0.05 over the same time.  The
+    energy at integer steps is the mean of the kinetic energies of the two
+    half steps plus the field energy; drift = slope of E / E_0 per step
+    (least squares over about 200 samples), err = max |E / E_0 - 1|."""
+    import numpy as np
+
+    import workloads as W
+    rows = []
+    for ratio in (0.5, 5.0, 20.0):
+        for gather in (0, 1):
+            for wdt in ((0.2, 0.1, 0.05) if ratio == 5.0 else (0.2,)):
+                n = int(round(steps * 0.2 / wdt))
+                every = max(1, n // 200)
+                wl = W.c2(ratio=ratio, gather=gather, ppc=1000, n_cells=512, wdt=wdt)
+                ctx = P.PicContext([wl])
+                ctx.set_schedule(sort_every=64, diag_every=0, tile=4096)
+                ctx.set_launch(graph=0, timing_every=0)
+                t0 = time.perf_counter()
+                xs, es = [], []
+                done = 0
+                while done < n:
+                    k = min(every, n - done)
+                    ctx.step(k)
+                    done += k
+                    L = ctx.ledger()
+                    xs.append(done)
+                    es.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+                dt_s = time.perf_counter() - t0
+                ctx.close()
+                e = np.array(es) / es[0]
+                rows.append(dict(dx_over_lambda_D=ratio, gather=("EC", "MC")[gather],
+                                 omega_p_dt=wdt, steps=n,
+                                 drift_per_step=float(np.polyfit(xs, e, 1)[0]),
+                                 max_rel_err=float(np.abs(e - 1.0).max()),
+                                 steps_per_s=n / dt_s))
+                log(f"[bench] drift {rows[-1]}")
+    return dict(measurement="energy drift, periodic thermal plasma, GPU path", rows=rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +192,10 @@ def main():
                     help="steps of the plain FP64 GPU form timed for comparison (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run the streaming copy kernel of BYTES and print its rate")
+    ap.add_argument("--drift", type=int, default=0, metavar="STEPS",
+                    help="only measure the energy drift of the periodic thermal plasma "
+                         "(512 cells, 1000 electrons per cell) over STEPS steps at "
+                         "omega_p dt = 0.2 (the same time at 0.1 and 0.05)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -162,6 +209,10 @@ def main():
         print(json.dumps(dict(calibration="copy", bytes_read=args.copy_calibration,
                               bytes_written=args.copy_calibration, ms_per_copy=ms,
                               GBps=2 * args.copy_calibration / (ms * 1e-3) / 1e9)), flush=True)
+        return
+
+    if args.drift:
+        print(json.dumps(drift_table(P, args.drift)), flush=True)
         return
 
     log(f"[bench] building inputs: {args.workload} scale {args.scale}")
