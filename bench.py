@@ -48,6 +48,9 @@ def make_workload(name, scale):
     import workloads as W
     if name == "ccp2048_explicit":
         return [W.c4(np_per_species=int(10_000_000 * scale))]
+    if name == "ccp2048_implicit":
+        # the same discharge stepped by the D1 implicit scheme
+        return [W.c4(np_per_species=int(10_000_000 * scale), scheme=1)]
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":

@@ -254,4 +254,19 @@ __device__ __forceinline__ void renorm(int& c, float& o)
     }
 }
 
+// D1 prediction from x_{n+1} = (c, o) with v_{n+1/2} and abar_n (cells per
+// step): v~ = v + abar/2, x~ = x + v~.  One rounding per operation, so that
+// k_step and k_collide reproduce the same prediction bit for bit.  Returns v~.
+__device__ __forceinline__ float predict(int& c, float& o, float vn, float abn)
+{
+    const float vst = fmaf(0.5f, abn, vn);
+    o = __fadd_rn(o, vst);
+    renorm(c, o);
+    return vst;
+}
+
+// Flag in the waiting-time field of a listed candidate's word (its count is
+// zero): k_step deposited the candidate's prediction without a collision.
+constexpr uint32_t kPredDeposited = 1u;
+
 }  // namespace pic

@@ -684,11 +684,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             int c2 = c1;
             float o2 = o1, vst = vn;
             bool dep_now = false;
+            uint32_t lflag = 0u;   // list flag of a candidate
             if (live && !isc) {
                 if (kImp) {
-                    vst = vn + 0.5f * abn;
-                    o2 = o1 + vst;
-                    renorm(c2, o2);
+                    vst = predict(c2, o2, vn, abn);
                     if (periodic) {
                         c2 %= N;
                         if (c2 < 0) c2 += N;
@@ -714,12 +713,39 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     }
                 }
             } else if (live) {
-                stg(cellp, i4, pack_cell(c1, wt));
-                stg(offp, i4, o1);
-                // explicit: v_{n+1/2} stands unless k_collide finds a real
-                // collision (the store joins the coalesced stream)
-                if (!kImp) stg(vxp, i4, vn);
-                dep_now = !kImp;
+                bool kept = false;
+                if (kImp) {
+                    // implicit: predicted as if the collision were a null one
+                    // (most are) and deposited; k_collide keeps that, or
+                    // undoes the deposit and predicts again after a real
+                    // collision.  A prediction outside the gap is left to
+                    // k_collide.
+                    int cp = c1;
+                    float op = o1;
+                    const float vp = predict(cp, op, vn, abn);
+                    if (periodic) {
+                        cp %= N;
+                        if (cp < 0) cp += N;
+                    }
+                    if (cp >= 0 && cp < N) {
+                        stg(cellp, i4, pack_cell(cp, wt));
+                        stg(offp, i4, op);
+                        stg(vxp, i4, vp);
+                        stg(abp, i4, abn);
+                        c2 = cp;
+                        o2 = op;
+                        lflag = kPredDeposited;
+                        kept = true;
+                    }
+                }
+                if (!kept) {
+                    stg(cellp, i4, pack_cell(c1, wt));
+                    stg(offp, i4, o1);
+                    // explicit: v_{n+1/2} stands unless k_collide finds a
+                    // real collision (the store joins the coalesced stream)
+                    if (!kImp) stg(vxp, i4, vn);
+                }
+                dep_now = !kImp || kept;
             }
             deposit_wave(dep, dep_now, c2, o2, lo, hi);
             // list the candidates of this wavefront in the workgroup's region
@@ -734,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     const uint32_t e4 = (uint32_t)e << 2;
                     stg(cq_idx, e4, i);
                     stg(cq_vn, e4, vn);
-                    stg(cq_w, e4, pack_cell(c1, wt));
+                    stg(cq_w, e4, pack_cell(c1, wt | lflag));
                     if (kImp) {
                         stg(cq_ab, e4, abn);
                         stg(cq_o, e4, o1);
@@ -839,6 +865,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     const PIC_GLOBAL float* __restrict__ cq_ab = gp(uniform_ptr((const float*)C->sp[s].cq_ab));
     const double inv_ion = C->sp[1].inv_log1mp;
     const long long cap0 = C->sp[0].capacity, cap1 = C->sp[1].capacity;
+    PIC_GLOBAL unsigned long long* gdep_cnt = gp(uniform_ptr(C->dep_cnt[s]));
+    PIC_GLOBAL unsigned long long* gdep_w = gp(uniform_ptr(C->dep_w[s]));
     // collision constants in LDS (stores to the particle arrays cannot alias them)
     for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
         ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
@@ -964,8 +992,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         const int e = e0 + tid;
         const bool act = e < ncand;
         int i = 0, c1 = 0;
-        float o1 = 0.0f, vn = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
+        float o1 = 0.0f, vn = 0.0f, vn0 = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
         uint64_t id = 0;
+        bool pred = false;  // implicit: k_step deposited the null prediction
         uint32_t nw = 0u;   // the particle's next waiting-time word
         int kind = -1;
         Child ch;
@@ -983,6 +1012,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             vy = rec_vy(r);
             vz = rec_vz(r);
             c1 = cell_of(w1);
+            vn0 = vn;
+            pred = kImp && (wait_of(w1) & kPredDeposited);
             const float v2b = vn * vn + vy * vy + vz * vz;
             bool is_cand = true;
             if (wait_of(w1) & PIC_WAIT_CAPPED) {
@@ -1027,10 +1058,30 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         float o2 = o1;
         if (act) {
             const uint32_t i4 = (uint32_t)i << 2;
-            if (kImp) {
-                const float vst = vn + 0.5f * abn;
-                o2 = o1 + vst;
-                renorm(c2, o2);
+            if (kImp && pred && kind < 0) {
+                // a null collision: the prediction k_step stored and
+                // deposited stands; only the waiting time is new
+                predict(c2, o2, vn, abn);
+                if (periodic) {
+                    c2 %= N;
+                    if (c2 < 0) c2 += N;
+                }
+                stg(cellp, i4, pack_cell(c2, nw));
+            } else if (kImp) {
+                if (pred) {
+                    // a real collision: undo k_step's deposit of the null
+                    // prediction (integer words, so exactly)
+                    int cp = c1;
+                    float op = o1;
+                    predict(cp, op, vn0, abn);
+                    if (periodic) {
+                        cp %= N;
+                        if (cp < 0) cp += N;
+                    }
+                    gatomic_add(&gdep_cnt[cp], ~0ull);
+                    gatomic_add(&gdep_w[cp], 0ull - (packw(op) & kWMask));
+                }
+                const float vst = predict(c2, o2, vn, abn);
                 bool gone = false;
                 if (periodic) {
                     c2 %= N;
