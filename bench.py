@@ -65,11 +65,17 @@ def make_workload(name, scale):
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex) of the kernel sources with comments and blank
+    space removed: a comment edit does not change the kernels."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("pic_kernels.hip", "pic_common.hpp", "pic_device.hpp"):
-        with open(os.path.join(ROOT, "paper_1310_5284_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1310_5284_amd", "csrc", f)) as fh:
+            t = fh.read()
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(" ".join(t.split()).encode())
     return h.hexdigest()[:16]
 
 

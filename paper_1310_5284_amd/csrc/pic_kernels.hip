@@ -824,14 +824,15 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
 
 // ---------------------------------------------------------------------------
 // k_collide: the null-collision MCC (Vahedi & Surendra 1995) of the
-// candidates that k_step listed, one workgroup per k_step workgroup, one
-// candidate per thread.  A candidate whose capped wait ran out first draws
-// its trial; a candidate draws its next waiting time, the process (u1 of
-// draw 0 against the cumulative n_g sigma_k v / nu_max) and the scattering;
-// ionizations are queued in LDS and append their electron and ion after the
-// loop.  Implicit candidates then
-// predict, are absorbed or deposit (privatised LDS grid).  The collision
-// terms of the ledger are added to the row of the same workgroup.
+// candidates that k_step listed: one or more workgroups (rounds) per k_step
+// workgroup, one candidate per thread.  A candidate whose capped wait ran out
+// first draws its trial; a candidate draws its next waiting time, the
+// process (u1 of draw 0 against the cumulative n_g sigma_k v / nu_max) and
+// the scattering; ionizations are queued in LDS and append their electron
+// and ion after the loop.  Implicit candidates keep the prediction k_step
+// made for a null collision, or after a real one undo its deposit, predict
+// again and are absorbed or deposit (privatised LDS grid).  The collision
+// terms of the ledger are added to the row of the k_step workgroup.
 // ---------------------------------------------------------------------------
 template <int SCHEME, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_collide(Params P)

@@ -84,3 +84,38 @@ def test_ionizing_beam_teacher_forced(scheme):
     rep = teacher_forced(ctx, wl, 8)
     print(n_ion, rep)
     assert_report(rep)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_max_cells_teacher_forced(scheme):
+    # the largest grid the library takes (PIC_MAX_CELLS = 4096 cells: the
+    # deposit grid and the field fill the most LDS), 300 V, 30 mTorr
+    wl = W.ccp_workload("ccp4096", n_cells=4096, np_per_species=40000 + 11, volts=300.0,
+                        dt=1.0 / (2000.0 * 13.56e6), p_mtorr=30.0, scheme=scheme, seed=0x4096)
+    ctx = ctx_for(wl, tile=4096)
+    rep = teacher_forced(ctx, wl, 20)
+    print(rep)
+    assert_report(rep)
+
+
+def test_ccp64_mc_explicit_teacher_forced():
+    # the momentum-conserving gather (CIC of the nodal field) on the RF
+    # discharge with electrodes and collisions
+    wl = W.c1(collisions=1, np_per_species=16384 + 77)
+    wl["case"]["gather"] = 1
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 60)
+    print(rep)
+    assert_report(rep)
+
+
+def test_ccp256_mc_implicit_teacher_forced():
+    # D1 implicit with the momentum-conserving gather
+    wl = W.c3(ppc=40, wdt=2.0)
+    wl["case"]["gather"] = 1
+    for sp in wl["species"]:
+        sp["capacity"] = 2 * sp["cell"].size
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 40)
+    print(rep)
+    assert_report(rep)
