@@ -489,9 +489,28 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         for (int k = 0; k < 2; ++k) r += s->sp[k].q * s->sp[k].w * s->Q[k][g] / s->dx;
         s->rho[g] = r;
     }
-    /* chi_{j+1/2} = beta dt^2 / (eps0 dx) * sum_s q_s^2 w_s / m_s * N_{s,j}, beta = 1/2 */
+    /* EC: chi_{j+1/2} = beta dt^2 / (eps0 dx) * sum_s q_s^2 w_s / m_s * N_{s,j},
+     * beta = 1/2, with N_{s,j} the count of predicted particles in cell j.
+     * MC: the susceptibility of the linear (CIC) weights at the nodes,
+     * chi_g = beta dt^2 / eps0 * sum_s q_s^2 w_s / m_s * Q_{s,g} / V_g (V_g = dx,
+     * dx/2 at Dirichlet electrodes), and
+     * chi_{j+1/2} = (chi_j + chi_{j+1}) / 2. */
     for (int32_t j = 0; j < N; ++j) {
         double x = 0.0;
+        if (use_chi && s->c.gather == ORC_GATHER_MC) {
+            for (int32_t g = j; g <= j + 1; ++g) {
+                double vol = s->dx;
+                if (!periodic && (g == 0 || g == N)) vol = 0.5 * s->dx;
+                for (int k = 0; k < 2; ++k) {
+                    if (!(s->sp[k].m > 0.0)) continue;
+                    /* the periodic deposit holds the folded node in Q_0 and Q_N */
+                    x += 0.5 * s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m *
+                         s->Q[k][g] / vol;
+                }
+            }
+            s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / EPS0 * x;
+            continue;
+        }
         if (use_chi)
             for (int k = 0; k < 2; ++k)
                 if (s->sp[k].m > 0.0)

@@ -142,3 +142,44 @@ def test_periodic_dense_solve(orc, with_chi):
     np.testing.assert_allclose(phi[:N], ref, rtol=1e-10, atol=1e-10 * abs(ref).max())
     assert abs(phi[N]) < 1e-9 * abs(ref).max()   # periodic potential
     assert abs(E.sum()) < 1e-9 * abs(E).max()
+
+
+def _chi(orc, N, xi, gather, periodic=False, dx=1e-4, dt=1e-10):
+    q, m, w = -1.602176634e-19, 9.1093837015e-31, 1e9
+    case = dict(n_cells=N, gap_m=N * dx, bc=1 if periodic else 0, scheme=1, gather=gather,
+                collisions=0, dt_s=dt, rf_volts=0.0, rf_freq_hz=0.0,
+                background_rho=0.0 if not periodic else 0.0)
+    xi = np.asarray(xi, dtype=np.float64)
+    z = np.zeros_like(xi)
+    sps = [dict(q=q, m=m, w=w, xi=xi, vx=z, vy=z, vz=z, abar=z, id=np.arange(xi.size, dtype=np.uint64)),
+           dict(q=-q, m=1e-25, w=w, xi=np.zeros(0), vx=np.zeros(0), vy=np.zeros(0), vz=np.zeros(0),
+                abar=np.zeros(0), id=np.zeros(0, dtype=np.uint64))]
+    sim = orc.Sim(case, sps, [], startup=False)
+    sim.compute_fields()
+    K = 0.5 * dt * dt / EPS0 * q * q * w / m      # beta dt^2 q^2 w / (eps0 m)
+    return sim.fields()["chi"], K / dx
+
+
+def test_mc_susceptibility_is_cic_at_nodes_closed_form(orc):
+    # 3 electrons at the centre of each of cells 0..3 of 8 (Dirichlet): node
+    # weights 1.5, 3, 3, 3, 1.5, 0, ..; densities with half a cell at the
+    # electrode node; cell values are the mean of the two nodes
+    N = 8
+    xi = np.repeat(np.arange(4) + 0.5, 3)
+    chi_mc, u = _chi(orc, N, xi, gather=1)
+    expect = u * np.array([3.0, 3.0, 3.0, 2.25, 0.75, 0.0, 0.0, 0.0])
+    assert np.allclose(chi_mc, expect, rtol=1e-12, atol=0.0)
+    # the energy-conserving scheme counts the particles of each cell
+    chi_ec, _ = _chi(orc, N, xi, gather=0)
+    assert np.allclose(chi_ec, u * np.array([3.0] * 4 + [0.0] * 4), rtol=1e-12, atol=0.0)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_mc_and_ec_susceptibility_agree_for_uniform_plasma(orc, periodic):
+    # c particles at every cell centre: CIC node density equals cell density
+    N = 6
+    xi = np.repeat(np.arange(N) + 0.5, 5)
+    chi_mc, u = _chi(orc, N, xi, gather=1, periodic=periodic)
+    chi_ec, _ = _chi(orc, N, xi, gather=0, periodic=periodic)
+    assert np.allclose(chi_mc, 5.0 * u, rtol=1e-12)
+    assert np.allclose(chi_ec, 5.0 * u, rtol=1e-12)
