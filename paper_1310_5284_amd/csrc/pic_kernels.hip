@@ -43,8 +43,12 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const bool periodic = Cc.bc == 1;
     const bool implicit = Cc.scheme == 1;
     const double dx = Cc.dx;
-    // X: chi_{j+1/2} of the cells (LDS, after the N+1 values of S)
+    // X: chi_{j+1/2} of the cells (LDS, after the N+1 values of S); Y: chi
+    // of the nodes (MC implicit: the susceptibility of the linear weights,
+    // a half cell at an electrode node, averaged to the cells)
     double* X = S + N + 1;
+    double* Y = X + N;
+    const bool node_chi = implicit && Cc.gather == 1;
     // node g = tid + k NT needs the counts and weights of cells g and g-1
     const PIC_GLOBAL unsigned long long* dc[2] = {gp((const unsigned long long*)Cc.dep_cnt[0]),
                                                   gp((const unsigned long long*)Cc.dep_cnt[1])};
@@ -80,13 +84,18 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         for (int k = 0; k < kB; ++k) {
             const int g = tid + (k0 + k) * NT;
             if (g > N) continue;
-            double rho = rho_bg;
+            double rho = rho_bg, chin = 0.0;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const long long q = cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
                 gp(Cc.qfix[s])[g] = q;
                 if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
                 rho += (double)q * (s == 0 ? qs0 : qs1);
+                chin += (double)q * (s == 0 ? chi0 : chi1);
+            }
+            if (node_chi) {
+                const bool end = !periodic && (g == 0 || g == N);
+                Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
             }
             gp(Cc.rho)[g] = rho;
             // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
@@ -94,13 +103,28 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             if (g < N) {
                 gp(Cc.ccount[0])[g] = cn[k][0];
                 gp(Cc.ccount[1])[g] = cn[k][1];
-                const double chi = implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
-                X[g] = chi;
-                gp(Cc.chi)[g] = chi;
+                if (!node_chi) {
+                    const double chi =
+                        implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
+                    X[g] = chi;
+                    gp(Cc.chi)[g] = chi;
+                }
             }
         }
     }
     lds_barrier();   // every deposit word has been read
+    if (node_chi) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = tid + k * NT;
+            if (j < N) {
+                const double chi = 0.5 * (Y[j] + Y[j + 1]);
+                X[j] = chi;
+                gp(Cc.chi)[j] = chi;
+            }
+        }
+        lds_barrier();
+    }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;

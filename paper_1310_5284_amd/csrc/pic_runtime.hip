@@ -173,6 +173,13 @@ size_t step_lds(int N, bool diag)
     return step_lds_layout(N, diag).total;
 }
 
+// k_finalize / k_solve: rho prefix S[N+1], chi per cell X[N], chi per node
+// Y[N+1] (fp64), and a reduction slot
+size_t fin_lds(int N)
+{
+    return 24 * ((size_t)N + 1) + 16;
+}
+
 // Null-collision bound: n_g max over table intervals of
 // max(sigma_T(e_i), sigma_T(e_{i+1})) v(e_{i+1}), v = sqrt(2 e eps / m).
 double nu_max(const std::vector<const pic_xsec*>& pr, double ng, double mass)
@@ -663,7 +670,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         hist_total += 2 * (size_t)N;
     }
     if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true), collide_lds_bytes(c->maxN)),
-                                   8 * (size_t)c->maxN)))
+                                   std::max(8 * (size_t)c->maxN, fin_lds(c->maxN)))))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
@@ -719,8 +726,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         Params p = params(c, 0);
         hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock), 8 * (size_t)c->maxN,
                            c->stream, p);
-        hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock),
-                           16 * ((size_t)c->maxN + 1) + 16, c->stream, p);
+        hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock), fin_lds(c->maxN),
+                           c->stream, p);
         INITCHK(hipGetLastError());
         INITCHK(hipStreamSynchronize(c->stream));
     }
@@ -812,8 +819,8 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             }
         }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock),
-                       16 * ((size_t)c->maxN + 1) + 16, c->stream, params(c, 0), diag ? 1 : 0);
+    hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock), fin_lds(c->maxN),
+                       c->stream, params(c, 0), diag ? 1 : 0);
     HIPCHK(c, hipGetLastError());
     if (++c->since_sort >= c->sort_every)
         if (compaction(c)) return PIC_E_DEVICE;
