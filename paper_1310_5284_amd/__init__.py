@@ -135,19 +135,137 @@ def lib():
     return _lib
 
 
-def copy_calibration(nbytes, reps=10):
-    """Milliseconds per copy of `nbytes` by the library's streaming copy kernel."""
-    ms = C.c_double()
-    rc = lib().pic_copy_calibration(int(nbytes), int(reps), C.byref(ms))
-    if rc != 0:
-        raise PicError(rc, "pic_copy_calibration")
-    return ms.value
-
-
 class PicError(RuntimeError):
     def __init__(self, code, msg=""):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
         self.code = code
+
+
+# ---------------------------------------------------------------------------
+# One Python function per entry point of include/pic.h, under the same name:
+# argument marshalling only; a non-zero return code raises PicError with the
+# context's last error text.
+# ---------------------------------------------------------------------------
+def _ok(h, rc, what):
+    if rc != PIC_OK:
+        msg = lib().pic_last_error(h) if h else None
+        raise PicError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+
+def pic_last_error(h):
+    msg = lib().pic_last_error(h)
+    return msg.decode() if msg else ""
+
+
+def pic_init(cases, species, xs, n_xs, stream=None, flags=0):
+    """cases: CaseConfig array, species: SpeciesInit array (2 per case), xs:
+    Xsec array with n_xs entries.  Returns the context handle."""
+    h = C.c_void_p()
+    rc = lib().pic_init(C.byref(h), len(cases), cases, species, xs, int(n_xs), stream,
+                        int(flags))
+    if rc != PIC_OK:
+        raise PicError(rc, "pic_init failed")
+    return h
+
+
+def pic_destroy(h):
+    lib().pic_destroy(h)
+
+
+def pic_step_explicit(h, n):
+    _ok(h, lib().pic_step_explicit(h, int(n)), "pic_step_explicit")
+
+
+def pic_step_implicit(h, n):
+    _ok(h, lib().pic_step_implicit(h, int(n)), "pic_step_implicit")
+
+
+def pic_step(h, n):
+    _ok(h, lib().pic_step(h, int(n)), "pic_step")
+
+
+def pic_diagnostics(h, case, mask, diag):
+    """Fills the Diag structure `diag` (its pointers name the caller's buffers)."""
+    _ok(h, lib().pic_diagnostics(h, int(case), int(mask), C.byref(diag)), "pic_diagnostics")
+    return diag
+
+
+def pic_set_schedule(h, sort_every, diag_every, tile):
+    _ok(h, lib().pic_set_schedule(h, int(sort_every), int(diag_every), int(tile)),
+        "pic_set_schedule")
+
+
+def pic_set_launch(h, graph, timing_every):
+    _ok(h, lib().pic_set_launch(h, int(graph), int(timing_every)), "pic_set_launch")
+
+
+def pic_autotune(h, tiles=None, sorts=None, steps_per_trial=32):
+    """Returns (tile, sort_every, device ms per step of each trial)."""
+    def arr(v):
+        return (None, 0) if v is None else ((C.c_int32 * len(v))(*v), len(v))
+    t, nt = arr(tiles)
+    so, ns = arr(sorts)
+    n_ms = (nt if tiles is not None else 6) + (ns if sorts is not None else 4)
+    ms = (C.c_double * n_ms)()
+    tile, sort = C.c_int32(0), C.c_int32(0)
+    _ok(h, lib().pic_autotune(h, t, nt, so, ns, int(steps_per_trial), C.byref(tile),
+                              C.byref(sort), ms), "pic_autotune")
+    return tile.value, sort.value, list(ms)
+
+
+def pic_reset_accumulators(h):
+    _ok(h, lib().pic_reset_accumulators(h), "pic_reset_accumulators")
+
+
+def pic_fp64_reference_init(h):
+    _ok(h, lib().pic_fp64_reference_init(h), "pic_fp64_reference_init")
+
+
+def pic_fp64_reference_step(h, n):
+    _ok(h, lib().pic_fp64_reference_step(h, int(n)), "pic_fp64_reference_step")
+
+
+def pic_fp64_reference_state(h, case, species, cap):
+    """Live particles of the FP64 form: xi (cells), v (cells/step), id."""
+    a = {k: np.zeros(cap) for k in ("xi", "vx", "vy", "vz")}
+    ids = np.zeros(cap, np.uint64)
+    n = C.c_int64()
+    _ok(h, lib().pic_fp64_reference_state(
+        h, int(case), int(species), int(cap),
+        *(a[k].ctypes.data_as(_D) for k in ("xi", "vx", "vy", "vz")),
+        ids.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n)), "pic_fp64_reference_state")
+    k = n.value
+    out = {key: v[:k].copy() for key, v in a.items()}
+    out["id"] = ids[:k].copy()
+    return out
+
+
+def pic_copy_calibration(nbytes, reps=10):
+    """Milliseconds per copy of `nbytes` by the library's streaming copy kernel."""
+    ms = C.c_double()
+    rc = lib().pic_copy_calibration(int(nbytes), int(reps), C.byref(ms))
+    if rc != PIC_OK:
+        raise PicError(rc, "pic_copy_calibration")
+    return ms.value
+
+
+copy_calibration = pic_copy_calibration
+
+
+def pic_last_timing(h):
+    """(ms, launches) of the timed particle-pass launches of the last step call."""
+    ms = C.c_double()
+    k = C.c_int64()
+    lib().pic_last_timing(h, C.byref(ms), C.byref(k))
+    return ms.value, k.value
+
+
+def pic_last_timing_collide(h):
+    """(ms, launches) of the timed collision-kernel launches of the last step call."""
+    ms = C.c_double()
+    k = C.c_int64()
+    lib().pic_last_timing_collide(h, C.byref(ms), C.byref(k))
+    return ms.value, k.value
 
 
 def _ptr(a):
@@ -164,7 +282,6 @@ class PicContext:
 
     def __init__(self, workloads, *, flags=0, history_steps=0, stream=None,
                  processes=None):
-        L = lib()
         self._keep = []
         n = len(workloads)
         cfgs = (CaseConfig * n)()
@@ -206,24 +323,17 @@ class PicContext:
             self._keep.append(sig)
             xs[i] = Xsec(species=p["species"], kind=p["kind"], threshold_eV=p["threshold_eV"],
                          e0_eV=p["e0_eV"], de_eV=p["de_eV"], n=sig.size, sigma_m2=sig.ctypes.data)
-        h = C.c_void_p()
-        rc = L.pic_init(C.byref(h), n, cfgs, sps, xs, len(procs), stream, flags)
-        self._keep = None
-        if rc != PIC_OK:
-            raise PicError(rc, "pic_init failed")
-        self._h = h
+        try:
+            self._h = pic_init(cfgs, sps, xs, len(procs), stream, flags)
+        finally:
+            self._keep = None
         self.n_cases = n
         self.schemes = [int(w["case"].get("scheme", 0)) for w in workloads]
 
     # ------------------------------------------------------------------
-    def _check(self, rc, what):
-        if rc != PIC_OK:
-            msg = lib().pic_last_error(self._h)
-            raise PicError(rc, f"{what}: {msg.decode() if msg else ''}")
-
     def close(self):
         if getattr(self, "_h", None):
-            lib().pic_destroy(self._h)
+            pic_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -233,40 +343,29 @@ class PicContext:
             pass
 
     def step(self, n=1):
-        self._check(lib().pic_step(self._h, n), "pic_step")
+        pic_step(self._h, n)
 
     def step_explicit(self, n=1):
-        self._check(lib().pic_step_explicit(self._h, n), "pic_step_explicit")
+        pic_step_explicit(self._h, n)
 
     def step_implicit(self, n=1):
-        self._check(lib().pic_step_implicit(self._h, n), "pic_step_implicit")
+        pic_step_implicit(self._h, n)
 
     def set_schedule(self, sort_every=64, diag_every=0, tile=0):
-        self._check(lib().pic_set_schedule(self._h, sort_every, diag_every, tile),
-                    "pic_set_schedule")
+        pic_set_schedule(self._h, sort_every, diag_every, tile)
 
     def set_launch(self, graph=0, timing_every=1):
         """Host launches (graph=0) or replay of a captured sort period
         (graph=1); HIP-event timing of every timing_every-th step."""
-        self._check(lib().pic_set_launch(self._h, int(graph), int(timing_every)),
-                    "pic_set_launch")
+        pic_set_launch(self._h, graph, timing_every)
 
     def autotune(self, tiles=None, sorts=None, steps_per_trial=32):
-        """Pick the fastest tile and sort period by timing real steps
-        (pic_autotune); returns (tile, sort_every, ms per step of each trial)."""
-        def arr(v):
-            return (None, 0) if v is None else ((C.c_int32 * len(v))(*v), len(v))
-        t, nt = arr(tiles)
-        so, ns = arr(sorts)
-        n_ms = (nt if tiles is not None else 6) + (ns if sorts is not None else 4)
-        ms = (C.c_double * n_ms)()
-        tile, sort = C.c_int32(0), C.c_int32(0)
-        self._check(lib().pic_autotune(self._h, t, nt, so, ns, int(steps_per_trial),
-                                       C.byref(tile), C.byref(sort), ms), "pic_autotune")
-        return tile.value, sort.value, list(ms)
+        """Pick the fastest tile and sort period by timing real steps;
+        returns (tile, sort_every, ms per step of each trial)."""
+        return pic_autotune(self._h, tiles, sorts, steps_per_trial)
 
     def reset_accumulators(self):
-        self._check(lib().pic_reset_accumulators(self._h), "pic_reset_accumulators")
+        pic_reset_accumulators(self._h)
 
     def sync(self):
         """Wait for the context's stream (pic_diagnostics synchronises it)."""
@@ -274,22 +373,15 @@ class PicContext:
 
     def last_timing(self):
         """(ms, launches) of the particle pass kernel over the last step call."""
-        ms = C.c_double()
-        k = C.c_int64()
-        lib().pic_last_timing(self._h, C.byref(ms), C.byref(k))
-        return ms.value, k.value
+        return pic_last_timing(self._h)
 
     def last_timing_collide(self):
         """(ms, launches) of the collision kernel over the last step call."""
-        ms = C.c_double()
-        k = C.c_int64()
-        lib().pic_last_timing_collide(self._h, C.byref(ms), C.byref(k))
-        return ms.value, k.value
+        return pic_last_timing_collide(self._h)
 
     # ------------------------------------------------------------------
     def _diag(self, case, mask, d):
-        self._check(lib().pic_diagnostics(self._h, case, mask, C.byref(d)), "pic_diagnostics")
-        return d
+        return pic_diagnostics(self._h, case, mask, d)
 
     def counts(self, case=0):
         d = self._diag(case, 0, Diag())
@@ -350,25 +442,16 @@ class PicContext:
     # ---- plain FP64 GPU form of the same explicit method ----------------
     def fp64_init(self):
         """Copy the current state into the plain FP64 form (explicit cases)."""
-        self._check(lib().pic_fp64_reference_init(self._h), "pic_fp64_reference_init")
+        pic_fp64_reference_init(self._h)
 
     def fp64_step(self, n=1):
-        self._check(lib().pic_fp64_reference_step(self._h, n), "pic_fp64_reference_step")
+        pic_fp64_reference_step(self._h, n)
 
     def fp64_state(self, case=0, species=0, cap=None):
         """Live particles of the FP64 form: xi (cells), v (cells/step), id."""
         if cap is None:
             cap = int(self.counts(case)["n_slots"][species]) * 2 + 1024
-        a = {k: np.zeros(cap) for k in ("xi", "vx", "vy", "vz")}
-        ids = np.zeros(cap, np.uint64)
-        n = C.c_int64()
-        self._check(lib().pic_fp64_reference_state(
-            self._h, case, species, cap, *(a[k].ctypes.data_as(_D) for k in ("xi", "vx", "vy", "vz")),
-            ids.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n)), "pic_fp64_reference_state")
-        k = n.value
-        out = {key: v[:k].copy() for key, v in a.items()}
-        out["id"] = ids[:k].copy()
-        return out
+        return pic_fp64_reference_state(self._h, case, species, cap)
 
     def density(self, case=0):
         N = self.n_cells[case]

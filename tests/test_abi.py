@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_has_a_function_of_the_same_name_for_every_entry_point():
+    import inspect
+
+    import paper_1310_5284_amd as P
+    for name in declared_functions():
+        assert inspect.isfunction(getattr(P, name, None)), name
+
+
 def test_struct_layouts_match_binding(tmp_path):
     import paper_1310_5284_amd as P
     prog = tmp_path / "sz.c"
