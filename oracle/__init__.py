@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXPLICIT, IMPLICIT = 0, 1
 BC_DIRICHLET, BC_PERIODIC = 0, 1
-GATHER_EC, GATHER_MC = 0, 1
+GATHER_EC, GATHER_MC, GATHER_EC2 = 0, 1, 2
 ELASTIC, EXCITATION, IONIZATION, CHARGE_EXCHANGE = 0, 1, 2, 3
 
 
@@ -97,6 +97,9 @@ def lib():
         L.orc_gather_ec.argtypes = [C.c_int32, _D, C.c_double]
         L.orc_gather_ec.restype = C.c_double
         L.orc_gather_mc.argtypes = [C.c_int32, C.c_int32, _D, C.c_double]
+        L.orc_deposit_quadratic.argtypes = [C.c_int32, C.c_int32, C.c_int64, _D, _D]
+        L.orc_gather_ec2.argtypes = [C.c_int32, C.c_int32, _D, C.c_double]
+        L.orc_gather_ec2.restype = C.c_double
         L.orc_gather_mc.restype = C.c_double
         L.orc_create.argtypes = [C.POINTER(Case)]
         L.orc_create.restype = C.c_void_p
@@ -159,6 +162,13 @@ def deposit_linear(N: int, xi, periodic: bool = False) -> np.ndarray:
     return Q
 
 
+def deposit_quadratic(N: int, xi, periodic: bool = False) -> np.ndarray:
+    xi = _f64(xi)
+    Q = np.zeros(N + 1)
+    lib().orc_deposit_quadratic(N, int(periodic), xi.size, _dp(xi), _dp(Q))
+    return Q
+
+
 def count_cells(N: int, xi) -> np.ndarray:
     xi = _f64(xi)
     c = np.zeros(N)
@@ -192,6 +202,11 @@ def gather_ec(N, E, xi) -> float:
 def gather_mc(N, E, xi, periodic=False) -> float:
     E = _f64(E)
     return lib().orc_gather_mc(N, int(periodic), _dp(E), float(xi))
+
+
+def gather_ec2(N, E, xi, periodic=False) -> float:
+    E = _f64(E)
+    return lib().orc_gather_ec2(N, int(periodic), _dp(E), float(xi))
 
 
 # ---------------------------------------------------------------------------

@@ -240,6 +240,48 @@ double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi)
     return (1.0 - f) * nodal_E(N, periodic, E, jj) + f * nodal_E(N, periodic, E, jj + 1);
 }
 
+/* Eq. (2) with S_2, the quadratic B-spline: S_2(x) = 3/4 - x^2 for |x| <=
+ * 1/2, (3/2 - |x|)^2 / 2 for 1/2 <= |x| <= 3/2.  The nearest node i takes
+ * 3/4 - d^2, its neighbours (1/2 -+ d)^2 / 2, d = xi - i in [-1/2, 1/2). */
+void orc_deposit_quadratic(int32_t N, int32_t periodic, int64_t n, const double* xi, double* Q)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double c = floor(xi[p] + 0.5);
+        double d = xi[p] - c;
+        int64_t i = (int64_t)c;
+        double w[3] = {0.5 * (0.5 - d) * (0.5 - d), 0.75 - d * d, 0.5 * (0.5 + d) * (0.5 + d)};
+        for (int k = 0; k < 3; ++k) {
+            int64_t g = i - 1 + k;
+            if (periodic) {
+                g = ((g % N) + N) % N;          /* node N is node 0 */
+            } else {
+                if (g < 0) g = 0;               /* folded into the electrode */
+                if (g > N) g = N;
+            }
+            Q[g] += w[k];
+        }
+    }
+    if (periodic) Q[N] = Q[0];
+}
+
+/* Eq. (3) with m = 2: sum_j E_{j+1/2} S_1(xi - (j + 1/2)). */
+static double half_E(int32_t N, int32_t periodic, const double* E, int64_t j)
+{
+    if (periodic) return E[((j % N) + N) % N];
+    if (j < 0 || j >= N) return 0.0;
+    return E[j];
+}
+
+double orc_gather_ec2(int32_t N, int32_t periodic, const double* E, double xi)
+{
+    double k = floor(xi - 0.5);
+    double t = xi - 0.5 - k;
+    int64_t kk = (int64_t)k;
+    return (1.0 - t) * half_E(N, periodic, E, kk) + t * half_E(N, periodic, E, kk + 1);
+}
+
+static double gather(const orc_sim* s, double xi);
+
 /* ------------------------------------------------------------------------ */
 /* Simulation object                                                        */
 /* ------------------------------------------------------------------------ */
@@ -248,6 +290,9 @@ static void* xcalloc(size_t n, size_t sz) { return calloc(n ? n : 1, sz); }
 orc_sim* orc_create(const orc_case* c)
 {
     if (c->n_cells < 2) return NULL;
+    if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
+    /* m = 2 is built for the explicit scheme only */
+    if (c->gather == ORC_GATHER_EC2 && c->scheme == ORC_IMPLICIT) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->c = *c;
     s->dx = c->gap_m / c->n_cells;
@@ -481,7 +526,10 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
     for (int k = 0; k < 2; ++k) {
         memset(s->Q[k], 0, sizeof(double) * ((size_t)N + 1));
         memset(s->cnt[k], 0, sizeof(double) * (size_t)N);
-        orc_deposit_linear(N, periodic, s->sp[k].n, s->sp[k].xi, s->Q[k]);
+        if (s->c.gather == ORC_GATHER_EC2)
+            orc_deposit_quadratic(N, periodic, s->sp[k].n, s->sp[k].xi, s->Q[k]);
+        else
+            orc_deposit_linear(N, periodic, s->sp[k].n, s->sp[k].xi, s->Q[k]);
         orc_count_cells(N, s->sp[k].n, s->sp[k].xi, s->cnt[k]);
     }
     for (int32_t g = 0; g <= N; ++g) {
@@ -757,10 +805,18 @@ static void end_ledger(orc_sim* s, const double* vhalf_x[2])
 /* phi_0 = V(t_n), gather (Eq. 3 for EC, CIC for MC), push, absorb/wrap,    */
 /* MCC on v_{n+1/2}.                                                        */
 /* ------------------------------------------------------------------------ */
-static void step_explicit(orc_sim* s)
+/* the field at a particle, by the case's gather */
+static double gather(const orc_sim* s, double xi)
 {
     int32_t N = s->c.n_cells;
     int periodic = s->c.bc == ORC_BC_PERIODIC;
+    if (s->c.gather == ORC_GATHER_MC) return orc_gather_mc(N, periodic, s->E, xi);
+    if (s->c.gather == ORC_GATHER_EC2) return orc_gather_ec2(N, periodic, s->E, xi);
+    return orc_gather_ec(N, s->E, xi);
+}
+
+static void step_explicit(orc_sim* s)
+{
     fields(s, 0, s->step);
     begin_ledger(s, 0);
     for (int k = 0; k < 2; ++k) {
@@ -769,8 +825,7 @@ static void step_explicit(orc_sim* s)
         double dt_dx = s->c.dt_s / s->dx;
         int64_t i = 0;
         while (i < p->n) {
-            double Ep = s->c.gather == ORC_GATHER_EC ? orc_gather_ec(N, s->E, p->xi[i])
-                                                     : orc_gather_mc(N, periodic, s->E, p->xi[i]);
+            double Ep = gather(s, p->xi[i]);
             double dv = qm_dt * Ep;
             /* 1/2 m (v+dv)^2 - 1/2 m v^2 written without cancellation */
             double dK = p->m * p->w * dv * (p->vx[i] + 0.5 * dv);
@@ -807,8 +862,6 @@ static void step_explicit(orc_sim* s)
 /* ------------------------------------------------------------------------ */
 static void step_implicit(orc_sim* s)
 {
-    int32_t N = s->c.n_cells;
-    int periodic = s->c.bc == ORC_BC_PERIODIC;
     double dt = s->c.dt_s, dt_dx = s->c.dt_s / s->dx;
     fields(s, 1, s->step + 1);
     begin_ledger(s, 1);
@@ -817,8 +870,7 @@ static void step_implicit(orc_sim* s)
         double qm = p->q / p->m;
         int64_t i = 0;
         while (i < p->n) {
-            double Ep = s->c.gather == ORC_GATHER_EC ? orc_gather_ec(N, s->E, p->xi[i])
-                                                     : orc_gather_mc(N, periodic, s->E, p->xi[i]);
+            double Ep = gather(s, p->xi[i]);
             double a = qm * Ep;
             double vold = p->vx[i] - 0.5 * dt * p->abar[i];    /* v_{n-1/2}  */
             double vnew = p->vx[i] + 0.5 * dt * a;             /* v_{n+1/2}  */

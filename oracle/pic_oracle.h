@@ -27,7 +27,11 @@ extern "C" {
 
 enum { ORC_BC_DIRICHLET = 0, ORC_BC_PERIODIC = 1 };
 enum { ORC_EXPLICIT = 0, ORC_IMPLICIT = 1 };
-enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1 };
+/* EC: Eqs. (2)-(3) with m = 1 (S_1 deposit, S_0 gather of the half-grid
+ * field); MC: S_1 deposit, S_1 gather of the nodal field; EC2: Eqs. (2)-(3)
+ * with m = 2 read as spline degree (S_2 deposit, S_1 gather of the half-grid
+ * field), explicit only. */
+enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1, ORC_GATHER_EC2 = 2 };
 enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONIZATION = 2, ORC_CHARGE_EXCHANGE = 3 };
 
 /* Null-collision waiting time word: count of non-candidate steps left
@@ -39,7 +43,7 @@ typedef struct {
     int32_t n_cells;        /* N cells, N+1 nodes                                  */
     int32_t bc;             /* ORC_BC_*                                            */
     int32_t scheme;         /* ORC_EXPLICIT or ORC_IMPLICIT (D1, beta = 1/2)       */
-    int32_t gather;         /* ORC_GATHER_EC (Eq. 3) or ORC_GATHER_MC (CIC)        */
+    int32_t gather;         /* ORC_GATHER_EC (Eq. 3), ORC_GATHER_MC (CIC), EC2     */
     int32_t collisions;     /* 0 / 1                                               */
     int32_t pad0;
     double gap_m;           /* L                                                   */
@@ -96,6 +100,16 @@ void orc_solve_periodic(int32_t N, double dx, const double* rho, const double* c
 /* Eq. (3) gathers at one particle. */
 double orc_gather_ec(int32_t N, const double* E, double xi);
 double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi);
+/* Eq. (2) with the quadratic spline S_2 (degree 2, support 3 cells): a
+ * particle at xi with nearest node i = floor(xi + 1/2) and d = xi - i gives
+ * (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2 to nodes i-1, i, i+1.  Nodes
+ * beyond an electrode fold into it (Dirichlet); periodic nodes wrap. */
+void orc_deposit_quadratic(int32_t N, int32_t periodic, int64_t n, const double* xi,
+                           double* Q);
+/* Eq. (3) with m = 2: S_1 interpolation of the half-grid field E_{j+1/2}
+ * (values at the cell centres); beyond an electrode the half-grid field is 0
+ * (the counterpart of folding the charge into the electrode node). */
+double orc_gather_ec2(int32_t N, int32_t periodic, const double* E, double xi);
 
 /* ---- the simulation object ---- */
 orc_sim* orc_create(const orc_case* c);

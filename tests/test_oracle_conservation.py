@@ -116,3 +116,19 @@ def test_split_run_equals_whole_run(orc, scheme):
         ox, oy = np.argsort(x["id"]), np.argsort(y["id"])
         for f in ("xi", "vx", "vy", "vz", "abar", "id"):
             assert np.array_equal(x[f][ox], y[f][oy]), f
+
+
+@pytest.mark.parametrize("ratio", [5.0, 20.0])
+def test_ec2_energy_error_shrinks_like_dt_squared(orc, ratio):
+    # m = 2 (quadratic deposit, linear gather of the half-grid field) is an
+    # energy-conserving pair too
+    errs = [thermal(orc, ratio, 2, w)[0] for w in (0.2, 0.1, 0.05)]
+    for a, b in zip(errs, errs[1:]):
+        assert 3.0 <= a / b <= 5.5, errs
+
+
+def test_ec2_does_not_heat_where_mc_does(orc):
+    rate_mc = thermal(orc, 20.0, 1, 0.2)[1]
+    rate_ec2 = thermal(orc, 20.0, 2, 0.2)[1]
+    assert rate_mc > 1e-3
+    assert abs(rate_ec2) < 0.05 * rate_mc

@@ -183,3 +183,71 @@ def test_mc_and_ec_susceptibility_agree_for_uniform_plasma(orc, periodic):
     chi_ec, _ = _chi(orc, N, xi, gather=0, periodic=periodic)
     assert np.allclose(chi_mc, 5.0 * u, rtol=1e-12)
     assert np.allclose(chi_ec, 5.0 * u, rtol=1e-12)
+
+
+def S2(x):
+    # quadratic B-spline: the convolution of the top hat with S_1
+    a = np.abs(x)
+    return np.where(a <= 0.5, 0.75 - a * a, np.where(a <= 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+@pytest.mark.parametrize("N,periodic", [(7, False), (9, True), (3, False)])
+def test_quadratic_deposit_brute_force(orc, N, periodic):
+    # Eq. (2) with m = 2 read as spline degree: every node -1..N+1 takes
+    # S_2(node - xi); nodes beyond an electrode fold into it, periodic wrap
+    rng = np.random.default_rng(5 + N)
+    xi = rng.uniform(0.0, N, 300)
+    xi[:3] = [0.0, N - 1e-9, 0.5]
+    Q = orc.deposit_quadratic(N, xi, periodic)
+    B = np.zeros(N + 3)          # nodes -1 .. N+1
+    for p in xi:
+        B += S2(np.arange(-1, N + 2) - p)
+    if periodic:
+        ref = np.zeros(N)
+        for g in range(-1, N + 2):
+            ref[g % N] += B[g + 1]
+        assert np.allclose(Q[:N], ref, rtol=1e-12, atol=1e-12)
+        assert Q[N] == Q[0]
+        assert abs(Q[:N].sum() - xi.size) < 1e-9
+    else:
+        ref = B[1:N + 2].copy()
+        ref[0] += B[0]
+        ref[N] += B[N + 2]
+        assert np.allclose(Q, ref, rtol=1e-12, atol=1e-12)
+        assert abs(Q.sum() - xi.size) < 1e-9
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_ec2_gather_brute_force(orc, periodic):
+    N = 6
+    rng = np.random.default_rng(11)
+    E = rng.normal(size=N)
+    for xi in np.concatenate([rng.uniform(0, N, 40), [0.0, 0.25, 0.5, N - 0.5, N - 1e-9]]):
+        ref = 0.0
+        for j in range(-1, N + 1):
+            if periodic:
+                e = E[j % N]
+            else:
+                e = E[j] if 0 <= j < N else 0.0   # no half-grid field beyond an electrode
+            ref += e * S1(xi - (j + 0.5))
+        assert abs(orc.gather_ec2(N, E, xi, periodic) - ref) < 1e-12
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_ec2_gather_is_minus_the_gradient_of_the_deposit_energy(orc, periodic):
+    # the energy-conserving pair: with E_{j+1/2} = phi_j - phi_{j+1} (dx = 1),
+    # the gathered field at xi equals -d/dxi sum_g phi_g w_g(xi), w_g the
+    # particle's own node weights (fold and wrap included)
+    N = 8
+    rng = np.random.default_rng(3)
+    phi = rng.normal(size=N + 1)
+    if periodic:
+        phi[N] = phi[0]
+    E = phi[:N] - phi[1:]
+    h = 1e-6
+    for xi in np.concatenate([rng.uniform(0.02, N - 0.02, 60), [0.3, N - 0.3]]):
+        def energy(x):
+            w = orc.deposit_quadratic(N, [x], periodic)
+            return (w[:N] * phi[:N]).sum() if periodic else (w * phi).sum()
+        grad = (energy(xi + h) - energy(xi - h)) / (2 * h)
+        assert abs(orc.gather_ec2(N, E, xi, periodic) + grad) < 1e-6
