@@ -50,7 +50,16 @@ enum {
 
 enum { PIC_BC_DIRICHLET_RF = 0, PIC_BC_PERIODIC = 1 };
 enum { PIC_EXPLICIT = 0, PIC_IMPLICIT_D1 = 1 };
-enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1 };
+/* Weighting and interpolation (Sec. II, Eqs. (2)-(3)):
+ * PIC_GATHER_EC: Eq. (2) with S_1 (linear deposit to the nodes) and Eq. (3)
+ *   with S_0 (the half-grid field of the particle's own cell), m = 1;
+ * PIC_GATHER_MC: S_1 deposit and S_1 interpolation of the nodal field
+ *   (momentum-conserving);
+ * PIC_GATHER_EC2: Eqs. (2)-(3) with m = 2 read as spline degree: quadratic
+ *   S_2 deposit (weights beyond an electrode fold into its node) and S_1
+ *   interpolation of the half-grid field (zero beyond an electrode); explicit
+ *   scheme only (else PIC_E_INVAL). */
+enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1, PIC_GATHER_EC2 = 2 };
 enum { PIC_ELASTIC = 0, PIC_EXCITATION = 1, PIC_IONIZATION = 2, PIC_CHARGE_EXCHANGE = 3 };
 
 /* pic_init flags */
@@ -70,7 +79,7 @@ typedef struct {
     int32_t n_cells;        /* N >= 2 and N <= PIC_MAX_CELLS                    */
     int32_t bc;             /* PIC_BC_*                                         */
     int32_t scheme;         /* PIC_EXPLICIT | PIC_IMPLICIT_D1 (beta = 1/2)      */
-    int32_t gather;         /* PIC_GATHER_EC (Eq. (3), S_0) | PIC_GATHER_MC     */
+    int32_t gather;         /* PIC_GATHER_EC | PIC_GATHER_MC | PIC_GATHER_EC2   */
     int32_t collisions;     /* 0 / 1                                            */
     int32_t history_steps;  /* ledger rows kept on the device (ring), >= 0      */
     double gap_m;
@@ -281,7 +290,8 @@ int pic_reset_accumulators(pic_ctx* ctx);
 /* Plain FP64 GPU form of the same explicit method (fp64 absolute positions
  * and velocities, fp64 global-atomic deposit, no sort, one launch per phase),
  * used as the throughput comparison point.  Advances its own copy of the
- * context's initial state. */
+ * context's initial state.  Explicit cases with PIC_GATHER_EC or
+ * PIC_GATHER_MC only (else PIC_E_INVAL). */
 int pic_fp64_reference_init(pic_ctx* ctx);
 int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
 int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,

@@ -198,7 +198,7 @@ __host__ __device__ inline StepLds step_lds_layout(int N, bool diag)
 {
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
-    L.heat = L.dep + align16(8 * (size_t)N);
+    L.heat = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;

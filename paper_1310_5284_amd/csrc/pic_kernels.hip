@@ -61,8 +61,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
     const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
     const double rho_bg = Cc.background_rho;
+    const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
-        long long cn[kB][2], wr[kB][2], wl[kB][2];
+        long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
             const int g = tid + (k0 + k) * NT;
@@ -75,9 +76,11 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             for (int s = 0; s < 2; ++s) {
                 const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
                 const long long l = (long long)dw[s][il];
+                const long long nq = (long long)dw[s][min(gg, N)];
                 cn[k][s] = hr ? c : 0;
                 wr[k][s] = hr ? r : 0;
                 wl[k][s] = hl ? l : 0;
+                qn[k][s] = in ? nq : 0;
             }
         }
 #pragma unroll
@@ -87,7 +90,8 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             double rho = rho_bg, chin = 0.0;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const long long q = cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
+                const long long q =
+                    ec2 ? qn[k][s] : cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
                 gp(Cc.qfix[s])[g] = q;
                 if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
                 rho += (double)q * (s == 0 ? qs0 : qs1);
@@ -128,7 +132,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
-        if (j < N) {
+        if (j <= N) {   // node N: the quadratic deposit's last node
             gp(Cc.dep_cnt[0])[j] = 0; gp(Cc.dep_cnt[1])[j] = 0;
             gp(Cc.dep_w[0])[j] = 0; gp(Cc.dep_w[1])[j] = 0;
         }
@@ -329,6 +333,66 @@ __device__ __forceinline__ float gather_mc(const float* en, int c, float o)
     return (1.0f - o) * en[c] + o * en[c + 1];
 }
 
+// Eq. (3) with m = 2 (spline degree): linear interpolation of the half-grid
+// field (cell values eh[N], at the cell centres) at offset o of cell c; no
+// half-grid field beyond an electrode, a periodic grid wraps.
+__device__ __forceinline__ float gather_ec2(const float* eh, int N, bool periodic, int c, float o)
+{
+    const bool up = o >= 0.5f;
+    const int k = up ? c : c - 1;            // half-grid point at or left of x
+    const float t = up ? o - 0.5f : o + 0.5f;
+    float e0, e1;
+    if (periodic) {
+        e0 = eh[k < 0 ? N - 1 : k];
+        e1 = eh[k + 1 >= N ? 0 : k + 1];
+    } else {
+        e0 = k >= 0 ? eh[k] : 0.0f;
+        e1 = k + 1 < N ? eh[k + 1] : 0.0f;
+    }
+    return (1.0f - t) * e0 + t * e1;
+}
+
+// Eq. (2) with m = 2: quadratic (S_2) weights of a particle at offset o of
+// cell c, in units of 2^-24 particle: nearest node i = c or c + 1,
+// d = c + o - i in [-1/2, 1/2); nodes i-1, i, i+1 take (1/2 - d)^2 / 2,
+// 3/4 - d^2, (1/2 + d)^2 / 2, the middle one as the exact complement.
+__device__ __forceinline__ int quad_weights(int c, float o, uint32_t w[3])
+{
+    const bool up = o >= 0.5f;
+    const float d = up ? o - 1.0f : o;
+    const float a = 0.5f - d, b = 0.5f + d;
+    w[0] = __float2uint_rn(0.5f * a * a * 16777216.0f);
+    w[2] = __float2uint_rn(0.5f * b * b * 16777216.0f);
+    w[1] = (1u << 24) - w[0] - w[2];
+    return c + (up ? 1 : 0);
+}
+
+// A node index of the quadratic weights: folded into the electrode beyond
+// which it lies (Dirichlet), wrapped (periodic).
+__device__ __forceinline__ int fold_node(int g, int N, bool periodic)
+{
+    if (periodic) return g < 0 ? g + N : (g >= N ? g - N : g);
+    return min(max(g, 0), N);
+}
+
+// Quadratic deposit of one particle into a privatised node grid (N+1 words):
+// weights in the low 40 bits; the particle's cell count rides on the word
+// of node c (always one of the three).
+__device__ __forceinline__ void deposit_quad(unsigned long long* dep, bool want, int c, float o,
+                                             int N, bool periodic, int& lo, int& hi)
+{
+    if (!want) return;
+    uint32_t w[3];
+    const int i = quad_weights(c, o, w);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int g0 = i - 1 + k;
+        const int g = fold_node(g0, N, periodic);
+        atomicAdd(&dep[g], (unsigned long long)w[k] + (g0 == c ? kCountOne : 0ull));
+        range_note(lo, hi, g);
+    }
+}
+
 // Nodal field of node g from the cell fields of one species: the mean of the
 // two adjacent cells; the electrodes take the field of their own cell, a
 // periodic grid wraps.
@@ -525,6 +589,24 @@ __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want,
     }
 }
 
+// Deposit of one particle straight into the case grids (ionization
+// children, rare): linear (count and weight of its cell) or quadratic.
+__device__ __forceinline__ void deposit_global(const Case* C, int s, int c, float o)
+{
+    PIC_GLOBAL unsigned long long* gcnt = gp(C->dep_cnt[s]);
+    PIC_GLOBAL unsigned long long* gw = gp(C->dep_w[s]);
+    if (C->gather == 2) {
+        uint32_t w[3];
+        const int i = quad_weights(c, o, w);
+        for (int k = 0; k < 3; ++k)
+            gatomic_add(&gw[fold_node(i - 1 + k, C->n_cells, C->bc == 1)],
+                        (unsigned long long)w[k]);
+    } else {
+        gatomic_add(&gw[c], packw(o) & kWMask);
+    }
+    gatomic_add(&gcnt[c], 1ull);
+}
+
 // ---------------------------------------------------------------------------
 // k_step: the particle pass of one step of every case in this launch.
 // Workgroup = a contiguous chunk of one species of one case.  Per particle
@@ -575,6 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const double kin_unit = C->sp[s].kin_unit;
     const bool periodic = C->bc == 1;
     const bool mc = C->gather == 1;
+    const bool ec2 = C->gather == 2;
     const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
     const StepLds L = step_lds_layout(N, DIAG);
@@ -596,6 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         dep[j] = 0ull;
         if (DIAG) heat[j] = 0.0f;
     }
+    if (tid == 0) dep[N] = 0ull;   // node N of the quadratic deposit
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
     if (tid == 0) {
@@ -664,7 +748,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             uint32_t wt = wait_of(c[k]);
             bool live = cc >= 0;
             float a = 0.0f;
-            if (live) a = mc ? gather_mc(eh, cc, o[k]) : eh[cc];
+            if (live) a = mc ? gather_mc(eh, cc, o[k])
+                             : (ec2 ? gather_ec2(eh, N, periodic, cc, o[k]) : eh[cc]);
             float vn, vold, abn = 0.0f, o1;
             if (kImp) {
                 vold = v[k] - 0.5f * ab[k];
@@ -771,7 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
                 dep_now = !kImp || kept;
             }
-            deposit_wave(dep, dep_now, c2, o2, lo, hi);
+            if (ec2)
+                deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi);
+            else
+                deposit_wave(dep, dep_now, c2, o2, lo, hi);
             // list the candidates of this wavefront in the workgroup's region
             const bool enq = live && isc;
             const unsigned long long qm = __ballot(enq);
@@ -990,8 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                                         4u, k0, k1);
                 write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
                                wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
-                gatomic_add(gp(&C->dep_cnt[0][ce]), 1ull);
-                gatomic_add(gp(&C->dep_w[0][ce]), packw(oe) & kWMask);
+                deposit_global(C, 0, ce, oe);
             } else {
                 atomicAdd(&acc.n_lost[0], 1u);
             }
@@ -1002,8 +1089,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                                         (1u << 28) | 4u, k0, k1);
                 write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
                                wait_encode(geo0(r4.x, inv_ion)), kImp);
-                gatomic_add(gp(&C->dep_cnt[1][ci]), 1ull);
-                gatomic_add(gp(&C->dep_w[1][ci]), packw(oi) & kWMask);
+                deposit_global(C, 1, ci, oi);
             } else {
                 atomicAdd(&acc.n_lost[1], 1u);
             }
@@ -1565,7 +1651,8 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     const Species& S = C->sp[w.s];
     const int N = C->n_cells;
     unsigned long long* dep = (unsigned long long*)smem;
-    for (int j = threadIdx.x; j < N; j += kBlock) dep[j] = 0ull;
+    for (int j = threadIdx.x; j <= N; j += kBlock) dep[j] = 0ull;
+    const bool ec2 = C->gather == 2, periodic = C->bc == 1;
     if (threadIdx.x == 0) {
         s_lo = kNoCell;
         s_hi = -1;
@@ -1579,8 +1666,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
         const int c = cell_of(S.cell[i]);
         if (c < 0) continue;
-        atomicAdd(&dep[c], packw(S.off[i]));
-        range_note(lo, hi, c);
+        if (ec2) {
+            deposit_quad(dep, true, c, S.off[i], N, periodic, lo, hi);
+        } else {
+            atomicAdd(&dep[c], packw(S.off[i]));
+            range_note(lo, hi, c);
+        }
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);

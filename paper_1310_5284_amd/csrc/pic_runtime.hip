@@ -380,7 +380,9 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         if (g.n_cells < 2 || g.n_cells > PIC_MAX_CELLS || !(g.gap_m > 0) || !(g.dt_s > 0) ||
             (g.bc != PIC_BC_DIRICHLET_RF && g.bc != PIC_BC_PERIODIC) ||
             (g.scheme != PIC_EXPLICIT && g.scheme != PIC_IMPLICIT_D1) ||
-            (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC) || g.history_steps < 0 ||
+            (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC &&
+             g.gather != PIC_GATHER_EC2) ||
+            (g.gather == PIC_GATHER_EC2 && g.scheme != PIC_EXPLICIT) || g.history_steps < 0 ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
             return bail(PIC_E_INVAL);
@@ -648,8 +650,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         // grids
         int rc = 0;
         for (int s = 0; s < 2; ++s) {
-            rc |= dalloc(c, h.allocs, &C.dep_cnt[s], N);
-            rc |= dalloc(c, h.allocs, &C.dep_w[s], N);
+            rc |= dalloc(c, h.allocs, &C.dep_cnt[s], N + 1);   // node N: quadratic deposit
+            rc |= dalloc(c, h.allocs, &C.dep_w[s], N + 1);
             rc |= dalloc(c, h.allocs, &C.ehat[s], N);
             rc |= dalloc(c, h.allocs, &C.qfix[s], N + 1);
             rc |= dalloc(c, h.allocs, &C.ccount[s], N);
@@ -670,7 +672,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         hist_total += 2 * (size_t)N;
     }
     if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true), collide_lds_bytes(c->maxN)),
-                                   std::max(8 * (size_t)c->maxN, fin_lds(c->maxN)))))
+                                   std::max(8 * ((size_t)c->maxN + 1), fin_lds(c->maxN)))))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
@@ -724,8 +726,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         INITCHK(hipGetLastError());
         if (compaction(c)) return bail(PIC_E_DEVICE);
         Params p = params(c, 0);
-        hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock), 8 * (size_t)c->maxN,
-                           c->stream, p);
+        hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock),
+                           8 * ((size_t)c->maxN + 1), c->stream, p);
         hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock), fin_lds(c->maxN),
                            c->stream, p);
         INITCHK(hipGetLastError());

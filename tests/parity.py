@@ -51,7 +51,7 @@ def normwise(a, b):
     return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
 
 
-def compare_fields(gf, of, implicit, case=None):
+def compare_fields(gf, of, implicit, case=None, gather=0):
     err = {}
     for k in ("rho", "phi", "E"):
         err[k] = normwise(gf[k], of[k])
@@ -60,8 +60,14 @@ def compare_fields(gf, of, implicit, case=None):
     for s, key in enumerate(("Qe", "Qi")):
         q = gf["qfix"][s].astype(np.float64) / 2 ** 24
         cnt = np.concatenate([of["cnt_e" if s == 0 else "cnt_i"], [0]])
-        # each particle's two weights are rounded to 2^-25 at most
-        bound = (cnt + np.roll(cnt, 1) + 1) * 2.0 ** -24 + 1e-9 * np.abs(of[key]).max()
+        if gather == 2:
+            # quadratic weights: a node takes the particles of cells g-2..g+1,
+            # each weight computed in float32 and rounded to 2^-24
+            near = cnt + np.roll(cnt, 1) + np.roll(cnt, 2) + np.roll(cnt, -1)
+            bound = 3.0 * (near + 1) * 2.0 ** -24 + 1e-9 * np.abs(of[key]).max()
+        else:
+            # each particle's two weights are rounded to 2^-25 at most
+            bound = (cnt + np.roll(cnt, 1) + 1) * 2.0 ** -24 + 1e-9 * np.abs(of[key]).max()
         assert np.all(np.abs(q - of[key]) <= bound), f"fixed-point deposit {key}"
         cg = gf["cell_count"][s].astype(np.float64)
         assert np.array_equal(cg, of["cnt_e" if s == 0 else "cnt_i"]), "cell counts"
@@ -129,7 +135,7 @@ def teacher_forced(ctx, wl, steps, case=0, check_ledger=True, verbose=False):
         sim = oracle.Sim(case_o, sps, wl["processes"], startup=False)
         sim.compute_fields()
         of = sim.fields()
-        fe = compare_fields(gf, of, implicit)
+        fe = compare_fields(gf, of, implicit, gather=c.get("gather", 0))
         for k, v in fe.items():
             rep["fields"][k] = max(rep["fields"].get(k, 0.0), v)
         sim.step(1)

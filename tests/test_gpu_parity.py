@@ -30,7 +30,7 @@ def test_ccp64_explicit_teacher_forced(collisions):
     assert_report(rep)
 
 
-@pytest.mark.parametrize("gather", [0, 1])
+@pytest.mark.parametrize("gather", [0, 1, 2])
 def test_periodic_thermal_teacher_forced(gather):
     wl = W.c2(ratio=5.0, gather=gather, ppc=100, n_cells=32)
     ctx = ctx_for(wl)
@@ -117,5 +117,16 @@ def test_ccp256_mc_implicit_teacher_forced():
         sp["capacity"] = 2 * sp["cell"].size
     ctx = ctx_for(wl)
     rep = teacher_forced(ctx, wl, 40)
+    print(rep)
+    assert_report(rep)
+
+
+def test_ccp64_ec2_explicit_teacher_forced():
+    # m = 2 read as spline degree: quadratic deposit (folded at the
+    # electrodes), linear interpolation of the half-grid field
+    wl = W.c1(collisions=1, np_per_species=16384 + 77)
+    wl["case"]["gather"] = 2
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 60)
     print(rep)
     assert_report(rep)

@@ -170,6 +170,7 @@ def test_grid_heating_mc_heats_ec_does_not_on_gpu():
     r = [gpu_thermal(20.0, 1, w) for w in (0.2, 0.1)]
     rate_mc = [x[1] for x in r]
     rate_ec = gpu_thermal(20.0, 0, 0.1)[1]
+    rate_ec2 = gpu_thermal(20.0, 2, 0.1)[1]
     wl = W.c2(ratio=20.0, gather=1, ppc=64, n_cells=32, wdt=0.2, seed=7)
     case, sps, procs = W.to_oracle(wl)
     sim = oracle.Sim(case, sps, procs)
@@ -180,10 +181,12 @@ def test_grid_heating_mc_heats_ec_does_not_on_gpu():
         tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
     tot = np.array(tot)
     rate_orc = np.polyfit(np.arange(200) * 0.2, tot / tot[0], 1)[0]
-    print(f"MC heating rate {rate_mc} (oracle {rate_orc:.4g}), EC {rate_ec:.3g}")
+    print(f"MC heating rate {rate_mc} (oracle {rate_orc:.4g}), EC {rate_ec:.3g}, "
+          f"EC m=2 {rate_ec2:.3g}")
     assert rate_mc[0] > 1e-3 and rate_mc[1] > 1e-3
     assert 0.7 < rate_mc[0] / rate_mc[1] < 1.4
     assert abs(rate_ec) < 0.05 * rate_mc[1]
+    assert abs(rate_ec2) < 0.05 * rate_mc[1]
     assert 0.7 < rate_mc[0] / rate_orc < 1.4
 
 
