@@ -48,6 +48,11 @@ def make_workload(name, scale):
     import workloads as W
     if name == "ccp2048_explicit":
         return [W.c4(np_per_species=int(10_000_000 * scale))]
+    if name == "ccp2048_ec2":
+        # the same discharge with m = 2 weighting (quadratic deposit)
+        wl = W.c4(np_per_species=int(10_000_000 * scale))
+        wl["case"]["gather"] = 2
+        return [wl]
     if name == "ccp2048_implicit":
         # the same discharge stepped by the D1 implicit scheme
         return [W.c4(np_per_species=int(10_000_000 * scale), scheme=1)]
@@ -137,7 +142,7 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge")
 def drift_table(P, steps):
     """Total-energy drift of the periodic thermal plasma (512 cells, 1000
     electrons per cell on a fixed neutralising background) on the GPU path,
-    EC and MC gathers, dx / lambda_D = 0.5, 5, 20 at omega_p dt = 0.2, and at
+    EC (m = 1 and m = 2) and MC weightings, dx / lambda_D = 0.5, 5, 20 at omega_p dt = 0.2, and at
     dx = 5 lambda_D also omega_p dt = 0.1 and 0.05 over the same time.  The
     energy at integer steps is the mean of the kinetic energies of the two
     half steps plus the field energy; drift = slope of E / E_0 per step
@@ -147,7 +152,7 @@ def drift_table(P, steps):
     import workloads as W
     rows = []
     for ratio in (0.5, 5.0, 20.0):
-        for gather in (0, 1):
+        for gather in (0, 1, 2):
             for wdt in ((0.2, 0.1, 0.05) if ratio == 5.0 else (0.2,)):
                 n = int(round(steps * 0.2 / wdt))
                 every = max(1, n // 200)
@@ -168,7 +173,7 @@ def drift_table(P, steps):
                 dt_s = time.perf_counter() - t0
                 ctx.close()
                 e = np.array(es) / es[0]
-                rows.append(dict(dx_over_lambda_D=ratio, gather=("EC", "MC")[gather],
+                rows.append(dict(dx_over_lambda_D=ratio, gather=("EC", "MC", "EC2")[gather],
                                  omega_p_dt=wdt, steps=n,
                                  drift_per_step=float(np.polyfit(xs, e, 1)[0]),
                                  max_rel_err=float(np.abs(e - 1.0).max()),
@@ -334,7 +339,8 @@ def main():
                roofline=roof, collide=collide)
     if tuned:
         out["autotune"] = tuned
-    if args.fp64_steps > 0 and all(sc == 0 for sc in schemes):
+    if args.fp64_steps > 0 and all(sc == 0 for sc in schemes) and \
+            all(w["case"].get("gather", 0) != 2 for w in wls):
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
         ctx.fp64_init()
