@@ -375,15 +375,52 @@ __device__ __forceinline__ int fold_node(int g, int N, bool periodic)
     return min(max(g, 0), N);
 }
 
-// Quadratic deposit of one particle into a privatised node grid (N+1 words):
-// weights in the low 40 bits; the particle's cell count rides on the word
-// of node c (always one of the three).
+// Quadratic deposit of one particle per lane into a privatised node grid
+// (N+1 words): weights in the low 40 bits; the particle's cell count rides on
+// the word of node c (always one of the three).  Called by whole wavefronts.
+// sorted: when every depositing lane is in one cell (cell-sorted ions), the
+// lanes on each side of the cell centre share their three nodes, and their
+// weights are summed across the wavefront before one atomic per node.
 __device__ __forceinline__ void deposit_quad(unsigned long long* dep, bool want, int c, float o,
-                                             int N, bool periodic, int& lo, int& hi)
+                                             int N, bool periodic, int& lo, int& hi,
+                                             bool sorted = false)
 {
+    uint32_t w[3] = {0u, 0u, 0u};
+    int i = c;
+    if (want) i = quad_weights(c, o, w);
+    if (sorted) {
+        const unsigned long long m = __ballot(want);
+        if (m == 0ull) return;
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)m) - 1;
+        const int cl = __builtin_amdgcn_readlane(c, leader);
+        if (__ballot(want && c != cl) == 0ull) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool mine = want && (i == cl + side);
+                const unsigned long long mg = __ballot(mine);
+                if (mg == 0ull) continue;
+                const int gl = __ffsll((long long)mg) - 1;
+                uint32_t t[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t[k] = wave_total_u32(mine ? w[k] : 0u);
+                if (lane == gl) {
+                    const int i0 = cl + side;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int g0 = i0 - 1 + k;
+                        const int g = fold_node(g0, N, periodic);
+                        atomicAdd(&dep[g], (unsigned long long)t[k] +
+                                               (g0 == cl ? (unsigned long long)__popcll(mg) *
+                                                               kCountOne : 0ull));
+                        range_note(lo, hi, g);
+                    }
+                }
+            }
+            return;
+        }
+    }
     if (!want) return;
-    uint32_t w[3];
-    const int i = quad_weights(c, o, w);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int g0 = i - 1 + k;
@@ -857,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 dep_now = !kImp || kept;
             }
             if (ec2)
-                deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi);
+                deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             else
                 deposit_wave(dep, dep_now, c2, o2, lo, hi);
             // list the candidates of this wavefront in the workgroup's region
