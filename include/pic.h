@@ -49,6 +49,12 @@ enum {
 };
 
 enum { PIC_BC_DIRICHLET_RF = 0, PIC_BC_PERIODIC = 1 };
+/* PIC_IMPLICIT_D1: the D1 direct-implicit push (beta = 1/2) with the field
+ * solve -d/dx(eps0 (1 + chi) dphi/dx) = rho~ of the predicted positions; the
+ * susceptibility chi_{j+1/2} = beta dt^2/(eps0 dx) sum_s q_s^2 w_s/m_s N_{s,j}
+ * counts the predicted particles of cell j (EC gather), or is the mean of
+ * the two node values beta dt^2/eps0 sum_s q_s^2 w_s/m_s Q_{s,g}/V_g of the
+ * linear node weights (MC gather; V_g = dx, dx/2 at an electrode node). */
 enum { PIC_EXPLICIT = 0, PIC_IMPLICIT_D1 = 1 };
 /* Weighting and interpolation (Sec. II, Eqs. (2)-(3)):
  * PIC_GATHER_EC: Eq. (2) with S_1 (linear deposit to the nodes) and Eq. (3)
@@ -188,7 +194,7 @@ typedef struct {
     double* rho;                /* [N+1] C/m^3                                  */
     double* phi;                /* [N+1] V                                      */
     double* E;                  /* [N]   V/m at x_{j+1/2}                       */
-    double* chi;                /* [N]   susceptibility (implicit), else 0      */
+    double* chi;                /* [N]   susceptibility chi_{j+1/2} (implicit), else 0 */
     int64_t* qfix[2];           /* [N+1] node deposits in units of 2^-24 particle */
     int64_t* cell_count[2];     /* [N]   particles per cell                     */
     /* PIC_DIAG_LEDGER */
