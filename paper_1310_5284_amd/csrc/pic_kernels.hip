@@ -71,16 +71,16 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             const int gl = gg > 0 ? gg - 1 : (periodic ? N - 1 : -1);
             const bool in = g <= N;
             const bool hr = in && gg < N, hl = in && gl >= 0;
-            const int ir = min(gg, N - 1), il = max(min(gl, N - 1), 0);
+            // m = 2 reads node words (N+1 of them); cell words otherwise
+            const int ir = min(gg, ec2 ? N : N - 1), il = max(min(gl, N - 1), 0);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
                 const long long l = (long long)dw[s][il];
-                const long long nq = (long long)dw[s][min(gg, N)];
                 cn[k][s] = hr ? c : 0;
                 wr[k][s] = hr ? r : 0;
                 wl[k][s] = hl ? l : 0;
-                qn[k][s] = in ? nq : 0;
+                qn[k][s] = in ? r : 0;
             }
         }
 #pragma unroll
