@@ -70,12 +70,13 @@ def make_workload(name, scale):
 
 
 def kernel_source_hash():
-    """sha256 (first 16 hex) of the kernel sources with comments and blank
-    space removed: a comment edit does not change the kernels."""
+    """sha256 (first 16 hex) of the sources of the particle kernels (k_step,
+    k_collide and the helpers they include) with comments and blank space
+    removed: a comment edit does not change the kernels."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("pic_kernels.hip", "pic_common.hpp", "pic_device.hpp"):
+    for f in ("pic_step.hip", "pic_weights.hpp", "pic_common.hpp", "pic_device.hpp"):
         with open(os.path.join(ROOT, "paper_1310_5284_amd", "csrc", f)) as fh:
             t = fh.read()
         t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)

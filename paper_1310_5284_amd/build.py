@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpicmcc.so")
-SOURCES = ["pic_kernels.hip", "pic_runtime.hip", "pic_fp64.hip", "pic_measure.hip"]
+SOURCES = ["pic_step.hip", "pic_grid.hip", "pic_runtime.hip", "pic_fp64.hip", "pic_measure.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,675 @@
+// HIP kernels of the grid side of a step for gfx950 (MI355X): k_finalize
+// (the FP64 field solve of the next step, Sec. II, and the energy ledger of
+// the step just taken, one workgroup each per case), the compaction and sort
+// of the particle arrays, and the set-up kernels (unit conversion, D1
+// start-up, first waits, first deposit and solve).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+#include "pic_common.hpp"
+#include "pic_device.hpp"
+#include "pic_weights.hpp"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// FP64 field solve of one case by one workgroup.
+//
+// Gauss's law between half-grid points, D_{j+1/2} - D_{j-1/2} = dx rho_j with
+// D = eps0 (1 + chi) E, is integrated by a prefix sum: D_{j+1/2} = D_{1/2} +
+// R_j, R_j = dx sum_{k=1..j} rho_k.  The one free constant follows from the
+// boundary condition sum_j E_{j+1/2} dx = phi_0 - phi_N (V(t) on the driven
+// electrode, or 0 for a periodic box).  chi = 0 is the Poisson solve of the
+// explicit cycle; chi from the predicted cell counts the susceptibility-
+// modified solve of the direct-implicit cycle.  O(log N) deep.
+// ---------------------------------------------------------------------------
+constexpr double kEps0 = 8.8541878128e-12;
+
+template <int NT>
+__device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step,
+                                           long long field_step, bool sample_density, double* S,
+                                           double* red)
+{
+    constexpr int kPer = (PIC_MAX_CELLS + 1 + NT - 1) / NT;   // nodes per thread
+    // register copy of the case: the stores below cannot alias it, so none
+    // of its pointers is reloaded after a store
+    const Case Cc = *C;
+    const int N = Cc.n_cells, tid = threadIdx.x;
+    const bool periodic = Cc.bc == 1;
+    const bool implicit = Cc.scheme == 1;
+    const double dx = Cc.dx;
+    // X: chi_{j+1/2} of the cells (LDS, after the N+1 values of S); Y: chi
+    // of the nodes (MC implicit: the susceptibility of the linear weights,
+    // a half cell at an electrode node, averaged to the cells)
+    double* X = S + N + 1;
+    double* Y = X + N;
+    const bool node_chi = implicit && Cc.gather == 1;
+    // node g = tid + k NT needs the counts and weights of cells g and g-1
+    const PIC_GLOBAL unsigned long long* dc[2] = {gp((const unsigned long long*)Cc.dep_cnt[0]),
+                                                  gp((const unsigned long long*)Cc.dep_cnt[1])};
+    const PIC_GLOBAL unsigned long long* dw[2] = {gp((const unsigned long long*)Cc.dep_w[0]),
+                                                  gp((const unsigned long long*)Cc.dep_w[1])};
+    // Nodes in batches of kB per thread; inside a batch every load is issued
+    // before any result is used (unconditional loads from clamped indices,
+    // selected afterwards, so that none waits behind a branch).
+    constexpr int kB = 3;
+    const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
+    const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
+    const double rho_bg = Cc.background_rho;
+    const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
+    for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
+        long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int g = tid + (k0 + k) * NT;
+            const int gg = (periodic && g == N) ? 0 : g;
+            const int gl = gg > 0 ? gg - 1 : (periodic ? N - 1 : -1);
+            const bool in = g <= N;
+            const bool hr = in && gg < N, hl = in && gl >= 0;
+            // m = 2 reads node words (N+1 of them); cell words otherwise
+            const int ir = min(gg, ec2 ? N : N - 1), il = max(min(gl, N - 1), 0);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
+                const long long l = (long long)dw[s][il];
+                cn[k][s] = hr ? c : 0;
+                wr[k][s] = hr ? r : 0;
+                wl[k][s] = hl ? l : 0;
+                qn[k][s] = in ? r : 0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int g = tid + (k0 + k) * NT;
+            if (g > N) continue;
+            double rho = rho_bg, chin = 0.0;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const long long q =
+                    ec2 ? qn[k][s] : cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
+                gp(Cc.qfix[s])[g] = q;
+                if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
+                rho += (double)q * (s == 0 ? qs0 : qs1);
+                chin += (double)q * (s == 0 ? chi0 : chi1);
+            }
+            if (node_chi) {
+                const bool end = !periodic && (g == 0 || g == N);
+                Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
+            }
+            gp(Cc.rho)[g] = rho;
+            // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
+            S[g] = g == 0 ? 0.0 : rho * dx;
+            if (g < N) {
+                gp(Cc.ccount[0])[g] = cn[k][0];
+                gp(Cc.ccount[1])[g] = cn[k][1];
+                if (!node_chi) {
+                    const double chi =
+                        implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
+                    X[g] = chi;
+                    gp(Cc.chi)[g] = chi;
+                }
+            }
+        }
+    }
+    lds_barrier();   // every deposit word has been read
+    if (node_chi) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = tid + k * NT;
+            if (j < N) {
+                const double chi = 0.5 * (Y[j] + Y[j + 1]);
+                X[j] = chi;
+                gp(Cc.chi)[j] = chi;
+            }
+        }
+        lds_barrier();
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j <= N) {   // node N: the quadratic deposit's last node
+            gp(Cc.dep_cnt[0])[j] = 0; gp(Cc.dep_cnt[1])[j] = 0;
+            gp(Cc.dep_w[0])[j] = 0; gp(Cc.dep_w[1])[j] = 0;
+        }
+    }
+    block_scan<double, NT>(S, N, red);             // S[j] = R_j
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            const double kap = kEps0 * (1.0 + X[j]);
+            a += S[j] / kap;
+            b += 1.0 / kap;
+        }
+    }
+    a = block_sum<double, NT>(a, red);
+    b = block_sum<double, NT>(b, red);
+    double V = 0.0;
+    if (!periodic) {
+        // V0 sin(2 pi f t) through the phase in cycles reduced to [0, 1)
+        const double cyc = Cc.rf_freq * ((double)next_step * Cc.dt);
+        V = Cc.rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
+    }
+    const double D0 = (V / dx - a) / b;
+    double we = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            const double E = (D0 + S[j]) / (kEps0 * (1.0 + X[j]));
+            X[j] = E;   // X now holds E
+            gp(Cc.E)[j] = E;
+            gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
+            gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
+            we += 0.5 * kEps0 * E * E * dx;
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) S[j] = X[j];
+    }
+    we = block_sum<double, NT>(we, red);
+    block_scan<double, NT>(S, N, red);
+    const double phi0 = periodic ? 0.0 : V;
+    if (tid == 0) gp(Cc.phi)[0] = phi0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) gp(Cc.phi)[j + 1] = phi0 - dx * S[j];
+    }
+    if (tid == 0) {
+        st->WE[field_step & 1] = we;
+        if (!isfinite(we)) atomicOr(&st->flags, 1);
+        if (sample_density) st->dens_samples += 1;
+    }
+    lds_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// Ledger: the workgroup reduces the partials of the case's workgroups (fixed
+// order: a strided per-thread sum, then a tree), then one thread writes the
+// row and folds the appended children into the occupied slots.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void reduce_partials(const double* pd_, const unsigned* pu_, int stride,
+                                                int fb, int nb, double* sd, long long* su)
+{
+    // wavefront w sums the fields w, w + NT/64, ...: every lane strides over
+    // the workgroup partials with kU loads in flight, then a wavefront tree
+    constexpr int kU = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const PIC_GLOBAL double* pd = gp(pd_);
+    const PIC_GLOBAL unsigned* pu = gp(pu_);
+    for (int f = wave; f < PD_N + PU_N; f += NT / 64) {
+        if (f < PD_N) {
+            double a[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) a[u] = 0.0;
+            // unconditional loads from clamped indices keep all kU in flight
+            const PIC_GLOBAL double* row = pd + (size_t)f * stride + fb;
+            for (int b = lane; b < nb; b += 64 * kU)
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const double x = row[min(b + 64 * u, nb - 1)];
+                    a[u] += b + 64 * u < nb ? x : 0.0;
+                }
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v += a[u];
+            v = wave_sum(v);
+            if (lane == 0) sd[f] = v;
+        } else {
+            // per-step counts of one case fit in 32 bits
+            unsigned a = 0u;
+            const PIC_GLOBAL unsigned* row = pu + (size_t)(f - PD_N) * stride + fb;
+            for (int b = lane; b < nb; b += 64 * kU)
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const unsigned x = row[min(b + 64 * u, nb - 1)];
+                    a += b + 64 * u < nb ? x : 0u;
+                }
+            a = wave_sum(a);
+            if (lane == 0) su[f - PD_N] = (long long)a;
+        }
+    }
+    lds_barrier();
+}
+
+// Called by every thread of the workgroup.  Thread 0 reads the case's state
+// in one batch (no load waits behind a store), builds the row in LDS and
+// writes the state back; the row is then copied out by many threads.
+__device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* sd, const long long* si)
+{
+    __shared__ pic_ledger row;
+    __shared__ int ring;
+    if (threadIdx.x == 0) {
+        // fields of the state owned by the ledger (the field solve of the
+        // same finalizer runs concurrently and owns step, WE[] and samples)
+        const long long lstep = st->ledger_step;
+        const double we = st->WE[lstep & 1];
+        const double K0[2] = {st->K[0], st->K[1]};
+        const int32_t slots[2] = {st->n_slots[0], st->n_slots[1]};
+        const int32_t child[2] = {st->n_child[0], st->n_child[1]};
+        const int32_t live[2] = {st->n_live[0], st->n_live[1]};
+        const long long lost[2] = {st->lost_total[0], st->lost_total[1]};
+        const long long hn = st->history_n;
+        const double ku0 = C->sp[0].kin_unit, ku1 = C->sp[1].kin_unit;
+        const long long cap0 = C->sp[0].capacity, cap1 = C->sp[1].capacity;
+        const int hl = C->history_len;
+        row.step = lstep;
+        row.WE = we;
+        bool finite = true;
+        int flags = 0;
+        for (int s = 0; s < 2; ++s) {
+            const double ku = s == 0 ? ku0 : ku1;
+            const long long cap = s == 0 ? cap0 : cap1;
+            const double kb = K0[s];
+            const double wk = sd[PD_WORK + s] * ku, cd = sd[PD_COLL + s] * ku;
+            const double a0 = sd[PD_ABSK + 2 * s] * ku, a1 = sd[PD_ABSK + 2 * s + 1] * ku;
+            const double ka = kb + wk - a0 - a1 + cd;
+            row.K_before[s] = kb;
+            row.work[s] = wk;
+            row.coll_dK[s] = cd;
+            row.absorbed_K[s][0] = a0;
+            row.absorbed_K[s][1] = a1;
+            row.K_after[s] = ka;
+            st->K[s] = ka;
+            finite = finite && isfinite(ka);
+            row.absorbed_n[s][0] = si[PU_ABS + 2 * s];
+            row.absorbed_n[s][1] = si[PU_ABS + 2 * s + 1];
+            for (int k = 0; k < 4; ++k) row.n_coll[s][k] = si[PU_COLL + 4 * s + k];
+            row.n_candidates[s] = si[PU_CAND + s];
+            row.n_created[s] = si[PU_CREATED + s];
+            row.n_over_table[s] = si[PU_OVER + s];
+            row.n_lost[s] = si[PU_LOST + s];
+            st->n_live[s] = live[s] + (int32_t)(si[PU_CREATED + s] - si[PU_ABS + 2 * s] -
+                                                si[PU_ABS + 2 * s + 1]);
+            st->lost_total[s] = lost[s] + si[PU_LOST + s];
+            const long long ns = (long long)slots[s] + child[s];
+            st->n_slots[s] = (int32_t)(ns < cap ? ns : cap);
+            if (ns > cap || si[PU_LOST + s] > 0) flags |= 2;
+            st->n_child[s] = 0;
+        }
+        if (!finite) flags |= 1;
+        if (flags) atomicOr(&st->flags, flags);
+        st->history_n = hn + 1;
+        st->ledger_step = lstep + 1;
+        ring = hl > 0 ? 1 + (int)(hn % hl) : -1;
+    }
+    lds_barrier();
+    constexpr int kW = (int)(sizeof(pic_ledger) / 8);
+    const long long* src = (const long long*)&row;
+    long long* h = (long long*)C->history;
+    for (int k = threadIdx.x; k < kW; k += blockDim.x) {
+        h[k] = src[k];
+        if (ring > 0) h[(size_t)ring * kW + k] = src[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize: two workgroups per case after the particle pass, running side
+// by side: the odd one closes the ledger of the step (reduction of the
+// workgroup partials), the even one solves the FP64 field of the next step.
+// They write disjoint fields of the case state (flags through atomics).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kFinBlock / 64];
+    __shared__ double sd[PD_N];
+    __shared__ long long si[PU_N];
+    Case* C = P.cases + (blockIdx.x >> 1);
+    State* st = P.state + (blockIdx.x >> 1);
+    if (blockIdx.x & 1) {
+        // ledger of the step just taken
+        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+        finish_ledger(C, st, sd, si);
+        return;
+    }
+    // field of the next step (thread 0 alone reads and writes st->step)
+    __shared__ long long s_step;
+    if (threadIdx.x == 0) s_step = st->step;
+    lds_barrier();
+    const long long next = s_step + 1;
+    solve_case<kFinBlock>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
+                          (double*)smem, red);
+    if (threadIdx.x == 0) {
+        if (sample) st->eedf_samples += 1;
+        st->step = next;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up: velocities from m/s to cells/step (unless given in internal
+// units) and the D1 start-up prediction x~_1 = x_0 + v_{-1/2} dt.
+// mode bit 0: convert units, bit 1: implicit start-up.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale0, double vscale1)
+{
+    const Work w = P.work[blockIdx.x];
+    Case* C = P.cases + w.c;
+    State* st = P.state + w.c;
+    const Species& S = C->sp[w.s];
+    const int N = C->n_cells;
+    const int n = st->n_slots[w.s];
+    int chunk = (n + w.nb - 1) / w.nb;
+    chunk = (chunk + 63) & ~63;
+    const int start = w.b * chunk, end = min(n, start + chunk);
+    const double vs = w.s == 0 ? vscale0 : vscale1;
+    const bool convert = P.mode & 1;
+    const bool startup = (P.mode & 2) && C->scheme == 1;
+    // waits drawn for a first trial at the start step (species loaded
+    // without them, collisions on)
+    const bool draw = ((P.mode >> (3 + w.s)) & 1) && C->collisions && S.n_proc > 0;
+    const uint32_t step32 = (uint32_t)st->step;
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+        if (convert) {
+            S.vx[i] = (float)((double)S.vx[i] * vs);
+            const u32x4 r = S.rec[i];
+            S.rec[i] = make_rec(rec_id(r), (float)((double)rec_vy(r) * vs),
+                                (float)((double)rec_vz(r) * vs));
+        }
+        const int32_t word = S.cell[i];
+        if (word < 0) continue;
+        int c = cell_of(word);
+        uint32_t wt = wait_of(word);
+        if (draw) {
+            const uint64_t id = rec_id(S.rec[i]);
+            const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
+                                    ((uint32_t)w.s << 28) | 4u, C->key0, C->key1);
+            wt = wait_encode(geo0(r4.x, S.inv_log1mp));
+        }
+        float o = S.off[i];
+        if (startup) {
+            S.abar[i] = 0.0f;
+            o += S.vx[i];
+            renorm(c, o);
+            if (C->bc == 1) {
+                c %= N;
+                if (c < 0) c += N;
+            } else if (c < 0 || c >= N) {
+                S.cell[i] = -1;
+                continue;
+            }
+            S.off[i] = o;
+        }
+        S.cell[i] = pack_cell(c, wt);
+    }
+}
+
+// LDS counter increment for the valid lanes of a wavefront.  Returns, for
+// each valid lane, the value a plain atomicAdd of 1 would have returned (its
+// slot).  When all valid lanes hit one cell (cell-sorted particles) a single
+// atomic serves the wavefront.
+__device__ __forceinline__ unsigned wave_count_add(unsigned* h, int c, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(valid);
+    if (m == 0ull) return 0u;
+    const int leader = __ffsll((long long)m) - 1;
+    const int key = __shfl(c, leader, 64);
+    if (__ballot(valid && c != key) == 0ull) {
+        // every valid lane hits one cell: one atomic for the wavefront
+        unsigned base = 0u;
+        if (lane == leader) base = atomicAdd(&h[key], (unsigned)__popcll(m));
+        base = __shfl(base, leader, 64);
+        return base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+    }
+    return valid ? atomicAdd(&h[c], 1u) : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: drop absorbed slots and sort every species by bucket with a
+// counting sort across workgroups (the order inside one bucket is
+// arbitrary).  Ions are sorted by cell; electrons, which cross many cells
+// between sorts, by buckets of 2^kElecBucketShift cells, so that every
+// workgroup writes its particles in a few long runs (the writes of a run
+// complete cache lines while they are resident instead of trickling out as
+// partial lines).
+// ---------------------------------------------------------------------------
+constexpr int kElecBucketShift = 4;
+
+__device__ __forceinline__ int bucket_shift(int s) { return s == 0 ? kElecBucketShift : 0; }
+__device__ __forceinline__ int n_buckets(int N, int s)
+{
+    return (N + (1 << bucket_shift(s)) - 1) >> bucket_shift(s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* hist_all,
+                                                         const int64_t* hist_off)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_lo, s_hi;
+    const Work w = P.work[blockIdx.x];
+    Case* C = P.cases + w.c;
+    State* st = P.state + w.c;
+    const int sh = bucket_shift(w.s);
+    const int NB = n_buckets(C->n_cells, w.s);
+    const PIC_GLOBAL int32_t* __restrict__ cellp = gp((const int32_t*)C->sp[w.s].cell);
+    PIC_GLOBAL uint32_t* hist = gp(hist_all + hist_off[2 * w.c + w.s]);
+    unsigned* lh = (unsigned*)smem;
+    for (int j = threadIdx.x; j < NB; j += kBlock) lh[j] = 0u;
+    if (threadIdx.x == 0) {
+        s_lo = kNoCell;
+        s_hi = -1;
+    }
+    lds_barrier();
+    const int n = st->n_slots[w.s];
+    int chunk = (n + w.nb - 1) / w.nb;
+    chunk = (chunk + 63) & ~63;
+    const int start = w.b * chunk, end = min(n, start + chunk);
+    int lo = kNoCell, hi = -1;
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int c = i < end ? cell_of(cellp[i]) : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        wave_count_add(lh, b, b >= 0);
+        if (b >= 0) range_note(lo, hi, b);
+    }
+    if (hi >= 0) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    lds_barrier();
+    for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock)
+        if (lh[j]) gatomic_add(&hist[j], lh[j]);
+}
+
+// one workgroup per (case, species): exclusive scan of the histogram
+__global__ __launch_bounds__(kBlock) void k_compact_scan(Params P, uint32_t* hist_all,
+                                                         uint32_t* cursor_all,
+                                                         const int64_t* hist_off)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned red[kWaves];
+    const int c = blockIdx.x >> 1, s = blockIdx.x & 1;
+    Case* C = P.cases + c;
+    State* st = P.state + c;
+    const int NB = n_buckets(C->n_cells, s);
+    PIC_GLOBAL uint32_t* hist = gp(hist_all + hist_off[2 * c + s]);
+    PIC_GLOBAL uint32_t* cur = gp(cursor_all + hist_off[2 * c + s]);
+    unsigned* a = (unsigned*)smem;
+    for (int j = threadIdx.x; j < NB; j += kBlock) {
+        a[j] = hist[j];
+        hist[j] = 0u;
+    }
+    lds_barrier();
+    block_scan(a, NB, red);
+    for (int j = threadIdx.x; j < NB; j += kBlock) cur[j] = j > 0 ? a[j - 1] : 0u;
+    if (threadIdx.x == 0) st->sort_live[s] = NB > 0 ? a[NB - 1] : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* cursor_all,
+                                                            const int64_t* hist_off)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_lo, s_hi;
+    __shared__ double red[kWaves];
+    const Work w = P.work[blockIdx.x];
+    Case* C = P.cases + w.c;
+    State* st = P.state + w.c;
+    const Species S = C->sp[w.s];
+    const int sh = bucket_shift(w.s);
+    const int NB = n_buckets(C->n_cells, w.s);
+    const bool imp = C->scheme == 1;
+    PIC_GLOBAL uint32_t* cur = gp(cursor_all + hist_off[2 * w.c + w.s]);
+    unsigned* lh = (unsigned*)smem;
+    unsigned* lb = lh + NB;
+    for (int j = threadIdx.x; j < NB; j += kBlock) lh[j] = 0u;
+    if (threadIdx.x == 0) {
+        s_lo = kNoCell;
+        s_hi = -1;
+    }
+    lds_barrier();
+    const int n = st->n_slots[w.s];
+    int chunk = (n + w.nb - 1) / w.nb;
+    chunk = (chunk + 63) & ~63;
+    const int start = w.b * chunk, end = min(n, start + chunk);
+    const PIC_GLOBAL int32_t* __restrict__ cellp = gp((const int32_t*)S.cell);
+    int lo = kNoCell, hi = -1;
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int c = i < end ? cell_of(cellp[i]) : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        wave_count_add(lh, b, b >= 0);
+        if (b >= 0) range_note(lo, hi, b);
+    }
+    if (hi >= 0) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    lds_barrier();
+    // one run per touched bucket
+    for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock) {
+        const unsigned k = lh[j];
+        if (k) lb[j] = gatomic_add(&cur[j], k);
+        lh[j] = 0u;
+    }
+    lds_barrier();
+    const PIC_GLOBAL float* __restrict__ offp = gp((const float*)S.off);
+    const PIC_GLOBAL float* __restrict__ vxp = gp((const float*)S.vx);
+    const PIC_GLOBAL u32x4* __restrict__ recp = gp((const u32x4*)S.rec);
+    const PIC_GLOBAL float* __restrict__ abp = gp((const float*)S.abar);
+    PIC_GLOBAL int32_t* __restrict__ cell2 = gp(S.cell2);
+    PIC_GLOBAL float* __restrict__ off2 = gp(S.off2);
+    PIC_GLOBAL float* __restrict__ vx2 = gp(S.vx2);
+    PIC_GLOBAL u32x4* __restrict__ rec2 = gp(S.rec2);
+    PIC_GLOBAL float* __restrict__ ab2 = gp(S.abar2);
+    double v2 = 0.0;
+    for (int base = start; base < end; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        const int j = min(i, end - 1);
+        const int32_t w0 = cellp[j];
+        const float o = offp[j], vx = vxp[j];
+        const u32x4 rc = recp[j];
+        const float vy = rec_vy(rc), vz = rec_vz(rc);
+        const float ab = imp ? abp[j] : 0.0f;
+        const int c = i < end ? cell_of(w0) : -1;
+        const int b = c >= 0 ? c >> sh : -1;
+        const unsigned r = wave_count_add(lh, b, b >= 0);
+        if (c < 0) continue;
+        const unsigned d = lb[b] + r;
+        cell2[d] = w0;
+        off2[d] = o;
+        vx2[d] = vx;
+        rec2[d] = rc;
+        float vh = vx;
+        if (imp) {
+            ab2[d] = ab;
+            vh = vx - 0.5f * ab;   // v_{n-1/2} from the stored prediction
+        }
+        v2 += (double)(vh * vh + vy * vy + vz * vz);
+    }
+    v2 = block_sum(v2, red);
+    if (threadIdx.x == 0) {
+        P.pd[(size_t)(PD_V2 + w.s) * P.stride + blockIdx.x] = v2;
+        P.pd[(size_t)(PD_V2 + 1 - w.s) * P.stride + blockIdx.x] = 0.0;
+    }
+}
+
+// one workgroup per case: swap buffers, set counts and the exact kinetic energy
+__global__ __launch_bounds__(kFinBlock) void k_compact_finish(Params P)
+{
+    __shared__ double sd[PD_N];
+    __shared__ long long si[PU_N];
+    Case* C = P.cases + blockIdx.x;
+    State* st = P.state + blockIdx.x;
+    reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+    if (threadIdx.x != 0) return;
+    for (int s = 0; s < 2; ++s) {
+        Species& S = C->sp[s];
+        st->K[s] = sd[PD_V2 + s] * S.kin_unit;
+        st->sortK[s] = st->K[s];
+        const int live = (int)st->sort_live[s];
+        st->n_slots[s] = live;
+        st->n_live[s] = live;
+        int32_t* t0 = S.cell; S.cell = S.cell2; S.cell2 = t0;
+        float* t1 = S.off; S.off = S.off2; S.off2 = t1;
+        t1 = S.vx; S.vx = S.vx2; S.vx2 = t1;
+        u32x4* t2 = S.rec; S.rec = S.rec2; S.rec2 = t2;
+        t1 = S.abar; S.abar = S.abar2; S.abar2 = t1;
+    }
+}
+
+// Deposit of the stored positions (set-up), then k_solve per case.
+__global__ __launch_bounds__(kBlock) void k_deposit(Params P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_lo, s_hi;
+    const Work w = P.work[blockIdx.x];
+    Case* C = P.cases + w.c;
+    State* st = P.state + w.c;
+    const Species& S = C->sp[w.s];
+    const int N = C->n_cells;
+    unsigned long long* dep = (unsigned long long*)smem;
+    for (int j = threadIdx.x; j <= N; j += kBlock) dep[j] = 0ull;
+    const bool ec2 = C->gather == 2, periodic = C->bc == 1;
+    if (threadIdx.x == 0) {
+        s_lo = kNoCell;
+        s_hi = -1;
+    }
+    lds_barrier();
+    const int n = st->n_slots[w.s];
+    int chunk = (n + w.nb - 1) / w.nb;
+    chunk = (chunk + 63) & ~63;
+    const int start = w.b * chunk, end = min(n, start + chunk);
+    int lo = kNoCell, hi = -1;
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+        const int c = cell_of(S.cell[i]);
+        if (c < 0) continue;
+        if (ec2) {
+            deposit_quad(dep, true, c, S.off[i], N, periodic, lo, hi);
+        } else {
+            atomicAdd(&dep[c], packw(S.off[i]));
+            range_note(lo, hi, c);
+        }
+    }
+    if (hi >= 0) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    lds_barrier();
+    for (int j = s_lo + (int)threadIdx.x; s_hi >= 0 && j <= s_hi; j += kBlock) {
+        const unsigned long long p = dep[j];
+        if (p) {
+            atomicAdd(&C->dep_cnt[w.s][j], p >> 40);
+            atomicAdd(&C->dep_w[w.s][j], p & kWMask);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_solve(Params P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kFinBlock / 64];
+    Case* C = P.cases + blockIdx.x;
+    State* st = P.state + blockIdx.x;
+    solve_case<kFinBlock>(C, st, st->step + (C->scheme == 1 ? 1 : 0), st->step, false,
+                          (double*)smem, red);
+}
+
+}  // namespace pic

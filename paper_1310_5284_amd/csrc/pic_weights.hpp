@@ -1,0 +1,140 @@
+// Weighting and interpolation shared by the particle pass and the set-up
+// deposit: the gathers of Eq. (3) (m = 1 own cell, m = 2 linear of the
+// half-grid field, MC linear of the nodal field), the packed linear weight of
+// Eq. (2) and the quadratic weights and deposit of Eq. (2) with m = 2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+#include "pic_common.hpp"
+#include "pic_device.hpp"
+
+namespace pic {
+
+// Momentum-conserving gather: linear interpolation of the nodal field (held
+// in LDS, N+1 nodes) at offset o of cell c.
+__device__ __forceinline__ float gather_mc(const float* en, int c, float o)
+{
+    return (1.0f - o) * en[c] + o * en[c + 1];
+}
+
+// Eq. (3) with m = 2 (spline degree): linear interpolation of the half-grid
+// field (cell values eh[N], at the cell centres) at offset o of cell c; no
+// half-grid field beyond an electrode, a periodic grid wraps.
+__device__ __forceinline__ float gather_ec2(const float* eh, int N, bool periodic, int c, float o)
+{
+    const bool up = o >= 0.5f;
+    const int k = up ? c : c - 1;            // half-grid point at or left of x
+    const float t = up ? o - 0.5f : o + 0.5f;
+    float e0, e1;
+    if (periodic) {
+        e0 = eh[k < 0 ? N - 1 : k];
+        e1 = eh[k + 1 >= N ? 0 : k + 1];
+    } else {
+        e0 = k >= 0 ? eh[k] : 0.0f;
+        e1 = k + 1 < N ? eh[k + 1] : 0.0f;
+    }
+    return (1.0f - t) * e0 + t * e1;
+}
+
+// Eq. (2) with m = 2: quadratic (S_2) weights of a particle at offset o of
+// cell c, in units of 2^-24 particle: nearest node i = c or c + 1,
+// d = c + o - i in [-1/2, 1/2); nodes i-1, i, i+1 take (1/2 - d)^2 / 2,
+// 3/4 - d^2, (1/2 + d)^2 / 2, the middle one as the exact complement.
+__device__ __forceinline__ int quad_weights(int c, float o, uint32_t w[3])
+{
+    const bool up = o >= 0.5f;
+    const float d = up ? o - 1.0f : o;
+    const float a = 0.5f - d, b = 0.5f + d;
+    w[0] = __float2uint_rn(0.5f * a * a * 16777216.0f);
+    w[2] = __float2uint_rn(0.5f * b * b * 16777216.0f);
+    w[1] = (1u << 24) - w[0] - w[2];
+    return c + (up ? 1 : 0);
+}
+
+// A node index of the quadratic weights: folded into the electrode beyond
+// which it lies (Dirichlet), wrapped (periodic).
+__device__ __forceinline__ int fold_node(int g, int N, bool periodic)
+{
+    if (periodic) return g < 0 ? g + N : (g >= N ? g - N : g);
+    return min(max(g, 0), N);
+}
+
+// Quadratic deposit of one particle per lane into a privatised node grid
+// (N+1 words): weights in the low 40 bits; the particle's cell count rides on
+// the word of node c (always one of the three).  Called by whole wavefronts.
+// sorted: when every depositing lane is in one cell (cell-sorted ions), the
+// lanes on each side of the cell centre share their three nodes, and their
+// weights are summed across the wavefront before one atomic per node.
+__device__ __forceinline__ void deposit_quad(unsigned long long* dep, bool want, int c, float o,
+                                             int N, bool periodic, int& lo, int& hi,
+                                             bool sorted = false)
+{
+    uint32_t w[3] = {0u, 0u, 0u};
+    int i = c;
+    if (want) i = quad_weights(c, o, w);
+    if (sorted) {
+        const unsigned long long m = __ballot(want);
+        if (m == 0ull) return;
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)m) - 1;
+        const int cl = __builtin_amdgcn_readlane(c, leader);
+        if (__ballot(want && c != cl) == 0ull) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool mine = want && (i == cl + side);
+                const unsigned long long mg = __ballot(mine);
+                if (mg == 0ull) continue;
+                const int gl = __ffsll((long long)mg) - 1;
+                uint32_t t[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t[k] = wave_total_u32(mine ? w[k] : 0u);
+                if (lane == gl) {
+                    const int i0 = cl + side;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int g0 = i0 - 1 + k;
+                        const int g = fold_node(g0, N, periodic);
+                        atomicAdd(&dep[g], (unsigned long long)t[k] +
+                                               (g0 == cl ? (unsigned long long)__popcll(mg) *
+                                                               kCountOne : 0ull));
+                        range_note(lo, hi, g);
+                    }
+                }
+            }
+            return;
+        }
+    }
+    if (!want) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int g0 = i - 1 + k;
+        const int g = fold_node(g0, N, periodic);
+        atomicAdd(&dep[g], (unsigned long long)w[k] + (g0 == c ? kCountOne : 0ull));
+        range_note(lo, hi, g);
+    }
+}
+
+// Nodal field of node g from the cell fields of one species: the mean of the
+// two adjacent cells; the electrodes take the field of their own cell, a
+// periodic grid wraps.
+__device__ __forceinline__ float nodal_field(const PIC_GLOBAL float* eh, int N, bool periodic,
+                                             int g)
+{
+    if (periodic) {
+        const int gl = g == 0 ? N - 1 : g - 1;
+        const int gr = g == N ? 0 : g;
+        return 0.5f * (eh[gl] + eh[gr]);
+    }
+    if (g == 0) return eh[0];
+    if (g == N) return eh[N - 1];
+    return 0.5f * (eh[g - 1] + eh[g]);
+}
+
+__device__ __forceinline__ unsigned long long packw(float o)
+{
+    return kCountOne + (unsigned long long)__float2uint_rn(o * 16777216.0f);
+}
+
+}  // namespace pic
