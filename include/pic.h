@@ -125,7 +125,8 @@ typedef struct {
 typedef struct {
     double q_C, m_kg, weight;
     int64_t n;              /* particles given                                  */
-    int64_t capacity;       /* slots reserved (>= n, < 2^29 - 1024); ionization
+    int64_t capacity;       /* slots reserved (>= n, <= 2^28 - 1024: the kernels
+                               address 16-byte records with 32-bit offsets); ionization
                                appends children after the occupied slots       */
     const int32_t* cell;
     const float* off;

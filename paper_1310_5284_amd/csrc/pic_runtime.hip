@@ -389,7 +389,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         }
         for (int s = 0; s < 2; ++s) {
             const pic_species_init& sp = species[2 * k + s];
-            if (sp.n < 0 || sp.capacity < sp.n || sp.capacity > ((int64_t)1 << 29) - 1024 || !(sp.m_kg > 0) ||
+            if (sp.n < 0 || sp.capacity < sp.n || sp.capacity > ((int64_t)1 << 28) - 1024 || !(sp.m_kg > 0) ||
                 (sp.n > 0 && (!sp.cell || !sp.off || !sp.vx || !sp.vy || !sp.vz || !sp.id))) {
                 fprintf(stderr, "pic_init: case %d species %d: bad arrays\n", k, s);
                 return bail(PIC_E_INVAL);

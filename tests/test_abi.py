@@ -81,6 +81,10 @@ def test_init_rejects_bad_input_without_a_gpu():
     cfg[0].gather = 3
     cfg[0].scheme = 0
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
+    # capacity beyond what 32-bit record offsets reach
+    cfg[0].gather = 0
+    sp[0].capacity = (1 << 28) - 1023
+    assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     assert not h.value
 
 
