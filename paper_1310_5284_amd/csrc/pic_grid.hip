@@ -199,39 +199,37 @@ __device__ __forceinline__ void reduce_partials(const double* pd_, const unsigne
                                                 int fb, int nb, double* sd, long long* su)
 {
     // wavefront w sums the fields w, w + NT/64, ...: every lane strides over
-    // the workgroup partials with kU loads in flight, then a wavefront tree
-    constexpr int kU = 8;
+    // the workgroup partials with kU loads in flight (one pass covers 64 kU
+    // rows), then a wavefront tree; the order of the sums is fixed
+    constexpr int kU = 24;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const PIC_GLOBAL double* pd = gp(pd_);
     const PIC_GLOBAL unsigned* pu = gp(pu_);
     for (int f = wave; f < PD_N + PU_N; f += NT / 64) {
         if (f < PD_N) {
-            double a[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) a[u] = 0.0;
+            double acc = 0.0;
             // unconditional loads from clamped indices keep all kU in flight
             const PIC_GLOBAL double* row = pd + (size_t)f * stride + fb;
-            for (int b = lane; b < nb; b += 64 * kU)
+            for (int b = lane; b < nb; b += 64 * kU) {
+                double x[kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const double x = row[min(b + 64 * u, nb - 1)];
-                    a[u] += b + 64 * u < nb ? x : 0.0;
-                }
-            double v = 0.0;
+                for (int u = 0; u < kU; ++u) x[u] = row[min(b + 64 * u, nb - 1)];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v += a[u];
-            v = wave_sum(v);
+                for (int u = 0; u < kU; ++u) acc += b + 64 * u < nb ? x[u] : 0.0;
+            }
+            const double v = wave_sum(acc);
             if (lane == 0) sd[f] = v;
         } else {
             // per-step counts of one case fit in 32 bits
             unsigned a = 0u;
             const PIC_GLOBAL unsigned* row = pu + (size_t)(f - PD_N) * stride + fb;
-            for (int b = lane; b < nb; b += 64 * kU)
+            for (int b = lane; b < nb; b += 64 * kU) {
+                unsigned x[kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const unsigned x = row[min(b + 64 * u, nb - 1)];
-                    a += b + 64 * u < nb ? x : 0u;
-                }
+                for (int u = 0; u < kU; ++u) x[u] = row[min(b + 64 * u, nb - 1)];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) a += b + 64 * u < nb ? x[u] : 0u;
+            }
             a = wave_sum(a);
             if (lane == 0) su[f - PD_N] = (long long)a;
         }
