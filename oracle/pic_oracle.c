@@ -60,6 +60,7 @@ struct orc_sim {
     double inv_log1mp[2];  /* 1 / ln(1 - P_null) */
     /* fields of the most recent solve */
     double *rho, *phi, *E, *chi, *Q[2], *cnt[2];
+    double* chw[2];        /* m = 2 implicit: susceptibility weights of the centres */
     double* heat[2];
     const double* ext_E;   /* when set, the next step uses this field (N values) */
     orc_ledger led;
@@ -280,6 +281,27 @@ double orc_gather_ec2(int32_t N, int32_t periodic, const double* E, double xi)
     return (1.0 - t) * half_E(N, periodic, E, kk) + t * half_E(N, periodic, E, kk + 1);
 }
 
+void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* xi, double* w)
+{
+    memset(w, 0, sizeof(double) * (size_t)N);
+    for (int64_t p = 0; p < n; ++p) {
+        /* the centres on either side: a = floor(xi - 1/2) and a + 1 */
+        double k = floor(xi[p] - 0.5);
+        double t = xi[p] - 0.5 - k;
+        int64_t c[2] = {(int64_t)k, (int64_t)k + 1};
+        double s1[2] = {1.0 - t, t};
+        int in[2];
+        double row = 0.0;
+        for (int e = 0; e < 2; ++e) {
+            if (periodic) c[e] = ((c[e] % N) + N) % N;
+            in[e] = periodic || (c[e] >= 0 && c[e] < N);
+            if (in[e]) row += s1[e];
+        }
+        for (int e = 0; e < 2; ++e)
+            if (in[e]) w[c[e]] += s1[e] * row;
+    }
+}
+
 static double gather(const orc_sim* s, double xi);
 
 /* ------------------------------------------------------------------------ */
@@ -291,8 +313,6 @@ orc_sim* orc_create(const orc_case* c)
 {
     if (c->n_cells < 2) return NULL;
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
-    /* m = 2 is built for the explicit scheme only */
-    if (c->gather == ORC_GATHER_EC2 && c->scheme == ORC_IMPLICIT) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->c = *c;
     s->dx = c->gap_m / c->n_cells;
@@ -305,6 +325,7 @@ orc_sim* orc_create(const orc_case* c)
     for (int k = 0; k < 2; ++k) {
         s->Q[k] = (double*)xcalloc((size_t)N + 1, sizeof(double));
         s->cnt[k] = (double*)xcalloc((size_t)N, sizeof(double));
+        s->chw[k] = (double*)xcalloc((size_t)N, sizeof(double));
         s->heat[k] = (double*)xcalloc((size_t)N, sizeof(double));
     }
     return s;
@@ -317,7 +338,7 @@ void orc_destroy(orc_sim* s)
         species_t* p = &s->sp[k];
         free(p->xi); free(p->vx); free(p->vy); free(p->vz); free(p->abar); free(p->id);
         free(p->wait);
-        free(s->Q[k]); free(s->cnt[k]); free(s->heat[k]);
+        free(s->Q[k]); free(s->cnt[k]); free(s->chw[k]); free(s->heat[k]);
     }
     for (int k = 0; k < s->n_proc; ++k) free(s->proc[k].sigma);
     free(s->rho); free(s->phi); free(s->E); free(s->chi);
@@ -531,6 +552,8 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         else
             orc_deposit_linear(N, periodic, s->sp[k].n, s->sp[k].xi, s->Q[k]);
         orc_count_cells(N, s->sp[k].n, s->sp[k].xi, s->cnt[k]);
+        if (use_chi && s->c.gather == ORC_GATHER_EC2)
+            orc_chi_weights_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k]);
     }
     for (int32_t g = 0; g <= N; ++g) {
         double r = s->c.background_rho;
@@ -542,7 +565,9 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
      * MC: the susceptibility of the linear (CIC) weights at the nodes,
      * chi_g = beta dt^2 / eps0 * sum_s q_s^2 w_s / m_s * Q_{s,g} / V_g (V_g = dx,
      * dx/2 at Dirichlet electrodes), and
-     * chi_{j+1/2} = (chi_j + chi_{j+1}) / 2. */
+     * chi_{j+1/2} = (chi_j + chi_{j+1}) / 2.
+     * EC with m = 2: as EC with N_{s,j} replaced by the susceptibility
+     * weights of the centres (orc_chi_weights_ec2). */
     for (int32_t j = 0; j < N; ++j) {
         double x = 0.0;
         if (use_chi && s->c.gather == ORC_GATHER_MC) {
@@ -560,9 +585,11 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
             continue;
         }
         if (use_chi)
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 2; ++k) {
+                const double* nj = s->c.gather == ORC_GATHER_EC2 ? s->chw[k] : s->cnt[k];
                 if (s->sp[k].m > 0.0)
-                    x += s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m * s->cnt[k][j];
+                    x += s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m * nj[j];
+            }
         s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * s->dx) * x;
     }
     if (periodic)

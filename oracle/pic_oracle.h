@@ -30,7 +30,8 @@ enum { ORC_EXPLICIT = 0, ORC_IMPLICIT = 1 };
 /* EC: Eqs. (2)-(3) with m = 1 (S_1 deposit, S_0 gather of the half-grid
  * field); MC: S_1 deposit, S_1 gather of the nodal field; EC2: Eqs. (2)-(3)
  * with m = 2 read as spline degree (S_2 deposit, S_1 gather of the half-grid
- * field), explicit only. */
+ * field); its direct-implicit solve takes the diagonal susceptibility of
+ * orc_chi_weights_ec2. */
 enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1, ORC_GATHER_EC2 = 2 };
 enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONIZATION = 2, ORC_CHARGE_EXCHANGE = 3 };
 
@@ -110,6 +111,16 @@ void orc_deposit_quadratic(int32_t N, int32_t periodic, int64_t n, const double*
  * (values at the cell centres); beyond an electrode the half-grid field is 0
  * (the counterpart of folding the charge into the electrode node). */
 double orc_gather_ec2(int32_t N, int32_t periodic, const double* E, double xi);
+/* Susceptibility weights of the direct-implicit scheme with m = 2, one per
+ * cell centre.  Displacing particle p by d_p moves, with the S_2 deposit,
+ * the charge flux S_1(x_p - x_h) d_p through centre h; the D1 correction d_p
+ * is proportional to the S_1 gather sum_h' S_1(x_p - x_h') E_h' (no field
+ * beyond an electrode).  The exact operator is therefore proportional to the
+ * tridiagonal M_hh' = sum_p S_1(x_p - x_h) S_1(x_p - x_h'); these weights
+ * are its row sums, w_h = sum_p S_1(x_p - x_h) sum_h' S_1(x_p - x_h'), the
+ * diagonal approximation of the implicit m = 2 solve (h, h' over the N
+ * centres of the grid, wrapped when periodic). */
+void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* xi, double* w);
 
 /* ---- the simulation object ---- */
 orc_sim* orc_create(const orc_case* c);

@@ -152,3 +152,75 @@ def test_implicit_field_equals_explicit_field_at_corrected_positions(orc):
     ex.compute_fields()
     fe = ex.fields()
     np.testing.assert_allclose(fi["E"], fe["E"], rtol=0, atol=1e-9 * abs(fe["E"]).max())
+
+
+def _implicit_residual(orc, wdt, gather=2):
+    """One implicit step of electrons and ions sitting at cell centres (where
+    the m = 2 susceptibility operator is diagonal): the largest difference
+    between the implicit field and the plain field of the charge at the
+    corrected positions, relative to that field, and the same difference
+    for the field of the uncorrected positions."""
+    rng = np.random.default_rng(9)
+    N, dx = 24, 2e-4
+    L = N * dx
+    n, n0 = 400, 5e15
+    w = n0 * L / n
+    wp = math.sqrt(n0 * E * E / (EPS0 * ME))
+    dt = wdt / wp
+    mi = 40 * 1.66053906660e-27
+    z = np.zeros(n)
+    sps = [dict(q=-E, m=ME, w=w, xi=rng.integers(0, N, n) + 0.5, vx=z, vy=z, vz=z, abar=None,
+                id=np.arange(n, dtype=np.uint64)),
+           dict(q=E, m=mi, w=w, xi=rng.integers(0, N, n) + 0.5, vx=z, vy=z, vz=z, abar=None,
+                id=np.arange(n, dtype=np.uint64))]
+    case = dict(n_cells=N, gap_m=L, bc=0, scheme=1, gather=gather, collisions=0, dt_s=dt,
+                rf_volts=3.0, rf_freq_hz=1e7)
+    imp = orc.Sim(case, sps, [], startup=False)
+    imp.step(1)
+    moved = []
+    for k in range(2):
+        after = imp.species(k)
+        x1 = after["xi"] - after["vx"] * dt / dx     # x_{n+1} from x~_{n+2}
+        moved.append(dict(sps[k], xi=x1, id=after["id"], vx=np.zeros(x1.size),
+                          vy=np.zeros(x1.size), vz=np.zeros(x1.size)))
+    fields = []
+    for sp in (moved, sps):
+        ex = orc.Sim(dict(case, scheme=0, step0=1), sp, [])
+        ex.compute_fields()
+        fields.append(ex.fields()["E"])
+    Ei, (E1, E0) = imp.fields()["E"], fields
+    scale = np.abs(E1).max()
+    return np.abs(Ei - E1).max() / scale, np.abs(E0 - E1).max() / scale
+
+
+def test_ec2_implicit_field_is_the_corrected_field_to_second_order(orc):
+    # The m = 2 deposit is quadratic in a particle's position, so the
+    # susceptibility (its linearisation) is exact to first order only: the
+    # implicit field misses the field of the corrected positions by O(d^2),
+    # d ~ dt^2, a residual that falls 16x per halving of dt.  Without the
+    # susceptibility, or with a wrong factor, it falls 4x.
+    r = [_implicit_residual(orc, wdt) for wdt in (0.2, 0.1, 0.05)]
+    for (a, a0), (b, b0) in zip(r, r[1:]):
+        assert 3.5 < a0 / b0 < 4.5          # the correction itself is O(dt^2)
+        assert a / b > 12.0
+    assert r[-1][0] < 1e-3 * r[-1][1]
+
+
+def test_ec2_implicit_damps_the_oscillation_explicit_cannot_follow(orc):
+    # omega_p dt = 2.5: leap-frog is unstable (omega_p dt > 2) and the energy
+    # of the cold plasma grows; the D1 push with the m = 2 susceptibility
+    # damps it.  A susceptibility of the wrong sign or size fails this.
+    energy = {}
+    for scheme in (0, 1):
+        case, sps, base, amp, dt, dx, wp = cold_setup(mode=2, wdt=2.5, A=0.05, scheme=scheme)
+        case["gather"] = 2
+        sps[0]["vx"] = np.zeros_like(sps[0]["vx"])
+        sim = orc.Sim(case, sps, [])
+        hist = []
+        for _ in range(100):
+            sim.step(1)
+            L = sim.ledger()
+            hist.append(L["WE"] + L["K_after"][0])
+        energy[scheme] = hist
+    assert energy[0][-1] > 100 * energy[0][0]
+    assert energy[1][-1] < 0.01 * energy[1][0]

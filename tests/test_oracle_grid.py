@@ -251,3 +251,54 @@ def test_ec2_gather_is_minus_the_gradient_of_the_deposit_energy(orc, periodic):
             return (w[:N] * phi[:N]).sum() if periodic else (w * phi).sum()
         grad = (energy(xi + h) - energy(xi - h)) / (2 * h)
         assert abs(orc.gather_ec2(N, E, xi, periodic) + grad) < 1e-6
+
+
+def _ec2_operator(N, xi, periodic):
+    # the exact susceptibility operator of the m = 2 implicit scheme, up to
+    # its constant: M[h, h'] = sum_p S_1(x_p - x_h) S_1(x_p - x_h') over the
+    # N cell centres (minimum-image distances when periodic)
+    xc = np.arange(N) + 0.5
+    d = xi[:, None] - xc[None, :]
+    if periodic:
+        d = (d + 0.5 * N) % N - 0.5 * N
+    W = S1(d)                     # particles x centres
+    return W.T @ W
+
+
+@pytest.mark.parametrize("N,periodic", [(6, False), (7, True), (2, False)])
+def test_ec2_susceptibility_weights_are_row_sums_of_the_operator(orc, N, periodic):
+    rng = np.random.default_rng(40 + N)
+    xi = rng.uniform(0.0, N, 250)
+    xi[:5] = [0.0, 0.25, 0.5, N - 0.5, N - 1e-9]   # electrode half cells and centres
+    w = orc.chi_weights_ec2(N, xi, periodic)
+    M = _ec2_operator(N, xi, periodic)
+    np.testing.assert_allclose(w, M.sum(axis=1), rtol=1e-12, atol=1e-12)
+    if periodic:
+        # every particle's weights sum to one
+        assert abs(w.sum() - xi.size) < 1e-9
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_ec2_susceptibility_at_centres_is_the_cell_count(orc, periodic):
+    # a particle at a centre sits on one centre only: the operator is
+    # diagonal and the implicit m = 2 solve takes the m = 1 susceptibility
+    N = 8
+    xi = np.repeat(np.arange(N) + 0.5, np.array([3, 0, 1, 4, 2, 2, 0, 5]))
+    chi2, u = _chi(orc, N, xi, gather=2, periodic=periodic)
+    chi1, _ = _chi(orc, N, xi, gather=0, periodic=periodic)
+    assert np.allclose(chi2, chi1, rtol=1e-12, atol=0.0)
+    assert np.allclose(chi1, u * np.array([3, 0, 1, 4, 2, 2, 0, 5]), rtol=1e-12)
+
+
+def test_ec2_susceptibility_next_to_an_electrode_closed_form(orc):
+    # a particle between an electrode and the first centre sees the field of
+    # that centre only, with weight 1/2 + xi; it polarises that centre by the
+    # square of the weight.  One particle at the middle of two centres gives
+    # 1/4 + 1/4 to each (row sum 1/2 per centre)
+    N = 4
+    chi, u = _chi(orc, N, np.array([0.2]), gather=2)
+    assert np.allclose(chi, u * np.array([0.49, 0, 0, 0]), rtol=1e-12, atol=0.0)
+    chi, u = _chi(orc, N, np.array([N - 0.1]), gather=2)
+    assert np.allclose(chi, u * np.array([0, 0, 0, 0.36]), rtol=1e-12, atol=0.0)
+    chi, u = _chi(orc, N, np.array([2.0]), gather=2)
+    assert np.allclose(chi, u * np.array([0, 0.5, 0.5, 0]), rtol=1e-12, atol=0.0)
