@@ -54,7 +54,12 @@ enum { PIC_BC_DIRICHLET_RF = 0, PIC_BC_PERIODIC = 1 };
  * susceptibility chi_{j+1/2} = beta dt^2/(eps0 dx) sum_s q_s^2 w_s/m_s N_{s,j}
  * counts the predicted particles of cell j (EC gather), or is the mean of
  * the two node values beta dt^2/eps0 sum_s q_s^2 w_s/m_s Q_{s,g}/V_g of the
- * linear node weights (MC gather; V_g = dx, dx/2 at an electrode node). */
+ * linear node weights (MC gather; V_g = dx, dx/2 at an electrode node).
+ * With PIC_GATHER_EC2, N_{s,j} is replaced by the row sum of the tridiagonal
+ * operator sum_p S_1(x_p - x_j) S_1(x_p - x_j') over the cell centres (the
+ * diagonal approximation of the exact susceptibility): a particle between
+ * centres adds its two linear weights, one between an electrode and the
+ * first centre the square of that centre's weight. */
 enum { PIC_EXPLICIT = 0, PIC_IMPLICIT_D1 = 1 };
 /* Weighting and interpolation (Sec. II, Eqs. (2)-(3)):
  * PIC_GATHER_EC: Eq. (2) with S_1 (linear deposit to the nodes) and Eq. (3)
@@ -63,8 +68,7 @@ enum { PIC_EXPLICIT = 0, PIC_IMPLICIT_D1 = 1 };
  *   (momentum-conserving);
  * PIC_GATHER_EC2: Eqs. (2)-(3) with m = 2 read as spline degree: quadratic
  *   S_2 deposit (weights beyond an electrode fold into its node) and S_1
- *   interpolation of the half-grid field (zero beyond an electrode); explicit
- *   scheme only (else PIC_E_INVAL). */
+ *   interpolation of the half-grid field (zero beyond an electrode). */
 enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1, PIC_GATHER_EC2 = 2 };
 enum { PIC_ELASTIC = 0, PIC_EXCITATION = 1, PIC_IONIZATION = 2, PIC_CHARGE_EXCHANGE = 3 };
 

@@ -99,6 +99,11 @@ struct Case {
     // per-case device arrays
     unsigned long long* dep_cnt[2];  // [N] particles per cell (accumulating)
     unsigned long long* dep_w[2];    // [N] sum of right-node weights
+    // m = 2 implicit: the dual grid of the susceptibility (word e = k + 1
+    // for the cell centres k, k + 1 on either side of a particle): counts and
+    // summed fractions towards centre k + 1 (null otherwise)
+    unsigned long long* chi_cnt[2];  // [N+1]
+    unsigned long long* chi_w[2];    // [N+1]
     float* ehat[2];                  // [N] accel * E of the next step, per species
     double* E;                       // [N] V/m
     double* phi;                     // [N+1]
@@ -191,24 +196,41 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 //   field[N+1] float  (EC: ehat of the cells; MC: nodal field)
 //   dep[N] u64        (privatised deposit, count << 40 | summed weight)
 //   DIAG: heat[N] float, eedf[kEedfBins] u32
+// (dual: the susceptibility words of the m = 2 implicit scheme follow dep)
 struct StepLds {
-    size_t dep, heat, eedf, total;
+    size_t dep, dual, heat, eedf, total;
 };
-__host__ __device__ inline StepLds step_lds_layout(int N, bool diag)
+__host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual = false)
 {
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
-    L.heat = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
+    L.dual = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
+    L.heat = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;
 }
 
-// Shared-memory layout of k_collide: dep[N] u64 (predicted positions of the
-// implicit candidates) | eedf[kEedfBins] u32
-__host__ __device__ inline size_t collide_lds_bytes(int N)
+// Shared-memory layout of k_collide: dep[N+1] u64 (predicted positions of
+// the implicit candidates) | (dual: susceptibility words[N+1] u64) |
+// eedf[kEedfBins] u32
+struct CollideLds {
+    size_t dual, eedf, total;
+};
+__host__ __device__ inline CollideLds collide_lds_layout(int N, bool dual)
 {
-    return align16(8 * (size_t)N) + align16(4 * (size_t)kEedfBins);
+    CollideLds L;
+    L.dual = align16(8 * ((size_t)N + 1));
+    L.eedf = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
+    L.total = L.eedf + align16(4 * (size_t)kEedfBins);
+    return L;
+}
+
+// The susceptibility of the implicit scheme with the m = 2 weighting has a
+// dual grid of its own.
+__host__ __device__ inline bool dual_chi(int scheme, int gather)
+{
+    return scheme == 1 && gather == 2;
 }
 
 }  // namespace pic

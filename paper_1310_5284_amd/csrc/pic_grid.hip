@@ -22,7 +22,9 @@ namespace pic {
 // boundary condition sum_j E_{j+1/2} dx = phi_0 - phi_N (V(t) on the driven
 // electrode, or 0 for a periodic box).  chi = 0 is the Poisson solve of the
 // explicit cycle; chi from the predicted cell counts the susceptibility-
-// modified solve of the direct-implicit cycle.  O(log N) deep.
+// modified solve of the direct-implicit cycle (with m = 2: from the words of
+// the dual grid, the row sums of the linearised deposit-gather operator).
+// O(log N) deep.
 // ---------------------------------------------------------------------------
 constexpr double kEps0 = 8.8541878128e-12;
 
@@ -58,6 +60,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
     const double rho_bg = Cc.background_rho;
     const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
+    const bool dual = implicit && ec2;  // susceptibility of the dual grid
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
         long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
@@ -103,12 +106,35 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             if (g < N) {
                 gp(Cc.ccount[0])[g] = cn[k][0];
                 gp(Cc.ccount[1])[g] = cn[k][1];
-                if (!node_chi) {
+                if (!node_chi && !dual) {
                     const double chi =
                         implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
                     X[g] = chi;
                     gp(Cc.chi)[g] = chi;
                 }
+            }
+        }
+    }
+    if (dual) {
+        // centre h takes count - fraction of dual word h+1 and the fraction
+        // of dual word h (periodic: word N for h = 0)
+        const PIC_GLOBAL unsigned long long* xc[2] = {
+            gp((const unsigned long long*)Cc.chi_cnt[0]), gp((const unsigned long long*)Cc.chi_cnt[1])};
+        const PIC_GLOBAL unsigned long long* xw[2] = {
+            gp((const unsigned long long*)Cc.chi_w[0]), gp((const unsigned long long*)Cc.chi_w[1])};
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int h = tid + k * NT;
+            if (h < N) {
+                const int hl = (periodic && h == 0) ? N : h;
+                long long v[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    v[s] = (long long)xc[s][h + 1] * (1ll << kFixBits) - (long long)xw[s][h + 1] +
+                           (long long)xw[s][hl];
+                const double chi = (chi0 * (double)v[0] + chi1 * (double)v[1]) / kFixScale;
+                X[h] = chi;
+                gp(Cc.chi)[h] = chi;
             }
         }
     }
@@ -131,6 +157,10 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         if (j <= N) {   // node N: the quadratic deposit's last node
             gp(Cc.dep_cnt[0])[j] = 0; gp(Cc.dep_cnt[1])[j] = 0;
             gp(Cc.dep_w[0])[j] = 0; gp(Cc.dep_w[1])[j] = 0;
+            if (dual) {
+                gp(Cc.chi_cnt[0])[j] = 0; gp(Cc.chi_cnt[1])[j] = 0;
+                gp(Cc.chi_w[0])[j] = 0; gp(Cc.chi_w[1])[j] = 0;
+            }
         }
     }
     block_scan<double, NT>(S, N, red);             // S[j] = R_j
@@ -623,9 +653,14 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     State* st = P.state + w.c;
     const Species& S = C->sp[w.s];
     const int N = C->n_cells;
-    unsigned long long* dep = (unsigned long long*)smem;
-    for (int j = threadIdx.x; j <= N; j += kBlock) dep[j] = 0ull;
     const bool ec2 = C->gather == 2, periodic = C->bc == 1;
+    const bool dual = dual_chi(C->scheme, C->gather);
+    unsigned long long* dep = (unsigned long long*)smem;
+    unsigned long long* dch = dep + (N + 1);   // dual: susceptibility words
+    for (int j = threadIdx.x; j <= N; j += kBlock) {
+        dep[j] = 0ull;
+        if (dual) dch[j] = 0ull;
+    }
     if (threadIdx.x == 0) {
         s_lo = kNoCell;
         s_hi = -1;
@@ -641,6 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         if (c < 0) continue;
         if (ec2) {
             deposit_quad(dep, true, c, S.off[i], N, periodic, lo, hi);
+            if (dual) deposit_chi(dch, true, c, S.off[i], N, periodic, lo, hi);
         } else {
             atomicAdd(&dep[c], packw(S.off[i]));
             range_note(lo, hi, c);
@@ -656,6 +692,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         if (p) {
             atomicAdd(&C->dep_cnt[w.s][j], p >> 40);
             atomicAdd(&C->dep_w[w.s][j], p & kWMask);
+        }
+        const unsigned long long d = dual ? dch[j] : 0ull;
+        if (d) {
+            atomicAdd(&C->chi_cnt[w.s][j], d >> 40);
+            atomicAdd(&C->chi_w[w.s][j], d & kWMask);
         }
     }
 }

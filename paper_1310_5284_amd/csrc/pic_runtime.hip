@@ -104,6 +104,8 @@ struct pic_ctx {
     int cgrp_off[2] = {0, 0}, cgrp_cnt[2] = {0, 0};
     CollideWork* d_cwork = nullptr;
     int grp_maxN[2] = {0, 0};
+    bool grp_dual[2] = {false, false};   // a case of the group has the dual grid
+    bool any_dual = false;
     int maxN = 0;
     int tile = 8192;
     int sort_every = 64;
@@ -166,11 +168,22 @@ int dalloc(pic_ctx* c, std::vector<void*>& list, T** p, size_t n)
 
 size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// Dynamic LDS of k_step: field[N+1] float | dep[N] u64 | (DIAG: heat[N] float |
-// eedf[kEedfBins] u32) | per-wavefront candidate queues.
-size_t step_lds(int N, bool diag)
+// Dynamic LDS of k_step: field[N+1] float | dep[N+1] u64 | (m = 2 implicit:
+// susceptibility words[N+1] u64) | (DIAG: heat[N] float | eedf[kEedfBins] u32).
+size_t step_lds(int N, bool diag, bool dual)
 {
-    return step_lds_layout(N, diag).total;
+    return step_lds_layout(N, diag, dual).total;
+}
+
+size_t collide_lds(int N, bool dual)
+{
+    return collide_lds_layout(N, dual).total;
+}
+
+// k_deposit: node words dep[N+1] | (dual) susceptibility words [N+1]
+size_t deposit_lds(int N, bool dual)
+{
+    return 8 * ((size_t)N + 1) * (dual ? 2 : 1);
 }
 
 // k_finalize / k_solve: rho prefix S[N+1], chi per cell X[N], chi per node
@@ -221,6 +234,7 @@ int build_work(pic_ctx* c)
     for (int g = 0; g < 2; ++g) {
         c->grp_off[g] = (int)c->work.size();
         c->grp_maxN[g] = 0;
+        c->grp_dual[g] = false;
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
@@ -233,6 +247,7 @@ int build_work(pic_ctx* c)
             C.n_blocks = (int)c->work.size() - C.first_block;
 
             c->grp_maxN[g] = std::max(c->grp_maxN[g], (int)h.cfg.n_cells);
+            c->grp_dual[g] = c->grp_dual[g] || dual_chi(h.cfg.scheme, h.cfg.gather);
         }
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
     }
@@ -382,7 +397,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             (g.scheme != PIC_EXPLICIT && g.scheme != PIC_IMPLICIT_D1) ||
             (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC &&
              g.gather != PIC_GATHER_EC2) ||
-            (g.gather == PIC_GATHER_EC2 && g.scheme != PIC_EXPLICIT) || g.history_steps < 0 ||
+            g.history_steps < 0 ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
             return bail(PIC_E_INVAL);
@@ -455,6 +470,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         C.key0 = (uint32_t)g.seed;
         C.key1 = (uint32_t)(g.seed >> 32);
         c->maxN = std::max(c->maxN, N);
+        c->any_dual = c->any_dual || dual_chi(g.scheme, g.gather);
         // Eq. (1): omega_p dt < 2 for the explicit leap-frog
         if (g.scheme == PIC_EXPLICIT && !(flags & PIC_FLAG_ALLOW_UNSTABLE)) {
             const pic_species_init& e = species[2 * k];
@@ -652,6 +668,10 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         for (int s = 0; s < 2; ++s) {
             rc |= dalloc(c, h.allocs, &C.dep_cnt[s], N + 1);   // node N: quadratic deposit
             rc |= dalloc(c, h.allocs, &C.dep_w[s], N + 1);
+            if (dual_chi(C.scheme, C.gather)) {
+                rc |= dalloc(c, h.allocs, &C.chi_cnt[s], N + 1);
+                rc |= dalloc(c, h.allocs, &C.chi_w[s], N + 1);
+            }
             rc |= dalloc(c, h.allocs, &C.ehat[s], N);
             rc |= dalloc(c, h.allocs, &C.qfix[s], N + 1);
             rc |= dalloc(c, h.allocs, &C.ccount[s], N);
@@ -671,8 +691,9 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         h.hist_off[1] = hist_total + N;
         hist_total += 2 * (size_t)N;
     }
-    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true), collide_lds_bytes(c->maxN)),
-                                   std::max(8 * ((size_t)c->maxN + 1), fin_lds(c->maxN)))))
+    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true, c->any_dual),
+                                            collide_lds(c->maxN, c->any_dual)),
+                                   std::max(deposit_lds(c->maxN, c->any_dual), fin_lds(c->maxN)))))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
@@ -727,7 +748,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         if (compaction(c)) return bail(PIC_E_DEVICE);
         Params p = params(c, 0);
         hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock),
-                           8 * ((size_t)c->maxN + 1), c->stream, p);
+                           deposit_lds(c->maxN, c->any_dual), c->stream, p);
         hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock), fin_lds(c->maxN),
                            c->stream, p);
         INITCHK(hipGetLastError());
@@ -809,11 +830,11 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             const bool rec = pool && pool->used + 2 <= (int)pool->ev.size();
             if (rec) HIPCHK(c, record(pool->ev[pool->used]));
             if (kind == 0)
-                hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock), step_lds(N, diag),
-                                   c->stream, p);
+                hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock),
+                                   step_lds(N, diag, c->grp_dual[g]), c->stream, p);
             else
                 hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
-                                   collide_lds_bytes(N), c->stream, pc);
+                                   collide_lds(N, c->grp_dual[g]), c->stream, pc);
             if (rec) {
                 HIPCHK(c, record(pool->ev[pool->used + 1]));
                 pool->used += 2;

@@ -207,21 +207,35 @@ __device__ __forceinline__ void deposit_wave(unsigned long long* dep, bool want,
 }
 
 // Deposit of one particle straight into the case grids (ionization
-// children, rare): linear (count and weight of its cell) or quadratic.
-__device__ __forceinline__ void deposit_global(const Case* C, int s, int c, float o)
+// children, and the undoing of a null prediction after a real collision of
+// an implicit particle; both rare): linear (count and weight of its cell) or
+// quadratic, with the susceptibility word of the m = 2 implicit scheme.
+// remove: take the particle's words out again (the same integers).
+__device__ __forceinline__ void deposit_global(const Case* C, int s, int c, float o,
+                                               bool remove = false)
 {
     PIC_GLOBAL unsigned long long* gcnt = gp(C->dep_cnt[s]);
     PIC_GLOBAL unsigned long long* gw = gp(C->dep_w[s]);
+    auto add = [&](PIC_GLOBAL unsigned long long* a, unsigned long long v) {
+        gatomic_add(a, remove ? 0ull - v : v);
+    };
+    const int N = C->n_cells;
+    const bool periodic = C->bc == 1;
     if (C->gather == 2) {
         uint32_t w[3];
         const int i = quad_weights(c, o, w);
         for (int k = 0; k < 3; ++k)
-            gatomic_add(&gw[fold_node(i - 1 + k, C->n_cells, C->bc == 1)],
-                        (unsigned long long)w[k]);
+            add(&gw[fold_node(i - 1 + k, N, periodic)], (unsigned long long)w[k]);
+        if (C->scheme == 1) {
+            float f;
+            const int e = chi_dual(c, o, N, periodic, f);
+            add(gp(&C->chi_cnt[s][e]), 1ull);
+            add(gp(&C->chi_w[s][e]), packw(f) & kWMask);
+        }
     } else {
-        gatomic_add(&gw[c], packw(o) & kWMask);
+        add(&gw[c], packw(o) & kWMask);
     }
-    gatomic_add(&gcnt[c], 1ull);
+    add(&gcnt[c], 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -275,11 +289,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const bool periodic = C->bc == 1;
     const bool mc = C->gather == 1;
     const bool ec2 = C->gather == 2;
+    const bool dual = kImp && ec2;   // susceptibility words of its own
     const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
-    const StepLds L = step_lds_layout(N, DIAG);
+    const StepLds L = step_lds_layout(N, DIAG, dual);
     float* eh = (float*)smem;
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
+    unsigned long long* dch = (unsigned long long*)(smem + L.dual);
     float* heat = (float*)(smem + L.heat);
     unsigned* eedf = (unsigned*)(smem + L.eedf);
     {
@@ -297,6 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         if (DIAG) heat[j] = 0.0f;
     }
     if (tid == 0) dep[N] = 0ull;   // node N of the quadratic deposit
+    if (dual)
+        for (int j = tid; j <= N; j += kBlock) dch[j] = 0ull;
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
     if (tid == 0) {
@@ -477,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             else
                 deposit_wave(dep, dep_now, c2, o2, lo, hi);
+            if (dual) deposit_chi(dch, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             // list the candidates of this wavefront in the workgroup's region
             const bool enq = live && isc;
             const unsigned long long qm = __ballot(enq);
@@ -515,6 +534,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             if (p) {
                 gatomic_add(&gcnt[j], p >> 40);
                 gatomic_add(&gw[j], p & kWMask);
+            }
+            if (dual) {
+                const unsigned long long d = dch[j];
+                if (d) {
+                    gatomic_add(gp(&C->chi_cnt[s][j]), d >> 40);
+                    gatomic_add(gp(&C->chi_w[s][j]), d & kWMask);
+                }
             }
             if (DIAG) {
                 const float h = heat[j];
@@ -601,14 +627,21 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
         ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
     const bool periodic = C->bc == 1;
+    const bool ec2 = C->gather == 2;
+    const bool dual = kImp && ec2;   // susceptibility words of its own
     const uint32_t k0 = C->key0, k1 = C->key1;
+    const CollideLds L = collide_lds_layout(N, dual);
     unsigned long long* dep = (unsigned long long*)smem;
-    unsigned* eedf = (unsigned*)(smem + align16(8 * (size_t)N));
+    unsigned long long* dch = (unsigned long long*)(smem + L.dual);
+    unsigned* eedf = (unsigned*)(smem + L.eedf);
     __shared__ float lbound[kBoundBins];
     if (s == 0 && C->sp[0].n_proc > 0)
         for (int j = tid; j < kBoundBins; j += kBlock) lbound[j] = C->sp[0].cbound[j];
     if (kImp)
-        for (int j = tid; j < N; j += kBlock) dep[j] = 0ull;
+        for (int j = tid; j <= N; j += kBlock) {
+            dep[j] = 0ull;
+            if (dual) dch[j] = 0ull;
+        }
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
     if (tid == 0) {
@@ -806,8 +839,12 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                         cp %= N;
                         if (cp < 0) cp += N;
                     }
-                    gatomic_add(&gdep_cnt[cp], ~0ull);
-                    gatomic_add(&gdep_w[cp], 0ull - (packw(op) & kWMask));
+                    if (ec2) {
+                        deposit_global(C, s, cp, op, true);
+                    } else {
+                        gatomic_add(&gdep_cnt[cp], ~0ull);
+                        gatomic_add(&gdep_w[cp], 0ull - (packw(op) & kWMask));
+                    }
                 }
                 const float vst = predict(c2, o2, vn, abn);
                 bool gone = false;
@@ -830,7 +867,14 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                 stg(cellp, i4, pack_cell(c1, nw));
             }
         }
-        if (kImp) deposit_wave(dep, dep_ok, c2, o2, lo, hi);
+        if (kImp) {
+            if (ec2) {
+                deposit_quad(dep, dep_ok, c2, o2, N, periodic, lo, hi);
+                deposit_chi(dch, dep_ok, c2, o2, N, periodic, lo, hi);
+            } else {
+                deposit_wave(dep, dep_ok, c2, o2, lo, hi);
+            }
+        }
         // ionization children: queued in LDS and written after the loop, so
         // that a workgroup pays the latency of the slot reservation once;
         // events beyond the queue are handled here
@@ -890,6 +934,13 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             if (p) {
                 gatomic_add(&gcnt[j], p >> 40);
                 gatomic_add(&gw[j], p & kWMask);
+            }
+            if (dual) {
+                const unsigned long long d = dch[j];
+                if (d) {
+                    gatomic_add(gp(&C->chi_cnt[s][j]), d >> 40);
+                    gatomic_add(gp(&C->chi_w[s][j]), d & kWMask);
+                }
             }
         }
     }

@@ -73,13 +73,9 @@ def test_init_rejects_bad_input_without_a_gpu():
     for s in range(2):
         sp[s].m_kg = 1.0
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
-    # the quadratic (m = 2) weighting is built for the explicit scheme only
+    # no weighting beyond m = 2
     cfg[0].n_cells = 8
-    cfg[0].gather = 2
-    cfg[0].scheme = 1
-    assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     cfg[0].gather = 3
-    cfg[0].scheme = 0
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     # capacity beyond what 32-bit record offsets reach
     cfg[0].gather = 0

@@ -221,3 +221,26 @@ def test_autotune_picks_a_candidate_and_steps_like_pic_step():
         ctx.autotune(tiles=[300], sorts=[8], steps_per_trial=2)
     ctx.close()
     ref.close()
+
+
+def test_batch_with_the_dual_grid_equals_separate_runs():
+    # an m = 1 and an m = 2 implicit case in one launch: the launch's shared
+    # memory holds the susceptibility words of the dual grid, and each case
+    # lays it out by its own weighting; both step as they do alone
+    wls = [W.c1(collisions=1, np_per_species=4096, scheme=1),
+           W.c1(collisions=1, np_per_species=6144 + 3, scheme=1, seed=0xD2)]
+    wls[1]["case"]["gather"] = 2
+    batch = P().PicContext(wls)
+    batch.set_schedule(sort_every=7, diag_every=0, tile=1024)
+    batch.step(30)
+    for k, wl in enumerate(wls):
+        alone = ctx_for(wl, sort_every=7)
+        alone.step(30)
+        for a, b in zip(sorted_state(batch, k), sorted_state(alone)):
+            for key in a:
+                assert np.array_equal(a[key], b[key]), (k, key)
+        fb, fa = batch.fields(k), alone.fields()
+        for key in ("rho", "phi", "E", "chi"):
+            assert np.array_equal(fb[key], fa[key]), (k, key)
+        alone.close()
+    batch.close()

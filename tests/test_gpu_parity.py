@@ -53,13 +53,15 @@ def test_ccp256_implicit_teacher_forced(wdt, steps):
     assert_report(rep)
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_ionizing_beam_teacher_forced(scheme):
+@pytest.mark.parametrize("scheme,gather", [(0, 0), (1, 0), (1, 2)])
+def test_ionizing_beam_teacher_forced(scheme, gather):
     # 100 eV isotropic electrons in dense gas: every electron is a candidate
     # in every step and about 5 % of them ionize, i.e. more ionizations per
     # collision workgroup than its LDS queue holds, so both the queued and
-    # the immediate child paths run
+    # the immediate child paths run (implicit: most candidates collide for
+    # real, so the deposit of their null prediction is undone)
     wl = W.c1(collisions=1, np_per_species=8192 + 33, scheme=scheme)
+    wl["case"]["gather"] = gather
     wl["case"]["gas_density_m3"] = W.gas_density(1000.0)
     e = wl["species"][0]
     n = e["cell"].size
@@ -86,12 +88,14 @@ def test_ionizing_beam_teacher_forced(scheme):
     assert_report(rep)
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_max_cells_teacher_forced(scheme):
+@pytest.mark.parametrize("scheme,gather", [(0, 0), (1, 0), (1, 2)])
+def test_max_cells_teacher_forced(scheme, gather):
     # the largest grid the library takes (PIC_MAX_CELLS = 4096 cells: the
-    # deposit grid and the field fill the most LDS), 300 V, 30 mTorr
+    # deposit grid and the field fill the most LDS, with m = 2 implicit also
+    # the susceptibility words), 300 V, 30 mTorr
     wl = W.ccp_workload("ccp4096", n_cells=4096, np_per_species=40000 + 11, volts=300.0,
                         dt=1.0 / (2000.0 * 13.56e6), p_mtorr=30.0, scheme=scheme, seed=0x4096)
+    wl["case"]["gather"] = gather
     ctx = ctx_for(wl, tile=4096)
     rep = teacher_forced(ctx, wl, 20)
     print(rep)
@@ -126,6 +130,30 @@ def test_ccp64_ec2_explicit_teacher_forced():
     # electrodes), linear interpolation of the half-grid field
     wl = W.c1(collisions=1, np_per_species=16384 + 77)
     wl["case"]["gather"] = 2
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 60)
+    print(rep)
+    assert_report(rep)
+
+
+def test_ccp256_ec2_implicit_teacher_forced():
+    # D1 implicit with m = 2: quadratic deposit of the predicted positions and
+    # the row-sum susceptibility of the dual grid (electrode half cells
+    # included: the sheaths hold ions there)
+    wl = W.c3(ppc=40, wdt=2.0)
+    wl["case"]["gather"] = 2
+    for sp in wl["species"]:
+        sp["capacity"] = 2 * sp["cell"].size
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 40)
+    print(rep)
+    assert_report(rep)
+
+
+def test_periodic_ec2_implicit_teacher_forced():
+    # the periodic dual grid: the centre left of cell 0 is the last centre
+    wl = W.c2(ratio=5.0, gather=2, ppc=100, n_cells=32, wdt=1.5)
+    wl["case"]["scheme"] = 1
     ctx = ctx_for(wl)
     rep = teacher_forced(ctx, wl, 60)
     print(rep)
