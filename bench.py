@@ -56,6 +56,12 @@ def make_workload(name, scale):
     if name == "ccp2048_implicit":
         # the same discharge stepped by the D1 implicit scheme
         return [W.c4(np_per_species=int(10_000_000 * scale), scheme=1)]
+    if name == "ccp2048_ec2_implicit":
+        # D1 implicit with m = 2 weighting (quadratic deposit, susceptibility
+        # of the dual grid)
+        wl = W.c4(np_per_species=int(10_000_000 * scale), scheme=1)
+        wl["case"]["gather"] = 2
+        return [wl]
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":
