@@ -45,7 +45,8 @@ class Case(C.Structure):
                 ("rf_volts", C.c_double), ("rf_freq_hz", C.c_double),
                 ("gas_density_m3", C.c_double), ("gas_temp_K", C.c_double),
                 ("gas_mass_kg", C.c_double), ("background_rho", C.c_double),
-                ("opal_B_eV", C.c_double), ("seed", C.c_uint64)]
+                ("opal_B_eV", C.c_double), ("seed", C.c_uint64),
+                ("cell_dx_m", C.POINTER(C.c_double))]
 
 
 class Ledger(C.Structure):
@@ -94,6 +95,8 @@ def lib():
         L.orc_solve_dirichlet.argtypes = [C.c_int32, C.c_double, _D, _D, C.c_double,
                                           C.c_double, _D, _D]
         L.orc_solve_periodic.argtypes = [C.c_int32, C.c_double, _D, _D, _D, _D]
+        L.orc_solve_dirichlet_nu.argtypes = [C.c_int32, _D, _D, _D, C.c_double, C.c_double,
+                                             _D, _D]
         L.orc_gather_ec.argtypes = [C.c_int32, _D, C.c_double]
         L.orc_gather_ec.restype = C.c_double
         L.orc_gather_mc.argtypes = [C.c_int32, C.c_int32, _D, C.c_double]
@@ -186,6 +189,16 @@ def solve_dirichlet(N, dx, rho, phi0, phiN, chi=None):
     return phi, E
 
 
+def solve_dirichlet_nu(w, sigma, phi0, phiN, chi=None):
+    w, sigma = _f64(w), _f64(sigma)
+    chi = None if chi is None else _f64(chi)
+    N = w.size
+    phi = np.zeros(N + 1)
+    E = np.zeros(N)
+    lib().orc_solve_dirichlet_nu(N, _dp(w), _dp(sigma), _dp(chi), phi0, phiN, _dp(phi), _dp(E))
+    return phi, E
+
+
 def solve_periodic(N, dx, rho, chi=None):
     rho = _f64(rho)
     chi = None if chi is None else _f64(chi)
@@ -233,6 +246,9 @@ class Sim:
                  gas_mass_kg=case.get("gas_mass_kg", 1.0),
                  background_rho=case.get("background_rho", 0.0),
                  opal_B_eV=case.get("opal_B_eV", 10.0), seed=case.get("seed", 0))
+        cdx = case.get("cell_dx")
+        self._cdx = None if cdx is None else _f64(cdx)   # held while orc_create copies it
+        c.cell_dx_m = _dp(self._cdx)
         self.case = dict(case)
         self.N = int(case["n_cells"])
         self.dx = case["gap_m"] / self.N

@@ -61,6 +61,8 @@ struct orc_sim {
     /* fields of the most recent solve */
     double *rho, *phi, *E, *chi, *Q[2], *cnt[2];
     double* chw[2];        /* m = 2 implicit: susceptibility weights of the centres */
+    double *cw, *edge;     /* nonuniform grid: cell widths, node positions (m)  */
+    double* sigma;         /* nonuniform grid: node charge per area (C/m^2)     */
     double* heat[2];
     const double* ext_E;   /* when set, the next step uses this field (N values) */
     orc_ledger led;
@@ -188,6 +190,39 @@ void orc_solve_dirichlet(int32_t N, double dx, const double* rho, const double* 
     for (int32_t j = 0; j < N; ++j) E[j] = (phi[j] - phi[j + 1]) / dx;
 }
 
+void orc_solve_dirichlet_nu(int32_t N, const double* w, const double* sigma, const double* chi,
+                            double phi0, double phiN, double* phi, double* E)
+{
+    phi[0] = phi0;
+    phi[N] = phiN;
+    int32_t m = N - 1;
+    if (m > 0) {
+        double* a = (double*)malloc(sizeof(double) * (size_t)m);
+        double* b = (double*)malloc(sizeof(double) * (size_t)m);
+        double* c = (double*)malloc(sizeof(double) * (size_t)m);
+        double* d = (double*)malloc(sizeof(double) * (size_t)m);
+        for (int32_t g = 1; g <= m; ++g) {
+            double kl = (1.0 + (chi ? chi[g - 1] : 0.0)) / w[g - 1];
+            double kr = (1.0 + (chi ? chi[g] : 0.0)) / w[g];
+            a[g - 1] = -kl;
+            b[g - 1] = kl + kr;
+            c[g - 1] = -kr;
+            d[g - 1] = sigma[g] / EPS0;
+        }
+        d[0] -= a[0] * phi0;
+        d[m - 1] -= c[m - 1] * phiN;
+        for (int32_t i = 1; i < m; ++i) {
+            double f = a[i] / b[i - 1];
+            b[i] -= f * c[i - 1];
+            d[i] -= f * d[i - 1];
+        }
+        phi[m] = d[m - 1] / b[m - 1];
+        for (int32_t i = m - 2; i >= 0; --i) phi[i + 1] = (d[i] - c[i] * phi[i + 2]) / b[i];
+        free(a); free(b); free(c); free(d);
+    }
+    for (int32_t j = 0; j < N; ++j) E[j] = (phi[j] - phi[j + 1]) / w[j];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Periodic field solve.  Gauss's law between neighbouring half-grid points */
 /*   D_{j+1/2} - D_{j-1/2} = dx rho_j,  D = eps0 (1+chi) E,                  */
@@ -313,9 +348,20 @@ orc_sim* orc_create(const orc_case* c)
 {
     if (c->n_cells < 2) return NULL;
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
+    if (c->cell_dx_m) {
+        /* nonuniform grids: EC gather between electrodes, widths summing to L */
+        if (c->gather != ORC_GATHER_EC || c->bc != ORC_BC_DIRICHLET) return NULL;
+        double L = 0.0;
+        for (int32_t j = 0; j < c->n_cells; ++j) {
+            if (!(c->cell_dx_m[j] > 0.0) || !isfinite(c->cell_dx_m[j])) return NULL;
+            L += c->cell_dx_m[j];
+        }
+        if (!(fabs(L - c->gap_m) <= 1e-9 * c->gap_m)) return NULL;
+    }
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->c = *c;
     s->dx = c->gap_m / c->n_cells;
+    s->c.cell_dx_m = NULL;   /* the caller's array is copied below */
     s->step = c->step0;
     int32_t N = c->n_cells;
     s->rho = (double*)xcalloc((size_t)N + 1, sizeof(double));
@@ -327,6 +373,15 @@ orc_sim* orc_create(const orc_case* c)
         s->cnt[k] = (double*)xcalloc((size_t)N, sizeof(double));
         s->chw[k] = (double*)xcalloc((size_t)N, sizeof(double));
         s->heat[k] = (double*)xcalloc((size_t)N, sizeof(double));
+    }
+    if (c->cell_dx_m) {
+        s->cw = (double*)xcalloc((size_t)N, sizeof(double));
+        s->edge = (double*)xcalloc((size_t)N + 1, sizeof(double));
+        s->sigma = (double*)xcalloc((size_t)N + 1, sizeof(double));
+        for (int32_t j = 0; j < N; ++j) {
+            s->cw[j] = c->cell_dx_m[j];
+            s->edge[j + 1] = s->edge[j] + s->cw[j];
+        }
     }
     return s;
 }
@@ -342,6 +397,7 @@ void orc_destroy(orc_sim* s)
     }
     for (int k = 0; k < s->n_proc; ++k) free(s->proc[k].sigma);
     free(s->rho); free(s->phi); free(s->E); free(s->chi);
+    free(s->cw); free(s->edge); free(s->sigma);
     free(s);
 }
 
@@ -539,7 +595,7 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         double we = 0.0;
         for (int32_t j = 0; j < N; ++j) {
             s->E[j] = s->ext_E[j];
-            we += 0.5 * EPS0 * s->E[j] * s->E[j] * s->dx;
+            we += 0.5 * EPS0 * s->E[j] * s->E[j] * (s->cw ? s->cw[j] : s->dx);
         }
         s->led.WE = we;
         return;
@@ -557,6 +613,17 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
     }
     for (int32_t g = 0; g <= N; ++g) {
         double r = s->c.background_rho;
+        if (s->cw) {
+            /* charge per area of node g; rho over the node's volume: half
+             * of each adjacent cell, the whole end cell at an electrode */
+            double vol = g == 0 ? s->cw[0]
+                       : g == N ? s->cw[N - 1] : 0.5 * (s->cw[g - 1] + s->cw[g]);
+            double sg = r * vol;
+            for (int k = 0; k < 2; ++k) sg += s->sp[k].q * s->sp[k].w * s->Q[k][g];
+            s->sigma[g] = sg;
+            s->rho[g] = sg / vol;
+            continue;
+        }
         for (int k = 0; k < 2; ++k) r += s->sp[k].q * s->sp[k].w * s->Q[k][g] / s->dx;
         s->rho[g] = r;
     }
@@ -590,15 +657,19 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
                 if (s->sp[k].m > 0.0)
                     x += s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m * nj[j];
             }
-        s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * s->dx) * x;
+        s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * (s->cw ? s->cw[j] : s->dx)) * x;
     }
     if (periodic)
         orc_solve_periodic(N, s->dx, s->rho, use_chi ? s->chi : NULL, s->phi, s->E);
+    else if (s->cw)
+        orc_solve_dirichlet_nu(N, s->cw, s->sigma, use_chi ? s->chi : NULL,
+                               rf_volts_at(s, step_for_bc), 0.0, s->phi, s->E);
     else
         orc_solve_dirichlet(N, s->dx, s->rho, use_chi ? s->chi : NULL,
                             rf_volts_at(s, step_for_bc), 0.0, s->phi, s->E);
     double we = 0.0;
-    for (int32_t j = 0; j < N; ++j) we += 0.5 * EPS0 * s->E[j] * s->E[j] * s->dx;
+    for (int32_t j = 0; j < N; ++j)
+        we += 0.5 * EPS0 * s->E[j] * s->E[j] * (s->cw ? s->cw[j] : s->dx);
     s->led.WE = we;
 }
 
@@ -631,6 +702,27 @@ static void append_particle(species_t* p, double xi, double vx, double vy, doubl
     p->xi[i] = xi; p->vx[i] = vx; p->vy[i] = vy; p->vz[i] = vz; p->abar[i] = abar;
     p->id[i] = id;
     p->wait[i] = wait;
+}
+
+/* A move by the physical distance d (m) on a nonuniform grid: the physical
+ * position X = e_c + (xi - c) w_c is moved and mapped back to the cell whose
+ * edges hold it (bisection over the node positions); beyond an electrode
+ * the width of the cell next to it continues the map, so that the boundary
+ * rule below absorbs the particle.  (On a uniform grid xi += d / dx.) */
+static void move_nonuniform(const orc_sim* s, double* xi, double d)
+{
+    int32_t N = s->c.n_cells;
+    int32_t c = (int32_t)floor(*xi);
+    double X = s->edge[c] + (*xi - c) * s->cw[c] + d;
+    if (X < 0.0) { *xi = X / s->cw[0]; return; }
+    if (X >= s->edge[N]) { *xi = N + (X - s->edge[N]) / s->cw[N - 1]; return; }
+    int32_t lo = 0, hi = N;   /* edge[lo] <= X < edge[hi] */
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) / 2;
+        if (s->edge[mid] <= X) lo = mid;
+        else hi = mid;
+    }
+    *xi = lo + (X - s->edge[lo]) / s->cw[lo];
 }
 
 /* Boundary rule.  Dirichlet: absorbed at the electrode it crossed
@@ -859,7 +951,8 @@ static void step_explicit(orc_sim* s)
             s->led.work[k] += dK;
             s->heat[k][(int64_t)floor(p->xi[i])] += dK;
             p->vx[i] += dv;
-            p->xi[i] += p->vx[i] * dt_dx;
+            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * s->c.dt_s);
+            else p->xi[i] += p->vx[i] * dt_dx;
             int e = boundary(s, &p->xi[i]);
             if (e >= 0) {
                 s->led.absorbed_n[k][e]++;
@@ -905,7 +998,8 @@ static void step_implicit(orc_sim* s)
             double dK = p->m * p->w * dv * (vold + 0.5 * dv);
             s->led.work[k] += dK;
             s->heat[k][(int64_t)floor(p->xi[i])] += dK;
-            p->xi[i] += 0.5 * dt * dt * a / s->dx;              /* x_{n+1}    */
+            if (s->cw) move_nonuniform(s, &p->xi[i], 0.5 * dt * dt * a);
+            else p->xi[i] += 0.5 * dt * dt * a / s->dx;         /* x_{n+1}    */
             p->vx[i] = vnew;
             p->abar[i] = 0.5 * (p->abar[i] + a);                 /* abar_n     */
             int e = boundary(s, &p->xi[i]);
@@ -928,7 +1022,8 @@ static void step_implicit(orc_sim* s)
         while (i < p->n) {
             double vt = p->vx[i] + 0.5 * dt * p->abar[i];
             p->vx[i] = vt;
-            p->xi[i] += vt * dt_dx;
+            if (s->cw) move_nonuniform(s, &p->xi[i], vt * dt);
+            else p->xi[i] += vt * dt_dx;
             int e = boundary(s, &p->xi[i]);
             if (e >= 0) {
                 double vh1 = vt - 0.5 * dt * p->abar[i];
@@ -953,7 +1048,8 @@ int orc_implicit_startup(orc_sim* s)
         int64_t i = 0;
         while (i < p->n) {
             p->abar[i] = 0.0;
-            p->xi[i] += p->vx[i] * dt_dx;
+            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * s->c.dt_s);
+            else p->xi[i] += p->vx[i] * dt_dx;
             if (boundary(s, &p->xi[i]) >= 0) { remove_particle(p, i); continue; }
             ++i;
         }

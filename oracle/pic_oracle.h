@@ -58,6 +58,10 @@ typedef struct {
     double background_rho;  /* fixed uniform charge density, C/m^3                 */
     double opal_B_eV;       /* energy-sharing parameter of ionization              */
     uint64_t seed;          /* Philox key                                          */
+    /* NULL: N equal cells of L/N.  Otherwise the N cell widths (m, summing to
+     * L; EC gather and electrodes only): a nonuniform grid, finer in the
+     * sheaths.  Positions stay logical (cell index + offset in the cell). */
+    const double* cell_dx_m;
 } orc_case;
 
 /* Per-step energy and particle ledger (all energies J/m^2). */
@@ -95,6 +99,13 @@ void orc_count_cells(int32_t N, int64_t n, const double* xi, double* cnt);
  * chi_{j+1/2}.  Output phi (N+1) and the staggered field E_{j+1/2} (N). */
 void orc_solve_dirichlet(int32_t N, double dx, const double* rho, const double* chi,
                          double phi0, double phiN, double* phi, double* E);
+/* Dirichlet solve on a nonuniform grid of cell widths w[N]:
+ *   (eps0 (1+chi_{g-1}) / w_{g-1}) (phi_g - phi_{g-1})
+ *     - (eps0 (1+chi_g) / w_g) (phi_{g+1} - phi_g) = sigma_g,  g = 1..N-1,
+ * sigma_g the charge per unit area of node g (C/m^2);
+ * E_{j+1/2} = (phi_j - phi_{j+1}) / w_j. */
+void orc_solve_dirichlet_nu(int32_t N, const double* w, const double* sigma, const double* chi,
+                            double phi0, double phiN, double* phi, double* E);
 void orc_solve_periodic(int32_t N, double dx, const double* rho, const double* chi,
                         double* phi, double* E);
 

@@ -1,0 +1,198 @@
+"""Pins of the oracle on a nonuniform grid (cells finer in the sheaths, the
+multi-scale remedy of the conclusions): positions stay logical (cell index +
+offset); a move is made in physical space; node charges are per unit area.
+
+* the solve: uniform charge gives the closed-form quadratic potential at the
+  nodes; with a susceptibility the discrete Gauss law and the potential
+  difference hold in first-integral form;
+* the mover: the physical displacement equals v dt across cells of different
+  widths (physical positions rebuilt here from the widths);
+* cold plasma: with the particle count of every cell proportional to its
+  width (uniform physical density) and a displacement uniform in each cell,
+  the EC scheme oscillates at exactly omega_p (leap-frog dispersion) and the
+  D1 scheme follows its closed recurrence, which fixes the widths in the
+  deposit, solve, gather, susceptibility and mover;
+* equal widths reproduce the uniform path."""
+import math
+
+import numpy as np
+import pytest
+
+E = 1.602176634e-19
+ME = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+
+MULT = np.array([1, 1, 2, 3, 5, 5, 3, 2, 1, 1])   # widths in units of the finest cell
+
+
+def test_solve_uniform_charge_closed_form(orc):
+    rng = np.random.default_rng(1)
+    w = rng.uniform(0.2e-3, 1.5e-3, 17)
+    xn = np.concatenate([[0.0], np.cumsum(w)])
+    L = xn[-1]
+    rho, V0, VN = 3e-4, 40.0, -5.0
+    vol = np.concatenate([[w[0]], 0.5 * (w[:-1] + w[1:]), [w[-1]]])
+    phi, Ef = orc.solve_dirichlet_nu(w, rho * vol, V0, VN)
+    exact = V0 + (VN - V0 + rho * L * L / (2 * EPS0)) * xn / L - rho * xn ** 2 / (2 * EPS0)
+    scale = np.abs(exact).max()
+    np.testing.assert_allclose(phi, exact, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(Ef, (exact[:-1] - exact[1:]) / w, rtol=1e-9)
+
+
+def test_solve_satisfies_gauss_law_with_susceptibility(orc):
+    rng = np.random.default_rng(2)
+    N = 23
+    w = rng.uniform(0.1e-3, 2e-3, N)
+    sigma = rng.normal(size=N + 1) * 1e-6
+    chi = rng.uniform(0.0, 30.0, N)
+    phi, Ef = orc.solve_dirichlet_nu(w, sigma, 12.0, 3.0, chi=chi)
+    D = EPS0 * (1.0 + chi) * Ef
+    np.testing.assert_allclose(D[1:] - D[:-1], sigma[1:N], rtol=0,
+                               atol=1e-9 * np.abs(sigma).max())
+    assert abs((Ef * w).sum() - (12.0 - 3.0)) < 1e-9 * 12.0
+    np.testing.assert_allclose(phi[:-1] - phi[1:], Ef * w, rtol=1e-10, atol=1e-12)
+
+
+def _two_species(xe, ve, we, m=ME):
+    z = np.zeros(xe.size)
+    return [dict(q=-E, m=m, w=we, xi=xe, vx=ve, vy=z, vz=z, abar=None,
+                 id=np.arange(xe.size, dtype=np.uint64)),
+            dict(q=E, m=40 * 1.66053906660e-27, w=we, xi=np.zeros(0), vx=np.zeros(0),
+                 vy=np.zeros(0), vz=np.zeros(0), abar=None, id=np.zeros(0, np.uint64))]
+
+
+def test_mover_keeps_the_physical_displacement(orc):
+    w = 1e-4 * MULT
+    edges = np.concatenate([[0.0], np.cumsum(w)])
+    dt = 1e-10
+    rng = np.random.default_rng(3)
+    n = 200
+    xi = rng.uniform(0.0, MULT.size, n)
+    v = rng.uniform(-3.0, 3.0, n) * w.max() / dt      # up to 3 of the widest cells
+    case = dict(n_cells=MULT.size, gap_m=edges[-1], bc=0, scheme=0, gather=0, collisions=0,
+                dt_s=dt, cell_dx=w)
+    sim = orc.Sim(case, _two_species(xi, v, 1e-30), [], startup=False)
+    sim.step(1)
+    st = sim.species(0)
+    X0 = edges[np.floor(xi).astype(int)] + (xi - np.floor(xi)) * w[np.floor(xi).astype(int)]
+    X1_want = X0 + v * dt
+    inside = (X1_want > 0) & (X1_want < edges[-1])
+    order = np.argsort(st["id"])
+    x1 = st["xi"][order]
+    c1 = np.floor(x1).astype(int)
+    X1 = edges[c1] + (x1 - c1) * w[c1]
+    assert x1.size == inside.sum()                   # the others were absorbed
+    np.testing.assert_allclose(X1, X1_want[inside], rtol=0, atol=1e-12 * edges[-1])
+
+
+def cold_nonuniform(wdt, scheme, A=0.06, ppc=6, n0=1e15):
+    """Electrons at uniform physical density n0 on a symmetric nonuniform
+    grid over a neutralising background; cell c holds MULT_c ppc electrons in
+    the middle half of the cell and is displaced by A s_c of the finest cell,
+    s antisymmetric about the centre (no mean displacement)."""
+    b = 1e-4
+    w = b * MULT
+    N = MULT.size
+    wp = math.sqrt(n0 * E * E / (EPS0 * ME))
+    dt = wdt / wp
+    weight = n0 * b / ppc
+    cells, offs = [], []
+    for c, m in enumerate(MULT):
+        k = m * ppc
+        cells.append(np.full(k, c))
+        offs.append(0.25 + 0.5 * (np.arange(k) + 0.5) / k)
+    cell = np.concatenate(cells)
+    off = np.concatenate(offs)
+    s = np.sin(2 * np.pi * (np.arange(N) + 0.5) / N)       # antisymmetric, sum_c s_c w_c = 0
+    delta = A * b * s[cell]                                  # physical displacement
+    xi = cell + off + delta / w[cell]
+    theta_c = 1 - 0.5 * wdt ** 2
+    v = delta * (1 - theta_c) / dt if scheme == 0 else np.zeros(cell.size)
+    case = dict(n_cells=N, gap_m=w.sum(), bc=0, scheme=scheme, gather=0, collisions=0,
+                dt_s=dt, background_rho=n0 * E, cell_dx=w)
+    return case, _two_species(xi, v, weight), cell, off, delta, w, dt, wp
+
+
+@pytest.mark.parametrize("wdt", [0.3, 1.2, 1.9])
+def test_ec_cold_plasma_oscillates_at_exactly_omega_p(orc, wdt):
+    case, sps, cell, off, delta, w, dt, wp = cold_nonuniform(wdt, 0)
+    sim = orc.Sim(case, sps, [])
+    theta = math.acos(1 - 0.5 * wdt ** 2)
+    for n in range(1, 81):
+        sim.step(1)
+        st = sim.species(0)
+        x = st["xi"][np.argsort(st["id"])]
+        got = (x - cell - off) * w[cell]                 # physical displacement
+        np.testing.assert_allclose(got, delta * math.cos(n * theta), rtol=0,
+                                   atol=1e-10 * np.abs(delta).max())
+
+
+@pytest.mark.parametrize("wdt", [0.5, 4.0])
+def test_d1_cold_plasma_follows_recurrence(orc, wdt):
+    case, sps, cell, off, delta, w, dt, wp = cold_nonuniform(wdt, 1)
+    sim = orc.Sim(case, sps, [])
+    # the D1 map of x'' = -wp^2 x from rest, per unit displacement
+    x, v, ab = 1.0, 0.0, 0.0
+    xt = x + dt * v
+    ref = []
+    for _ in range(40):
+        xn = xt / (1 + 0.5 * wp ** 2 * dt ** 2)
+        a = -wp ** 2 * xn
+        v = v + 0.5 * dt * ab + 0.5 * dt * a
+        ab = 0.5 * (ab + a)
+        xt = xn + dt * (v + 0.5 * dt * ab)
+        ref.append(xt)
+    for n in range(40):
+        sim.step(1)
+        st = sim.species(0)
+        x1 = st["xi"][np.argsort(st["id"])]
+        got = (x1 - cell - off) * w[cell]
+        np.testing.assert_allclose(got, delta * ref[n], rtol=0, atol=1e-10 * np.abs(delta).max())
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_equal_widths_reproduce_the_uniform_grid(orc, scheme):
+    import workloads as W
+    wl = W.c1(collisions=1, np_per_species=3000, scheme=scheme)
+    case, sps, procs = W.to_oracle(wl)
+    N = case["n_cells"]
+    a = orc.Sim(case, sps, procs)
+    b = orc.Sim(dict(case, cell_dx=np.full(N, case["gap_m"] / N)), sps, procs)
+    a.step(30)
+    b.step(30)
+    for s in range(2):
+        sa, sb = a.species(s), b.species(s)
+        assert np.array_equal(sa["id"], sb["id"])
+        np.testing.assert_allclose(sb["xi"], sa["xi"], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(sb["vx"], sa["vx"], rtol=1e-9, atol=1e-6)
+    fa, fb = a.fields(), b.fields()
+    np.testing.assert_allclose(fb["E"], fa["E"], rtol=0, atol=1e-9 * np.abs(fa["E"]).max())
+
+
+def test_rejects_what_the_grid_does_not_support(orc):
+    w = np.full(8, 1e-3)
+    base = dict(n_cells=8, gap_m=8e-3, bc=0, scheme=0, gather=0, collisions=0, dt_s=1e-11)
+    sps = _two_species(np.array([0.5]), np.zeros(1), 1.0)
+    for bad in (dict(gather=1), dict(gather=2), dict(bc=1), dict(gap_m=9e-3)):
+        with pytest.raises(ValueError):
+            orc.Sim(dict(base, cell_dx=w, **bad), sps, [])
+    with pytest.raises(ValueError):
+        orc.Sim(dict(base, cell_dx=np.concatenate([w[:-1], [0.0]])), sps, [])
+
+
+def test_ec_energy_error_shrinks_like_dt_squared(orc):
+    # field energy sum 1/2 eps0 E^2 w_j plus kinetic energy (mean of the two
+    # half steps) is conserved up to the leap-frog error
+    errs = []
+    for wdt in (0.3, 0.15, 0.075):
+        case, sps, cell, off, delta, w, dt, wp = cold_nonuniform(wdt, 0)
+        sim = orc.Sim(case, sps, [])
+        tot = []
+        for _ in range(int(round(20 / wdt))):
+            sim.step(1)
+            L = sim.ledger()
+            tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+        tot = np.array(tot)
+        errs.append(np.abs(tot / tot[0] - 1).max())
+    for a, b in zip(errs, errs[1:]):
+        assert 3.0 <= a / b <= 5.5, errs
