@@ -62,6 +62,11 @@ def make_workload(name, scale):
         wl = W.c4(np_per_species=int(10_000_000 * scale), scheme=1)
         wl["case"]["gather"] = 2
         return [wl]
+    if name == "ccp2048_nonuniform":
+        # the same discharge on a sheath-refined grid (cells about 4x narrower
+        # within 15 % of the gap from either electrode)
+        return [W.c4(np_per_species=int(10_000_000 * scale),
+                     cell_dx=W.sheath_refined_widths(2048, 0.025))]
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":
@@ -347,7 +352,8 @@ def main():
     if tuned:
         out["autotune"] = tuned
     if args.fp64_steps > 0 and all(sc == 0 for sc in schemes) and \
-            all(w["case"].get("gather", 0) != 2 for w in wls):
+            all(w["case"].get("gather", 0) != 2 and w["case"].get("cell_dx") is None
+                for w in wls):
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
         ctx.fp64_init()

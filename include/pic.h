@@ -103,6 +103,13 @@ typedef struct {
     double background_rho;  /* fixed uniform charge density, C/m^3              */
     double opal_B_eV;       /* energy-sharing parameter of ionization (10 eV)   */
     uint64_t seed;          /* Philox4x32-10 key of this case                   */
+    /* NULL: N equal cells of gap_m / N.  Otherwise N cell widths in metres
+     * (host memory, read during pic_init only), positive and summing to
+     * gap_m within 1e-9: a nonuniform grid, finer in the sheaths (the
+     * multi-scale grid the conclusions propose).  PIC_GATHER_EC and
+     * PIC_BC_DIRICHLET_RF only (else PIC_E_INVAL).  Positions stay logical
+     * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */
+    const double* cell_dx_m;
 } pic_case_config;
 
 #define PIC_MAX_CELLS 4096
@@ -302,7 +309,7 @@ int pic_reset_accumulators(pic_ctx* ctx);
  * and velocities, fp64 global-atomic deposit, no sort, one launch per phase),
  * used as the throughput comparison point.  Advances its own copy of the
  * context's initial state.  Explicit cases with PIC_GATHER_EC or
- * PIC_GATHER_MC only (else PIC_E_INVAL). */
+ * PIC_GATHER_MC on uniform grids only (else PIC_E_INVAL). */
 int pic_fp64_reference_init(pic_ctx* ctx);
 int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
 int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,

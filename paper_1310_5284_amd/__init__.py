@@ -40,7 +40,8 @@ class CaseConfig(C.Structure):
                 ("rf_volts", C.c_double), ("rf_freq_hz", C.c_double),
                 ("gas_density_m3", C.c_double), ("gas_temp_K", C.c_double),
                 ("gas_mass_kg", C.c_double), ("background_rho", C.c_double),
-                ("opal_B_eV", C.c_double), ("seed", C.c_uint64)]
+                ("opal_B_eV", C.c_double), ("seed", C.c_uint64),
+                ("cell_dx_m", C.POINTER(C.c_double))]
 
 
 # null-collision waiting-time word: count (17 bits) | capped flag
@@ -298,6 +299,11 @@ class PicContext:
                 gas_temp_K=c.get("gas_temp_K", 300.0), gas_mass_kg=c.get("gas_mass_kg", 1.0),
                 background_rho=c.get("background_rho", 0.0), opal_B_eV=c.get("opal_B_eV", 10.0),
                 seed=c.get("seed", 0))
+            cdx = c.get("cell_dx")
+            if cdx is not None:
+                cdx = np.ascontiguousarray(cdx, dtype=np.float64)
+                self._keep.append(cdx)
+                cfgs[k].cell_dx_m = cdx.ctypes.data_as(C.POINTER(C.c_double))
             self.n_cells.append(int(c["n_cells"]))
             for s, sp in enumerate(wl["species"]):
                 arrs = {}

@@ -265,6 +265,62 @@ __device__ __forceinline__ float predict(int& c, float& o, float vn, float abn)
     return vst;
 }
 
+// A move by d (units of the reference width L/N) on a nonuniform grid with
+// r[c] = (L/N) / w_c: inside cell c the offset changes by d r_c; at an edge
+// the rest of the move continues in the next cell.  Past an electrode the
+// walk stops with the cell index -1 or N, which the boundary rule absorbs.
+// At most N cells are visited.  One rounding per operation, so that every
+// kernel reproduces the same walk bit for bit.
+template <class RP>
+__device__ __forceinline__ void walk(int& c, float& o, float d, RP r, int N)
+{
+    if (d >= 0.0f) {
+        for (;;) {
+            const float rc = r[c];
+            const float x = fmaf(d, rc, o);
+            if (x < 1.0f) {
+                o = x;
+                return;
+            }
+            d = __fsub_rn(d, __fdiv_rn(__fsub_rn(1.0f, o), rc));
+            ++c;
+            o = 0.0f;
+            if (c >= N || d <= 0.0f) return;
+        }
+    }
+    for (;;) {
+        const float rc = r[c];
+        const float x = fmaf(d, rc, o);
+        if (x >= 0.0f) {
+            if (x >= 1.0f) {   // a rest too small to leave the right edge
+                ++c;
+                o = 0.0f;
+            } else {
+                o = x;
+            }
+            return;
+        }
+        d = __fadd_rn(d, __fdiv_rn(o, rc));
+        --c;
+        o = 1.0f;   // the right edge of the cell entered
+        if (c < 0) return;
+        if (d >= 0.0f) {   // the move ended on the edge
+            ++c;
+            o = 0.0f;
+            return;
+        }
+    }
+}
+
+// The D1 prediction on a nonuniform grid (the walk in place of renorm).
+template <class RP>
+__device__ __forceinline__ float predict_nu(int& c, float& o, float vn, float abn, RP r, int N)
+{
+    const float vst = fmaf(0.5f, abn, vn);
+    walk(c, o, vst, r, N);
+    return vst;
+}
+
 // Flag in the waiting-time field of a listed candidate's word (its count is
 // zero): k_step deposited the candidate's prediction without a collision.
 constexpr uint32_t kPredDeposited = 1u;

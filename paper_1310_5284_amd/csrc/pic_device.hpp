@@ -91,7 +91,9 @@ struct Case {
     int32_t first_block;  // this case's first workgroup in the work table
     int32_t n_blocks;
     int32_t history_len;
-    double dx, dt;
+    int32_t nonuniform;   // cell widths of their own (EC gather, electrodes)
+    int32_t pad1;
+    double dx, dt;        // dx: the reference width L/N (velocity unit dx/dt)
     double rf_volts, rf_omega, rf_freq;
     double background_rho;
     uint32_t key0, key1;  // Philox key = seed
@@ -104,6 +106,10 @@ struct Case {
     // summed fractions towards centre k + 1 (null otherwise)
     unsigned long long* chi_cnt[2];  // [N+1]
     unsigned long long* chi_w[2];    // [N+1]
+    // nonuniform grid (null otherwise): r_c = dx / w_c for the moves and
+    // w_c / dx for the solve
+    float* cell_r;                   // [N]
+    double* cell_wr;                 // [N]
     float* ehat[2];                  // [N] accel * E of the next step, per species
     double* E;                       // [N] V/m
     double* phi;                     // [N+1]
@@ -194,18 +200,21 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 
 // Shared-memory layout of k_step for a case of N cells:
 //   field[N+1] float  (EC: ehat of the cells; MC: nodal field)
-//   dep[N] u64        (privatised deposit, count << 40 | summed weight)
+//   dep[N+1] u64      (privatised deposit, count << 40 | summed weight)
 //   DIAG: heat[N] float, eedf[kEedfBins] u32
-// (dual: the susceptibility words of the m = 2 implicit scheme follow dep)
+// (dual: the susceptibility words of the m = 2 implicit scheme follow dep;
+// nu: the width ratios r_c of a nonuniform grid, N floats, follow those)
 struct StepLds {
-    size_t dep, dual, heat, eedf, total;
+    size_t dep, dual, ratio, heat, eedf, total;
 };
-__host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual = false)
+__host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual = false,
+                                                   bool nu = false)
 {
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
     L.dual = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
-    L.heat = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
+    L.ratio = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
+    L.heat = L.ratio + (nu ? align16(4 * (size_t)N) : 0);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;

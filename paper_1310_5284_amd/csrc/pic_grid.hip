@@ -24,6 +24,9 @@ namespace pic {
 // explicit cycle; chi from the predicted cell counts the susceptibility-
 // modified solve of the direct-implicit cycle (with m = 2: from the words of
 // the dual grid, the row sums of the linearised deposit-gather operator).
+// On a nonuniform grid the node charges are per unit area (rho times the
+// node's volume), and the cell widths w_j enter the potential condition
+// sum_j E_{j+1/2} w_j, the susceptibility (1/w_j) and the field energy.
 // O(log N) deep.
 // ---------------------------------------------------------------------------
 constexpr double kEps0 = 8.8541878128e-12;
@@ -61,6 +64,8 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double rho_bg = Cc.background_rho;
     const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
     const bool dual = implicit && ec2;  // susceptibility of the dual grid
+    const bool nu = Cc.nonuniform != 0;
+    const PIC_GLOBAL double* wjr = gp((const double*)Cc.cell_wr);   // nu: w_j / dx
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
         long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
@@ -100,15 +105,24 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                 const bool end = !periodic && (g == 0 || g == N);
                 Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
             }
+            double sg = rho * dx;
+            if (nu) {
+                // node volume / dx: half of each adjacent cell, the whole end cell
+                const double vg =
+                    g == 0 ? wjr[0] : (g == N ? wjr[N - 1] : 0.5 * (wjr[g - 1] + wjr[g]));
+                sg = (rho - rho_bg) * dx + rho_bg * dx * vg;
+                rho = sg / (dx * vg);
+            }
             gp(Cc.rho)[g] = rho;
-            // R_j = dx sum_{k=1..j} rho_k: the summand of node 0 is zero
-            S[g] = g == 0 ? 0.0 : rho * dx;
+            // R_j = sum_{k=1..j} (charge per area of node k): node 0's is zero
+            S[g] = g == 0 ? 0.0 : sg;
             if (g < N) {
                 gp(Cc.ccount[0])[g] = cn[k][0];
                 gp(Cc.ccount[1])[g] = cn[k][1];
                 if (!node_chi && !dual) {
-                    const double chi =
+                    double chi =
                         implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
+                    if (nu) chi /= wjr[g];
                     X[g] = chi;
                     gp(Cc.chi)[g] = chi;
                 }
@@ -169,9 +183,11 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
         if (j < N) {
+            // om = w_j / dx (exactly 1 on a uniform grid)
+            const double om = nu ? wjr[j] : 1.0;
             const double kap = kEps0 * (1.0 + X[j]);
-            a += S[j] / kap;
-            b += 1.0 / kap;
+            a += S[j] * om / kap;
+            b += om / kap;
         }
     }
     a = block_sum<double, NT>(a, red);
@@ -188,12 +204,13 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
         if (j < N) {
+            const double om = nu ? wjr[j] : 1.0;
             const double E = (D0 + S[j]) / (kEps0 * (1.0 + X[j]));
-            X[j] = E;   // X now holds E
+            X[j] = E * om;   // X now holds E w_j / dx
             gp(Cc.E)[j] = E;
             gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
             gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
-            we += 0.5 * kEps0 * E * E * dx;
+            we += 0.5 * kEps0 * E * E * dx * om;
         }
     }
     lds_barrier();
@@ -414,8 +431,12 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
         float o = S.off[i];
         if (startup) {
             S.abar[i] = 0.0f;
-            o += S.vx[i];
-            renorm(c, o);
+            if (C->nonuniform) {
+                walk(c, o, S.vx[i], C->cell_r, N);
+            } else {
+                o += S.vx[i];
+                renorm(c, o);
+            }
             if (C->bc == 1) {
                 c %= N;
                 if (c < 0) c += N;

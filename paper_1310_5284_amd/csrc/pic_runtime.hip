@@ -50,6 +50,7 @@ struct HostCase {
     int64_t cap[2];
     int64_t n0[2];
     double vscale;          // (m/s) -> cells/step
+    std::vector<double> cell_w;   // nonuniform grid: widths (m); empty if uniform
     // float64 values of the per-species collision constants that the float
     // path stores as float32 (for the plain FP64 form): eps_unit, opal_B,
     // recoil2, vth_neutral, vth_newion, t_scale, t_off, t_max, thr_v2[4]
@@ -105,6 +106,7 @@ struct pic_ctx {
     CollideWork* d_cwork = nullptr;
     int grp_maxN[2] = {0, 0};
     bool grp_dual[2] = {false, false};   // a case of the group has the dual grid
+    bool grp_nu[2] = {false, false};     // a case of the group has a nonuniform grid
     bool any_dual = false;
     int maxN = 0;
     int tile = 8192;
@@ -170,9 +172,9 @@ size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Dynamic LDS of k_step: field[N+1] float | dep[N+1] u64 | (m = 2 implicit:
 // susceptibility words[N+1] u64) | (DIAG: heat[N] float | eedf[kEedfBins] u32).
-size_t step_lds(int N, bool diag, bool dual)
+size_t step_lds(int N, bool diag, bool dual, bool nu)
 {
-    return step_lds_layout(N, diag, dual).total;
+    return step_lds_layout(N, diag, dual, nu).total;
 }
 
 size_t collide_lds(int N, bool dual)
@@ -235,6 +237,7 @@ int build_work(pic_ctx* c)
         c->grp_off[g] = (int)c->work.size();
         c->grp_maxN[g] = 0;
         c->grp_dual[g] = false;
+        c->grp_nu[g] = false;
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
@@ -248,6 +251,7 @@ int build_work(pic_ctx* c)
 
             c->grp_maxN[g] = std::max(c->grp_maxN[g], (int)h.cfg.n_cells);
             c->grp_dual[g] = c->grp_dual[g] || dual_chi(h.cfg.scheme, h.cfg.gather);
+            c->grp_nu[g] = c->grp_nu[g] || !h.cell_w.empty();
         }
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
     }
@@ -398,9 +402,23 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC &&
              g.gather != PIC_GATHER_EC2) ||
             g.history_steps < 0 ||
+            (g.cell_dx_m && (g.gather != PIC_GATHER_EC || g.bc != PIC_BC_DIRICHLET_RF)) ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
             return bail(PIC_E_INVAL);
+        }
+        if (g.cell_dx_m) {
+            double L = 0.0;
+            bool ok = true;
+            for (int32_t j = 0; j < g.n_cells; ++j) {
+                const double wj = g.cell_dx_m[j];
+                ok = ok && wj > 0.0 && std::isfinite(wj);
+                L += wj;
+            }
+            if (!ok || !(std::fabs(L - g.gap_m) <= 1e-9 * g.gap_m)) {
+                fprintf(stderr, "pic_init: case %d: bad cell widths\n", k);
+                return bail(PIC_E_INVAL);
+            }
         }
         for (int s = 0; s < 2; ++s) {
             const pic_species_init& sp = species[2 * k + s];
@@ -452,6 +470,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         Case& C = c->cases_h[k];
         std::memset(&C, 0, sizeof(Case));
         h.cfg = g;
+        h.cfg.cell_dx_m = nullptr;   // the caller's array is copied
+        if (g.cell_dx_m) h.cell_w.assign(g.cell_dx_m, g.cell_dx_m + g.n_cells);
         const int N = g.n_cells;
         const double dx = g.gap_m / N, dt = g.dt_s;
         h.vscale = dt / dx;
@@ -461,6 +481,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         C.gather = g.gather;
         C.collisions = g.collisions;
         C.history_len = g.history_steps;
+        C.nonuniform = g.cell_dx_m ? 1 : 0;
         C.dx = dx;
         C.dt = dt;
         C.rf_volts = g.rf_volts;
@@ -686,12 +707,27 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         pic_ledger* hist = nullptr;
         rc |= dalloc(c, h.allocs, &hist, (size_t)g.history_steps + 1);
         C.history = hist;
+        if (!h.cell_w.empty()) {
+            // the moves take r_c = dx / w_c (float), the solve w_c / dx (double)
+            rc |= dalloc(c, h.allocs, &C.cell_r, N);
+            rc |= dalloc(c, h.allocs, &C.cell_wr, N);
+        }
         if (rc) return bail(PIC_E_NOMEM);
+        if (!h.cell_w.empty()) {
+            std::vector<float> r(N);
+            std::vector<double> wr(N);
+            for (int j = 0; j < N; ++j) {
+                r[j] = (float)(C.dx / h.cell_w[j]);
+                wr[j] = h.cell_w[j] / C.dx;
+            }
+            INITCHK(hipMemcpy(C.cell_r, r.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
+            INITCHK(hipMemcpy(C.cell_wr, wr.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
+        }
         h.hist_off[0] = hist_total;
         h.hist_off[1] = hist_total + N;
         hist_total += 2 * (size_t)N;
     }
-    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true, c->any_dual),
+    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true, c->any_dual, true),
                                             collide_lds(c->maxN, c->any_dual)),
                                    std::max(deposit_lds(c->maxN, c->any_dual), fin_lds(c->maxN)))))
         return bail(PIC_E_INVAL);
@@ -831,7 +867,8 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             if (rec) HIPCHK(c, record(pool->ev[pool->used]));
             if (kind == 0)
                 hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock),
-                                   step_lds(N, diag, c->grp_dual[g]), c->stream, p);
+                                   step_lds(N, diag, c->grp_dual[g], c->grp_nu[g]), c->stream,
+                                   p);
             else
                 hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
                                    collide_lds(N, c->grp_dual[g]), c->stream, pc);
@@ -1255,8 +1292,14 @@ extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic
             std::vector<long long> acc(N + 1);
             HIPCHK(ctx, hipMemcpy(acc.data(), C.dens_acc[s], 8 * (N + 1), hipMemcpyDeviceToHost));
             std::vector<double> d(N + 1);
+            const std::vector<double>& cw = h.cell_w;
             for (size_t g = 0; g <= N; ++g) {
                 double vol = (C.bc == PIC_BC_DIRICHLET_RF && (g == 0 || g == N)) ? 0.5 : 1.0;
+                if (!cw.empty()) {
+                    // node volume in units of dx: half of each adjacent cell
+                    const double wl = g > 0 ? cw[g - 1] : 0.0, wr = g < N ? cw[g] : 0.0;
+                    vol = 0.5 * (wl + wr) / C.dx;
+                }
                 d[g] = st.dens_samples > 0
                            ? (double)acc[g] / kFixScale * C.sp[s].dens_unit / vol / st.dens_samples
                            : 0.0;

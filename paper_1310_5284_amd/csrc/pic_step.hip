@@ -290,12 +290,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const bool mc = C->gather == 1;
     const bool ec2 = C->gather == 2;
     const bool dual = kImp && ec2;   // susceptibility words of its own
+    const bool nu = C->nonuniform != 0;
     const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
-    const StepLds L = step_lds_layout(N, DIAG, dual);
+    const StepLds L = step_lds_layout(N, DIAG, dual, nu);
     float* eh = (float*)smem;
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
     unsigned long long* dch = (unsigned long long*)(smem + L.dual);
+    float* rl = (float*)(smem + L.ratio);   // nonuniform: dx / w_c
     float* heat = (float*)(smem + L.heat);
     unsigned* eedf = (unsigned*)(smem + L.eedf);
     {
@@ -315,6 +317,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     if (tid == 0) dep[N] = 0ull;   // node N of the quadratic deposit
     if (dual)
         for (int j = tid; j <= N; j += kBlock) dch[j] = 0ull;
+    if (nu) {
+        const PIC_GLOBAL float* rg = gp(C->cell_r);
+        for (int j = tid; j < N; j += kBlock) rl[j] = rg[j];
+    }
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
     if (tid == 0) {
@@ -385,17 +391,18 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             float a = 0.0f;
             if (live) a = mc ? gather_mc(eh, cc, o[k])
                              : (ec2 ? gather_ec2(eh, N, periodic, cc, o[k]) : eh[cc]);
-            float vn, vold, abn = 0.0f, o1;
+            float vn, vold, abn = 0.0f, o1, mv;
             if (kImp) {
                 vold = v[k] - 0.5f * ab[k];
                 vn = v[k] + 0.5f * a;
                 abn = 0.5f * (ab[k] + a);
-                o1 = o[k] + 0.5f * a;
+                mv = 0.5f * a;
             } else {
                 vold = v[k];
                 vn = v[k] + a;
-                o1 = o[k] + vn;
+                mv = vn;
             }
+            o1 = o[k] + mv;
             int c1 = cc;
             if (live) {
                 const float dk = (vn - vold) * (vn + vold);
@@ -404,7 +411,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     atomicAdd(&heat[cc], dk);
                     range_note(lo, hi, cc);
                 }
-                renorm(c1, o1);
+                if (nu) {
+                    o1 = o[k];
+                    walk(c1, o1, mv, rl, N);
+                } else {
+                    renorm(c1, o1);
+                }
                 if (periodic) {
                     c1 %= N;
                     if (c1 < 0) c1 += N;
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             uint32_t lflag = 0u;   // list flag of a candidate
             if (live && !isc) {
                 if (kImp) {
-                    vst = predict(c2, o2, vn, abn);
+                    vst = nu ? predict_nu(c2, o2, vn, abn, rl, N) : predict(c2, o2, vn, abn);
                     if (periodic) {
                         c2 %= N;
                         if (c2 < 0) c2 += N;
@@ -466,7 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     // k_collide.
                     int cp = c1;
                     float op = o1;
-                    const float vp = predict(cp, op, vn, abn);
+                    const float vp =
+                        nu ? predict_nu(cp, op, vn, abn, rl, N) : predict(cp, op, vn, abn);
                     if (periodic) {
                         cp %= N;
                         if (cp < 0) cp += N;
@@ -629,6 +642,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     const bool periodic = C->bc == 1;
     const bool ec2 = C->gather == 2;
     const bool dual = kImp && ec2;   // susceptibility words of its own
+    const bool nu = C->nonuniform != 0;
+    const PIC_GLOBAL float* rg = gp(uniform_ptr((const float*)C->cell_r));   // nu: dx / w_c
     const uint32_t k0 = C->key0, k1 = C->key1;
     const CollideLds L = collide_lds_layout(N, dual);
     unsigned long long* dep = (unsigned long long*)smem;
@@ -696,10 +711,15 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             atomicAdd(&acc.n_created[1], 1u);
             want_e = want_i = true;
             if (kImp) {
-                oe = o1 + ch.vx;
-                renorm(ce, oe);
-                oi = o1 + ch.ix;
-                renorm(ci, oi);
+                if (nu) {
+                    walk(ce, oe, ch.vx, rg, N);
+                    walk(ci, oi, ch.ix, rg, N);
+                } else {
+                    oe = o1 + ch.vx;
+                    renorm(ce, oe);
+                    oi = o1 + ch.ix;
+                    renorm(ci, oi);
+                }
                 if (periodic) {
                     ce %= N; if (ce < 0) ce += N;
                     ci %= N; if (ci < 0) ci += N;
@@ -822,7 +842,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             if (kImp && pred && kind < 0) {
                 // a null collision: the prediction k_step stored and
                 // deposited stands; only the waiting time is new
-                predict(c2, o2, vn, abn);
+                if (nu) predict_nu(c2, o2, vn, abn, rg, N);
+                else predict(c2, o2, vn, abn);
                 if (periodic) {
                     c2 %= N;
                     if (c2 < 0) c2 += N;
@@ -834,7 +855,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                     // prediction (integer words, so exactly)
                     int cp = c1;
                     float op = o1;
-                    predict(cp, op, vn0, abn);
+                    if (nu) predict_nu(cp, op, vn0, abn, rg, N);
+                    else predict(cp, op, vn0, abn);
                     if (periodic) {
                         cp %= N;
                         if (cp < 0) cp += N;
@@ -846,7 +868,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                         gatomic_add(&gdep_w[cp], 0ull - (packw(op) & kWMask));
                     }
                 }
-                const float vst = predict(c2, o2, vn, abn);
+                const float vst =
+                    nu ? predict_nu(c2, o2, vn, abn, rg, N) : predict(c2, o2, vn, abn);
                 bool gone = false;
                 if (periodic) {
                     c2 %= N;

@@ -81,6 +81,19 @@ def test_init_rejects_bad_input_without_a_gpu():
     cfg[0].gather = 0
     sp[0].capacity = (1 << 28) - 1023
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
+    sp[0].capacity = 0
+    # nonuniform grids: EC gather between electrodes, positive widths summing
+    # to the gap
+    good = (C.c_double * 8)(*([0.01 / 8] * 8))
+    for field, value in (("gather", 1), ("gather", 2), ("bc", 1)):
+        setattr(cfg[0], field, value)
+        cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
+        assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL, field
+        setattr(cfg[0], field, 0)
+    for widths in ([0.01 / 8] * 7 + [0.0], [0.01 / 7] * 8, [0.02] + [-0.01 / 7] * 7):
+        arr = (C.c_double * 8)(*widths)
+        cfg[0].cell_dx_m = C.cast(arr, C.POINTER(C.c_double))
+        assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     assert not h.value
 
 

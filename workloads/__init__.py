@@ -55,12 +55,34 @@ def argon_like_tables(e_max_eV: float = 1000.0, de_eV: float = 0.05):
             mk(1, CHARGE_EXCHANGE, 0.0, cx)]
 
 
+def sheath_refined_widths(n_cells, gap_m, ratio=4.0, sheath_frac=0.15):
+    """Cell widths of a grid refined next to both electrodes: the cells within
+    sheath_frac of the gap from either electrode are about `ratio` times
+    narrower than the bulk cells; the widths sum to gap_m."""
+    ns = int(round(n_cells * ratio * sheath_frac / ((1 - 2 * sheath_frac) + 2 * ratio * sheath_frac)))
+    ns = min(max(ns, 1), (n_cells - 1) // 2)
+    nb = n_cells - 2 * ns
+    ws = sheath_frac * gap_m / ns
+    wb = (1 - 2 * sheath_frac) * gap_m / nb
+    w = np.concatenate([np.full(ns, ws), np.full(nb, wb), np.full(ns, ws)])
+    return w * (gap_m / w.sum())
+
+
 def load_species(rng, n, N, q, m, w, T_eV, capacity=None, lo_cell=0, hi_cell=None,
-                 id_base=0):
-    """Uniform positions over cells [lo_cell, hi_cell) and a Maxwellian at T_eV."""
+                 id_base=0, widths=None):
+    """Uniform positions over cells [lo_cell, hi_cell) (with widths: uniform in
+    physical space over the gap) and a Maxwellian at T_eV."""
     hi_cell = N if hi_cell is None else hi_cell
-    cell = rng.integers(lo_cell, hi_cell, size=n, dtype=np.int64).astype(np.int32)
-    off = rng.random(n, dtype=np.float32)
+    if widths is None:
+        cell = rng.integers(lo_cell, hi_cell, size=n, dtype=np.int64).astype(np.int32)
+        off = rng.random(n, dtype=np.float32)
+    else:
+        edges = np.concatenate([[0.0], np.cumsum(widths)])
+        X = rng.random(n) * edges[-1]
+        c = np.clip(np.searchsorted(edges, X, side="right") - 1, 0, N - 1)
+        cell = c.astype(np.int32)
+        off = np.minimum((X - edges[c]) / widths[c], np.nextafter(1.0, 0.0)).astype(np.float32)
+        off = np.where(off >= 1.0, np.float32(0.0), off).astype(np.float32)
     vt = math.sqrt(T_eV * E_CHARGE / m)
     v = (vt * rng.standard_normal((3, n))).astype(np.float32)
     return dict(q=q, m=m, w=w, cell=cell, off=off, vx=v[0].copy(), vy=v[1].copy(),
@@ -84,16 +106,19 @@ def ccp_case(*, n_cells, gap_m, volts, freq, dt, p_mtorr, scheme=0, collisions=1
 
 def ccp_workload(name, *, n_cells, np_per_species, gap_m=0.025, volts=100.0, freq=13.56e6,
                  dt=None, p_mtorr=50.0, n0=1e15, Te=2.0, Ti=0.026, scheme=0, collisions=1,
-                 seed=0, steps=1000, capacity_factor=1.25, e_max_eV=1000.0, gather=0):
+                 seed=0, steps=1000, capacity_factor=1.25, e_max_eV=1000.0, gather=0,
+                 cell_dx=None):
     dt = dt if dt is not None else 1.0 / (400.0 * freq)
     rng = np.random.Generator(np.random.PCG64(seed))
     w = n0 * gap_m / np_per_species
     cap = int(math.ceil(np_per_species * capacity_factor)) + 64
-    e = load_species(rng, np_per_species, n_cells, -E_CHARGE, M_E, w, Te, cap)
-    i = load_species(rng, np_per_species, n_cells, E_CHARGE, M_AR, w, Ti, cap)
+    e = load_species(rng, np_per_species, n_cells, -E_CHARGE, M_E, w, Te, cap, widths=cell_dx)
+    i = load_species(rng, np_per_species, n_cells, E_CHARGE, M_AR, w, Ti, cap, widths=cell_dx)
     case = ccp_case(n_cells=n_cells, gap_m=gap_m, volts=volts, freq=freq, dt=dt,
                     p_mtorr=p_mtorr, scheme=scheme, collisions=collisions, seed=seed,
                     gather=gather)
+    if cell_dx is not None:
+        case["cell_dx"] = np.asarray(cell_dx, dtype=np.float64)
     return dict(name=name, case=case, species=[e, i], processes=argon_like_tables(e_max_eV),
                 n_steps=steps, n0=n0, Te=Te)
 
@@ -145,13 +170,14 @@ def c3(wdt=5.0, scheme=1, ppc=200, collisions=1, seed=0xC3, steps=None):
                         steps=steps if steps is not None else 100 * per)
 
 
-def c4(np_per_species=10_000_000, seed=0xC4, scheme=0):
+def c4(np_per_species=10_000_000, seed=0xC4, scheme=0, cell_dx=None):
     """Production explicit EC CCP: 2048 cells over 2.5 cm, 1e7 e + 1e7 Ar+,
-    30 mTorr, 300 V at 13.56 MHz, dt = 1/(2000 f)."""
+    30 mTorr, 300 V at 13.56 MHz, dt = 1/(2000 f) (cell_dx: a nonuniform grid
+    of the same cell count)."""
     freq = 13.56e6
     return ccp_workload("ccp2048_explicit", n_cells=2048, np_per_species=np_per_species,
                         volts=300.0, freq=freq, dt=1.0 / (2000.0 * freq), p_mtorr=30.0,
-                        scheme=scheme, seed=seed, steps=2_000_000)
+                        scheme=scheme, seed=seed, steps=2_000_000, cell_dx=cell_dx)
 
 
 def c5(n_cases=64, seed=5, np_scale=1.0):
