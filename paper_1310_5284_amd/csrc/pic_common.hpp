@@ -266,13 +266,16 @@ __device__ __forceinline__ float predict(int& c, float& o, float vn, float abn)
 }
 
 // A move by d (units of the reference width L/N) on a nonuniform grid with
-// r[c] = (L/N) / w_c: inside cell c the offset changes by d r_c; at an edge
-// the rest of the move continues in the next cell.  Past an electrode the
-// walk stops with the cell index -1 or N, which the boundary rule absorbs.
-// At most N cells are visited.  One rounding per operation, so that every
-// kernel reproduces the same walk bit for bit.
-template <class RP>
-__device__ __forceinline__ void walk(int& c, float& o, float d, RP r, int N)
+// r[c] = (L/N) / w_c, where run[c] holds the first (low 16 bits) and last
+// (high 16 bits) cell of the run of equal widths that contains c.  Inside a
+// run the move is the uniform one (offset + d r_c, whole cells carried into
+// the index); at the end of a run the rest of the move continues in the
+// next run.  Past an electrode the walk stops with the cell index -1 or N,
+// which the boundary rule absorbs.  Each run is visited at most once.  One
+// rounding per operation, so that every kernel reproduces the same walk bit
+// for bit.
+template <class RP, class UP>
+__device__ __forceinline__ void walk(int& c, float& o, float d, RP r, UP run, int N)
 {
     if (d >= 0.0f) {
         for (;;) {
@@ -282,8 +285,20 @@ __device__ __forceinline__ void walk(int& c, float& o, float d, RP r, int N)
                 o = x;
                 return;
             }
-            d = __fsub_rn(d, __fdiv_rn(__fsub_rn(1.0f, o), rc));
-            ++c;
+            const int hi = (int)(run[c] >> 16);
+            const float fl = floorf(x);
+            if ((float)(hi - c) >= fl) {   // ends inside the run
+                c += (int)fl;
+                o = x - fl;
+                if (o >= 1.0f) {
+                    o = 0.0f;
+                    c += 1;
+                }
+                return;
+            }
+            // to the right end of the run, then on into the next one
+            d = __fsub_rn(d, __fdiv_rn(__fsub_rn((float)(hi + 1 - c), o), rc));
+            c = hi + 1;
             o = 0.0f;
             if (c >= N || d <= 0.0f) return;
         }
@@ -300,12 +315,24 @@ __device__ __forceinline__ void walk(int& c, float& o, float d, RP r, int N)
             }
             return;
         }
-        d = __fadd_rn(d, __fdiv_rn(o, rc));
-        --c;
+        const int lo = (int)(run[c] & 0xFFFFu);
+        const float fl = floorf(x);   // negative
+        if ((float)(lo - c) <= fl) {   // ends inside the run
+            c += (int)fl;
+            o = x - fl;
+            if (o >= 1.0f) {
+                o = 0.0f;
+                c += 1;
+            }
+            return;
+        }
+        // to the left end of the run, then on into the previous one
+        d = __fadd_rn(d, __fdiv_rn(__fadd_rn((float)(c - lo), o), rc));
+        c = lo - 1;
         o = 1.0f;   // the right edge of the cell entered
         if (c < 0) return;
         if (d >= 0.0f) {   // the move ended on the edge
-            ++c;
+            c = lo;
             o = 0.0f;
             return;
         }
@@ -313,11 +340,12 @@ __device__ __forceinline__ void walk(int& c, float& o, float d, RP r, int N)
 }
 
 // The D1 prediction on a nonuniform grid (the walk in place of renorm).
-template <class RP>
-__device__ __forceinline__ float predict_nu(int& c, float& o, float vn, float abn, RP r, int N)
+template <class RP, class UP>
+__device__ __forceinline__ float predict_nu(int& c, float& o, float vn, float abn, RP r, UP run,
+                                            int N)
 {
     const float vst = fmaf(0.5f, abn, vn);
-    walk(c, o, vst, r, N);
+    walk(c, o, vst, r, run, N);
     return vst;
 }
 

@@ -110,6 +110,7 @@ struct Case {
     // w_c / dx for the solve
     float* cell_r;                   // [N]
     double* cell_wr;                 // [N]
+    uint32_t* cell_run;              // [N] first | last << 16 cell of c's run of equal widths
     float* ehat[2];                  // [N] accel * E of the next step, per species
     double* E;                       // [N] V/m
     double* phi;                     // [N+1]
@@ -203,7 +204,8 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 //   dep[N+1] u64      (privatised deposit, count << 40 | summed weight)
 //   DIAG: heat[N] float, eedf[kEedfBins] u32
 // (dual: the susceptibility words of the m = 2 implicit scheme follow dep;
-// nu: the width ratios r_c of a nonuniform grid, N floats, follow those)
+// nu: the width ratios r_c of a nonuniform grid, N floats, and the runs of
+// equal widths, N u32, follow those)
 struct StepLds {
     size_t dep, dual, ratio, heat, eedf, total;
 };
@@ -214,7 +216,7 @@ __host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual =
     L.dep = align16(4 * ((size_t)N + 1));
     L.dual = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
     L.ratio = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
-    L.heat = L.ratio + (nu ? align16(4 * (size_t)N) : 0);
+    L.heat = L.ratio + (nu ? 2 * align16(4 * (size_t)N) : 0);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;

@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
         if (startup) {
             S.abar[i] = 0.0f;
             if (C->nonuniform) {
-                walk(c, o, S.vx[i], C->cell_r, N);
+                walk(c, o, S.vx[i], C->cell_r, C->cell_run, N);
             } else {
                 o += S.vx[i];
                 renorm(c, o);

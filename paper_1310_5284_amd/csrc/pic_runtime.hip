@@ -711,6 +711,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             // the moves take r_c = dx / w_c (float), the solve w_c / dx (double)
             rc |= dalloc(c, h.allocs, &C.cell_r, N);
             rc |= dalloc(c, h.allocs, &C.cell_wr, N);
+            rc |= dalloc(c, h.allocs, &C.cell_run, N);
         }
         if (rc) return bail(PIC_E_NOMEM);
         if (!h.cell_w.empty()) {
@@ -720,8 +721,17 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                 r[j] = (float)(C.dx / h.cell_w[j]);
                 wr[j] = h.cell_w[j] / C.dx;
             }
+            // runs of equal ratios: first | last << 16
+            std::vector<uint32_t> run(N);
+            for (int j = 0, a = 0; j < N; ++j) {
+                if (j + 1 == N || r[j + 1] != r[j]) {
+                    for (int t = a; t <= j; ++t) run[t] = (uint32_t)a | ((uint32_t)j << 16);
+                    a = j + 1;
+                }
+            }
             INITCHK(hipMemcpy(C.cell_r, r.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
             INITCHK(hipMemcpy(C.cell_wr, wr.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
+            INITCHK(hipMemcpy(C.cell_run, run.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
         }
         h.hist_off[0] = hist_total;
         h.hist_off[1] = hist_total + N;

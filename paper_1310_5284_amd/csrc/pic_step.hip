@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
     unsigned long long* dch = (unsigned long long*)(smem + L.dual);
     float* rl = (float*)(smem + L.ratio);   // nonuniform: dx / w_c
+    uint32_t* ul = (uint32_t*)(smem + L.ratio + align16(4 * (size_t)N));   // and the runs
     float* heat = (float*)(smem + L.heat);
     unsigned* eedf = (unsigned*)(smem + L.eedf);
     {
@@ -319,7 +320,11 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         for (int j = tid; j <= N; j += kBlock) dch[j] = 0ull;
     if (nu) {
         const PIC_GLOBAL float* rg = gp(C->cell_r);
-        for (int j = tid; j < N; j += kBlock) rl[j] = rg[j];
+        const PIC_GLOBAL uint32_t* ug = gp(C->cell_run);
+        for (int j = tid; j < N; j += kBlock) {
+            rl[j] = rg[j];
+            ul[j] = ug[j];
+        }
     }
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
                 if (nu) {
                     o1 = o[k];
-                    walk(c1, o1, mv, rl, N);
+                    walk(c1, o1, mv, rl, ul, N);
                 } else {
                     renorm(c1, o1);
                 }
@@ -443,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             uint32_t lflag = 0u;   // list flag of a candidate
             if (live && !isc) {
                 if (kImp) {
-                    vst = nu ? predict_nu(c2, o2, vn, abn, rl, N) : predict(c2, o2, vn, abn);
+                    vst = nu ? predict_nu(c2, o2, vn, abn, rl, ul, N) : predict(c2, o2, vn, abn);
                     if (periodic) {
                         c2 %= N;
                         if (c2 < 0) c2 += N;
@@ -479,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     int cp = c1;
                     float op = o1;
                     const float vp =
-                        nu ? predict_nu(cp, op, vn, abn, rl, N) : predict(cp, op, vn, abn);
+                        nu ? predict_nu(cp, op, vn, abn, rl, ul, N) : predict(cp, op, vn, abn);
                     if (periodic) {
                         cp %= N;
                         if (cp < 0) cp += N;
@@ -644,6 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
     const bool dual = kImp && ec2;   // susceptibility words of its own
     const bool nu = C->nonuniform != 0;
     const PIC_GLOBAL float* rg = gp(uniform_ptr((const float*)C->cell_r));   // nu: dx / w_c
+    const PIC_GLOBAL uint32_t* ug = gp(uniform_ptr((const uint32_t*)C->cell_run));   // and runs
     const uint32_t k0 = C->key0, k1 = C->key1;
     const CollideLds L = collide_lds_layout(N, dual);
     unsigned long long* dep = (unsigned long long*)smem;
@@ -712,8 +718,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             want_e = want_i = true;
             if (kImp) {
                 if (nu) {
-                    walk(ce, oe, ch.vx, rg, N);
-                    walk(ci, oi, ch.ix, rg, N);
+                    walk(ce, oe, ch.vx, rg, ug, N);
+                    walk(ci, oi, ch.ix, rg, ug, N);
                 } else {
                     oe = o1 + ch.vx;
                     renorm(ce, oe);
@@ -842,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
             if (kImp && pred && kind < 0) {
                 // a null collision: the prediction k_step stored and
                 // deposited stands; only the waiting time is new
-                if (nu) predict_nu(c2, o2, vn, abn, rg, N);
+                if (nu) predict_nu(c2, o2, vn, abn, rg, ug, N);
                 else predict(c2, o2, vn, abn);
                 if (periodic) {
                     c2 %= N;
@@ -855,7 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                     // prediction (integer words, so exactly)
                     int cp = c1;
                     float op = o1;
-                    if (nu) predict_nu(cp, op, vn0, abn, rg, N);
+                    if (nu) predict_nu(cp, op, vn0, abn, rg, ug, N);
                     else predict(cp, op, vn0, abn);
                     if (periodic) {
                         cp %= N;
@@ -869,7 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
                     }
                 }
                 const float vst =
-                    nu ? predict_nu(c2, o2, vn, abn, rg, N) : predict(c2, o2, vn, abn);
+                    nu ? predict_nu(c2, o2, vn, abn, rg, ug, N) : predict(c2, o2, vn, abn);
                 bool gone = false;
                 if (periodic) {
                     c2 %= N;
