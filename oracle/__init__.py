@@ -40,7 +40,7 @@ def build(force: bool = True) -> str:
 
 class Case(C.Structure):
     _fields_ = [("n_cells", C.c_int32), ("bc", C.c_int32), ("scheme", C.c_int32),
-                ("gather", C.c_int32), ("collisions", C.c_int32), ("pad0", C.c_int32),
+                ("gather", C.c_int32), ("collisions", C.c_int32), ("ion_subcycle", C.c_int32),
                 ("gap_m", C.c_double), ("dt_s", C.c_double), ("step0", C.c_int64),
                 ("rf_volts", C.c_double), ("rf_freq_hz", C.c_double),
                 ("gas_density_m3", C.c_double), ("gas_temp_K", C.c_double),
@@ -238,7 +238,8 @@ class Sim:
 
     def __init__(self, case: dict, species: list, processes: list, startup: bool = True):
         c = Case(n_cells=case["n_cells"], bc=case.get("bc", 0), scheme=case.get("scheme", 0),
-                 gather=case.get("gather", 0), collisions=case.get("collisions", 0), pad0=0,
+                 gather=case.get("gather", 0), collisions=case.get("collisions", 0),
+                 ion_subcycle=case.get("ion_subcycle", 0),
                  gap_m=case["gap_m"], dt_s=case["dt_s"], step0=case.get("step0", 0),
                  rf_volts=case.get("rf_volts", 0.0), rf_freq_hz=case.get("rf_freq_hz", 0.0),
                  gas_density_m3=case.get("gas_density_m3", 0.0),

@@ -339,6 +339,18 @@ void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* x
 
 static double gather(const orc_sim* s, double xi);
 
+/* Ion subcycling: the time step of species sp in units of dt, and whether
+ * the species moves in the current step. */
+static double substep(const orc_sim* s, int sp)
+{
+    return (sp == 1 && s->c.ion_subcycle > 1) ? (double)s->c.ion_subcycle : 1.0;
+}
+
+static int moves(const orc_sim* s, int sp)
+{
+    return !(sp == 1 && s->c.ion_subcycle > 1) || s->step % s->c.ion_subcycle == 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Simulation object                                                        */
 /* ------------------------------------------------------------------------ */
@@ -348,6 +360,7 @@ orc_sim* orc_create(const orc_case* c)
 {
     if (c->n_cells < 2) return NULL;
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
+    if (c->ion_subcycle < 0 || (c->ion_subcycle > 1 && c->scheme != ORC_EXPLICIT)) return NULL;
     if (c->cell_dx_m) {
         /* nonuniform grids: EC gather between electrodes, widths summing to L */
         if (c->gather != ORC_GATHER_EC || c->bc != ORC_BC_DIRICHLET) return NULL;
@@ -563,7 +576,7 @@ int orc_prepare(orc_sim* s)
             if (cand > best) best = cand;
         }
         s->numax[sp] = s->c.gas_density_m3 * best;
-        s->pnull[sp] = 1.0 - exp(-s->numax[sp] * s->c.dt_s);
+        s->pnull[sp] = 1.0 - exp(-s->numax[sp] * s->c.dt_s * substep(s, sp));
     }
     for (int sp = 0; sp < 2; ++sp) {
         double p = s->pnull[sp];
@@ -888,7 +901,7 @@ static void mcc_all(orc_sim* s)
 {
     int64_t n0 = s->sp[0].n, n1 = s->sp[1].n;
     mcc_species(s, 0, n0, s->step);
-    mcc_species(s, 1, n1, s->step);
+    if (moves(s, 1)) mcc_species(s, 1, n1, s->step);
 }
 
 static void begin_ledger(orc_sim* s, int implicit)
@@ -940,8 +953,10 @@ static void step_explicit(orc_sim* s)
     begin_ledger(s, 0);
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
-        double qm_dt = p->q / p->m * s->c.dt_s;
-        double dt_dx = s->c.dt_s / s->dx;
+        if (!moves(s, k)) continue;   /* a subcycled species stands */
+        double h = substep(s, k);     /* the species' time step in units of dt */
+        double qm_dt = p->q / p->m * s->c.dt_s * h;
+        double dt_dx = s->c.dt_s / s->dx * h;
         int64_t i = 0;
         while (i < p->n) {
             double Ep = gather(s, p->xi[i]);
@@ -951,7 +966,7 @@ static void step_explicit(orc_sim* s)
             s->led.work[k] += dK;
             s->heat[k][(int64_t)floor(p->xi[i])] += dK;
             p->vx[i] += dv;
-            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * s->c.dt_s);
+            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * s->c.dt_s * h);
             else p->xi[i] += p->vx[i] * dt_dx;
             int e = boundary(s, &p->xi[i]);
             if (e >= 0) {

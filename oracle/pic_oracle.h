@@ -46,7 +46,11 @@ typedef struct {
     int32_t scheme;         /* ORC_EXPLICIT or ORC_IMPLICIT (D1, beta = 1/2)       */
     int32_t gather;         /* ORC_GATHER_EC (Eq. 3), ORC_GATHER_MC (CIC), EC2     */
     int32_t collisions;     /* 0 / 1                                               */
-    int32_t pad0;
+    /* Ion subcycling K (explicit scheme; 0 or 1: none): ions are pushed,
+     * absorbed and collided only in steps n with n % K == 0, with the time
+     * step K dt (null-collision probability 1 - exp(-nu_max K dt)); in the
+     * other steps they stand and keep their charge on the grid. */
+    int32_t ion_subcycle;
     double gap_m;           /* L                                                   */
     double dt_s;
     int64_t step0;          /* absolute index of the first step to take            */
