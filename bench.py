@@ -67,6 +67,11 @@ def make_workload(name, scale):
         # within 15 % of the gap from either electrode)
         return [W.c4(np_per_species=int(10_000_000 * scale),
                      cell_dx=W.sheath_refined_widths(2048, 0.025))]
+    if name == "ccp2048_subcycle8":
+        # the same discharge with the ions pushed every 8th step with 8 dt
+        wl = W.c4(np_per_species=int(10_000_000 * scale))
+        wl["case"]["ion_subcycle"] = 8
+        return [wl]
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":
@@ -257,6 +262,11 @@ def main():
                      tile_ms_per_step={str(t): round(m, 4) for t, m in zip(tiles, ms[:6])},
                      sort_ms_per_step={str(t): round(m, 4) for t, m in zip(sorts, ms[6:])})
         log(f"[bench] autotune: tile {tile}, sort every {sort_every}")
+    # event samples every timing_every-th step: with subcycled ions that
+    # period is made coprime to K, so that the samples visit every phase
+    ks = [max(1, int(w["case"].get("ion_subcycle", 0))) for w in wls]
+    while args.timing_every > 1 and any(math.gcd(args.timing_every, k) > 1 for k in ks):
+        args.timing_every += 1
     ctx.set_launch(graph=args.graph, timing_every=args.timing_every)
     schemes = [int(w["case"]["scheme"]) for w in wls]
     implicit = all(sc == 1 for sc in schemes)
@@ -264,7 +274,14 @@ def main():
     stepper = ctx.step
 
     def live_per_case():
-        return [sum(ctx.counts(k)["n"]) for k in range(len(wls))]
+        # particle-steps per step: subcycled ions count in their push steps
+        # only (1/K of them per step on average)
+        out = []
+        for k, w in enumerate(wls):
+            n = ctx.counts(k)["n"]
+            ksub = max(1, int(w["case"].get("ion_subcycle", 0)))
+            out.append(n[0] + n[1] / ksub)
+        return out
 
     log(f"[bench] warmup {args.warmup} steps")
     done = 0
@@ -352,8 +369,8 @@ def main():
     if tuned:
         out["autotune"] = tuned
     if args.fp64_steps > 0 and all(sc == 0 for sc in schemes) and \
-            all(w["case"].get("gather", 0) != 2 and w["case"].get("cell_dx") is None
-                for w in wls):
+            all(w["case"].get("gather", 0) != 2 and w["case"].get("cell_dx") is None and
+                w["case"].get("ion_subcycle", 0) <= 1 for w in wls):
         # the plain FP64 GPU form of the same method, from the same state
         log(f"[bench] plain FP64 GPU form: {args.fp64_steps} steps")
         ctx.fp64_init()

@@ -110,6 +110,13 @@ typedef struct {
      * PIC_BC_DIRICHLET_RF only (else PIC_E_INVAL).  Positions stay logical
      * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */
     const double* cell_dx_m;
+    /* Ion subcycling K (PIC_EXPLICIT only; 0 or 1: none; at most 4096):
+     * ions are pushed, absorbed and collided only in the steps n with
+     * n % K == 0, with the time step K dt_s (null-collision probability
+     * 1 - exp(-nu_max K dt_s)); in between they stand and their charge stays
+     * on the grid. */
+    int32_t ion_subcycle;
+    int32_t reserved;       /* 0 */
 } pic_case_config;
 
 #define PIC_MAX_CELLS 4096
@@ -309,7 +316,7 @@ int pic_reset_accumulators(pic_ctx* ctx);
  * and velocities, fp64 global-atomic deposit, no sort, one launch per phase),
  * used as the throughput comparison point.  Advances its own copy of the
  * context's initial state.  Explicit cases with PIC_GATHER_EC or
- * PIC_GATHER_MC on uniform grids only (else PIC_E_INVAL). */
+ * PIC_GATHER_MC on uniform grids without subcycling only (else PIC_E_INVAL). */
 int pic_fp64_reference_init(pic_ctx* ctx);
 int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
 int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,

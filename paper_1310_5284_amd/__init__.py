@@ -41,7 +41,8 @@ class CaseConfig(C.Structure):
                 ("gas_density_m3", C.c_double), ("gas_temp_K", C.c_double),
                 ("gas_mass_kg", C.c_double), ("background_rho", C.c_double),
                 ("opal_B_eV", C.c_double), ("seed", C.c_uint64),
-                ("cell_dx_m", C.POINTER(C.c_double))]
+                ("cell_dx_m", C.POINTER(C.c_double)), ("ion_subcycle", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 # null-collision waiting-time word: count (17 bits) | capped flag
@@ -298,7 +299,7 @@ class PicContext:
                 rf_freq_hz=c.get("rf_freq_hz", 0.0), gas_density_m3=c.get("gas_density_m3", 0.0),
                 gas_temp_K=c.get("gas_temp_K", 300.0), gas_mass_kg=c.get("gas_mass_kg", 1.0),
                 background_rho=c.get("background_rho", 0.0), opal_B_eV=c.get("opal_B_eV", 10.0),
-                seed=c.get("seed", 0))
+                seed=c.get("seed", 0), ion_subcycle=c.get("ion_subcycle", 0))
             cdx = c.get("cell_dx")
             if cdx is not None:
                 cdx = np.ascontiguousarray(cdx, dtype=np.float64)

@@ -92,7 +92,7 @@ struct Case {
     int32_t n_blocks;
     int32_t history_len;
     int32_t nonuniform;   // cell widths of their own (EC gather, electrodes)
-    int32_t pad1;
+    int32_t ion_sub;      // ion subcycling K >= 1: ions move in the steps n % K == 0
     double dx, dt;        // dx: the reference width L/N (velocity unit dx/dt)
     double rf_volts, rf_omega, rf_freq;
     double background_rho;

@@ -431,8 +431,10 @@ extern "C" int pic_fp64_reference_init(pic_ctx* ctx)
         double scale[2];
         int64_t cap[2];
         if (pic__ctx_case_info(ctx, k, &cfg, scale, cap)) return PIC_E_STATE;
-        // the plain form has the m = 1 EC and the MC weighting on uniform grids only
-        if (cfg.scheme != PIC_EXPLICIT || cfg.gather == PIC_GATHER_EC2 || C.nonuniform)
+        // the plain form has the m = 1 EC and the MC weighting on uniform grids,
+        // without subcycling
+        if (cfg.scheme != PIC_EXPLICIT || cfg.gather == PIC_GATHER_EC2 || C.nonuniform ||
+            C.ion_sub > 1)
             return PIC_E_INVAL;
         Case64& D = r->cases_h[k];
         std::memset(&D, 0, sizeof(Case64));

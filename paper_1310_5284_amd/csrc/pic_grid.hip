@@ -66,6 +66,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const bool dual = implicit && ec2;  // susceptibility of the dual grid
     const bool nu = Cc.nonuniform != 0;
     const PIC_GLOBAL double* wjr = gp((const double*)Cc.cell_wr);   // nu: w_j / dx
+    // subcycled ions keep their deposit until the step in which they move
+    // (and deposit again)
+    const bool ions_move = Cc.ion_sub <= 1 || next_step % Cc.ion_sub == 0;
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
         long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
@@ -169,8 +172,12 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     for (int k = 0; k < kPer; ++k) {
         const int j = tid + k * NT;
         if (j <= N) {   // node N: the quadratic deposit's last node
-            gp(Cc.dep_cnt[0])[j] = 0; gp(Cc.dep_cnt[1])[j] = 0;
-            gp(Cc.dep_w[0])[j] = 0; gp(Cc.dep_w[1])[j] = 0;
+            gp(Cc.dep_cnt[0])[j] = 0;
+            gp(Cc.dep_w[0])[j] = 0;
+            if (ions_move) {
+                gp(Cc.dep_cnt[1])[j] = 0;
+                gp(Cc.dep_w[1])[j] = 0;
+            }
             if (dual) {
                 gp(Cc.chi_cnt[0])[j] = 0; gp(Cc.chi_cnt[1])[j] = 0;
                 gp(Cc.chi_w[0])[j] = 0; gp(Cc.chi_w[1])[j] = 0;

@@ -401,7 +401,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             (g.scheme != PIC_EXPLICIT && g.scheme != PIC_IMPLICIT_D1) ||
             (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC &&
              g.gather != PIC_GATHER_EC2) ||
-            g.history_steps < 0 ||
+            g.history_steps < 0 || g.ion_subcycle < 0 || g.ion_subcycle > 4096 ||
+            (g.ion_subcycle > 1 && g.scheme != PIC_EXPLICIT) ||
             (g.cell_dx_m && (g.gather != PIC_GATHER_EC || g.bc != PIC_BC_DIRICHLET_RF)) ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
@@ -482,6 +483,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         C.collisions = g.collisions;
         C.history_len = g.history_steps;
         C.nonuniform = g.cell_dx_m ? 1 : 0;
+        C.ion_sub = g.ion_subcycle > 1 ? g.ion_subcycle : 1;
         C.dx = dx;
         C.dt = dt;
         C.rf_volts = g.rf_volts;
@@ -549,7 +551,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             if (S.n_proc > 0) {
                 const pic_xsec* a = proc[s][0];
                 const double numax = nu_max(proc[s], g.gas_density_m3, m);
-                const double pnull = 1.0 - std::exp(-numax * dt);
+                // a subcycled species takes its trials with the step K dt
+                const double pnull = 1.0 - std::exp(-numax * dt * (s == 1 ? C.ion_sub : 1));
                 S.cand_thr = numax > 0 ? candidate_threshold(pnull) : 0u;
                 S.inv_log1mp = (pnull > 0.0 && pnull < 1.0) ? 1.0 / std::log1p(-pnull) : 0.0;
                 const double scale = numax > 0 ? g.gas_density_m3 * (dx / dt) / numax : 0.0;

@@ -344,7 +344,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     int chunk = (n + w.nb - 1) / w.nb;
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk;
-    const int end = min(n, start + chunk);
+    // subcycled ions stand in the steps between their pushes (the workgroup
+    // still writes its zero ledger row and empty list); a push takes K dt
+    const int ksub = s == 1 ? C->ion_sub : 1;
+    const bool stands = ksub > 1 && (st->step % ksub) != 0;
+    const float kf = (float)ksub;
+    const int end = stands ? start : min(n, start + chunk);
 
     double work = 0.0;
     int lo = kNoCell, hi = -1;
@@ -404,8 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 mv = 0.5f * a;
             } else {
                 vold = v[k];
-                vn = v[k] + a;
-                mv = vn;
+                vn = fmaf(kf, a, v[k]);   // kf = 1 but for subcycled ions
+                mv = kf * vn;
             }
             o1 = o[k] + mv;
             int c1 = cc;

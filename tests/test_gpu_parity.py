@@ -174,3 +174,18 @@ def test_ccp64_nonuniform_teacher_forced(scheme, steps_per_period):
     rep = teacher_forced(ctx, wl, 60)
     print(rep)
     assert_report(rep)
+
+
+@pytest.mark.parametrize("K,step0", [(4, 0), (7, 5)])
+def test_ccp64_subcycled_ions_teacher_forced(K, step0):
+    # ions pushed, absorbed and collided every K-th step with K dt; in
+    # between their deposit stays on the grid (high pressure: ion
+    # collisions in most push steps)
+    wl = W.c1(collisions=1, np_per_species=16384 + 77)
+    wl["case"]["ion_subcycle"] = K
+    wl["case"]["step0"] = step0
+    wl["case"]["gas_density_m3"] = W.gas_density(500.0)
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 6 * K)
+    print(rep)
+    assert_report(rep)
