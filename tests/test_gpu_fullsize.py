@@ -30,7 +30,8 @@ def full_fields(ctx, wl, k):
     sim = oracle.Sim(dict(wl["case"], step0=st["step"]), to_oracle_species(st, wl),
                      wl["processes"], startup=False)
     sim.compute_fields()
-    return compare_fields(ctx.fields(k), sim.fields(), wl["case"].get("scheme", 0) == 1)
+    return compare_fields(ctx.fields(k), sim.fields(), wl["case"].get("scheme", 0) == 1,
+                          gather=wl["case"].get("gather", 0))
 
 
 def sampled_step(ctx, wls, cases, n_sample, seed):
@@ -92,6 +93,33 @@ def test_ccp2048_full_size():
     check(rep)
     fe = full_fields(ctx, wls[0], 0)
     print(fe)
+    assert max(fe.values()) <= FIELD_TOL, fe
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["ccp2048_ec2_implicit", "ccp2048_nonuniform",
+                                  "ccp2048_subcycle8"])
+def test_widened_workloads_full_size(name):
+    # the benchmark's other 2048-cell discharges (m = 2 implicit, the
+    # sheath-refined grid, ions subcycled at K = 8) at tile 16384, sort 64;
+    # the subcycled one is sampled in a step where the ions stand (65) and in
+    # one where they move (72)
+    import bench
+    wls = bench.make_workload(name, 1.0)
+    ctx = P().PicContext(wls)
+    ctx.set_schedule(sort_every=64, diag_every=0, tile=16384)
+    ctx.step(65)
+    rep = sampled_step(ctx, wls, [0], 8192, seed=43)
+    print(name, rep)
+    check(rep)
+    if name == "ccp2048_subcycle8":
+        ctx.step(6)
+        assert ctx.state()["step"] % 8 == 0
+        rep = sampled_step(ctx, wls, [0], 8192, seed=44)
+        print(name, rep)
+        check(rep)
+    fe = full_fields(ctx, wls[0], 0)
+    print(name, fe)
     assert max(fe.values()) <= FIELD_TOL, fe
     ctx.close()
 
