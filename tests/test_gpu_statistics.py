@@ -1,7 +1,8 @@
 """Long free-running comparison of the HIP path with the FP64 oracle.
 
 Both start from the same 64-cell capacitive discharge (16k electrons and 16k
-ions, 50 mTorr, 100 V at 13.56 MHz) and run 10 RF periods on their own.
+ions, 50 mTorr, 100 V at 13.56 MHz; on a uniform and on a sheath-refined
+grid) and run 10 RF periods on their own.
 Float32 particle state against float64 makes the two microstates drift apart
 (the motion is chaotic), so they are compared through statistics over the
 last 4 periods: the time-averaged node densities, the electron energy
@@ -24,11 +25,18 @@ PERIOD = 400          # steps per RF period at dt = 1/(400 f)
 TOL = 0.02
 
 
-def test_ccp64_ten_periods_statistics_match_oracle():
+@pytest.mark.parametrize("grid", ["uniform", "sheath_refined"])
+def test_ccp64_ten_periods_statistics_match_oracle(grid):
     import paper_1310_5284_amd as P
-    wl = W.c1(collisions=1, np_per_species=16384)
+    if grid == "uniform":
+        wl = W.c1(collisions=1, np_per_species=16384)
+    else:
+        # cells about 4x narrower within 15 % of the gap from either electrode
+        wl = W.ccp_workload("ccp64_nonuniform", n_cells=64, np_per_species=16384,
+                            volts=100.0, p_mtorr=50.0, seed=0xC1,
+                            cell_dx=W.sheath_refined_widths(64, 0.025))
     N = wl["case"]["n_cells"]
-    dx = wl["case"]["gap_m"] / N
+    w = wl["case"].get("cell_dx", np.full(N, wl["case"]["gap_m"] / N))
     t0, tw = 6 * PERIOD, 4 * PERIOD
 
     ctx = P.PicContext([wl], history_steps=t0 + tw)
@@ -71,8 +79,8 @@ def test_ccp64_ten_periods_statistics_match_oracle():
                 eedf_o += np.bincount(b, minlength=eedf_g.size)
     h1 = sim.heating()
 
-    vol = np.full(N + 1, dx)
-    vol[0] = vol[-1] = dx / 2          # half cells at the electrodes
+    # node volumes: half of each adjacent cell (half cells at the electrodes)
+    vol = 0.5 * (np.concatenate([[0.0], w]) + np.concatenate([w, [0.0]]))
     for s in range(2):
         do = dens_o[s] / tw / vol
         err = np.linalg.norm(dens_g[s] - do) / np.linalg.norm(do)
