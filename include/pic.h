@@ -210,7 +210,9 @@ typedef struct {
     double vel_unit;            /* m/s per internal velocity unit (dx/dt)       */
     double acc_unit;            /* m/s^2 per internal abar unit (dx/dt^2)       */
     /* PIC_DIAG_FIELDS: the fields of the solve the next step uses */
-    double* rho;                /* [N+1] C/m^3                                  */
+    double* rho;                /* [N+1] C/m^3 (nonuniform grid: node charge per
+                                 * area over half of each adjacent cell, the
+                                 * whole end cell at an electrode)           */
     double* phi;                /* [N+1] V                                      */
     double* E;                  /* [N]   V/m at x_{j+1/2}                       */
     double* chi;                /* [N]   susceptibility chi_{j+1/2} (implicit), else 0 */
@@ -231,7 +233,9 @@ typedef struct {
     uint64_t* id[2];
     float* abar[2];
     uint32_t* mcc_wait[2];      /* null-collision waiting-time words            */
-    /* PIC_DIAG_DENSITY: mean over sampled steps of the node density (m^-3) */
+    /* PIC_DIAG_DENSITY: mean over sampled steps of the node density (m^-3):
+     * the node's deposit over its volume, half of each adjacent cell (half a
+     * cell at an electrode node; the widths of a nonuniform grid) */
     double* density[2];         /* [N+1]                                        */
     int64_t density_samples;
     /* PIC_DIAG_HEATING: sum over sampled steps of the field work per cell */
