@@ -69,6 +69,12 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // subcycled ions keep their deposit until the step in which they move
     // (and deposit again)
     const bool ions_move = Cc.ion_sub <= 1 || next_step % Cc.ion_sub == 0;
+    // m = 2 implicit: the second moment words (counts of the particles left
+    // of their nearest node, sums of their weights to the node after it)
+    const PIC_GLOBAL unsigned long long* dx_c[2] = {
+        gp((const unsigned long long*)Cc.chi_cnt[0]), gp((const unsigned long long*)Cc.chi_cnt[1])};
+    const PIC_GLOBAL unsigned long long* dx_w[2] = {
+        gp((const unsigned long long*)Cc.chi_w[0]), gp((const unsigned long long*)Cc.chi_w[1])};
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
         long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
@@ -82,6 +88,29 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             const int ir = min(gg, ec2 ? N : N - 1), il = max(min(gl, N - 1), 0);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
+                if (dual) {
+                    // moment words of the nodes (deposit_moments): counts and
+                    // weight sums of nodes g-1, g, g+1, folded or wrapped
+                    const int g0 = min(gg, N);
+                    const int gp1 = periodic ? (gg + 1 == N ? 0 : gg + 1) : min(g0 + 1, N);
+                    const int gm1 = periodic ? gl : max(g0 - 1, 0);
+                    const long long a0 = (long long)dw[s][g0], a1 = (long long)dw[s][gp1];
+                    const long long b0 = (long long)dx_w[s][g0], bm = (long long)dx_w[s][gm1];
+                    const long long n0 = (long long)dc[s][g0] + (long long)dx_c[s][g0];
+                    const long long ncell = (long long)dc[s][g0] + (long long)dx_c[s][gp1];
+                    long long q = n0 * (1ll << kFixBits) - a0 - b0;
+                    if (periodic) {
+                        q += a1 + bm;
+                    } else {
+                        q += g0 < N ? a1 : b0;   // node N keeps its own P2 (folded)
+                        q += g0 > 0 ? bm : a0;   // node 0 keeps its own P0 (folded)
+                    }
+                    qn[k][s] = in ? q : 0;
+                    cn[k][s] = hr ? ncell : 0;
+                    wr[k][s] = 0;
+                    wl[k][s] = 0;
+                    continue;
+                }
                 const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
                 const long long l = (long long)dw[s][il];
                 cn[k][s] = hr ? c : 0;
@@ -133,22 +162,32 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         }
     }
     if (dual) {
-        // centre h takes count - fraction of dual word h+1 and the fraction
-        // of dual word h (periodic: word N for h = 0)
-        const PIC_GLOBAL unsigned long long* xc[2] = {
-            gp((const unsigned long long*)Cc.chi_cnt[0]), gp((const unsigned long long*)Cc.chi_cnt[1])};
-        const PIC_GLOBAL unsigned long long* xw[2] = {
-            gp((const unsigned long long*)Cc.chi_w[0]), gp((const unsigned long long*)Cc.chi_w[1])};
+        // Row sums of the susceptibility operator at the centres (the
+        // diagonal approximation): the particles with nearest node e lie
+        // between centres e-1 and e at fraction t towards e; centre h takes
+        // sum (1 - t) of node h+1 and sum t of node h, i.e. n(h+1) 2^24 -
+        // F(h+1) + F(h) with F(e) = sum t 2^24 = n(e) 2^23 + W2(e) - W0(e).
+        // Next to an electrode the field beyond is zero and the centre takes
+        // the square of its weight: F(0) = sum t^2 = 2 W2(0), and
+        // n(N) 2^24 - F(N) = sum (1 - t)^2 = 2 W0(N).  Periodic: node N is 0.
+        auto F = [&](int s, int e) -> long long {
+            const long long n = (long long)dc[s][e] + (long long)dx_c[s][e];
+            const long long a = (long long)dw[s][e], b = (long long)dx_w[s][e];
+            if (!periodic && e == 0) return 2 * b;
+            if (!periodic && e == N) return n * (1ll << kFixBits) - 2 * a;
+            return n * (1ll << (kFixBits - 1)) + b - a;
+        };
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int h = tid + k * NT;
             if (h < N) {
-                const int hl = (periodic && h == 0) ? N : h;
+                const int e1 = (periodic && h + 1 == N) ? 0 : h + 1;
                 long long v[2];
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    v[s] = (long long)xc[s][h + 1] * (1ll << kFixBits) - (long long)xw[s][h + 1] +
-                           (long long)xw[s][hl];
+                for (int s = 0; s < 2; ++s) {
+                    const long long n1 = (long long)dc[s][e1] + (long long)dx_c[s][e1];
+                    v[s] = n1 * (1ll << kFixBits) - F(s, e1) + F(s, h);
+                }
                 const double chi = (chi0 * (double)v[0] + chi1 * (double)v[1]) / kFixScale;
                 X[h] = chi;
                 gp(Cc.chi)[h] = chi;
@@ -702,9 +741,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
         const int c = cell_of(S.cell[i]);
         if (c < 0) continue;
-        if (ec2) {
+        if (dual) {
+            deposit_moments(dep, dch, true, c, S.off[i], N, periodic, lo, hi);
+        } else if (ec2) {
             deposit_quad(dep, true, c, S.off[i], N, periodic, lo, hi);
-            if (dual) deposit_chi(dch, true, c, S.off[i], N, periodic, lo, hi);
         } else {
             atomicAdd(&dep[c], packw(S.off[i]));
             range_note(lo, hi, c);

@@ -221,17 +221,23 @@ __device__ __forceinline__ void deposit_global(const Case* C, int s, int c, floa
     };
     const int N = C->n_cells;
     const bool periodic = C->bc == 1;
+    if (C->gather == 2 && C->scheme == 1) {
+        // the moment form of deposit_moments: counts and sums of node i
+        uint32_t w[3];
+        int i = quad_weights(c, o, w);
+        if (periodic && i == N) i = 0;
+        const bool left = o >= 0.5f;
+        add(&gcnt[i], left ? 0ull : 1ull);
+        add(&gw[i], (unsigned long long)w[0]);
+        add(gp(&C->chi_cnt[s][i]), left ? 1ull : 0ull);
+        add(gp(&C->chi_w[s][i]), (unsigned long long)w[2]);
+        return;
+    }
     if (C->gather == 2) {
         uint32_t w[3];
         const int i = quad_weights(c, o, w);
         for (int k = 0; k < 3; ++k)
             add(&gw[fold_node(i - 1 + k, N, periodic)], (unsigned long long)w[k]);
-        if (C->scheme == 1) {
-            float f;
-            const int e = chi_dual(c, o, N, periodic, f);
-            add(gp(&C->chi_cnt[s][e]), 1ull);
-            add(gp(&C->chi_w[s][e]), packw(f) & kWMask);
-        }
     } else {
         add(&gw[c], packw(o) & kWMask);
     }
@@ -514,11 +520,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 }
                 dep_now = !kImp || kept;
             }
-            if (ec2)
+            if (dual)
+                deposit_moments(dep, dch, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
+            else if (ec2)
                 deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             else
                 deposit_wave(dep, dep_now, c2, o2, lo, hi);
-            if (dual) deposit_chi(dch, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             // list the candidates of this wavefront in the workgroup's region
             const bool enq = live && isc;
             const unsigned long long qm = __ballot(enq);
@@ -903,8 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(Params P)
         }
         if (kImp) {
             if (ec2) {
-                deposit_quad(dep, dep_ok, c2, o2, N, periodic, lo, hi);
-                deposit_chi(dch, dep_ok, c2, o2, N, periodic, lo, hi);
+                deposit_moments(dep, dch, dep_ok, c2, o2, N, periodic, lo, hi);
             } else {
                 deposit_wave(dep, dep_ok, c2, o2, lo, hi);
             }

@@ -1,8 +1,8 @@
 // Weighting and interpolation shared by the particle pass and the set-up
 // deposit: the gathers of Eq. (3) (m = 1 own cell, m = 2 linear of the
 // half-grid field, MC linear of the nodal field), the packed linear weight of
-// Eq. (2), the quadratic weights and deposit of Eq. (2) with m = 2, and the
-// susceptibility words of the implicit scheme with m = 2.
+// Eq. (2), the quadratic weights and deposit of Eq. (2) with m = 2, and its
+// moment form for the implicit scheme (node charges and susceptibility).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -138,69 +138,64 @@ __device__ __forceinline__ unsigned long long packw(float o)
     return kCountOne + (unsigned long long)__float2uint_rn(o * 16777216.0f);
 }
 
-// Susceptibility of the D1 solve with the m = 2 weighting, Sec. II: the exact
-// operator is proportional to sum_p S_1(x_p - x_h) S_1(x_p - x_h') over the
-// cell centres h, h' (the flux of the quadratic deposit times the linear
-// gather); its diagonal approximation is the row sum.  A particle between
-// centres k and k+1 (fraction t towards k+1) adds 1 - t to k and t to k+1;
-// between an electrode and the first centre only that centre's field acts
-// on it, and the centre takes the square of its weight.
-// Returned: the dual word e = k + 1 (periodic: k = -1 is k = N-1, word N)
-// and the fraction f such that centre k takes 1 - f and centre k+1 takes f
-// (f = t; t^2 at the left electrode, t (2 - t) at the right one).
-__device__ __forceinline__ int chi_dual(int c, float o, int N, bool periodic, float& f)
+// The quadratic deposit of the implicit scheme with m = 2, in moment form.
+// Its susceptibility (Sec. II, degree reading): displacing a particle moves,
+// through the quadratic deposit, the flux S_1(x_p - x_h) d_p through centre
+// h, and the D1 correction d_p follows the linear gather of the half-grid
+// field, so the exact operator is proportional to sum_p S_1(x_p - x_h)
+// S_1(x_p - x_h'); the solve takes its row sums.  A particle with nearest
+// node i lies between centres i-1 and i, at fraction t = 1/2 + d towards i.
+// Words:
+// per nearest node i (the dual word of the susceptibility), word A[i] =
+// (particles of cell i) << 40 | sum of their weights P0 to node i-1, and
+// B[i] = (particles of cell i-1) << 40 | sum of the weights P2 to node i+1
+// (P0, P2 of quad_weights; a periodic node N is node 0).  From these the
+// solve forms the same node charges as the deposit of deposit_quad, the cell
+// counts, and the susceptibility fractions (t = 1/2 + (P2 - P0) 2^-24, t^2 =
+// 2 P2 2^-24, (1 - t)^2 = 2 P0 2^-24 per particle).  sorted: the lanes of a
+// cell-sorted species share at most two nodes; their words are summed
+// across the wavefront first (called by whole wavefronts then).
+__device__ __forceinline__ void deposit_moments(unsigned long long* A, unsigned long long* B,
+                                                bool want, int c, float o, int N, bool periodic,
+                                                int& lo, int& hi, bool sorted = false)
 {
-    const bool up = o >= 0.5f;
-    const int k = up ? c : c - 1;
-    const float t = up ? o - 0.5f : o + 0.5f;
-    f = t;
-    if (periodic) return k < 0 ? N : k + 1;
-    if (k < 0) f = t * t;
-    else if (k == N - 1) f = t * (2.0f - t);
-    return k + 1;
-}
-
-// Susceptibility words of one particle per lane into a privatised dual grid
-// (N+1 words, packed as the linear deposit: count << 40 | fraction).
-// sorted: the lanes of a cell-sorted species share at most two words; their
-// fractions are summed across the wavefront first (called by whole
-// wavefronts then).
-__device__ __forceinline__ void deposit_chi(unsigned long long* dch, bool want, int c, float o,
-                                            int N, bool periodic, int& lo, int& hi,
-                                            bool sorted = false)
-{
-    float f = 0.0f;
-    int e = 0;
-    if (want) e = chi_dual(c, o, N, periodic, f);
-    const unsigned long long pw = want ? packw(f) : 0ull;
+    uint32_t w[3] = {0u, 0u, 0u};
+    int i = c;
+    if (want) i = quad_weights(c, o, w);
+    if (periodic && i == N) i = 0;
+    const bool left = o >= 0.5f;   // the particle lies left of node i (in cell i-1)
     if (sorted) {
         const unsigned long long m = __ballot(want);
         if (m == 0ull) return;
         const int lane = threadIdx.x & 63;
-        const int ea = __builtin_amdgcn_readlane(e, __ffsll((long long)m) - 1);
-        const unsigned long long ma = __ballot(want && e == ea);
+        const int ia = __builtin_amdgcn_readlane(i, __ffsll((long long)m) - 1);
+        const unsigned long long ma = __ballot(want && i == ia);
         const unsigned long long mb = m & ~ma;
-        const int eb = mb ? __builtin_amdgcn_readlane(e, __ffsll((long long)mb) - 1) : ea;
-        if (__ballot(want && e != ea && e != eb) == 0ull) {
+        const int ib = mb ? __builtin_amdgcn_readlane(i, __ffsll((long long)mb) - 1) : ia;
+        if (__ballot(want && i != ia && i != ib) == 0ull) {
+            const unsigned long long ml = __ballot(want && left);
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 const unsigned long long mg = g == 0 ? ma : mb;
                 if (mg == 0ull) continue;
-                // at most 64 * 2^24 = 2^30
+                // at most 64 * 2^23 per sum
                 const bool mine = ((mg >> lane) & 1ull) != 0ull;
-                const unsigned t = wave_total_u32(mine ? (unsigned)(pw & kWMask) : 0u);
+                const unsigned t0 = wave_total_u32(mine ? w[0] : 0u);
+                const unsigned t2 = wave_total_u32(mine ? w[2] : 0u);
                 if (lane == __ffsll((long long)mg) - 1) {
-                    const int eg = g == 0 ? ea : eb;
-                    atomicAdd(&dch[eg], (unsigned long long)__popcll(mg) * kCountOne + t);
-                    range_note(lo, hi, eg);
+                    const int ig = g == 0 ? ia : ib;
+                    atomicAdd(&A[ig], (unsigned long long)__popcll(mg & ~ml) * kCountOne + t0);
+                    atomicAdd(&B[ig], (unsigned long long)__popcll(mg & ml) * kCountOne + t2);
+                    range_note(lo, hi, ig);
                 }
             }
             return;
         }
     }
     if (!want) return;
-    atomicAdd(&dch[e], pw);
-    range_note(lo, hi, e);
+    atomicAdd(&A[i], (left ? 0ull : kCountOne) + (unsigned long long)w[0]);
+    atomicAdd(&B[i], (left ? kCountOne : 0ull) + (unsigned long long)w[2]);
+    range_note(lo, hi, i);
 }
 
 }  // namespace pic
