@@ -31,7 +31,10 @@ namespace pic {
 // ---------------------------------------------------------------------------
 constexpr double kEps0 = 8.8541878128e-12;
 
-template <int NT>
+// kDual: the code of the implicit m = 2 moment words is compiled in (the
+// launches of batches without such a case leave it out: its registers would
+// make the rest spill).
+template <int NT, bool kDual>
 __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step,
                                            long long field_step, bool sample_density, double* S,
                                            double* red)
@@ -63,7 +66,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
     const double rho_bg = Cc.background_rho;
     const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
-    const bool dual = implicit && ec2;  // susceptibility of the dual grid
+    const bool dual = kDual && implicit && ec2;   // moment words (deposit_moments)
     const bool nu = Cc.nonuniform != 0;
     const PIC_GLOBAL double* wjr = gp((const double*)Cc.cell_wr);   // nu: w_j / dx
     // subcycled ions keep their deposit until the step in which they move
@@ -75,6 +78,70 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         gp((const unsigned long long*)Cc.chi_cnt[0]), gp((const unsigned long long*)Cc.chi_cnt[1])};
     const PIC_GLOBAL unsigned long long* dx_w[2] = {
         gp((const unsigned long long*)Cc.chi_w[0]), gp((const unsigned long long*)Cc.chi_w[1])};
+    // node g's outputs from its fixed-point charges q0, q1 and (g < N) the
+    // particle counts c0, c1 of cell g
+    auto emit_node = [&](int g, long long q0, long long q1, long long c0, long long c1) {
+        double rho = rho_bg, chin = 0.0;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const long long q = s == 0 ? q0 : q1;
+            gp(Cc.qfix[s])[g] = q;
+            if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
+            rho += (double)q * (s == 0 ? qs0 : qs1);
+            chin += (double)q * (s == 0 ? chi0 : chi1);
+        }
+        if (node_chi) {
+            const bool end = !periodic && (g == 0 || g == N);
+            Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
+        }
+        double sg = rho * dx;
+        if (nu) {
+            // node volume / dx: half of each adjacent cell, the whole end cell
+            const double vg =
+                g == 0 ? wjr[0] : (g == N ? wjr[N - 1] : 0.5 * (wjr[g - 1] + wjr[g]));
+            sg = (rho - rho_bg) * dx + rho_bg * dx * vg;
+            rho = sg / (dx * vg);
+        }
+        gp(Cc.rho)[g] = rho;
+        // R_j = sum_{k=1..j} (charge per area of node k): node 0's is zero
+        S[g] = g == 0 ? 0.0 : sg;
+        if (g < N) {
+            gp(Cc.ccount[0])[g] = c0;
+            gp(Cc.ccount[1])[g] = c1;
+            if (!node_chi && !dual) {
+                double chi = implicit ? chi0 * (double)c0 + chi1 * (double)c1 : 0.0;
+                if (nu) chi /= wjr[g];
+                X[g] = chi;
+                gp(Cc.chi)[g] = chi;
+            }
+        }
+    };
+    if (dual) {
+        // moment words (deposit_moments), one node at a time: counts and
+        // weight sums of nodes g-1, g, g+1, folded at electrodes or wrapped
+#pragma unroll 1
+        for (int g = tid; g <= N; g += NT) {
+            const int gg = (periodic && g == N) ? 0 : g;
+            const int gp1 = periodic ? (gg + 1 == N ? 0 : gg + 1) : min(gg + 1, N);
+            const int gm1 = periodic ? (gg > 0 ? gg - 1 : N - 1) : max(gg - 1, 0);
+            long long q[2], nc[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const long long a0 = (long long)dw[s][gg], a1 = (long long)dw[s][gp1];
+                const long long b0 = (long long)dx_w[s][gg], bm = (long long)dx_w[s][gm1];
+                const long long n0 = (long long)dc[s][gg] + (long long)dx_c[s][gg];
+                nc[s] = (long long)dc[s][gg] + (long long)dx_c[s][gp1];
+                q[s] = n0 * (1ll << kFixBits) - a0 - b0;
+                if (periodic) {
+                    q[s] += a1 + bm;
+                } else {
+                    q[s] += gg < N ? a1 : b0;   // node N keeps its own P2 (folded)
+                    q[s] += gg > 0 ? bm : a0;   // node 0 keeps its own P0 (folded)
+                }
+            }
+            emit_node(g, q[0], q[1], nc[0], nc[1]);
+        }
+    } else {
     for (int k0 = 0; k0 < kPer && k0 * NT <= N; k0 += kB) {
         long long cn[kB][2], wr[kB][2], wl[kB][2], qn[kB][2];
 #pragma unroll
@@ -88,29 +155,6 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             const int ir = min(gg, ec2 ? N : N - 1), il = max(min(gl, N - 1), 0);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                if (dual) {
-                    // moment words of the nodes (deposit_moments): counts and
-                    // weight sums of nodes g-1, g, g+1, folded or wrapped
-                    const int g0 = min(gg, N);
-                    const int gp1 = periodic ? (gg + 1 == N ? 0 : gg + 1) : min(g0 + 1, N);
-                    const int gm1 = periodic ? gl : max(g0 - 1, 0);
-                    const long long a0 = (long long)dw[s][g0], a1 = (long long)dw[s][gp1];
-                    const long long b0 = (long long)dx_w[s][g0], bm = (long long)dx_w[s][gm1];
-                    const long long n0 = (long long)dc[s][g0] + (long long)dx_c[s][g0];
-                    const long long ncell = (long long)dc[s][g0] + (long long)dx_c[s][gp1];
-                    long long q = n0 * (1ll << kFixBits) - a0 - b0;
-                    if (periodic) {
-                        q += a1 + bm;
-                    } else {
-                        q += g0 < N ? a1 : b0;   // node N keeps its own P2 (folded)
-                        q += g0 > 0 ? bm : a0;   // node 0 keeps its own P0 (folded)
-                    }
-                    qn[k][s] = in ? q : 0;
-                    cn[k][s] = hr ? ncell : 0;
-                    wr[k][s] = 0;
-                    wl[k][s] = 0;
-                    continue;
-                }
                 const long long c = (long long)dc[s][ir], r = (long long)dw[s][ir];
                 const long long l = (long long)dw[s][il];
                 cn[k][s] = hr ? c : 0;
@@ -123,43 +167,13 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         for (int k = 0; k < kB; ++k) {
             const int g = tid + (k0 + k) * NT;
             if (g > N) continue;
-            double rho = rho_bg, chin = 0.0;
+            long long q[2];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const long long q =
-                    ec2 ? qn[k][s] : cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
-                gp(Cc.qfix[s])[g] = q;
-                if (sample_density) gatomic_add(gp(&Cc.dens_acc[s][g]), (unsigned long long)q);
-                rho += (double)q * (s == 0 ? qs0 : qs1);
-                chin += (double)q * (s == 0 ? chi0 : chi1);
-            }
-            if (node_chi) {
-                const bool end = !periodic && (g == 0 || g == N);
-                Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
-            }
-            double sg = rho * dx;
-            if (nu) {
-                // node volume / dx: half of each adjacent cell, the whole end cell
-                const double vg =
-                    g == 0 ? wjr[0] : (g == N ? wjr[N - 1] : 0.5 * (wjr[g - 1] + wjr[g]));
-                sg = (rho - rho_bg) * dx + rho_bg * dx * vg;
-                rho = sg / (dx * vg);
-            }
-            gp(Cc.rho)[g] = rho;
-            // R_j = sum_{k=1..j} (charge per area of node k): node 0's is zero
-            S[g] = g == 0 ? 0.0 : sg;
-            if (g < N) {
-                gp(Cc.ccount[0])[g] = cn[k][0];
-                gp(Cc.ccount[1])[g] = cn[k][1];
-                if (!node_chi && !dual) {
-                    double chi =
-                        implicit ? chi0 * (double)cn[k][0] + chi1 * (double)cn[k][1] : 0.0;
-                    if (nu) chi /= wjr[g];
-                    X[g] = chi;
-                    gp(Cc.chi)[g] = chi;
-                }
-            }
+            for (int s = 0; s < 2; ++s)
+                q[s] = ec2 ? qn[k][s] : cn[k][s] * (1ll << kFixBits) - wr[k][s] + wl[k][s];
+            emit_node(g, q[0], q[1], cn[k][0], cn[k][1]);
         }
+    }
     }
     if (dual) {
         // Row sums of the susceptibility operator at the centres (the
@@ -177,10 +191,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             if (!periodic && e == N) return n * (1ll << kFixBits) - 2 * a;
             return n * (1ll << (kFixBits - 1)) + b - a;
         };
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int h = tid + k * NT;
-            if (h < N) {
+#pragma unroll 1
+        for (int h = tid; h < N; h += NT) {
+            {
                 const int e1 = (periodic && h + 1 == N) ? 0 : h + 1;
                 long long v[2];
 #pragma unroll
@@ -407,6 +420,7 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
 // workgroup partials), the even one solves the FP64 field of the next step.
 // They write disjoint fields of the case state (flags through atomics).
 // ---------------------------------------------------------------------------
+template <bool kDual>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -426,13 +440,15 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
     if (threadIdx.x == 0) s_step = st->step;
     lds_barrier();
     const long long next = s_step + 1;
-    solve_case<kFinBlock>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
-                          (double*)smem, red);
+    solve_case<kFinBlock, kDual>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
+                                 (double*)smem, red);
     if (threadIdx.x == 0) {
         if (sample) st->eedf_samples += 1;
         st->step = next;
     }
 }
+template __global__ void k_finalize<false>(Params, int);
+template __global__ void k_finalize<true>(Params, int);
 
 // ---------------------------------------------------------------------------
 // Set-up: velocities from m/s to cells/step (unless given in internal
@@ -775,7 +791,7 @@ __global__ __launch_bounds__(kFinBlock) void k_solve(Params P)
     __shared__ double red[kFinBlock / 64];
     Case* C = P.cases + blockIdx.x;
     State* st = P.state + blockIdx.x;
-    solve_case<kFinBlock>(C, st, st->step + (C->scheme == 1 ? 1 : 0), st->step, false,
+    solve_case<kFinBlock, true>(C, st, st->step + (C->scheme == 1 ? 1 : 0), st->step, false,
                           (double*)smem, red);
 }
 

@@ -29,6 +29,7 @@ __global__ void k_compact_scatter(Params P, uint32_t* cursor_all, const int64_t*
 __global__ void k_compact_finish(Params P);
 __global__ void k_deposit(Params P);
 __global__ void k_solve(Params P);
+template <bool kDual>
 __global__ void k_finalize(Params P, int sample);
 }  // namespace pic
 
@@ -357,7 +358,7 @@ int set_lds_limits(pic_ctx* c, size_t need)
                         (const void*)k_collide<1, false>, (const void*)k_collide<1, true>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
                         (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve,
-                        (const void*)k_finalize};
+                        (const void*)k_finalize<false>, (const void*)k_finalize<true>};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v);
         if (e != hipSuccess) {
@@ -892,7 +893,8 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             }
         }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(2 * c->n_cases), dim3(kFinBlock), fin_lds(c->maxN),
+    hipLaunchKernelGGL(c->any_dual ? k_finalize<true> : k_finalize<false>, dim3(2 * c->n_cases),
+                       dim3(kFinBlock), fin_lds(c->maxN),
                        c->stream, params(c, 0), diag ? 1 : 0);
     HIPCHK(c, hipGetLastError());
     if (++c->since_sort >= c->sort_every)
