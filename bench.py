@@ -122,11 +122,10 @@ def measured_traffic(workload, kernel):
         return None
 
 
-def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge"):
-    """The FP64 oracle (single thread) on a particle sample of the workload."""
+def _oracle_sample(wl, frac):
+    """A particle sample of the workload in the oracle's form (same densities)."""
     import numpy as np
 
-    import oracle
     import workloads as W
     case, sps, procs = W.to_oracle(wl)
     rng = np.random.default_rng(1)
@@ -141,19 +140,50 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge")
         d["abar"] = None
         d["w"] = sp["w"] / frac          # same densities with fewer particles
         sub.append(d)
+    return case, sub, procs
+
+
+def _oracle_rate(case, sub, procs, budget_s):
+    """Particle-steps per second of the FP64 oracle (one thread) on a sample."""
+    import oracle
     sim = oracle.Sim(case, sub, procs)
     sim.step(2)
-    n_ps = 0
-    steps = 0
+    n_ps = steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < steps_budget_s:
+    while time.perf_counter() - t0 < budget_s:
         n_ps += sim.count(0) + sim.count(1)
         sim.step(1)
         steps += 1
-    dt = time.perf_counter() - t0
-    return dict(value=n_ps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+    return n_ps / (time.perf_counter() - t0), steps
+
+
+def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge", max_procs=16):
+    """The FP64 oracle on a particle sample of the workload, as it stands (one
+    thread per process): one process per usable host core (at most
+    max_procs), each stepping the same sample; value = their summed rate."""
+    import multiprocessing as mp
+    case, sub, procs = _oracle_sample(wl, frac)
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    n = max(1, min(ncpu, max_procs))
+    try:
+        with mp.get_context("spawn").Pool(n) as pool:
+            job = pool.starmap_async(_oracle_rate, [(case, sub, procs, steps_budget_s)] * n)
+            res = job.get(timeout=steps_budget_s + 120.0)   # a worker that died raises here
+    except Exception as e:   # no child processes here: one thread in this one
+        log(f"[bench] oracle processes failed ({e}); timing one thread")
+        n = 1
+        res = [_oracle_rate(case, sub, procs, steps_budget_s)]
+    rates = [r for r, _ in res]
+    return dict(value=sum(rates), unit="particle-steps/s", cores=n, kind="oracle",
+                per_core_value=sum(rates) / n,
                 sample=f"{frac:g} of the particles of {where} (weights scaled "
-                       f"to keep the densities), {steps} steps, FP64, single thread")
+                       f"to keep the densities), FP64, {n} single-thread processes "
+                       f"stepping it for {steps_budget_s:g} s each "
+                       f"({min(s for _, s in res)}-{max(s for _, s in res)} steps); "
+                       f"{ncpu} usable host cores")
 
 
 def drift_table(P, steps):
@@ -248,6 +278,13 @@ def main():
 
     log(f"[bench] building inputs: {args.workload} scale {args.scale}")
     wls = make_workload(args.workload, args.scale)
+    cpu = None
+    if not args.no_cpu:
+        # before this process touches the GPU: the oracle runs in fresh
+        # child interpreters
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(wls[0], args.cpu_seconds,
+                           where="the same discharge" if len(wls) == 1 else "case 0 of the batch")
     log("[bench] pic_init")
     ctx = P.PicContext(wls)
     tile = args.tile or 16384
@@ -384,11 +421,8 @@ def main():
                                     ms_per_step=(t1 - t0) * 1e3 / args.fp64_steps,
                                     steps=args.fp64_steps)
         out["speedup_vs_fp64_form"] = value / v64
-    if not args.no_cpu:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(
-            wls[0], args.cpu_seconds,
-            where="the same discharge" if len(wls) == 1 else "case 0 of the batch")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     ctx.close()
     print(json.dumps(out), flush=True)
 
