@@ -61,7 +61,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // Nodes in batches of kB per thread; inside a batch every load is issued
     // before any result is used (unconditional loads from clamped indices,
     // selected afterwards, so that none waits behind a branch).
-    constexpr int kB = 3;
+    constexpr int kB = kDual ? 1 : 3;   // (3 with the moment path would spill)
     const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
     const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
     const double rho_bg = Cc.background_rho;
