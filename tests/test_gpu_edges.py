@@ -104,9 +104,26 @@ def test_determinism_of_state_and_fields():
         assert np.array_equal(f1[k], f2[k]), k
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_resume_equals_uninterrupted(scheme):
-    wl = W.c1(collisions=1, np_per_species=4096, scheme=scheme)
+def _variant(name, np_per_species=4096):
+    # the 64-cell discharge as is, implicit, with ions subcycled (K = 3), on
+    # a sheath-refined grid (implicit), or m = 2 implicit
+    if name == "nonuniform_implicit":
+        return W.ccp_workload("ccp64_nonuniform", n_cells=64, np_per_species=np_per_species,
+                              volts=100.0, p_mtorr=50.0, scheme=1, seed=0x65,
+                              cell_dx=W.sheath_refined_widths(64, 0.025))
+    wl = W.c1(collisions=1, np_per_species=np_per_species,
+              scheme=1 if "implicit" in name else 0)
+    if name == "subcycle3":
+        wl["case"]["ion_subcycle"] = 3
+    if name == "ec2_implicit":
+        wl["case"]["gather"] = 2
+    return wl
+
+
+@pytest.mark.parametrize("variant", ["explicit", "implicit", "subcycle3", "nonuniform_implicit"])
+def test_resume_equals_uninterrupted(variant):
+    # 40 steps: a subcycled run resumes between two ion pushes
+    wl = _variant(variant)
     a = ctx_for(wl, sort_every=1000)
     a.step(40)
     st = a.state()
@@ -186,6 +203,29 @@ def test_graph_replay_equals_host_launches(timing_every):
             for k in a:
                 assert np.array_equal(a[k], b[k]), k
         for k in ("rho", "phi", "E"):
+            assert np.array_equal(f1[k], f2[k]), k
+
+
+def test_graph_replay_with_every_grid_variant():
+    # one batch of a subcycled, a sheath-refined and an m = 2 implicit case:
+    # the subcycling phase is read on the device, so replays of a captured
+    # sort period step exactly as host launches do
+    wls = [_variant("subcycle3", 3000), _variant("nonuniform_implicit", 3000),
+           _variant("ec2_implicit", 3000)]
+    outs = []
+    for graph in (0, 1):
+        ctx = P().PicContext(wls)
+        ctx.set_schedule(sort_every=5, diag_every=0, tile=1024)
+        ctx.set_launch(graph=graph, timing_every=0)
+        for n in (4, 13, 7):
+            ctx.step(n)
+        outs.append([(sorted_state(ctx, k), ctx.fields(k)) for k in range(len(wls))])
+        ctx.close()
+    for (s1, f1), (s2, f2) in zip(*outs):
+        for a, b in zip(s1, s2):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
+        for k in ("rho", "phi", "E", "chi"):
             assert np.array_equal(f1[k], f2[k]), k
 
 
