@@ -2,7 +2,8 @@
 
 Both start from the same 64-cell capacitive discharge (16k electrons and 16k
 ions, 50 mTorr, 100 V at 13.56 MHz; on a uniform and on a sheath-refined
-grid) and run 10 RF periods on their own.
+grid, with subcycled ions, and with the m = 2 implicit scheme) and run 10 RF
+periods on their own.
 Float32 particle state against float64 makes the two microstates drift apart
 (the motion is chaotic), so they are compared through statistics over the
 last 4 periods: the time-averaged node densities, the electron energy
@@ -25,16 +26,20 @@ PERIOD = 400          # steps per RF period at dt = 1/(400 f)
 TOL = 0.02
 
 
-@pytest.mark.parametrize("grid", ["uniform", "sheath_refined"])
+@pytest.mark.parametrize("grid", ["uniform", "sheath_refined", "subcycle4", "ec2_implicit"])
 def test_ccp64_ten_periods_statistics_match_oracle(grid):
     import paper_1310_5284_amd as P
-    if grid == "uniform":
-        wl = W.c1(collisions=1, np_per_species=16384)
-    else:
+    if grid == "sheath_refined":
         # cells about 4x narrower within 15 % of the gap from either electrode
         wl = W.ccp_workload("ccp64_nonuniform", n_cells=64, np_per_species=16384,
                             volts=100.0, p_mtorr=50.0, seed=0xC1,
                             cell_dx=W.sheath_refined_widths(64, 0.025))
+    else:
+        wl = W.c1(collisions=1, np_per_species=16384, scheme=1 if grid == "ec2_implicit" else 0)
+        if grid == "subcycle4":
+            wl["case"]["ion_subcycle"] = 4      # ions every 4th step with 4 dt
+        if grid == "ec2_implicit":
+            wl["case"]["gather"] = 2            # m = 2, D1 implicit
     N = wl["case"]["n_cells"]
     w = wl["case"].get("cell_dx", np.full(N, wl["case"]["gap_m"] / N))
     t0, tw = 6 * PERIOD, 4 * PERIOD
