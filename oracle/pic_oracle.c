@@ -276,6 +276,26 @@ double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi)
     return (1.0 - f) * nodal_E(N, periodic, E, jj) + f * nodal_E(N, periodic, E, jj + 1);
 }
 
+/* MC gather on a nonuniform grid of cell widths w (electrodes): the nodal
+ * field is the centred difference of the potential over the node's two
+ * cells, (phi_{g-1} - phi_{g+1}) / (w_{g-1} + w_g), i.e. the width-weighted
+ * mean of the two half-grid fields; an electrode node takes its only cell's
+ * field.  Linear interpolation in the logical coordinate. */
+static double nodal_E_nu(int32_t N, const double* w, const double* E, int64_t g)
+{
+    if (g == 0) return E[0];
+    if (g == N) return E[N - 1];
+    return (w[g - 1] * E[g - 1] + w[g] * E[g]) / (w[g - 1] + w[g]);
+}
+
+double orc_gather_mc_nu(int32_t N, const double* w, const double* E, double xi)
+{
+    double j = floor(xi);
+    double f = xi - j;
+    int64_t jj = (int64_t)j;
+    return (1.0 - f) * nodal_E_nu(N, w, E, jj) + f * nodal_E_nu(N, w, E, jj + 1);
+}
+
 /* Eq. (2) with S_2, the quadratic B-spline: S_2(x) = 3/4 - x^2 for |x| <=
  * 1/2, (3/2 - |x|)^2 / 2 for 1/2 <= |x| <= 3/2.  The nearest node i takes
  * 3/4 - d^2, its neighbours (1/2 -+ d)^2 / 2, d = xi - i in [-1/2, 1/2). */
@@ -362,8 +382,9 @@ orc_sim* orc_create(const orc_case* c)
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
     if (c->ion_subcycle < 0 || (c->ion_subcycle > 1 && c->scheme != ORC_EXPLICIT)) return NULL;
     if (c->cell_dx_m) {
-        /* nonuniform grids: EC gather between electrodes, widths summing to L */
-        if (c->gather != ORC_GATHER_EC || c->bc != ORC_BC_DIRICHLET) return NULL;
+        /* nonuniform grids: EC or MC gather between electrodes, widths
+         * summing to L */
+        if (c->gather == ORC_GATHER_EC2 || c->bc != ORC_BC_DIRICHLET) return NULL;
         double L = 0.0;
         for (int32_t j = 0; j < c->n_cells; ++j) {
             if (!(c->cell_dx_m[j] > 0.0) || !isfinite(c->cell_dx_m[j])) return NULL;
@@ -654,6 +675,8 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
             for (int32_t g = j; g <= j + 1; ++g) {
                 double vol = s->dx;
                 if (!periodic && (g == 0 || g == N)) vol = 0.5 * s->dx;
+                if (s->cw)   /* half of each adjacent cell */
+                    vol = 0.5 * ((g > 0 ? s->cw[g - 1] : 0.0) + (g < N ? s->cw[g] : 0.0));
                 for (int k = 0; k < 2; ++k) {
                     if (!(s->sp[k].m > 0.0)) continue;
                     /* the periodic deposit holds the folded node in Q_0 and Q_N */
@@ -942,6 +965,7 @@ static double gather(const orc_sim* s, double xi)
 {
     int32_t N = s->c.n_cells;
     int periodic = s->c.bc == ORC_BC_PERIODIC;
+    if (s->c.gather == ORC_GATHER_MC && s->cw) return orc_gather_mc_nu(N, s->cw, s->E, xi);
     if (s->c.gather == ORC_GATHER_MC) return orc_gather_mc(N, periodic, s->E, xi);
     if (s->c.gather == ORC_GATHER_EC2) return orc_gather_ec2(N, periodic, s->E, xi);
     return orc_gather_ec(N, s->E, xi);

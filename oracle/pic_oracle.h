@@ -63,7 +63,7 @@ typedef struct {
     double opal_B_eV;       /* energy-sharing parameter of ionization              */
     uint64_t seed;          /* Philox key                                          */
     /* NULL: N equal cells of L/N.  Otherwise the N cell widths (m, summing to
-     * L; EC gather and electrodes only): a nonuniform grid, finer in the
+     * L; EC or MC gather, electrodes only): a nonuniform grid, finer in the
      * sheaths.  Positions stay logical (cell index + offset in the cell). */
     const double* cell_dx_m;
 } orc_case;
@@ -116,6 +116,9 @@ void orc_solve_periodic(int32_t N, double dx, const double* rho, const double* c
 /* Eq. (3) gathers at one particle. */
 double orc_gather_ec(int32_t N, const double* E, double xi);
 double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi);
+/* MC gather on a nonuniform grid of cell widths w[N] (electrodes): linear
+ * interpolation of the nodal field (phi_{g-1} - phi_{g+1}) / (w_{g-1} + w_g). */
+double orc_gather_mc_nu(int32_t N, const double* w, const double* E, double xi);
 /* Eq. (2) with the quadratic spline S_2 (degree 2, support 3 cells): a
  * particle at xi with nearest node i = floor(xi + 1/2) and d = xi - i gives
  * (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2 to nodes i-1, i, i+1.  Nodes

@@ -150,10 +150,11 @@ def test_d1_cold_plasma_follows_recurrence(orc, wdt):
         np.testing.assert_allclose(got, delta * ref[n], rtol=0, atol=1e-10 * np.abs(delta).max())
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_equal_widths_reproduce_the_uniform_grid(orc, scheme):
+@pytest.mark.parametrize("scheme,gather", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_equal_widths_reproduce_the_uniform_grid(orc, scheme, gather):
     import workloads as W
     wl = W.c1(collisions=1, np_per_species=3000, scheme=scheme)
+    wl["case"]["gather"] = gather
     case, sps, procs = W.to_oracle(wl)
     N = case["n_cells"]
     a = orc.Sim(case, sps, procs)
@@ -173,7 +174,7 @@ def test_rejects_what_the_grid_does_not_support(orc):
     w = np.full(8, 1e-3)
     base = dict(n_cells=8, gap_m=8e-3, bc=0, scheme=0, gather=0, collisions=0, dt_s=1e-11)
     sps = _two_species(np.array([0.5]), np.zeros(1), 1.0)
-    for bad in (dict(gather=1), dict(gather=2), dict(bc=1), dict(gap_m=9e-3)):
+    for bad in (dict(gather=2), dict(bc=1), dict(gap_m=9e-3)):
         with pytest.raises(ValueError):
             orc.Sim(dict(base, cell_dx=w, **bad), sps, [])
     with pytest.raises(ValueError):
@@ -196,3 +197,41 @@ def test_ec_energy_error_shrinks_like_dt_squared(orc):
         errs.append(np.abs(tot / tot[0] - 1).max())
     for a, b in zip(errs, errs[1:]):
         assert 3.0 <= a / b <= 5.5, errs
+
+
+def test_mc_gather_is_the_centred_potential_difference(orc):
+    # the nodal field of the momentum-conserving gather on a nonuniform grid:
+    # (phi_{g-1} - phi_{g+1}) / (x_{g+1} - x_{g-1}) from the node positions,
+    # the electrode nodes taking their only cell's field; linear in between
+    rng = np.random.default_rng(5)
+    w = 1e-4 * MULT
+    N = w.size
+    xn = np.concatenate([[0.0], np.cumsum(w)])
+    phi = rng.normal(size=N + 1)
+    Ef = (phi[:-1] - phi[1:]) / w
+    En = np.empty(N + 1)
+    En[1:N] = (phi[:N - 1] - phi[2:]) / (xn[2:] - xn[:N - 1])
+    En[0], En[N] = Ef[0], Ef[-1]
+    for xi in np.concatenate([rng.uniform(0, N, 50), [0.0, 0.5, N - 1e-9, 3.0]]):
+        j = min(int(np.floor(xi)), N - 1)
+        f = xi - j
+        ref = (1 - f) * En[j] + f * En[j + 1]
+        assert abs(orc.gather_mc_nu(w, Ef, xi) - ref) < 1e-12 * np.abs(En).max()
+
+
+def test_mc_susceptibility_of_a_uniform_plasma_is_the_same_on_every_grid(orc):
+    # electrons at uniform physical density (each cell's count proportional
+    # to its width, evenly spread): the node susceptibility of the linear
+    # weights over the node volumes is beta (omega_p dt)^2 in every cell away
+    # from the electrodes, whatever the widths
+    case, sps, cell, off, delta, w, dt, wp = cold_nonuniform(0.7, 1)
+    N = w.size
+    k = MULT * 6
+    cells = np.repeat(np.arange(N), k)
+    offs = np.concatenate([(np.arange(m) + 0.5) / m for m in k])
+    sps[0] = dict(sps[0], xi=cells + offs, vx=np.zeros(cells.size), vy=np.zeros(cells.size),
+                  vz=np.zeros(cells.size), id=np.arange(cells.size, dtype=np.uint64))
+    sim = orc.Sim(dict(case, gather=1), sps, [], startup=False)
+    sim.compute_fields()
+    chi = sim.fields()["chi"]
+    np.testing.assert_allclose(chi[1:-1], 0.5 * (wp * dt) ** 2, rtol=1e-9)
