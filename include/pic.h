@@ -106,8 +106,10 @@ typedef struct {
     /* NULL: N equal cells of gap_m / N.  Otherwise N cell widths in metres
      * (host memory, read during pic_init only), positive and summing to
      * gap_m within 1e-9: a nonuniform grid, finer in the sheaths (the
-     * multi-scale grid the conclusions propose).  PIC_GATHER_EC and
-     * PIC_BC_DIRICHLET_RF only (else PIC_E_INVAL).  Positions stay logical
+     * multi-scale grid the conclusions propose).  PIC_GATHER_EC or
+     * PIC_GATHER_MC (nodal field: the centred potential difference over the
+     * node's two cells), PIC_BC_DIRICHLET_RF only (else PIC_E_INVAL).
+     * Positions stay logical
      * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */
     const double* cell_dx_m;
     /* Ion subcycling K (PIC_EXPLICIT only; 0 or 1: none; at most 4096):

@@ -92,7 +92,13 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         }
         if (node_chi) {
             const bool end = !periodic && (g == 0 || g == N);
-            Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
+            if (nu) {
+                // over the node's volume / dx: half of each adjacent cell
+                const double vh = 0.5 * ((g > 0 ? wjr[g - 1] : 0.0) + (g < N ? wjr[g] : 0.0));
+                Y[g] = chin / (kFixScale * vh);
+            } else {
+                Y[g] = chin * ((end ? 2.0 : 1.0) / kFixScale);
+            }
         }
         double sg = rho * dx;
         if (nu) {

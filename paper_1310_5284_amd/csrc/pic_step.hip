@@ -310,7 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     {
         const PIC_GLOBAL float* ehg = gp(C->ehat[s]);
         if (mc) {
-            for (int g = tid; g <= N; g += kBlock) eh[g] = nodal_field(ehg, N, periodic, g);
+            if (nu) {
+                const PIC_GLOBAL float* rg = gp(C->cell_r);
+                for (int g = tid; g <= N; g += kBlock) eh[g] = nodal_field_nu(ehg, rg, N, g);
+            } else {
+                for (int g = tid; g <= N; g += kBlock) eh[g] = nodal_field(ehg, N, periodic, g);
+            }
         } else {
 #pragma unroll 8
             for (int j = tid; j < N; j += kBlock) eh[j] = ehg[j];

@@ -133,6 +133,18 @@ __device__ __forceinline__ float nodal_field(const PIC_GLOBAL float* eh, int N, 
     return 0.5f * (eh[g - 1] + eh[g]);
 }
 
+// The same on a nonuniform grid (electrodes) with r[c] = (L/N) / w_c: the
+// centred difference of the potential over the node's two cells, i.e. the
+// width-weighted mean (w_{g-1} E_{g-1} + w_g E_g) / (w_{g-1} + w_g) =
+// (r_g E_{g-1} + r_{g-1} E_g) / (r_{g-1} + r_g).
+__device__ __forceinline__ float nodal_field_nu(const PIC_GLOBAL float* eh,
+                                                const PIC_GLOBAL float* r, int N, int g)
+{
+    if (g == 0) return eh[0];
+    if (g == N) return eh[N - 1];
+    return (r[g] * eh[g - 1] + r[g - 1] * eh[g]) / (r[g - 1] + r[g]);
+}
+
 __device__ __forceinline__ unsigned long long packw(float o)
 {
     return kCountOne + (unsigned long long)__float2uint_rn(o * 16777216.0f);

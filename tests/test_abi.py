@@ -85,7 +85,7 @@ def test_init_rejects_bad_input_without_a_gpu():
     # nonuniform grids: EC gather between electrodes, positive widths summing
     # to the gap
     good = (C.c_double * 8)(*([0.01 / 8] * 8))
-    for field, value in (("gather", 1), ("gather", 2), ("bc", 1)):
+    for field, value in (("gather", 2), ("bc", 1)):
         setattr(cfg[0], field, value)
         cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
         assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL, field
