@@ -624,8 +624,9 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
 // again and are absorbed or deposit (privatised LDS grid).  The collision
 // terms of the ledger are added to the row of the k_step workgroup.
 // ---------------------------------------------------------------------------
+// (at most 128 VGPRs: 4 wavefronts per SIMD; it fits without spilling)
 template <int SCHEME, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_collide(Params P)
+__global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
 {
     const CollideWork cw = P.cwork[P.mode + (int)blockIdx.x];
     const int gblk = cw.step_blk;
