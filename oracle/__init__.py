@@ -106,6 +106,8 @@ def lib():
         L.orc_chi_weights_ec2.argtypes = [C.c_int32, C.c_int32, C.c_int64, _D, _D]
         L.orc_gather_mc_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
         L.orc_gather_mc_nu.restype = C.c_double
+        L.orc_gather_ec2_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
+        L.orc_gather_ec2_nu.restype = C.c_double
         L.orc_gather_mc.restype = C.c_double
         L.orc_create.argtypes = [C.POINTER(Case)]
         L.orc_create.restype = C.c_void_p
@@ -228,6 +230,11 @@ def gather_ec2(N, E, xi, periodic=False) -> float:
 def gather_mc_nu(w, E, xi) -> float:
     w, E = _f64(w), _f64(E)
     return lib().orc_gather_mc_nu(w.size, _dp(w), _dp(E), float(xi))
+
+
+def gather_ec2_nu(w, E, xi) -> float:
+    w, E = _f64(w), _f64(E)
+    return lib().orc_gather_ec2_nu(w.size, _dp(w), _dp(E), float(xi))
 
 
 def chi_weights_ec2(N: int, xi, periodic: bool = False) -> np.ndarray:

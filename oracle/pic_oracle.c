@@ -359,6 +359,23 @@ void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* x
 
 static double gather(const orc_sim* s, double xi);
 
+/* Eq. (3) with m = 2 on a nonuniform grid (electrodes): minus the derivative
+ * of the deposit's field energy with respect to the physical position,
+ * (1 / w_c) sum_h (phi_h - phi_{h+1}) S_1(xi - (h + 1/2)) with c the
+ * particle's cell, phi_h - phi_{h+1} = E_{h+1/2} w_h (zero beyond an
+ * electrode). */
+double orc_gather_ec2_nu(int32_t N, const double* w, const double* E, double xi)
+{
+    double k = floor(xi - 0.5);
+    double t = xi - 0.5 - k;
+    int64_t a = (int64_t)k, b = a + 1;
+    double da = (a >= 0 && a < N) ? E[a] * w[a] : 0.0;
+    double db = (b >= 0 && b < N) ? E[b] * w[b] : 0.0;
+    int64_t c = (int64_t)floor(xi);
+    if (c > N - 1) c = N - 1;
+    return ((1.0 - t) * da + t * db) / w[c];
+}
+
 /* Ion subcycling: the time step of species sp in units of dt, and whether
  * the species moves in the current step. */
 static double substep(const orc_sim* s, int sp)
@@ -382,9 +399,10 @@ orc_sim* orc_create(const orc_case* c)
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
     if (c->ion_subcycle < 0 || (c->ion_subcycle > 1 && c->scheme != ORC_EXPLICIT)) return NULL;
     if (c->cell_dx_m) {
-        /* nonuniform grids: EC or MC gather between electrodes, widths
+        /* nonuniform grids: between electrodes (m = 2: explicit), widths
          * summing to L */
-        if (c->gather == ORC_GATHER_EC2 || c->bc != ORC_BC_DIRICHLET) return NULL;
+        if (c->bc != ORC_BC_DIRICHLET) return NULL;
+        if (c->gather == ORC_GATHER_EC2 && c->scheme != ORC_EXPLICIT) return NULL;
         double L = 0.0;
         for (int32_t j = 0; j < c->n_cells; ++j) {
             if (!(c->cell_dx_m[j] > 0.0) || !isfinite(c->cell_dx_m[j])) return NULL;
@@ -967,6 +985,7 @@ static double gather(const orc_sim* s, double xi)
     int periodic = s->c.bc == ORC_BC_PERIODIC;
     if (s->c.gather == ORC_GATHER_MC && s->cw) return orc_gather_mc_nu(N, s->cw, s->E, xi);
     if (s->c.gather == ORC_GATHER_MC) return orc_gather_mc(N, periodic, s->E, xi);
+    if (s->c.gather == ORC_GATHER_EC2 && s->cw) return orc_gather_ec2_nu(N, s->cw, s->E, xi);
     if (s->c.gather == ORC_GATHER_EC2) return orc_gather_ec2(N, periodic, s->E, xi);
     return orc_gather_ec(N, s->E, xi);
 }

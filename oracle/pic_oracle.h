@@ -63,7 +63,7 @@ typedef struct {
     double opal_B_eV;       /* energy-sharing parameter of ionization              */
     uint64_t seed;          /* Philox key                                          */
     /* NULL: N equal cells of L/N.  Otherwise the N cell widths (m, summing to
-     * L; EC or MC gather, electrodes only): a nonuniform grid, finer in the
+     * L; electrodes only, m = 2 explicit only): a nonuniform grid, finer in the
      * sheaths.  Positions stay logical (cell index + offset in the cell). */
     const double* cell_dx_m;
 } orc_case;
@@ -119,6 +119,10 @@ double orc_gather_mc(int32_t N, int32_t periodic, const double* E, double xi);
 /* MC gather on a nonuniform grid of cell widths w[N] (electrodes): linear
  * interpolation of the nodal field (phi_{g-1} - phi_{g+1}) / (w_{g-1} + w_g). */
 double orc_gather_mc_nu(int32_t N, const double* w, const double* E, double xi);
+/* Eq. (3) with m = 2 on a nonuniform grid of widths w[N] (electrodes): minus
+ * the derivative of the quadratic deposit's field energy with respect to the
+ * physical position, (1/w_c) sum_h E_{h+1/2} w_h S_1(xi - (h + 1/2)). */
+double orc_gather_ec2_nu(int32_t N, const double* w, const double* E, double xi);
 /* Eq. (2) with the quadratic spline S_2 (degree 2, support 3 cells): a
  * particle at xi with nearest node i = floor(xi + 1/2) and d = xi - i gives
  * (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2 to nodes i-1, i, i+1.  Nodes

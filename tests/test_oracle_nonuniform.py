@@ -174,7 +174,7 @@ def test_rejects_what_the_grid_does_not_support(orc):
     w = np.full(8, 1e-3)
     base = dict(n_cells=8, gap_m=8e-3, bc=0, scheme=0, gather=0, collisions=0, dt_s=1e-11)
     sps = _two_species(np.array([0.5]), np.zeros(1), 1.0)
-    for bad in (dict(gather=2), dict(bc=1), dict(gap_m=9e-3)):
+    for bad in (dict(gather=2, scheme=1), dict(bc=1), dict(gap_m=9e-3)):
         with pytest.raises(ValueError):
             orc.Sim(dict(base, cell_dx=w, **bad), sps, [])
     with pytest.raises(ValueError):
@@ -235,3 +235,47 @@ def test_mc_susceptibility_of_a_uniform_plasma_is_the_same_on_every_grid(orc):
     sim.compute_fields()
     chi = sim.fields()["chi"]
     np.testing.assert_allclose(chi[1:-1], 0.5 * (wp * dt) ** 2, rtol=1e-9)
+
+
+def test_ec2_gather_is_minus_the_physical_gradient_of_the_deposit_energy(orc):
+    # the energy-conserving pair on a nonuniform grid: with E_{j+1/2} =
+    # (phi_j - phi_{j+1}) / w_j, the gathered field at a particle equals
+    # -d/dX sum_g phi_g w_g(xi(X)), X the physical position (finite
+    # differences of the quadratic deposit's own weights, folded at the
+    # electrodes)
+    rng = np.random.default_rng(8)
+    w = 1e-4 * MULT
+    N = w.size
+    edges = np.concatenate([[0.0], np.cumsum(w)])
+    phi = rng.normal(size=N + 1)
+    Ef = (phi[:-1] - phi[1:]) / w
+
+    def energy(X):
+        c = min(int(np.searchsorted(edges, X, side="right") - 1), N - 1)
+        xi = c + (X - edges[c]) / w[c]
+        return (orc.deposit_quadratic(N, [xi]) * phi).sum()
+    for xi in np.concatenate([rng.uniform(0.05, N - 0.05, 60), [0.3, N - 0.3]]):
+        c = int(np.floor(xi))
+        o = xi - c
+        if min(o, 1 - o) < 1e-3 or abs(o - 0.5) < 1e-3:
+            continue   # keep the difference inside one piece of the weights
+        X = edges[c] + o * w[c]
+        h = 1e-6 * w[c]
+        grad = (energy(X + h) - energy(X - h)) / (2 * h)
+        assert abs(orc.gather_ec2_nu(w, Ef, xi) + grad) < 1e-5 * np.abs(Ef).max()
+
+
+def test_ec2_energy_error_shrinks_like_dt_squared_on_a_nonuniform_grid(orc):
+    errs = []
+    for wdt in (0.3, 0.15, 0.075):
+        case, sps, cell, off, delta, w, dt, wp = cold_nonuniform(wdt, 0)
+        sim = orc.Sim(dict(case, gather=2), sps, [])
+        tot = []
+        for _ in range(int(round(20 / wdt))):
+            sim.step(1)
+            L = sim.ledger()
+            tot.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+        tot = np.array(tot)
+        errs.append(np.abs(tot / tot[0] - 1).max())
+    for a, b in zip(errs, errs[1:]):
+        assert 3.0 <= a / b <= 5.5, errs
