@@ -106,9 +106,11 @@ typedef struct {
     /* NULL: N equal cells of gap_m / N.  Otherwise N cell widths in metres
      * (host memory, read during pic_init only), positive and summing to
      * gap_m within 1e-9: a nonuniform grid, finer in the sheaths (the
-     * multi-scale grid the conclusions propose).  PIC_GATHER_EC or
-     * PIC_GATHER_MC (nodal field: the centred potential difference over the
-     * node's two cells), PIC_BC_DIRICHLET_RF only (else PIC_E_INVAL).
+     * multi-scale grid the conclusions propose).  PIC_BC_DIRICHLET_RF only;
+     * PIC_GATHER_MC takes as nodal field the centred potential difference
+     * over the node's two cells, PIC_GATHER_EC2 (PIC_EXPLICIT only) gathers
+     * minus the physical gradient of the quadratic deposit's field energy
+     * (else PIC_E_INVAL).
      * Positions stay logical
      * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */
     const double* cell_dx_m;

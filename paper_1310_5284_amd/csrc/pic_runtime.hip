@@ -404,7 +404,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
              g.gather != PIC_GATHER_EC2) ||
             g.history_steps < 0 || g.ion_subcycle < 0 || g.ion_subcycle > 4096 ||
             (g.ion_subcycle > 1 && g.scheme != PIC_EXPLICIT) ||
-            (g.cell_dx_m && (g.gather == PIC_GATHER_EC2 || g.bc != PIC_BC_DIRICHLET_RF)) ||
+            (g.cell_dx_m && (g.bc != PIC_BC_DIRICHLET_RF ||
+                             (g.gather == PIC_GATHER_EC2 && g.scheme != PIC_EXPLICIT))) ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
             return bail(PIC_E_INVAL);

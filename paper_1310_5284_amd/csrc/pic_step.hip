@@ -316,6 +316,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             } else {
                 for (int g = tid; g <= N; g += kBlock) eh[g] = nodal_field(ehg, N, periodic, g);
             }
+        } else if (ec2 && nu) {
+            // m = 2 on a nonuniform grid: the potential differences E w_j
+            // (in units of dx) are interpolated, and the result divided by
+            // the width of the particle's cell (minus the physical gradient
+            // of the deposit's field energy)
+            const PIC_GLOBAL float* rg = gp(C->cell_r);
+            for (int j = tid; j < N; j += kBlock) eh[j] = ehg[j] / rg[j];
         } else {
 #pragma unroll 8
             for (int j = tid; j < N; j += kBlock) eh[j] = ehg[j];
@@ -411,7 +418,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             bool live = cc >= 0;
             float a = 0.0f;
             if (live) a = mc ? gather_mc(eh, cc, o[k])
-                             : (ec2 ? gather_ec2(eh, N, periodic, cc, o[k]) : eh[cc]);
+                             : (ec2 ? gather_ec2(eh, N, periodic, cc, o[k]) * (nu ? rl[cc] : 1.0f)
+                                    : eh[cc]);
             float vn, vold, abn = 0.0f, o1, mv;
             if (kImp) {
                 vold = v[k] - 0.5f * ab[k];

@@ -87,9 +87,11 @@ def test_init_rejects_bad_input_without_a_gpu():
     good = (C.c_double * 8)(*([0.01 / 8] * 8))
     for field, value in (("gather", 2), ("bc", 1)):
         setattr(cfg[0], field, value)
+        cfg[0].scheme = 1          # m = 2 on a nonuniform grid: explicit only
         cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
         assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL, field
         setattr(cfg[0], field, 0)
+        cfg[0].scheme = 0
     for widths in ([0.01 / 8] * 7 + [0.0], [0.01 / 7] * 8, [0.02] + [-0.01 / 7] * 7):
         arr = (C.c_double * 8)(*widths)
         cfg[0].cell_dx_m = C.cast(arr, C.POINTER(C.c_double))
