@@ -266,7 +266,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+              "(sharding over several GPUs is designed but not built)", file=sys.stderr)
         sys.exit(2)
 
     import paper_1310_5284_amd as P
