@@ -265,7 +265,7 @@ def main():
                          "omega_p dt = 0.2 (the same time at 0.1 and 0.05)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
               "(sharding over several GPUs is designed but not built)", file=sys.stderr)
         sys.exit(2)
 
