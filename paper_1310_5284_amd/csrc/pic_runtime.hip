@@ -227,7 +227,9 @@ uint32_t candidate_threshold(double pnull)
 }
 
 // k_collide rounds: candidates per thread aimed at, and the most rounds
-constexpr double kCandPerThread = 8.0;
+// (8 and 16 measured slower than 32 on a batch of high-pressure cases, where
+// most particles are candidates; lists of a few % of a tile take one round)
+constexpr double kCandPerThread = 32.0;
 constexpr int kMaxRounds = 32;
 
 int build_work(pic_ctx* c)
