@@ -250,7 +250,7 @@ def main():
                          "off when --tile or --sort-every is given)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="replay whole sort periods from a captured HIP graph")
-    ap.add_argument("--timing-every", type=int, default=8,
+    ap.add_argument("--timing-every", type=int, default=16,
                     help="HIP events around the kernels of every n-th step (they cost "
                          "about 4 us each)")
     ap.add_argument("--no-cpu", action="store_true")
