@@ -71,22 +71,24 @@ class Ledger(C.Structure):
         }
 
 
-# null-collision waiting-time word: count (17 bits) | capped flag
-WAIT_MAX = 0x1FFFF
-WAIT_CAPPED = 0x20000
-
 _lib = None
 _D = C.POINTER(C.c_double)
 _U64 = C.POINTER(C.c_uint64)
 _U32 = C.POINTER(C.c_uint32)
+_I64 = C.POINTER(C.c_int64)
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        # PIC_ORACLE_LIB: another build of the oracle's source (the mutation
+        # test loads copies with planted mistakes this way)
+        path = os.environ.get("PIC_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(path)
         L.orc_philox4x32_10.argtypes = [_U32, _U32, _U32]
         L.orc_u01.argtypes = [C.c_uint32]
         L.orc_u01.restype = C.c_double
@@ -113,7 +115,7 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_species.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
-                                      C.c_double, C.c_int64, _D, _D, _D, _D, _D, _U64, _U32]
+                                      C.c_double, C.c_int64, _D, _D, _D, _D, _D, _U64, _I64]
         L.orc_add_process.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double,
                                       C.c_double, C.c_double, C.c_int32, _D]
         L.orc_prepare.argtypes = [C.c_void_p]
@@ -125,9 +127,11 @@ def lib():
         L.orc_count.restype = C.c_int64
         L.orc_step_index.argtypes = [C.c_void_p]
         L.orc_step_index.restype = C.c_int64
-        L.orc_get_species.argtypes = [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D, _U64, _U32]
-        L.orc_mcc_wait_step.argtypes = [C.c_void_p, C.c_int32, C.c_uint64, C.c_int64, _U32]
+        L.orc_get_species.argtypes = [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D, _U64, _I64]
+        L.orc_mcc_wait_step.argtypes = [C.c_void_p, C.c_int32, C.c_uint64, C.c_int64, _I64]
         L.orc_mcc_wait_step.restype = C.c_int
+        L.orc_mcc_first_wait.argtypes = [C.c_void_p, C.c_int32, C.c_uint64, C.c_int64]
+        L.orc_mcc_first_wait.restype = C.c_int64
         L.orc_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D, _D, _D, _D, _D]
         L.orc_get_ledger.argtypes = [C.c_void_p, C.POINTER(Ledger)]
         L.orc_get_heating.argtypes = [C.c_void_p, _D, _D]
@@ -278,11 +282,11 @@ class Sim:
             ids = np.ascontiguousarray(sp["id"], dtype=np.uint64)
             vx, vy, vz = _f64(sp["vx"]), _f64(sp["vy"]), _f64(sp["vz"])
             wt = sp.get("wait")
-            wt = None if wt is None else np.ascontiguousarray(wt, dtype=np.uint32)
+            wt = None if wt is None else np.ascontiguousarray(wt, dtype=np.int64)
             rc = lib().orc_set_species(self._h, k, sp["q"], sp["m"], sp["w"], n, _dp(xi),
                                        _dp(vx), _dp(vy), _dp(vz), _dp(ab),
                                        ids.ctypes.data_as(_U64),
-                                       None if wt is None else wt.ctypes.data_as(_U32))
+                                       None if wt is None else wt.ctypes.data_as(_I64))
             if rc:
                 raise ValueError("bad species")
         self.q = [sp["q"] for sp in species]
@@ -331,10 +335,10 @@ class Sim:
         n = self.count(sp)
         out = {k: np.zeros(n) for k in ("xi", "vx", "vy", "vz", "abar")}
         ids = np.zeros(n, dtype=np.uint64)
-        wt = np.zeros(n, dtype=np.uint32)
+        wt = np.zeros(n, dtype=np.int64)
         lib().orc_get_species(self._h, sp, _dp(out["xi"]), _dp(out["vx"]), _dp(out["vy"]),
                               _dp(out["vz"]), _dp(out["abar"]), ids.ctypes.data_as(_U64),
-                              wt.ctypes.data_as(_U32))
+                              wt.ctypes.data_as(_I64))
         out["id"] = ids
         out["wait"] = wt
         return out
@@ -358,10 +362,14 @@ class Sim:
         return he, hi
 
     def wait_step(self, sp: int, pid: int, step: int, wait: int):
-        """One step of the candidacy rule: (is_candidate, new wait word)."""
-        w = C.c_uint32(int(wait))
+        """One step of the candidacy rule: (is_candidate, new wait)."""
+        w = C.c_int64(int(wait))
         r = lib().orc_mcc_wait_step(self._h, sp, pid, step, C.byref(w))
         return bool(r), int(w.value)
+
+    def first_wait(self, sp: int, pid: int, step: int) -> int:
+        """The wait of a particle whose first trial is at `step`."""
+        return int(lib().orc_mcc_first_wait(self._h, sp, pid, step))
 
     def collide_one(self, sp: int, pid: int, step: int, v):
         v = _f64(v).copy()

@@ -44,7 +44,7 @@ typedef struct {
     int64_t n, cap;
     double *xi, *vx, *vy, *vz, *abar;
     uint64_t* id;
-    uint32_t* wait;      /* null-collision waiting time (see orc_mcc_wait_step) */
+    int64_t* wait;       /* null-collision waiting time (see orc_mcc_wait_step) */
     int32_t wait_given;  /* waits supplied by the caller (else drawn by prepare) */
 } species_t;
 
@@ -464,13 +464,13 @@ static void species_reserve(species_t* p, int64_t need)
     p->vz = (double*)realloc(p->vz, sizeof(double) * (size_t)cap);
     p->abar = (double*)realloc(p->abar, sizeof(double) * (size_t)cap);
     p->id = (uint64_t*)realloc(p->id, sizeof(uint64_t) * (size_t)cap);
-    p->wait = (uint32_t*)realloc(p->wait, sizeof(uint32_t) * (size_t)cap);
+    p->wait = (int64_t*)realloc(p->wait, sizeof(int64_t) * (size_t)cap);
     p->cap = cap;
 }
 
 int orc_set_species(orc_sim* s, int32_t k, double q, double m, double w, int64_t n,
                     const double* xi, const double* vx, const double* vy, const double* vz,
-                    const double* abar, const uint64_t* id, const uint32_t* wait)
+                    const double* abar, const uint64_t* id, const int64_t* wait)
 {
     if (k < 0 || k > 1 || n < 0 || m <= 0.0) return -1;
     species_t* p = &s->sp[k];
@@ -484,7 +484,7 @@ int orc_set_species(orc_sim* s, int32_t k, double q, double m, double w, int64_t
         p->vz[i] = vz[i];
         p->abar[i] = abar ? abar[i] : 0.0;
         p->id[i] = id[i];
-        p->wait[i] = wait ? wait[i] : 0u;
+        p->wait[i] = wait ? wait[i] : 0;
     }
     p->wait_given = wait != NULL;
     return 0;
@@ -529,54 +529,34 @@ static int beyond_table(const orc_sim* s, int32_t sp, double eps)
 /* carries the number of non-candidate steps left before its next           */
 /* candidacy, W ~ Geo0(P_null), P(W = k) = (1 - P_null)^k P_null, drawn by  */
 /* inversion W = floor(ln u / ln(1 - P_null)) from a uniform u of the       */
-/* particle's Philox stream.  Stored word: count (17 bits) | capped << 17;  */
-/* a draw above the count range is stored as the largest count with the     */
-/* capped flag, and when such a wait runs out the step's trial is drawn     */
-/* afresh (the geometric law is memoryless, so the sequence of trials stays */
-/* Bernoulli).                                                              */
+/* particle's Philox stream.  W is held as a plain integer (a wait longer   */
+/* than 2^63 steps, possible only for P_null below about 2e-18, is held as  */
+/* the largest int64: never reached).                                       */
 /* ------------------------------------------------------------------------ */
-static double geo0(const orc_sim* s, int32_t sp, double u)
+static int64_t geo0(const orc_sim* s, int32_t sp, double u)
 {
-    if (s->pnull[sp] >= 1.0) return 0.0;
-    return floor(log(u) * s->inv_log1mp[sp]);
+    if (s->pnull[sp] >= 1.0) return 0;
+    double W = floor(log(u) * s->inv_log1mp[sp]);
+    return W < 9.0e18 ? (int64_t)W : INT64_MAX;
 }
 
-static uint32_t wait_encode(double W)
-{
-    if (W > (double)ORC_WAIT_MAX) return ORC_WAIT_MAX | ORC_WAIT_CAPPED;
-    return (uint32_t)W;
-}
-
-/* first trial of a particle at step `step`: draw 4 of its stream */
-static uint32_t initial_wait(const orc_sim* s, int32_t sp, uint64_t id, int64_t step)
+int64_t orc_mcc_first_wait(const orc_sim* s, int32_t sp, uint64_t id, int64_t step)
 {
     double u[4];
     draw4(s, sp, id, step, 4, u);
-    return wait_encode(geo0(s, sp, u[0]));
+    return geo0(s, sp, u[0]);
 }
 
-int orc_mcc_wait_step(const orc_sim* s, int32_t sp, uint64_t id, int64_t step, uint32_t* wait)
+int orc_mcc_wait_step(const orc_sim* s, int32_t sp, uint64_t id, int64_t step, int64_t* wait)
 {
-    uint32_t w = *wait;
-    uint32_t cnt = w & ORC_WAIT_MAX;
-    if (cnt > 0) {
-        *wait = (cnt - 1) | (w & ORC_WAIT_CAPPED);
+    if (*wait > 0) {
+        *wait -= 1;
         return 0;
-    }
-    if (w & ORC_WAIT_CAPPED) {
-        /* a capped wait ran out: this step's trial is still open */
-        double u[4];
-        draw4(s, sp, id, step, 4, u);
-        double W = geo0(s, sp, u[0]);
-        if (W >= 1.0) {
-            *wait = wait_encode(W - 1.0);
-            return 0;
-        }
     }
     /* candidate: the next waiting time comes from u0 of draw 0 */
     double u[4];
     draw4(s, sp, id, step, 0, u);
-    *wait = wait_encode(geo0(s, sp, u[0]));
+    *wait = geo0(s, sp, u[0]);
     return 1;
 }
 
@@ -623,7 +603,7 @@ int orc_prepare(orc_sim* s)
         /* particles loaded without waits take their first trial at step0 */
         species_t* q = &s->sp[sp];
         if (!q->wait_given)
-            for (int64_t i = 0; i < q->n; ++i) q->wait[i] = initial_wait(s, sp, q->id[i], s->step);
+            for (int64_t i = 0; i < q->n; ++i) q->wait[i] = orc_mcc_first_wait(s, sp, q->id[i], s->step);
     }
     return 0;
 }
@@ -749,7 +729,7 @@ static void remove_particle(species_t* p, int64_t i)
 }
 
 static void append_particle(species_t* p, double xi, double vx, double vy, double vz,
-                            double abar, uint64_t id, uint32_t wait)
+                            double abar, uint64_t id, int64_t wait)
 {
     species_reserve(p, p->n + 1);
     int64_t i = p->n++;
@@ -927,9 +907,9 @@ static void mcc_species(orc_sim* s, int32_t sp, int64_t n0, int64_t step)
             uint64_t idi = child_id(s, p->id[i], step, 1);
             double x = p->xi[i];
             append_particle(&s->sp[0], x, ve[0], ve[1], ve[2], 0.0, ide,
-                            initial_wait(s, 0, ide, step));
+                            orc_mcc_first_wait(s, 0, ide, step));
             append_particle(&s->sp[1], x, vi[0], vi[1], vi[2], 0.0, idi,
-                            initial_wait(s, 1, idi, step));
+                            orc_mcc_first_wait(s, 1, idi, step));
             s->led.coll_dK[0] += kin(&s->sp[0], ve[0], ve[1], ve[2]);
             s->led.coll_dK[1] += kin(&s->sp[1], vi[0], vi[1], vi[2]);
             s->led.n_created[0]++;
@@ -1136,7 +1116,7 @@ int64_t orc_count(const orc_sim* s, int32_t sp) { return s->sp[sp].n; }
 int64_t orc_step_index(const orc_sim* s) { return s->step; }
 
 void orc_get_species(const orc_sim* s, int32_t sp, double* xi, double* vx, double* vy,
-                     double* vz, double* abar, uint64_t* id, uint32_t* wait)
+                     double* vz, double* abar, uint64_t* id, int64_t* wait)
 {
     const species_t* p = &s->sp[sp];
     for (int64_t i = 0; i < p->n; ++i) {

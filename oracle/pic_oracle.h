@@ -35,11 +35,6 @@ enum { ORC_EXPLICIT = 0, ORC_IMPLICIT = 1 };
 enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1, ORC_GATHER_EC2 = 2 };
 enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONIZATION = 2, ORC_CHARGE_EXCHANGE = 3 };
 
-/* Null-collision waiting time word: count of non-candidate steps left
- * (17 bits) and a flag for a draw that exceeded the count range. */
-#define ORC_WAIT_MAX 0x1FFFFu
-#define ORC_WAIT_CAPPED 0x20000u
-
 typedef struct {
     int32_t n_cells;        /* N cells, N+1 nodes                                  */
     int32_t bc;             /* ORC_BC_*                                            */
@@ -148,12 +143,13 @@ void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* x
 orc_sim* orc_create(const orc_case* c);
 void orc_destroy(orc_sim* s);
 /* species 0 = electrons, 1 = ions.  Arrays are copied.  abar may be NULL;
- * wait (null-collision waiting times) may be NULL: orc_prepare then draws
- * them for a first trial at step0. */
+ * wait (null-collision waiting times: the number of steps, >= 0, before the
+ * particle's next candidacy) may be NULL: orc_prepare then draws them for a
+ * first trial at step0. */
 int orc_set_species(orc_sim* s, int32_t sp, double q, double m, double w, int64_t n,
                     const double* xi, const double* vx, const double* vy,
                     const double* vz, const double* abar, const uint64_t* id,
-                    const uint32_t* wait);
+                    const int64_t* wait);
 /* One collision process on a uniform energy grid e0 + k*de, k = 0..n-1. */
 int orc_add_process(orc_sim* s, int32_t sp, int32_t kind, double threshold_eV,
                     double e0_eV, double de_eV, int32_t n, const double* sigma_m2);
@@ -175,7 +171,7 @@ int orc_step_with_field(orc_sim* s, const double* E);
 int64_t orc_count(const orc_sim* s, int32_t sp);
 int64_t orc_step_index(const orc_sim* s);
 void orc_get_species(const orc_sim* s, int32_t sp, double* xi, double* vx, double* vy,
-                     double* vz, double* abar, uint64_t* id, uint32_t* wait);
+                     double* vz, double* abar, uint64_t* id, int64_t* wait);
 /* Fields of the most recent solve: rho (N+1), phi (N+1), E (N), chi (N),
  * Q per species (N+1, dimensionless deposit), cell counts per species (N). */
 void orc_get_fields(const orc_sim* s, double* rho, double* phi, double* E, double* chi,
@@ -187,11 +183,16 @@ double orc_numax(const orc_sim* s, int32_t sp);
 
 /* ---- collision kernels exposed for the statistical pins ---- */
 /* One step of the candidacy rule of particle id of species sp at `step` with
- * waiting-time word *wait (updated): returns 1 if the particle is a
- * null-collision candidate in this step (the next wait is then drawn from u0
- * of draw 0), else 0.  Each particle is a candidate in each step with
- * probability P_null, independently (Vahedi & Surendra 1995). */
-int orc_mcc_wait_step(const orc_sim* s, int32_t sp, uint64_t id, int64_t step, uint32_t* wait);
+ * waiting time *wait (updated): returns 1 if the particle is a null-collision
+ * candidate in this step (*wait was 0; the next wait is then drawn from u0
+ * of draw 0), else 0 (*wait decremented).  Each particle is a candidate in
+ * each step with probability P_null, independently (Vahedi & Surendra
+ * 1995).  Waits are plain integers with no upper limit. */
+int orc_mcc_wait_step(const orc_sim* s, int32_t sp, uint64_t id, int64_t step, int64_t* wait);
+/* The wait of a particle whose first trial is at `step` (loaded without a
+ * wait, or born by ionization in the step before): Geo0(P_null) from u0 of
+ * draw 4 of its stream at `step`. */
+int64_t orc_mcc_first_wait(const orc_sim* s, int32_t sp, uint64_t id, int64_t step);
 /* Collision of one candidate with velocity v (m/s, in place): draw 0 gives
  * the process (u1) and the scattering angles (u2, u3).  Returns the process
  * kind that happened or -2 (null collision).

@@ -55,23 +55,18 @@ def _pnull(sim, case, sp):
 
 
 def test_waiting_times_are_geometric(orc):
-    # the initial wait W of a particle loaded at step0 is Geo0(P_null):
+    # the first wait W of a particle loaded at step0 is Geo0(P_null):
     # P(W = k) = (1 - p)^k p; checked on the first few k and the mean
     sim, case, procs = beam_sim(orc, p_mtorr=10.0)
     p = _pnull(sim, case, 0)
     assert 0.05 < p < 0.5
     n = 40000
-    ws = []
-    for pid in range(n):
-        cand, w = sim.wait_step(0, pid, 7, orc.WAIT_CAPPED)   # open trial -> fresh draw
-        ws.append(-1 if cand else w + 1)    # -1: candidate now (W = 0)
-    ws = np.array(ws)
+    ws = np.array([sim.first_wait(0, pid, 7) for pid in range(n)])
     for k in range(4):
         pk = (1 - p) ** k * p
-        cnt = int((ws == k).sum()) if k > 0 else int((ws == -1).sum())
+        cnt = int((ws == k).sum())
         assert abs(cnt - n * pk) <= 5 * math.sqrt(n * pk * (1 - pk)), (k, cnt, n * pk)
-    W = np.where(ws < 0, 0, ws)
-    assert abs(W.mean() - (1 - p) / p) <= 5 * math.sqrt((1 - p) / p ** 2 / n)
+    assert abs(ws.mean() - (1 - p) / p) <= 5 * math.sqrt((1 - p) / p ** 2 / n)
 
 
 def test_candidacy_is_bernoulli_per_step(orc):
@@ -82,7 +77,7 @@ def test_candidacy_is_bernoulli_per_step(orc):
     n, T = 3000, 40
     c = np.zeros((n, T), bool)
     for pid in range(n):
-        w = int(orc.WAIT_CAPPED)
+        w = sim.first_wait(0, pid, 100)
         for t in range(T):
             c[pid, t], w = sim.wait_step(0, pid, 100 + t, w)
     rate = c.mean()
@@ -92,7 +87,7 @@ def test_candidacy_is_bernoulli_per_step(orc):
     assert abs(both - p * p) <= 5 * math.sqrt(p * p * (1 - p * p) / (n * (T - 1))) + 1e-4
     # every step is decided by the stream of that step alone: the same
     # particle run twice gives the same sequence
-    w = int(orc.WAIT_CAPPED)
+    w = sim.first_wait(0, 5, 100)
     seq = []
     for t in range(T):
         cand, w = sim.wait_step(0, 5, 100 + t, w)
@@ -100,22 +95,38 @@ def test_candidacy_is_bernoulli_per_step(orc):
     assert np.array_equal(np.array(seq), c[5])
 
 
-def test_capped_wait_counts_down_then_redraws(orc):
+def test_wait_counts_down_and_draws_only_at_zero(orc):
     sim, case, procs = beam_sim(orc, p_mtorr=10.0)
-    cand, w = sim.wait_step(0, 3, 10, orc.WAIT_CAPPED | 2)
-    assert not cand and w == (orc.WAIT_CAPPED | 1)
-    cand, w = sim.wait_step(0, 3, 11, w)
-    assert not cand and w == orc.WAIT_CAPPED
-    # the open trial is Bernoulli(P_null) (the wait law is memoryless)
-    p = _pnull(sim, case, 0)
-    n = 20000
-    hits = sum(sim.wait_step(0, pid, 12, orc.WAIT_CAPPED)[0] for pid in range(n))
-    assert abs(hits - n * p) <= 5 * math.sqrt(n * p * (1 - p))
-    # a plain count decrements and never draws
+    # a positive wait decrements and never draws, whatever its size
     assert sim.wait_step(0, 3, 12, 5) == (False, 4)
     assert sim.wait_step(0, 3, 12, 1) == (False, 0)
+    assert sim.wait_step(0, 3, 12, 10 ** 15) == (False, 10 ** 15 - 1)
+    # zero: a candidate, the next wait drawn from the step's stream
     cand, w = sim.wait_step(0, 3, 12, 0)
-    assert cand and w <= orc.WAIT_MAX
+    assert cand and w >= 0
+    assert sim.wait_step(0, 3, 12, 0) == (True, w)
+
+
+def test_waits_have_no_upper_limit(orc):
+    # at a tiny P_null the geometric waits run to ~1/p and beyond: the wait
+    # law holds far past any fixed word size (mean (1 - p)/p, and the tail
+    # P(W >= k) = (1 - p)^k at k = 2^17 and 2^20)
+    sim, case, procs = beam_sim(orc, p_mtorr=50.0)
+    numax = sim.numax(0)
+    p = 2.0e-6
+    case = dict(case, dt_s=-math.log(1 - p) / numax)
+    sps = W.to_oracle(W.c1(collisions=1, np_per_species=4))[1]
+    sim = orc.Sim(case, sps, procs)
+    assert abs(1 - math.exp(-sim.numax(0) * case["dt_s"]) - p) < 1e-12
+    n = 30000
+    ws = np.array([sim.first_wait(0, pid, 3) for pid in range(n)], dtype=np.float64)
+    mean, sd = (1 - p) / p, math.sqrt(1 - p) / p
+    assert abs(ws.mean() - mean) <= 5 * sd / math.sqrt(n), (ws.mean(), mean)
+    for k in (2 ** 17, 2 ** 20):
+        q = (1 - p) ** k
+        cnt = int((ws >= k).sum())
+        assert abs(cnt - n * q) <= 5 * math.sqrt(n * q * (1 - q)) + 1, (k, cnt, n * q)
+    assert ws.max() > 2 ** 22
 
 
 def test_numax_bounds_every_table_interval(orc):
