@@ -585,7 +585,9 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     gatomic_add(gp(&C->chi_w[s][j]), d & kWMask);
                 }
             }
-            if (DIAG) {
+            // the range covers nodes (up to N for the quadratic deposit);
+            // the heating profile has the N cells only
+            if (DIAG && j < N) {
                 const float h = heat[j];
                 if (h != 0.0f) gatomic_add(gp(&C->heat_acc[s][j]), (double)h * kin_unit);
             }

@@ -13,8 +13,8 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import (FIELD_TOL, POS_TOL, VEL_TOL, compare_fields, compare_particles,
-                    to_oracle_species)
+from parity import (FIELD_TOL, POS_TOL, VEL_TOL, check_children, compare_fields,
+                    compare_particles, to_oracle_species)
 
 pytestmark = pytest.mark.gpu
 
@@ -60,18 +60,23 @@ def sampled_step(ctx, wls, cases, n_sample, seed):
         wl = wls[k]
         c = wl["case"]
         g2 = to_oracle_species(ctx.state(k), wl)
+        errs = [None, None]
         for s in range(2):
             o = sims[k].species(s)
             keep = np.isin(g2[s]["id"], np.concatenate([picked[k][s], o["id"]]))
             g = {key: (v[keep] if isinstance(v, np.ndarray) else v) for key, v in g2[s].items()}
             vr = float(np.sqrt(np.mean(o["vx"] ** 2 + o["vy"] ** 2 + o["vz"] ** 2))) \
                 if o["vx"].size else 0.0
-            err, mism = compare_particles(g, o, c["n_cells"], c.get("bc", 0) == 1, vr)
+            err, mism = compare_particles(g, o, c["n_cells"], c.get("bc", 0) == 1, vr,
+                                          prev_ids=picked[k][s],
+                                          implicit=c.get("scheme", 0) == 1)
+            errs[s] = err
             rep["pos"] = max(rep["pos"], err["pos"])
             rep["vel"] = max(rep["vel"], err["vel"])
             rep["abar"] = max(rep["abar"], err.get("abar", 0.0))
             rep["mismatches"] += mism
             rep["n"] += err["n"]
+        check_children(errs)
     return rep
 
 
