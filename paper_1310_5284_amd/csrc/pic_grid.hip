@@ -242,57 +242,102 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             }
         }
     }
-    block_scan<double, NT>(S, N, red);             // S[j] = R_j
-    double a = 0.0, b = 0.0;
+    // One pass of an associative scan gives every prefix the solve needs.
+    // With sigma_j the charge per area of node j (sigma_0 = 0 stands for the
+    // electrode or the periodic seam), kap_j = eps0 (1 + chi_j), om_j = w_j/dx
+    // and c_j = om_j / kap_j, the running sums over cells k <= j are
+    //   R_j = sum sigma_k,  B_j = sum c_k,  T_j = sum R_k c_k,
+    // and then D_{j+1/2} = D0 + R_j, E_j = (D0 + R_j) / kap_j,
+    // phi_{j+1} = phi_0 - dx (D0 B_j + T_j), with D0 fixed by
+    // dx sum E_j om_j = phi_0 - phi_N: D0 = (V/dx - T_{N-1}) / B_{N-1}.
+    // A run of cells summarises to (R, B, T); a run A followed by a run B
+    // combines to (R_A + R_B, B_A + B_B, T_A + T_B + R_A B_B).  Thread t
+    // takes the kPer cells [t kPer, t kPer + kPer) in order; lanes combine
+    // by shuffles, wavefronts through LDS.
+    constexpr int kWv = NT / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int Kr = (N + NT - 1) / NT;   // cells per thread (<= kPer)
+    const int j0 = tid * Kr;
+    double rs = 0.0, bs = 0.0, ts = 0.0;   // this thread's run
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int j = tid + k * NT;
-        if (j < N) {
-            // om = w_j / dx (exactly 1 on a uniform grid)
+        const int j = j0 + k;
+        if (k < Kr && j < N) {
             const double om = nu ? wjr[j] : 1.0;
-            const double kap = kEps0 * (1.0 + X[j]);
-            a += S[j] * om / kap;
-            b += om / kap;
+            const double c = om / (kEps0 * (1.0 + X[j]));
+            rs += S[j];
+            bs += c;
+            ts += rs * c;
         }
     }
-    a = block_sum<double, NT>(a, red);
-    b = block_sum<double, NT>(b, red);
+    // inclusive scan over the lanes of the wavefront
+    double ri = rs, bi = bs, ti = ts;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double rp = __shfl_up(ri, o, 64), bp = __shfl_up(bi, o, 64),
+                     tp = __shfl_up(ti, o, 64);
+        if (lane >= o) {
+            ti = tp + ti + rp * bi;
+            ri = rp + ri;
+            bi = bp + bi;
+        }
+    }
+    __shared__ double wtot[kWv][3];
+    if (lane == 63) {
+        wtot[wave][0] = ri;
+        wtot[wave][1] = bi;
+        wtot[wave][2] = ti;
+    }
+    // the lanes before this one (exclusive)
+    double re = __shfl_up(ri, 1, 64), be = __shfl_up(bi, 1, 64), te = __shfl_up(ti, 1, 64);
+    if (lane == 0) re = be = te = 0.0;
+    lds_barrier();
+    // the wavefronts before this one, then every wavefront (the totals)
+    double rw = 0.0, bw = 0.0, tw = 0.0, rt = 0.0, bt = 0.0, tt = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWv; ++w) {
+        const double r2 = wtot[w][0], b2 = wtot[w][1], t2 = wtot[w][2];
+        if (w < wave) {
+            tw = tw + t2 + rw * b2;
+            rw += r2;
+            bw += b2;
+        }
+        tt = tt + t2 + rt * b2;
+        rt += r2;
+        bt += b2;
+    }
+    // this thread's starting prefix: the earlier wavefronts, then the
+    // earlier lanes
+    double R = rw + re, B = bw + be, T = tw + te + rw * be;
     double V = 0.0;
     if (!periodic) {
         // V0 sin(2 pi f t) through the phase in cycles reduced to [0, 1)
         const double cyc = Cc.rf_freq * ((double)next_step * Cc.dt);
         V = Cc.rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
     }
-    const double D0 = (V / dx - a) / b;
+    const double D0 = (V / dx - tt) / bt;
+    const double phi0 = periodic ? 0.0 : V;
+    if (tid == 0) gp(Cc.phi)[0] = phi0;
     double we = 0.0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int j = tid + k * NT;
-        if (j < N) {
+        const int j = j0 + k;
+        if (k < Kr && j < N) {
             const double om = nu ? wjr[j] : 1.0;
-            const double E = (D0 + S[j]) / (kEps0 * (1.0 + X[j]));
-            X[j] = E * om;   // X now holds E w_j / dx
+            const double kap = kEps0 * (1.0 + X[j]);
+            const double c = om / kap;
+            R += S[j];
+            B += c;
+            T += R * c;
+            const double E = (D0 + R) / kap;
             gp(Cc.E)[j] = E;
             gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
             gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
+            gp(Cc.phi)[j + 1] = phi0 - dx * (D0 * B + T);
             we += 0.5 * kEps0 * E * E * dx * om;
         }
     }
-    lds_barrier();
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int j = tid + k * NT;
-        if (j < N) S[j] = X[j];
-    }
     we = block_sum<double, NT>(we, red);
-    block_scan<double, NT>(S, N, red);
-    const double phi0 = periodic ? 0.0 : V;
-    if (tid == 0) gp(Cc.phi)[0] = phi0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int j = tid + k * NT;
-        if (j < N) gp(Cc.phi)[j + 1] = phi0 - dx * S[j];
-    }
     if (tid == 0) {
         st->WE[field_step & 1] = we;
         if (!isfinite(we)) atomicOr(&st->flags, 1);
@@ -441,11 +486,9 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
         finish_ledger(C, st, sd, si);
         return;
     }
-    // field of the next step (thread 0 alone reads and writes st->step)
-    __shared__ long long s_step;
-    if (threadIdx.x == 0) s_step = st->step;
-    lds_barrier();
-    const long long next = s_step + 1;
+    // field of the next step (every thread reads st->step; thread 0 writes it
+    // after the solve's last barrier)
+    const long long next = *(volatile long long*)&st->step + 1;
     solve_case<kFinBlock, kDual>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
                                  (double*)smem, red);
     if (threadIdx.x == 0) {
