@@ -271,6 +271,24 @@ int pic_step_implicit(pic_ctx* ctx, int64_t n_steps);
 /* Advance a mixed batch: each case by its own scheme, one launch per step. */
 int pic_step(pic_ctx* ctx, int64_t n_steps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): pic_step
+ * with no allocation of any kind.  Advances every case by n_steps exactly as
+ * pic_step does (same kernels, bitwise the same results), with host launches
+ * only (no graph replay, no timing events; pic_last_timing* then report 0)
+ * and the kernels' per-step scratch -- the ledger partial rows and candidate
+ * counts of every particle-pass workgroup and the compaction's bucket
+ * histograms and cursors -- taken from a fixed device array of 2 MiB per
+ * device instead of the context's buffers.  The array is shared by every
+ * context and call on a device and keeps the last call's contents; calls
+ * that overlap on one device (two host threads, or work on two streams in
+ * flight at once) race on it and must not be made.  Synchronises the
+ * context's stream.  Errors: PIC_E_INVAL if the schedule needs more scratch
+ * than the array holds (rows x 164 bytes + 8 bytes per histogram bucket;
+ * about 10 000 workgroups, i.e. choose a larger tile), or if the context's
+ * device is not current; then those of pic_step. */
+int pic_step_noalloc(pic_ctx* ctx, int64_t n_steps);
+
 /* Synchronises the stream and copies what what_mask asks for, for one case,
  * into the caller's buffers.  Returns PIC_E_CAPACITY if a state buffer is
  * too small (out->n_particles then tells the size needed). */

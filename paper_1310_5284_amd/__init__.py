@@ -115,6 +115,7 @@ def lib():
         L.pic_step_explicit.argtypes = [_P, C.c_int64]
         L.pic_step_implicit.argtypes = [_P, C.c_int64]
         L.pic_step.argtypes = [_P, C.c_int64]
+        L.pic_step_noalloc.argtypes = [_P, C.c_int64]
         L.pic_diagnostics.argtypes = [_P, C.c_int32, C.c_uint32, C.POINTER(Diag)]
         L.pic_set_schedule.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
         L.pic_set_launch.argtypes = [_P, C.c_int32, C.c_int32]
@@ -184,6 +185,12 @@ def pic_step_implicit(h, n):
 
 def pic_step(h, n):
     _ok(h, lib().pic_step(h, int(n)), "pic_step")
+
+
+def pic_step_noalloc(h, n):
+    """pic_step with no allocation: host launches, the per-step scratch in the
+    library's fixed device array."""
+    _ok(h, lib().pic_step_noalloc(h, int(n)), "pic_step_noalloc")
 
 
 def pic_diagnostics(h, case, mask, diag):
@@ -351,6 +358,9 @@ class PicContext:
 
     def step(self, n=1):
         pic_step(self._h, n)
+
+    def step_noalloc(self, n=1):
+        pic_step_noalloc(self._h, n)
 
     def step_explicit(self, n=1):
         pic_step_explicit(self._h, n)

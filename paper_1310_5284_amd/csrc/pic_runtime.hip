@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -126,9 +127,40 @@ struct pic_ctx {
     void* fp64 = nullptr;          // FP64 reference form (pic_fp64.hip)
     std::vector<void*> allocs;     // context-level allocations
     std::vector<std::vector<double>> sigma[2];   // float64 copy of the input tables
+    size_t hist_total = 0;         // compaction histogram words (all cases, species)
+    int device = 0;                // HIP device current at pic_init
+    void* fixed_scratch = nullptr; // this device's address of the fixed scratch array
+    // pic_step_noalloc: the step's scratch (workgroup partials, candidate
+    // counts, compaction histograms and cursors) is taken from the fixed
+    // array while `use_fixed` is set
+    bool use_fixed = false;
+    double* fx_pd = nullptr;
+    unsigned* fx_pu = nullptr;
+    int32_t* fx_cand_n = nullptr;
+    uint32_t* fx_hist = nullptr;
+    uint32_t* fx_cursor = nullptr;
 };
 
+// Fixed scratch of pic_step_noalloc: the per-step scratch of the kernels
+// (ledger partial rows and candidate counts of every k_step workgroup, the
+// compaction's bucket histograms and cursors) for callers that cannot
+// allocate.  One array per device, held until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives on that
+// device (resolve_fixed_scratch).
+constexpr size_t kFixedScratchBytes = (size_t)2 << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_ptr[kMaxDevices] = {};
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = v;
+}
 
 int fail(pic_ctx* c, int code, const std::string& msg)
 {
@@ -166,6 +198,25 @@ int dalloc(pic_ctx* c, std::vector<void*>& list, T** p, size_t n)
     }
     list.push_back(q);
     *p = (T*)q;
+    return PIC_OK;
+}
+
+// The address of this device's fixed scratch array, resolved once per device
+// (with that device current) and kept for every later context on it.
+int resolve_fixed_scratch(pic_ctx* c)
+{
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(c, PIC_E_DEVICE, "device index beyond the fixed-scratch table");
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_fixed_ptr[dev] = ptr;
+    }
+    c->device = dev;
+    c->fixed_scratch = g_fixed_ptr[dev];
     return PIC_OK;
 }
 
@@ -322,12 +373,12 @@ Params params(pic_ctx* c, int mode)
     p.cases = c->d_cases;
     p.state = c->d_state;
     p.work = c->d_work;
-    p.pd = c->d_pd;
-    p.pu = c->d_pu;
+    p.pd = c->use_fixed ? c->fx_pd : c->d_pd;
+    p.pu = c->use_fixed ? c->fx_pu : c->d_pu;
     p.stride = (int32_t)c->work.size();
     p.n_cases = c->n_cases;
     p.mode = mode;
-    p.cand_n = c->d_cand_n;
+    p.cand_n = c->use_fixed ? c->fx_cand_n : c->d_cand_n;
     p.cwork = c->d_cwork;
 
     return p;
@@ -337,12 +388,14 @@ int compaction(pic_ctx* c)
 {
     Params p = params(c, 0);
     size_t l1 = 4 * (size_t)c->maxN, l2 = 8 * (size_t)c->maxN;
+    uint32_t* hist = c->use_fixed ? c->fx_hist : c->d_hist;
+    uint32_t* cursor = c->use_fixed ? c->fx_cursor : c->d_cursor;
     hipLaunchKernelGGL(k_compact_hist, dim3(c->n_blocks), dim3(kBlock), l1, c->stream, p,
-                       c->d_hist, (const int64_t*)c->d_hist_off);
+                       hist, (const int64_t*)c->d_hist_off);
     hipLaunchKernelGGL(k_compact_scan, dim3(2 * c->n_cases), dim3(kBlock), l1, c->stream, p,
-                       c->d_hist, c->d_cursor, (const int64_t*)c->d_hist_off);
+                       hist, cursor, (const int64_t*)c->d_hist_off);
     hipLaunchKernelGGL(k_compact_scatter, dim3(c->n_blocks), dim3(kBlock), l2, c->stream, p,
-                       c->d_cursor, (const int64_t*)c->d_hist_off);
+                       cursor, (const int64_t*)c->d_hist_off);
     hipLaunchKernelGGL(k_compact_finish, dim3(c->n_cases), dim3(kFinBlock), 0, c->stream, p);
     HIPCHK(c, hipGetLastError());
     c->since_sort = 0;
@@ -467,6 +520,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         c->own_stream = true;
     }
     (void)hipGetLastError();   // start from a clean error state
+    if (resolve_fixed_scratch(c)) return bail(PIC_E_DEVICE);
     // ---- per case ----
     size_t hist_total = 0;
     for (int k = 0; k < n_cases; ++k) {
@@ -749,6 +803,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                                    std::max(deposit_lds(c->maxN, c->any_dual), fin_lds(c->maxN)))))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
+    c->hist_total = hist_total;
     if (dalloc(c, c->allocs, &c->d_cases, n_cases) || dalloc(c, c->allocs, &c->d_state, n_cases) ||
         dalloc(c, c->allocs, &c->d_hist, hist_total) ||
         dalloc(c, c->allocs, &c->d_cursor, hist_total) ||
@@ -1034,6 +1089,71 @@ extern "C" int pic_step(pic_ctx* ctx, int64_t n)
 {
     if (!ctx) return PIC_E_INVAL;
     return run_steps(ctx, n, -1);
+}
+
+extern "C" int pic_step_noalloc(pic_ctx* ctx, int64_t n)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, "context failed earlier: " + ctx->err);
+    if (n < 0) return fail(ctx, PIC_E_INVAL, "negative step count");
+    if (!ctx->fixed_scratch) return fail(ctx, PIC_E_STATE, "no fixed scratch on this device");
+    int dev = -1;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    if (dev != ctx->device) return fail(ctx, PIC_E_INVAL, "the context's device is not current");
+    // layout of the step's scratch in the fixed array (256-byte aligned parts)
+    const size_t rows = ctx->work.size();
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = used;
+        used += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_pd = take(sizeof(double) * PD_N * rows);
+    const size_t o_pu = take(sizeof(unsigned) * PU_N * rows);
+    const size_t o_cn = take(sizeof(int32_t) * rows);
+    const size_t o_hist = take(sizeof(uint32_t) * ctx->hist_total);
+    const size_t o_cur = take(sizeof(uint32_t) * ctx->hist_total);
+    if (used > kFixedScratchBytes)
+        return fail(ctx, PIC_E_INVAL,
+                    "pic_step_noalloc: the schedule needs " + std::to_string(used) +
+                        " bytes of scratch (" + std::to_string(rows) +
+                        " workgroups), the fixed array holds " +
+                        std::to_string(kFixedScratchBytes) + " (use a larger tile)");
+    char* base = (char*)ctx->fixed_scratch;
+    ctx->fx_pd = (double*)(base + o_pd);
+    ctx->fx_pu = (unsigned*)(base + o_pu);
+    ctx->fx_cand_n = (int32_t*)(base + o_cn);
+    ctx->fx_hist = (uint32_t*)(base + o_hist);
+    ctx->fx_cursor = (uint32_t*)(base + o_cur);
+    // the histograms must start at zero (every compaction leaves them zero;
+    // an earlier call may have left anything); the partial rows and counts
+    // are written whole by each step's particle pass before they are read
+    if (ctx->hist_total > 0) {
+        const uint32_t nh = (uint32_t)ctx->hist_total;
+        hipLaunchKernelGGL(k_fill_u32, dim3(std::min<uint32_t>((nh + 255) / 256, 1024)),
+                           dim3(256), 0, ctx->stream, ctx->fx_hist, nh, 0u);
+    }
+    ctx->use_fixed = true;
+    int rc = PIC_OK;
+    for (int64_t it = 0; it < n && rc == PIC_OK; ++it) {
+        const bool diag = ctx->diag_every > 0 && (ctx->steps_taken % ctx->diag_every == 0);
+        rc = enqueue_step(ctx, diag, nullptr, false);
+        if (rc == PIC_OK) ctx->steps_taken++;
+    }
+    ctx->use_fixed = false;
+    if (rc != PIC_OK) return rc;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->last_ms = ctx->last_ms_coll = 0.0;
+    ctx->last_launches = ctx->last_launches_coll = 0;
+    // the flags of every case, read without host containers
+    int out = PIC_OK;
+    for (int k = 0; k < ctx->n_cases; ++k) {
+        State st;
+        HIPCHK(ctx, hipMemcpy(&st, ctx->d_state + k, sizeof(State), hipMemcpyDeviceToHost));
+        if (st.flags & 1) return fail(ctx, PIC_E_DIVERGED, "non-finite field or energy");
+        if (st.flags & 2) out = fail(ctx, PIC_E_CAPACITY, "particle capacity exceeded");
+    }
+    return out;
 }
 
 extern "C" int pic_last_timing(const pic_ctx* ctx, double* ms, int64_t* launches)
