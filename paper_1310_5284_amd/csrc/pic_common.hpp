@@ -57,6 +57,18 @@ __device__ __forceinline__ void stg(PIC_GLOBAL T* base, uint32_t byte_off, T v)
 {
     *(PIC_GLOBAL T*)((PIC_GLOBAL char*)base + byte_off) = v;
 }
+// The same with the non-temporal cache policy (scattered accesses that touch
+// a small part of a line).
+template <class T>
+__device__ __forceinline__ T ldg_nt(const PIC_GLOBAL T* base, uint32_t byte_off)
+{
+    return __builtin_nontemporal_load((const PIC_GLOBAL T*)((const PIC_GLOBAL char*)base + byte_off));
+}
+template <class T>
+__device__ __forceinline__ void stg_nt(PIC_GLOBAL T* base, uint32_t byte_off, T v)
+{
+    __builtin_nontemporal_store(v, (PIC_GLOBAL T*)((PIC_GLOBAL char*)base + byte_off));
+}
 
 // The collision record of a particle: id (x, y), vy (z), vz (w).
 __device__ __forceinline__ uint64_t rec_id(u32x4 r) { return (uint64_t)r.x | ((uint64_t)r.y << 32); }

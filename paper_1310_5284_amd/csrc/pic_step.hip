@@ -822,7 +822,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
             // the list carries x_{n+1}; one 16-byte record holds id, vy, vz
             const int32_t w1 = ldg(cq_w, q4);
             if (kImp) o1 = ldg(cq_o, q4);
-            const u32x4 r = ldg((const PIC_GLOBAL u32x4*)recp, i4 << 2);
+            // a candidate's record is one scattered 16-byte read: loaded with
+            // the non-temporal policy, which on gfx950 moves about half the
+            // bytes of a cached line fill for such reads
+            const u32x4 r = ldg_nt((const PIC_GLOBAL u32x4*)recp, i4 << 2);
             id = rec_id(r);
             vy = rec_vy(r);
             vz = rec_vz(r);
