@@ -338,16 +338,24 @@ int pic_autotune(pic_ctx* ctx, const int32_t* tiles, int32_t n_tiles, const int3
 /* Zero the density, heating and EEDF accumulators of every case. */
 int pic_reset_accumulators(pic_ctx* ctx);
 
-/* Plain FP64 GPU form of the same explicit method (fp64 absolute positions
- * and velocities, fp64 global-atomic deposit, no sort, one launch per phase),
- * used as the throughput comparison point.  Advances its own copy of the
- * context's initial state.  Explicit cases with PIC_GATHER_EC or
- * PIC_GATHER_MC on uniform grids without subcycling only (else PIC_E_INVAL). */
+/* Plain FP64 GPU form of the same method (fp64 absolute positions and
+ * velocities, fp64 global-atomic deposit, no sort, one launch per phase),
+ * used as the throughput comparison point: the explicit leap-frog and the D1
+ * direct-implicit scheme (Sec. II schemes (1)-(4); beta = 1/2, the
+ * susceptibility from fp64 cell counts (EC) or node weights (MC)), with the
+ * null-collision MCC of Sec. III.  pic_fp64_reference_init copies the
+ * context's current state (implicit cases: the predicted x~, v~ and abar)
+ * and advances its own copy of it.  Cases with PIC_GATHER_EC or
+ * PIC_GATHER_MC on uniform grids without subcycling only (else PIC_E_INVAL).
+ * pic_fp64_reference_state: live particles, xi in cells, velocities in cells
+ * per step (implicit: the predicted v~).  pic_fp64_reference_ledger: the
+ * energy and particle ledger of the form's last step (as pic_ledger). */
 int pic_fp64_reference_init(pic_ctx* ctx);
 int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
 int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,
                              double* xi, double* vx, double* vy, double* vz, uint64_t* id,
                              int64_t* n_out);
+int pic_fp64_reference_ledger(pic_ctx* ctx, int32_t case_id, pic_ledger* out);
 
 /* Measurement helper, independent of any context: allocates two device
  * buffers of `bytes` (a multiple of 16), copies one into the other `reps`

@@ -127,6 +127,7 @@ def lib():
         L.pic_fp64_reference_step.argtypes = [_P, C.c_int64]
         L.pic_fp64_reference_state.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D,
                                                _D, C.POINTER(C.c_uint64), _I64]
+        L.pic_fp64_reference_ledger.argtypes = [_P, C.c_int32, C.POINTER(Ledger)]
         L.pic_copy_calibration.argtypes = [C.c_int64, C.c_int32, _D]
         L.pic_destroy.argtypes = [_P]
         L.pic_destroy.restype = None
@@ -247,6 +248,14 @@ def pic_fp64_reference_state(h, case, species, cap):
     out = {key: v[:k].copy() for key, v in a.items()}
     out["id"] = ids[:k].copy()
     return out
+
+
+def pic_fp64_reference_ledger(h, case):
+    """The energy and particle ledger of the FP64 form's last step (dict)."""
+    L = Ledger()
+    _ok(h, lib().pic_fp64_reference_ledger(h, int(case), C.byref(L)),
+        "pic_fp64_reference_ledger")
+    return L.as_dict()
 
 
 def pic_copy_calibration(nbytes, reps=10):
@@ -469,6 +478,10 @@ class PicContext:
         if cap is None:
             cap = int(self.counts(case)["n_slots"][species]) * 2 + 1024
         return pic_fp64_reference_state(self._h, case, species, cap)
+
+    def fp64_ledger(self, case=0):
+        """The energy and particle ledger of the FP64 form's last step."""
+        return pic_fp64_reference_ledger(self._h, case)
 
     def density(self, case=0):
         N = self.n_cells[case]
