@@ -259,7 +259,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const int Kr = (N + NT - 1) / NT;   // cells per thread (<= kPer)
     const int j0 = tid * Kr;
     double rs = 0.0, bs = 0.0, ts = 0.0;   // this thread's run
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < kPer; ++k) {
         const int j = j0 + k;
         if (k < Kr && j < N) {
@@ -319,7 +319,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double phi0 = periodic ? 0.0 : V;
     if (tid == 0) gp(Cc.phi)[0] = phi0;
     double we = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < kPer; ++k) {
         const int j = j0 + k;
         if (k < Kr && j < N) {
