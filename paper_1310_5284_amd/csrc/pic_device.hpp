@@ -194,7 +194,8 @@ struct Params {
 };
 
 constexpr int kBoundBins = 256;   // bins of the null-collision bound table
-constexpr int kFinBlock = 1024;   // threads of the per-case finalizing workgroup
+constexpr int kFinBlock = 1024;   // threads of the set-up solve and compaction workgroups
+constexpr int kFinStep = 512;     // threads of a k_finalize workgroup (no register spill)
 constexpr int kILP = 4;           // particles in flight per thread in k_step
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -236,6 +237,9 @@ __host__ __device__ inline CollideLds collide_lds_layout(int N, bool dual)
     L.total = L.eedf + align16(4 * (size_t)kEedfBins);
     return L;
 }
+
+// particles per thread moved together by k_compact_scatter
+constexpr int kScatterILP = 4;
 
 // The susceptibility of the implicit scheme with the m = 2 weighting has a
 // dual grid of its own.

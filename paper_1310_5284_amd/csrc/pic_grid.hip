@@ -466,30 +466,30 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// k_finalize: two workgroups per case after the particle pass, running side
+// k_finalize: two workgroups per case (kFinStep threads) after the particle pass, running side
 // by side: the odd one closes the ledger of the step (reduction of the
 // workgroup partials), the even one solves the FP64 field of the next step.
 // They write disjoint fields of the case state (flags through atomics).
 // ---------------------------------------------------------------------------
 template <bool kDual>
-__global__ __launch_bounds__(kFinBlock) void k_finalize(Params P, int sample)
+__global__ __launch_bounds__(kFinStep) void k_finalize(Params P, int sample)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kFinBlock / 64];
+    __shared__ double red[kFinStep / 64];
     __shared__ double sd[PD_N];
     __shared__ long long si[PU_N];
     Case* C = P.cases + (blockIdx.x >> 1);
     State* st = P.state + (blockIdx.x >> 1);
     if (blockIdx.x & 1) {
         // ledger of the step just taken
-        reduce_partials<kFinBlock>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
+        reduce_partials<kFinStep>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);
         finish_ledger(C, st, sd, si);
         return;
     }
     // field of the next step (every thread reads st->step; thread 0 writes it
     // after the solve's last barrier)
     const long long next = *(volatile long long*)&st->step + 1;
-    solve_case<kFinBlock, kDual>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
+    solve_case<kFinStep, kDual>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
                                  (double*)smem, red);
     if (threadIdx.x == 0) {
         if (sample) st->eedf_samples += 1;
@@ -623,12 +623,19 @@ __global__ __launch_bounds__(kBlock) void k_compact_hist(Params P, uint32_t* his
     chunk = (chunk + 63) & ~63;
     const int start = w.b * chunk, end = min(n, start + chunk);
     int lo = kNoCell, hi = -1;
-    for (int base = start; base < end; base += kBlock) {
-        const int i = base + (int)threadIdx.x;
-        const int c = i < end ? cell_of(cellp[i]) : -1;
-        const int b = c >= 0 ? c >> sh : -1;
-        wave_count_add(lh, b, b >= 0);
-        if (b >= 0) range_note(lo, hi, b);
+    for (int base = start; base < end; base += kBlock * kScatterILP) {
+        int32_t cw[kScatterILP];
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k)
+            cw[k] = cellp[min(base + k * kBlock + (int)threadIdx.x, end - 1)];
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k) {
+            const int i = base + k * kBlock + (int)threadIdx.x;
+            const int c = i < end ? cell_of(cw[k]) : -1;
+            const int b = c >= 0 ? c >> sh : -1;
+            wave_count_add(lh, b, b >= 0);
+            if (b >= 0) range_note(lo, hi, b);
+        }
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
@@ -663,6 +670,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(Params P, uint32_t* his
     if (threadIdx.x == 0) st->sort_live[s] = NB > 0 ? a[NB - 1] : 0;
 }
 
+// The scatter moves kScatterILP particles per thread at a time: their loads
+// are issued together, then their slots are taken (LDS counters of the
+// chunk's runs), then they are stored.
 __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* cursor_all,
                                                             const int64_t* hist_off)
 {
@@ -691,12 +701,19 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     const int start = w.b * chunk, end = min(n, start + chunk);
     const PIC_GLOBAL int32_t* __restrict__ cellp = gp((const int32_t*)S.cell);
     int lo = kNoCell, hi = -1;
-    for (int base = start; base < end; base += kBlock) {
-        const int i = base + (int)threadIdx.x;
-        const int c = i < end ? cell_of(cellp[i]) : -1;
-        const int b = c >= 0 ? c >> sh : -1;
-        wave_count_add(lh, b, b >= 0);
-        if (b >= 0) range_note(lo, hi, b);
+    for (int base = start; base < end; base += kBlock * kScatterILP) {
+        int32_t cw[kScatterILP];
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k)
+            cw[k] = cellp[min(base + k * kBlock + (int)threadIdx.x, end - 1)];
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k) {
+            const int i = base + k * kBlock + (int)threadIdx.x;
+            const int c = i < end ? cell_of(cw[k]) : -1;
+            const int b = c >= 0 ? c >> sh : -1;
+            wave_count_add(lh, b, b >= 0);
+            if (b >= 0) range_note(lo, hi, b);
+        }
     }
     if (hi >= 0) {
         atomicMin(&s_lo, lo);
@@ -720,29 +737,39 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     PIC_GLOBAL u32x4* __restrict__ rec2 = gp(S.rec2);
     PIC_GLOBAL float* __restrict__ ab2 = gp(S.abar2);
     double v2 = 0.0;
-    for (int base = start; base < end; base += kBlock) {
-        const int i = base + (int)threadIdx.x;
-        const int j = min(i, end - 1);
-        const int32_t w0 = cellp[j];
-        const float o = offp[j], vx = vxp[j];
-        const u32x4 rc = recp[j];
-        const float vy = rec_vy(rc), vz = rec_vz(rc);
-        const float ab = imp ? abp[j] : 0.0f;
-        const int c = i < end ? cell_of(w0) : -1;
-        const int b = c >= 0 ? c >> sh : -1;
-        const unsigned r = wave_count_add(lh, b, b >= 0);
-        if (c < 0) continue;
-        const unsigned d = lb[b] + r;
-        cell2[d] = w0;
-        off2[d] = o;
-        vx2[d] = vx;
-        rec2[d] = rc;
-        float vh = vx;
-        if (imp) {
-            ab2[d] = ab;
-            vh = vx - 0.5f * ab;   // v_{n-1/2} from the stored prediction
+    for (int base = start; base < end; base += kBlock * kScatterILP) {
+        int32_t w0[kScatterILP];
+        float o[kScatterILP], vx[kScatterILP], ab[kScatterILP];
+        u32x4 rc[kScatterILP];
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k) {
+            const int j = min(base + k * kBlock + (int)threadIdx.x, end - 1);
+            w0[k] = cellp[j];
+            o[k] = offp[j];
+            vx[k] = vxp[j];
+            rc[k] = recp[j];
+            ab[k] = imp ? abp[j] : 0.0f;
         }
-        v2 += (double)(vh * vh + vy * vy + vz * vz);
+#pragma unroll
+        for (int k = 0; k < kScatterILP; ++k) {
+            const int i = base + k * kBlock + (int)threadIdx.x;
+            const int c = i < end ? cell_of(w0[k]) : -1;
+            const int b = c >= 0 ? c >> sh : -1;
+            const unsigned r = wave_count_add(lh, b, b >= 0);
+            if (c < 0) continue;
+            const unsigned d = lb[b] + r;
+            cell2[d] = w0[k];
+            off2[d] = o[k];
+            vx2[d] = vx[k];
+            rec2[d] = rc[k];
+            float vh = vx[k];
+            if (imp) {
+                ab2[d] = ab[k];
+                vh = vx[k] - 0.5f * ab[k];   // v_{n-1/2} from the stored prediction
+            }
+            const float vy = rec_vy(rc[k]), vz = rec_vz(rc[k]);
+            v2 += (double)(vh * vh + vy * vy + vz * vz);
+        }
     }
     v2 = block_sum(v2, red);
     if (threadIdx.x == 0) {

@@ -952,7 +952,7 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
         }
     }
     hipLaunchKernelGGL(c->any_dual ? k_finalize<true> : k_finalize<false>, dim3(2 * c->n_cases),
-                       dim3(kFinBlock), fin_lds(c->maxN),
+                       dim3(kFinStep), fin_lds(c->maxN),
                        c->stream, params(c, 0), diag ? 1 : 0);
     HIPCHK(c, hipGetLastError());
     if (++c->since_sort >= c->sort_every)
