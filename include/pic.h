@@ -348,13 +348,14 @@ int pic_reset_accumulators(pic_ctx* ctx);
  * and advances its own copy of it.  Cases with PIC_GATHER_EC or
  * PIC_GATHER_MC on uniform grids without subcycling only (else PIC_E_INVAL).
  * pic_fp64_reference_state: live particles, xi in cells, velocities in cells
- * per step (implicit: the predicted v~).  pic_fp64_reference_ledger: the
+ * per step (implicit: the predicted x~ and v~ = v_{n+1/2} + abar/2), abar in
+ * cells per step^2 (0 for explicit cases); any output pointer may be NULL.  pic_fp64_reference_ledger: the
  * energy and particle ledger of the form's last step (as pic_ledger). */
 int pic_fp64_reference_init(pic_ctx* ctx);
 int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps);
 int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t species, int64_t cap,
-                             double* xi, double* vx, double* vy, double* vz, uint64_t* id,
-                             int64_t* n_out);
+                             double* xi, double* vx, double* vy, double* vz, double* abar,
+                             uint64_t* id, int64_t* n_out);
 int pic_fp64_reference_ledger(pic_ctx* ctx, int32_t case_id, pic_ledger* out);
 
 /* Measurement helper, independent of any context: allocates two device

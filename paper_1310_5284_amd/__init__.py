@@ -126,7 +126,7 @@ def lib():
         L.pic_fp64_reference_init.argtypes = [_P]
         L.pic_fp64_reference_step.argtypes = [_P, C.c_int64]
         L.pic_fp64_reference_state.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D,
-                                               _D, C.POINTER(C.c_uint64), _I64]
+                                               _D, _D, C.POINTER(C.c_uint64), _I64]
         L.pic_fp64_reference_ledger.argtypes = [_P, C.c_int32, C.POINTER(Ledger)]
         L.pic_copy_calibration.argtypes = [C.c_int64, C.c_int32, _D]
         L.pic_destroy.argtypes = [_P]
@@ -236,13 +236,14 @@ def pic_fp64_reference_step(h, n):
 
 
 def pic_fp64_reference_state(h, case, species, cap):
-    """Live particles of the FP64 form: xi (cells), v (cells/step), id."""
-    a = {k: np.zeros(cap) for k in ("xi", "vx", "vy", "vz")}
+    """Live particles of the FP64 form: xi (cells), v (cells/step), abar
+    (cells/step^2), id."""
+    a = {k: np.zeros(cap) for k in ("xi", "vx", "vy", "vz", "abar")}
     ids = np.zeros(cap, np.uint64)
     n = C.c_int64()
     _ok(h, lib().pic_fp64_reference_state(
         h, int(case), int(species), int(cap),
-        *(a[k].ctypes.data_as(_D) for k in ("xi", "vx", "vy", "vz")),
+        *(a[k].ctypes.data_as(_D) for k in ("xi", "vx", "vy", "vz", "abar")),
         ids.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n)), "pic_fp64_reference_state")
     k = n.value
     out = {key: v[:k].copy() for key, v in a.items()}

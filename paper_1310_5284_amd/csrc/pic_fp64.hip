@@ -773,7 +773,7 @@ extern "C" int pic_fp64_reference_step(pic_ctx* ctx, int64_t n_steps)
 
 extern "C" int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t s, int64_t cap,
                                         double* xi, double* vx, double* vy, double* vz,
-                                        uint64_t* id, int64_t* n_out)
+                                        double* abar, uint64_t* id, int64_t* n_out)
 {
     if (!ctx || s < 0 || s > 1) return PIC_E_INVAL;
     void** slot = nullptr;
@@ -790,13 +790,14 @@ extern "C" int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t s
         return PIC_E_DEVICE;
     const Species64& S = r->cases_h[case_id].sp[s];
     const size_t n = (size_t)st.n_next[s];
-    std::vector<double> a(n), b(n), c(n), e(n);
+    std::vector<double> a(n), b(n), c(n), e(n), f(n);
     std::vector<uint64_t> ii(n);
     std::vector<int32_t> al(n);
     if (n && (hipMemcpy(a.data(), S.xi, 8 * n, hipMemcpyDeviceToHost) ||
               hipMemcpy(b.data(), S.vx, 8 * n, hipMemcpyDeviceToHost) ||
               hipMemcpy(c.data(), S.vy, 8 * n, hipMemcpyDeviceToHost) ||
               hipMemcpy(e.data(), S.vz, 8 * n, hipMemcpyDeviceToHost) ||
+              hipMemcpy(f.data(), S.abar, 8 * n, hipMemcpyDeviceToHost) ||
               hipMemcpy(ii.data(), S.id, 8 * n, hipMemcpyDeviceToHost) ||
               hipMemcpy(al.data(), S.alive, 4 * n, hipMemcpyDeviceToHost)))
         return PIC_E_DEVICE;
@@ -808,6 +809,7 @@ extern "C" int pic_fp64_reference_state(pic_ctx* ctx, int32_t case_id, int32_t s
             if (vx) vx[k] = b[i];
             if (vy) vy[k] = c[i];
             if (vz) vz[k] = e[i];
+            if (abar) abar[k] = f[i];
             if (id) id[k] = ii[i];
         }
         ++k;

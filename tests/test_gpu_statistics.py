@@ -208,3 +208,48 @@ def test_ec_energy_error_shrinks_like_dt_squared_on_gpu():
     errs = [gpu_thermal(5.0, 0, w)[0] for w in (0.2, 0.1)]
     print("EC energy error", errs)
     assert 3.0 <= errs[0] / errs[1] <= 5.5, errs
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_mixed_path_eedf_matches_fp64_form_at_2048_cells(scheme):
+    # the benchmark discharge itself (2048 cells, 1e7 electrons + 1e7 ions,
+    # 30 mTorr, 300 V): from one state after 300 steps, the float32 / int64
+    # path and the plain FP64 GPU form (explicit, or D1 implicit at the same
+    # dt) each take 300 more steps; their electron energy distributions
+    # (sampled every 30 steps, 0.5 eV bins over 0-128 eV, compared on 1 eV
+    # bins) and mean energies agree to 2 %
+    import paper_1310_5284_amd as P
+    wl = W.c4(np_per_species=10_000_000, scheme=scheme)
+    ctx = P.PicContext([wl])
+    ctx.set_schedule(sort_every=64, diag_every=0, tile=16384)
+    ctx.step(300)
+    ctx.fp64_init()
+    ctx.reset_accumulators()
+    every, T = 30, 300
+    ctx.set_schedule(sort_every=64, diag_every=every, tile=16384)
+    ctx.step(T)
+    eedf_g, bin_eV, samples = ctx.eedf()
+    assert samples == T // every
+    vu = ctx.counts()["vel_unit"]
+    eedf_f = np.zeros(eedf_g.size)
+    for _ in range(T // every):
+        ctx.fp64_step(every)
+        sp = ctx.fp64_state(0, 0)
+        # v_{n+1/2} (the implicit state holds v~ = v_{n+1/2} + abar/2), as the
+        # mixed path samples it
+        vx = sp["vx"] - 0.5 * sp["abar"]
+        eps = 0.5 * ME * vu * vu * (vx ** 2 + sp["vy"] ** 2 + sp["vz"] ** 2) / E
+        b = np.minimum(np.floor(eps / bin_eV).astype(np.int64), eedf_g.size - 1)
+        eedf_f += np.bincount(b, minlength=eedf_g.size)
+    led_g, led_f = ctx.ledger(), ctx.fp64_ledger()
+    ctx.close()
+    pg = eedf_g.reshape(-1, 2).sum(1) / eedf_g.sum()
+    pf = eedf_f.reshape(-1, 2).sum(1) / eedf_f.sum()
+    l1 = np.abs(pg - pf).sum()
+    c = (np.arange(pg.size) + 0.5) * 2 * bin_eV
+    mg, mf = (pg * c).sum(), (pf * c).sum()
+    print(f"2048 cells, scheme {scheme}: EEDF L1 {l1:.4f}, mean energy {mg:.4f} / {mf:.4f} eV; "
+          f"kinetic energy {led_g['K_after'].sum():.5e} / {led_f['K_after'].sum():.5e}")
+    assert l1 < TOL
+    assert abs(mg - mf) / mf < TOL
+    assert abs(led_g["K_after"].sum() - led_f["K_after"].sum()) / led_f["K_after"].sum() < TOL
