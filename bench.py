@@ -192,14 +192,17 @@ def cpu_baseline(wl, steps_budget_s=12.0, frac=0.05, where="the same discharge",
                        f"{ncpu} usable host cores")
 
 
-def drift_table(P, steps):
+def drift_table(P, steps, fp64_steps=0):
     """Total-energy drift of the periodic thermal plasma (512 cells, 1000
     electrons per cell on a fixed neutralising background) on the GPU path,
     EC (m = 1 and m = 2) and MC weightings, dx / lambda_D = 0.5, 5, 20 at omega_p dt = 0.2, and at
     dx = 5 lambda_D also omega_p dt = 0.1 and 0.05 over the same time.  The
     energy at integer steps is the mean of the kinetic energies of the two
     half steps plus the field energy; drift = slope of E / E_0 per step
-    (least squares over about 200 samples), err = max |E / E_0 - 1|."""
+    (least squares over about 200 samples), err = max |E / E_0 - 1|.  With
+    fp64_steps > 0 the plain FP64 GPU form runs the EC and MC rows too, from
+    the same initial state, over fp64_steps steps at omega_p dt = 0.2 (the
+    same time at the smaller steps)."""
     import numpy as np
 
     import workloads as W
@@ -224,15 +227,176 @@ def drift_table(P, steps):
                     xs.append(done)
                     es.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
                 dt_s = time.perf_counter() - t0
-                ctx.close()
                 e = np.array(es) / es[0]
-                rows.append(dict(dx_over_lambda_D=ratio, gather=("EC", "MC", "EC2")[gather],
-                                 omega_p_dt=wdt, steps=n,
-                                 drift_per_step=float(np.polyfit(xs, e, 1)[0]),
-                                 max_rel_err=float(np.abs(e - 1.0).max()),
-                                 steps_per_s=n / dt_s))
+                row = dict(dx_over_lambda_D=ratio, gather=("EC", "MC", "EC2")[gather],
+                           omega_p_dt=wdt, steps=n,
+                           drift_per_step=float(np.polyfit(xs, e, 1)[0]),
+                           max_rel_err=float(np.abs(e - 1.0).max()),
+                           steps_per_s=n / dt_s)
+                if gather != 2 and fp64_steps > 0:
+                    # the plain FP64 GPU form from the same initial state
+                    ctx.close()
+                    ctx = P.PicContext([wl])
+                    ctx.fp64_init()
+                    n64 = int(round(fp64_steps * 0.2 / wdt))
+                    ev64 = max(1, n64 // 200)
+                    xs64, es64 = [], []
+                    done = 0
+                    t0 = time.perf_counter()
+                    while done < n64:
+                        k = min(ev64, n64 - done)
+                        ctx.fp64_step(k)
+                        done += k
+                        L = ctx.fp64_ledger()
+                        xs64.append(done)
+                        es64.append(0.5 * (L["K_before"][0] + L["K_after"][0]) + L["WE"])
+                    t64 = time.perf_counter() - t0
+                    e64 = np.array(es64) / es64[0]
+                    row["fp64"] = dict(steps=n64, drift_per_step=float(np.polyfit(xs64, e64, 1)[0]),
+                                       max_rel_err=float(np.abs(e64 - 1.0).max()),
+                                       steps_per_s=n64 / t64)
+                ctx.close()
+                rows.append(row)
                 log(f"[bench] drift {rows[-1]}")
     return dict(measurement="energy drift, periodic thermal plasma, GPU path", rows=rows)
+
+
+def batch_record(P, steps=256, seq_steps=64):
+    """The 64-case batch (sweep64: 128-1024 cells, 1e4-2e6 particles per
+    species, explicit and implicit mixed) stepped by one context, against the
+    same cases stepped one context after another (the sequential per-case
+    baseline).  Both at tile 16384 and sort period 128, timed over whole sort
+    periods after a warm-up; returns the sub-record of the JSON line."""
+    wls = make_workload("sweep64", 1.0)
+    schemes = [int(w["case"]["scheme"]) for w in wls]
+
+    def run(ctx_wls, n, warm):
+        ctx = P.PicContext(ctx_wls)
+        ctx.set_schedule(sort_every=1, diag_every=0, tile=16384)
+        ctx.set_launch(graph=0, timing_every=0)
+        ctx.step(warm)
+        ctx.set_schedule(sort_every=128 if n % 128 == 0 else n, diag_every=0, tile=16384)
+        live = lambda: [sum(ctx.counts(k)["n"]) for k in range(len(ctx_wls))]
+        a = live()
+        ctx.sync()
+        t0 = time.perf_counter()
+        ctx.step(n)
+        ctx.sync()
+        t = time.perf_counter() - t0
+        b = live()
+        ctx.close()
+        return [0.5 * (x + y) for x, y in zip(a, b)], t
+
+    log("[bench] batch: 64 cases in one context")
+    per, t = run(wls, steps, 64)
+    value = sum(per) * steps / t
+    stream = sum((48.0 if schemes[k] else 40.0) * per[k] for k in range(len(wls))) / sum(per)
+    log("[bench] batch: the same cases one context after another")
+    seq_ps = seq_t = 0.0
+    for k, wl in enumerate(wls):
+        pk, tk = run([wl], seq_steps, 16)
+        seq_ps += pk[0] * seq_steps
+        seq_t += tk
+    seq = seq_ps / seq_t
+    return dict(workload="sweep64", cases=len(wls), particles=int(sum(per)),
+                implicit_cases=int(sum(schemes)), tile=16384, sort_every=128, steps=steps,
+                ms_per_step=t * 1e3 / steps, value=value, unit="particle-steps/s",
+                step_equivalent=dict(bytes_per_particle_step=round(stream, 2),
+                                     GBps=round(value * stream / 1e9, 1),
+                                     frac=round(value * stream / 1e9 / PEAK_HBM_GBS, 4)),
+                sequential=dict(value=seq, steps_per_case=seq_steps,
+                                note="each case alone in its own context, one after another"),
+                speedup_vs_sequential=value / seq)
+
+
+def param_study(P, periods, window=10, ppc=400, scale=1.0):
+    """The paper's parameter study (Sec. III, Table 1 workload), qualitatively:
+    a 1D capacitive discharge in argon-like gas at 50 mTorr, 4 cm gap, 200 V at
+    27 MHz, no secondary emission, initial density 2e16 m^-3 (Te 2 eV, Ti
+    0.026 eV), dt = 1.5e-11 s (2469 steps per RF period), ppc particles per
+    cell and species, on grids of 800, 400, 200, 100 and 64 cells, with the
+    four schemes (momentum- or energy-conserving gather x leap-frog or D1
+    implicit): 20 cases in one batched context.  The synthetic cross sections
+    stand in for the argon data, and the run covers `periods` RF periods
+    instead of the paper's 16-22 thousand, so only the direction of the
+    paper's findings can be checked: growth of the macro-particle count and
+    heating of the electrons where the momentum-conserving gather meets
+    dx > 3 lambda_D, the energy-conserving cases staying bounded, and the
+    trends of the density and of the heating peak with dx.  Returns the
+    per-case histories (per RF period) and window averages."""
+    import numpy as np
+
+    import workloads as W
+    freq, volts, gap, p_mtorr, n0, dt = 27.12e6, 200.0, 0.04, 50.0, 2e16, 1.5e-11
+    per = int(round(1.0 / (freq * dt)))
+    grids = (800, 400, 200, 100, 64)
+    schemes = [("MC", "explicit", 1, 0), ("EC", "explicit", 0, 0),
+               ("MC", "implicit", 1, 1), ("EC", "implicit", 0, 1)]
+    wls, tags = [], []
+    k = 0
+    for gname, sname, gather, scheme in schemes:
+        for N in grids:
+            wl = W.ccp_workload(f"table1_{gname}_{sname}_{N}", n_cells=N,
+                                np_per_species=int(ppc * N * scale), gap_m=gap, volts=volts,
+                                freq=freq, dt=dt, p_mtorr=p_mtorr, n0=n0, Te=2.0,
+                                scheme=scheme, gather=gather, seed=0x7AB1E + k,
+                                capacity_factor=4.0)
+            wls.append(wl)
+            tags.append(dict(gather=gname, scheme=sname, cells=N))
+            k += 1
+    lam = math.sqrt(8.8541878128e-12 * 2.0 / (n0 * 1.602176634e-19))
+    ctx = P.PicContext(wls)
+    ctx.set_schedule(sort_every=64, diag_every=0, tile=16384)
+    ctx.set_launch(graph=0, timing_every=0)
+    hist = [dict(n_e=[], n_i=[], K_e=[]) for _ in wls]
+    t0 = time.perf_counter()
+    for p_ in range(periods):
+        if p_ == periods - window:
+            ctx.reset_accumulators()
+            ctx.set_schedule(sort_every=64, diag_every=1, tile=16384)
+        try:
+            ctx.step(per)
+        except Exception as e:   # a case that outgrew its capacity ends the study
+            log(f"[bench] study stopped after {p_} periods: {e}")
+            break
+        for c in range(len(wls)):
+            cnt = ctx.counts(c)
+            L = ctx.ledger(c)
+            hist[c]["n_e"].append(int(cnt["n"][0]))
+            hist[c]["n_i"].append(int(cnt["n"][1]))
+            hist[c]["K_e"].append(float(L["K_after"][0]))
+        log(f"[bench] study period {p_ + 1}/{periods} ({time.perf_counter() - t0:.0f} s): "
+            + " ".join(str(h["n_e"][-1]) for h in hist))
+    rows = []
+    for c, tag in enumerate(tags):
+        N = tag["cells"]
+        dx = gap / N
+        dens, ns = ctx.density(c)
+        heat = ctx.heating(c)
+        eedf, bin_eV, es = ctx.eedf(c)
+        ne = hist[c]["n_e"]
+        row = dict(tag, dx_over_lambda_D0=round(dx / lam, 2), history=hist[c])
+        if ns > 0:
+            de = np.asarray(dens[0])
+            he = np.asarray(heat[0]) / max(ns * dt, 1e-300)   # W/m^2 per cell
+            x = (np.arange(N) + 0.5) * dx
+            half = N // 2
+            peak = int(np.argmax(he[:half]))
+            pe = eedf.reshape(-1, 2).sum(1).astype(np.float64)
+            pe /= max(pe.sum(), 1.0)
+            row.update(window_periods=window, n_e_peak=float(de.max()),
+                       n_e_centre=float(de[N // 2]),
+                       heating_peak_x_mm=float(x[peak] * 1e3),
+                       absorbed_power_W_m2=float(sum(np.asarray(h).sum() for h in heat)
+                                                 / max(ns * dt, 1e-300)),
+                       mean_electron_eV=float((pe * (np.arange(pe.size) + 0.5) * 2 * bin_eV).sum()))
+        row["growth_e"] = (ne[-1] / ne[0]) if ne and ne[0] else None
+        rows.append(row)
+    ctx.close()
+    return dict(study="Table 1 workload, qualitative (synthetic cross sections)",
+                rf_periods=periods, window_periods=window, steps_per_period=per,
+                lambda_D0_m=lam, ppc=int(ppc * scale), cases=rows,
+                wall_s=time.perf_counter() - t0)
 
 
 def main():
@@ -250,9 +414,16 @@ def main():
                          "off when --tile or --sort-every is given)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="replay whole sort periods from a captured HIP graph")
-    ap.add_argument("--timing-every", type=int, default=16,
-                    help="HIP events around the kernels of every n-th step (they cost "
-                         "about 4 us each)")
+    ap.add_argument("--timing-every", type=int, default=0,
+                    help="HIP events around the kernels of every n-th step of the timed "
+                         "window (they cost about 4 us each; default 0: none there, the "
+                         "kernel durations come from the sample after the window)")
+    ap.add_argument("--sample-steps", type=int, default=64,
+                    help="untimed steps after the timed window with HIP events around "
+                         "every particle and collision kernel (the roofline's durations)")
+    ap.add_argument("--batch", type=int, default=1, choices=(0, 1),
+                    help="also run the 64-case batch (sweep64) and its sequential "
+                         "per-case baseline (default workload only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--fp64-steps", type=int, default=20,
@@ -263,6 +434,11 @@ def main():
                     help="only measure the energy drift of the periodic thermal plasma "
                          "(512 cells, 1000 electrons per cell) over STEPS steps at "
                          "omega_p dt = 0.2 (the same time at 0.1 and 0.05)")
+    ap.add_argument("--study", type=int, default=0, metavar="PERIODS",
+                    help="only run the paper's parameter study (Table 1 workload, grids "
+                         "800-64 x four schemes) for PERIODS RF periods")
+    ap.add_argument("--drift-fp64", type=int, default=0, metavar="STEPS",
+                    help="with --drift: also the plain FP64 GPU form over STEPS steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
@@ -279,7 +455,11 @@ def main():
         return
 
     if args.drift:
-        print(json.dumps(drift_table(P, args.drift)), flush=True)
+        print(json.dumps(drift_table(P, args.drift, args.drift_fp64)), flush=True)
+        return
+
+    if args.study:
+        print(json.dumps(param_study(P, args.study, scale=args.scale)), flush=True)
         return
 
     log(f"[bench] building inputs: {args.workload} scale {args.scale}")
@@ -305,12 +485,6 @@ def main():
                      tile_ms_per_step={str(t): round(m, 4) for t, m in zip(tiles, ms[:6])},
                      sort_ms_per_step={str(t): round(m, 4) for t, m in zip(sorts, ms[6:])})
         log(f"[bench] autotune: tile {tile}, sort every {sort_every}")
-    # event samples every timing_every-th step: with subcycled ions that
-    # period is made coprime to K, so that the samples visit every phase
-    ks = [max(1, int(w["case"].get("ion_subcycle", 0))) for w in wls]
-    while args.timing_every > 1 and any(math.gcd(args.timing_every, k) > 1 for k in ks):
-        args.timing_every += 1
-    ctx.set_launch(graph=args.graph, timing_every=args.timing_every)
     schemes = [int(w["case"]["scheme"]) for w in wls]
     implicit = all(sc == 1 for sc in schemes)
     groups = len(set(schemes))          # one k_step and one k_collide launch per group
@@ -326,6 +500,19 @@ def main():
             out.append(n[0] + n[1] / ksub)
         return out
 
+    def coprime(every):
+        # event samples every `every`-th step: with subcycled ions that
+        # period is made coprime to K, so that the samples visit every phase
+        ks = [max(1, int(w["case"].get("ion_subcycle", 0))) for w in wls]
+        while every > 1 and any(math.gcd(every, k) > 1 for k in ks):
+            every += 1
+        return every
+
+    # The timed window holds whole sort periods, so that it carries its share
+    # of the compaction: the period is the tuned one when it divides the
+    # window, else the largest divisor of the window below it.
+    period = max(d for d in range(1, min(sort_every, args.steps) + 1) if args.steps % d == 0)
+    ctx.set_launch(graph=args.graph, timing_every=0)
     log(f"[bench] warmup {args.warmup} steps")
     done = 0
     while done < args.warmup:
@@ -333,20 +520,50 @@ def main():
         stepper(k)
         done += k
         log(f"[bench] warmup {done}/{args.warmup}")
+    # start the window right after a compaction: one step with a period of 1
+    ctx.set_schedule(sort_every=1, diag_every=0, tile=tile)
+    stepper(1)
+    ctx.set_schedule(sort_every=period, diag_every=0, tile=tile)
+    ctx.set_launch(graph=args.graph, timing_every=coprime(args.timing_every))
     n_before = live_per_case()
     ctx.sync()
-    log(f"[bench] timing {args.steps} steps, {sum(n_before)} particles")
+    log(f"[bench] timing {args.steps} steps ({args.steps // period} sort periods of "
+        f"{period}), {sum(n_before)} particles")
     t0 = time.perf_counter()
     stepper(args.steps)
     ctx.sync()
     t1 = time.perf_counter()
-    kern_ms, launches = ctx.last_timing()
-    coll_ms, coll_launches = ctx.last_timing_collide()
     n_after = live_per_case()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     per_case = [0.5 * (a + b) for a, b in zip(n_before, n_after)]
     particles = sum(per_case)
     value = particles * args.steps / (t1 - t0)
+    # kernel durations: HIP events around every particle and collision kernel
+    # of an untimed sample after the window (the events cost ~4 us each, so
+    # they stay out of the window)
+    ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+    ctx.set_launch(graph=0, timing_every=1)
+    stepper(args.sample_steps)
+    kern_ms, launches = ctx.last_timing()
+    coll_ms, coll_launches = ctx.last_timing_collide()
+    steady = None
+    if period != sort_every:
+        # the same workload over whole periods of the tuned sort period
+        ctx.set_launch(graph=args.graph, timing_every=0)
+        ctx.set_schedule(sort_every=1, diag_every=0, tile=tile)
+        stepper(1)
+        ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
+        nb = sum(live_per_case())
+        ctx.sync()
+        n_st = 2 * sort_every
+        s0 = time.perf_counter()
+        stepper(n_st)
+        ctx.sync()
+        s1 = time.perf_counter()
+        na = sum(live_per_case())
+        steady = dict(sort_every=sort_every, steps=n_st,
+                      ms_per_step=(s1 - s0) * 1e3 / n_st,
+                      value=0.5 * (nb + na) * n_st / (s1 - s0))
 
     # algorithmic bytes of one step from the particles and the candidates and
     # collisions of the last step (ledger); per launch = per step / groups
@@ -361,7 +578,7 @@ def main():
         step_bytes += PASS_BYTES[sc] * per_case[k] + LIST_BYTES[sc] * ck
         coll_step_bytes += COLLIDE_BYTES[sc] * ck + COLLISION_BYTES[sc] * rk
     if launches == 0:
-        log("[bench] no timed launch in the timed steps (see --timing-every)")
+        log("[bench] no timed launch in the sample (see --sample-steps)")
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     alg_bytes = step_bytes / groups
     achieved = alg_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
@@ -372,7 +589,10 @@ def main():
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
                 kernel=kname, avg_launch_ms=round(avg_launch_s * 1e3, 4),
-                timed_launches=launches, alg_bytes_per_launch=int(alg_bytes),
+                timed_launches=launches,
+                timed_in="untimed sample of %d steps after the window, events around "
+                         "every launch" % args.sample_steps,
+                alg_bytes_per_launch=int(alg_bytes),
                 alg_bytes_rule=rule)
     coll_avg_s = coll_ms / 1e3 / max(coll_launches, 1)
     coll_bytes = coll_step_bytes / groups
@@ -407,11 +627,15 @@ def main():
                            particles=int(particles), tile=tile, sort_every=sort_every,
                            scheme=("explicit", "implicit", "mixed")[
                                2 if groups == 2 else schemes[0]],
-                           graph=args.graph, timing_every=args.timing_every),
+                           graph=args.graph, timing_every=args.timing_every,
+                           window_sort_every=period,
+                           window_sort_periods=args.steps // period),
                roofline=roof, collide=collide)
+    if steady:
+        out["steady_state"] = steady
     if tuned:
         out["autotune"] = tuned
-    if args.fp64_steps > 0 and all(sc == 0 for sc in schemes) and \
+    if args.fp64_steps > 0 and \
             all(w["case"].get("gather", 0) != 2 and w["case"].get("cell_dx") is None and
                 w["case"].get("ion_subcycle", 0) <= 1 for w in wls):
         # the plain FP64 GPU form of the same method, from the same state
@@ -427,9 +651,11 @@ def main():
                                     ms_per_step=(t1 - t0) * 1e3 / args.fp64_steps,
                                     steps=args.fp64_steps)
         out["speedup_vs_fp64_form"] = value / v64
+    ctx.close()
+    if args.batch and args.workload == "ccp2048_explicit" and args.scale == 1.0:
+        out["batched"] = batch_record(P)
     if cpu is not None:
         out["cpu_baseline"] = cpu
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
