@@ -313,7 +313,7 @@ def param_study(P, periods, window=10, ppc=400, scale=1.0):
     """The paper's parameter study (Sec. III, Table 1 workload), qualitatively:
     a 1D capacitive discharge in argon-like gas at 50 mTorr, 4 cm gap, 200 V at
     27 MHz, no secondary emission, initial density 2e16 m^-3 (Te 2 eV, Ti
-    0.026 eV), dt = 1.5e-11 s (2469 steps per RF period), ppc particles per
+    0.026 eV), dt = 1.5e-11 s (2458 steps per RF period), ppc particles per
     cell and species, on grids of 800, 400, 200, 100 and 64 cells, with the
     four schemes (momentum- or energy-conserving gather x leap-frog or D1
     implicit): 20 cases in one batched context.  The synthetic cross sections

@@ -152,9 +152,34 @@ __device__ __forceinline__ uint64_t child_id(uint64_t parent, uint32_t step, uin
 
 // ---------------------------------------------------------------------------
 // Particle cell word: bit 31 set (negative) for an empty slot, else the cell
-// index in bits 0..12 and the null-collision waiting-time word (count in 17
-// bits | capped flag, PIC_WAIT_*) in bits 13..30.
+// index in bits 0..12 and the null-collision waiting-time field in bits
+// 13..30: 17 bits of expiry and the capped flag (PIC_WAIT_CAPPED).
+//
+// The field holds the value of the species' clock at which the particle's
+// count of non-candidate steps reaches zero, modulo 2^17: count =
+// (expiry - clock) mod 2^17.  The clock counts the steps in which the
+// species takes collision trials (every step; subcycled ions every K-th,
+// n / K; none, and the clock stands at 0, when the species has no
+// collision process or collisions are off).  The count thus falls by one
+// per trial step without the word being rewritten, and a particle's word
+// changes only when its cell does or at a candidacy.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t wait_count(uint32_t field, uint32_t clock)
+{
+    return (field - clock) & PIC_WAIT_MAX;
+}
+// The field of a count | capped code valid at the given clock.
+__host__ __device__ inline uint32_t wait_field(uint32_t clock, uint32_t code)
+{
+    return ((clock + (code & PIC_WAIT_MAX)) & PIC_WAIT_MAX) | (code & PIC_WAIT_CAPPED);
+}
+// The species' clock of the first step at or after `step` in which it takes
+// trials (trials: whether it takes any).
+__host__ __device__ inline uint32_t clock_from(long long step, int ksub, bool trials)
+{
+    if (!trials) return 0u;
+    return (uint32_t)(ksub > 1 ? (step + ksub - 1) / ksub : step);
+}
 constexpr int kCellBits = 13;
 constexpr int32_t kCellMask = (1 << kCellBits) - 1;
 

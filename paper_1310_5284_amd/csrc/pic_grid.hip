@@ -522,6 +522,9 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
     // without them, collisions on)
     const bool draw = ((P.mode >> (3 + w.s)) & 1) && C->collisions && S.n_proc > 0;
     const uint32_t step32 = (uint32_t)st->step;
+    // the clock of the species' first move (drawn waits count from it)
+    const uint32_t clk0 = clock_from(st->step, w.s == 1 ? C->ion_sub : 1,
+                                     C->collisions && S.n_proc > 0);
     for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
         if (convert) {
             S.vx[i] = (float)((double)S.vx[i] * vs);
@@ -537,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
             const uint64_t id = rec_id(S.rec[i]);
             const uint4 r4 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
                                     ((uint32_t)w.s << 28) | 4u, C->key0, C->key1);
-            wt = wait_encode(geo0(r4.x, S.inv_log1mp));
+            wt = wait_field(clk0, wait_encode(geo0(r4.x, S.inv_log1mp)));
         }
         float o = S.off[i];
         if (startup) {

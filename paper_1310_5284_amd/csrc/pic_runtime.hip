@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "pic.h"
+#include "pic_common.hpp"
 #include "pic_device.hpp"
 
 namespace pic {
@@ -739,7 +740,10 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
                                     k, s, i);
                             return bail(PIC_E_INVAL);
                         }
-                        cc[i] |= (int32_t)(ww[i] << kCellWordBits);
+                        // count at the species' first move -> expiry field
+                        const int ks = s == 1 ? std::max(1, (int)g.ion_subcycle) : 1;
+                        const uint32_t clk = clock_from(g.start_step, ks, S.n_proc > 0);
+                        cc[i] |= (int32_t)(wait_field(clk, ww[i]) << kCellWordBits);
                     }
                     INITCHK(hipMemcpy(S.cell, cc.data(), 4 * n, hipMemcpyHostToDevice));
                 }
@@ -1396,11 +1400,16 @@ extern "C" int pic_diagnostics(pic_ctx* ctx, int32_t case_id, uint32_t what, pic
             }
             std::vector<uint32_t> wt(ns);
             size_t k = 0;
+            // waiting-time fields are expiries of the species' clock: the
+            // count left at its next move, with the capped flag
+            const int ks = s == 1 ? std::max(1, (int)C.ion_sub) : 1;
+            const uint32_t clk = clock_from(st.step, ks, S.n_proc > 0);
             for (size_t i = 0; i < ns; ++i) {
                 if (cell[i] < 0) continue;
                 const int32_t word = cell[i];
                 cell[k] = word & ((1 << kCellWordBits) - 1);
-                wt[k] = (uint32_t)word >> kCellWordBits;
+                const uint32_t f = (uint32_t)word >> kCellWordBits;
+                wt[k] = wait_count(f, clk) | (f & PIC_WAIT_CAPPED);
                 off[k] = off[i]; vx[k] = vx[i]; vy[k] = vy[i];
                 vz[k] = vz[i]; ab[k] = ab[i]; id[k] = id[i];
                 ++k;

@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const int ksub = s == 1 ? C->ion_sub : 1;
     const bool stands = ksub > 1 && (st->step % ksub) != 0;
     const float kf = (float)ksub;
+    const uint32_t clk = clock_from(st->step, ksub, coll);   // the species' clock
     const int end = stands ? start : min(n, start + chunk);
 
     double work = 0.0;
@@ -458,14 +459,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             // null-collision candidacy by waiting time: a count above zero is
             // a non-candidate step; at zero the particle is a candidate (or,
             // for a capped wait, its trial is still open: decided by k_collide)
-            bool isc = false;
-            if (live && coll) {
-                const uint32_t cnt = wt & PIC_WAIT_MAX;
-                if (cnt > 0) wt = (cnt - 1) | (wt & PIC_WAIT_CAPPED);
-                else isc = true;
-            }
+            const bool isc = live && coll && wait_count(wt, clk) == 0u;
             // non-candidates finish here; candidates store x_{n+1} (final
-            // for the explicit scheme, which deposits it now)
+            // for the explicit scheme, which deposits it now) but not their
+            // cell word, which k_collide writes with the next waiting time
             int c2 = c1;
             float o2 = o1, vst = vn;
             bool dep_now = false;
@@ -483,7 +480,9 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     }
                 }
                 if (live) {
-                    stg(cellp, i4, pack_cell(c2, wt));
+                    // the word changes only with the cell (the waiting-time
+                    // field is an expiry)
+                    if (c2 != cc) stg(cellp, i4, pack_cell(c2, wt));
                     stg(offp, i4, o2);
                     stg(vxp, i4, vst);
                     if (kImp) stg(abp, i4, abn);
@@ -514,7 +513,6 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                         if (cp < 0) cp += N;
                     }
                     if (cp >= 0 && cp < N) {
-                        stg(cellp, i4, pack_cell(cp, wt));
                         stg(offp, i4, op);
                         stg(vxp, i4, vp);
                         stg(abp, i4, abn);
@@ -525,7 +523,6 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     }
                 }
                 if (!kept) {
-                    stg(cellp, i4, pack_cell(c1, wt));
                     stg(offp, i4, o1);
                     // explicit: v_{n+1/2} stands unless k_collide finds a
                     // real collision (the store joins the coalesced stream)
@@ -551,7 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     const uint32_t e4 = (uint32_t)e << 2;
                     stg(cq_idx, e4, i);
                     stg(cq_vn, e4, vn);
-                    stg(cq_w, e4, pack_cell(c1, wt | lflag));
+                    // the list word carries the capped flag and the
+                    // prediction flag in its waiting-time field
+                    stg(cq_w, e4, pack_cell(c1, (wt & PIC_WAIT_CAPPED) | lflag));
                     if (kImp) {
                         stg(cq_ab, e4, abn);
                         stg(cq_o, e4, o1);
@@ -711,6 +710,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     lds_barrier();
 
     const uint32_t step32 = (uint32_t)st->step;
+    // the species' clock after this step, and the children's clocks
+    const int ksub = s == 1 ? C->ion_sub : 1;
+    // (k_collide runs only for species with trials; an ion species without a
+    // process keeps its clock at 0)
+    const uint32_t clk1 = clock_from(st->step, ksub, true) + 1u;
+    const uint32_t clk_e = clock_from(st->step + 1, 1, true),
+                   clk_i = clock_from(st->step + 1, C->ion_sub, C->sp[1].n_proc > 0);
     const int ns0 = st->n_slots[0], ns1 = st->n_slots[1];
     const int n = st->n_slots[s];
     int chunk = (n + w.nb - 1) / w.nb;
@@ -781,7 +787,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                 const uint4 r4 = philox((uint32_t)ch.ide, (uint32_t)(ch.ide >> 32), step32,
                                         4u, k0, k1);
                 write_particle(C->sp[0], se, ce, oe, ch.vx, ch.vy, ch.vz, ch.ide,
-                               wait_encode(geo0(r4.x, S.inv_log1mp)), kImp);
+                               wait_field(clk_e, wait_encode(geo0(r4.x, S.inv_log1mp))), kImp);
                 deposit_global(C, 0, ce, oe);
             } else {
                 atomicAdd(&acc.n_lost[0], 1u);
@@ -792,7 +798,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                 const uint4 r4 = philox((uint32_t)ch.idi, (uint32_t)(ch.idi >> 32), step32,
                                         (1u << 28) | 4u, k0, k1);
                 write_particle(C->sp[1], si, ci, oi, ch.ix, ch.iy, ch.iz, ch.idi,
-                               wait_encode(geo0(r4.x, inv_ion)), kImp);
+                               wait_field(clk_i, wait_encode(geo0(r4.x, inv_ion))), kImp);
                 deposit_global(C, 1, ci, oi);
             } else {
                 atomicAdd(&acc.n_lost[1], 1u);
@@ -841,14 +847,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                 const double W = geo0(r4.x, S.inv_log1mp);
                 if (W >= 1.0) {
                     is_cand = false;
-                    nw = wait_encode(W - 1.0);
+                    nw = wait_field(clk1, wait_encode(W - 1.0));
                 }
             }
             if (is_cand) {
                 const uint4 r0 = philox((uint32_t)id, (uint32_t)(id >> 32), step32,
                                         (uint32_t)s << 28, k0, k1);
                 ++cand;
-                nw = wait_encode(geo0(r0.x, S.inv_log1mp));
+                nw = wait_field(clk1, wait_encode(geo0(r0.x, S.inv_log1mp)));
                 bool over = false;
                 kind = s == 0 ? collide_electron(S, lbound, r0, id, step32, k0, k1, vn, vy, vz,
                                                  over, ch)
