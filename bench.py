@@ -403,7 +403,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     # about 2000 steps (autotuning trials included) before the timed window
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2048)
     ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--workload", default="ccp2048_explicit")
     ap.add_argument("--scale", type=float, default=1.0)
@@ -508,10 +508,11 @@ def main():
             every += 1
         return every
 
-    # The timed window holds whole sort periods, so that it carries its share
-    # of the compaction: the period is the tuned one when it divides the
-    # window, else the largest divisor of the window below it.
-    period = max(d for d in range(1, min(sort_every, args.steps) + 1) if args.steps % d == 0)
+    # The timed window runs at the tuned sort period; the default K (2048, a
+    # multiple of every period the autotuner tries) makes it whole periods,
+    # so that it carries its share of the compaction.
+    period = sort_every
+    steps = args.steps
     ctx.set_launch(graph=args.graph, timing_every=0)
     log(f"[bench] warmup {args.warmup} steps")
     done = 0
@@ -527,17 +528,17 @@ def main():
     ctx.set_launch(graph=args.graph, timing_every=coprime(args.timing_every))
     n_before = live_per_case()
     ctx.sync()
-    log(f"[bench] timing {args.steps} steps ({args.steps // period} sort periods of "
+    log(f"[bench] timing {steps} steps ({steps // period} sort periods of "
         f"{period}), {sum(n_before)} particles")
     t0 = time.perf_counter()
-    stepper(args.steps)
+    stepper(steps)
     ctx.sync()
     t1 = time.perf_counter()
     n_after = live_per_case()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
     per_case = [0.5 * (a + b) for a, b in zip(n_before, n_after)]
     particles = sum(per_case)
-    value = particles * args.steps / (t1 - t0)
+    value = particles * steps / (t1 - t0)
     # kernel durations: HIP events around every particle and collision kernel
     # of an untimed sample after the window (the events cost ~4 us each, so
     # they stay out of the window)
@@ -546,24 +547,6 @@ def main():
     stepper(args.sample_steps)
     kern_ms, launches = ctx.last_timing()
     coll_ms, coll_launches = ctx.last_timing_collide()
-    steady = None
-    if period != sort_every:
-        # the same workload over whole periods of the tuned sort period
-        ctx.set_launch(graph=args.graph, timing_every=0)
-        ctx.set_schedule(sort_every=1, diag_every=0, tile=tile)
-        stepper(1)
-        ctx.set_schedule(sort_every=sort_every, diag_every=0, tile=tile)
-        nb = sum(live_per_case())
-        ctx.sync()
-        n_st = 2 * sort_every
-        s0 = time.perf_counter()
-        stepper(n_st)
-        ctx.sync()
-        s1 = time.perf_counter()
-        na = sum(live_per_case())
-        steady = dict(sort_every=sort_every, steps=n_st,
-                      ms_per_step=(s1 - s0) * 1e3 / n_st,
-                      value=0.5 * (nb + na) * n_st / (s1 - s0))
 
     # algorithmic bytes of one step from the particles and the candidates and
     # collisions of the last step (ledger); per launch = per step / groups
@@ -629,10 +612,8 @@ def main():
                                2 if groups == 2 else schemes[0]],
                            graph=args.graph, timing_every=args.timing_every,
                            window_sort_every=period,
-                           window_sort_periods=args.steps // period),
+                           window_sort_periods=round(steps / period, 3)),
                roofline=roof, collide=collide)
-    if steady:
-        out["steady_state"] = steady
     if tuned:
         out["autotune"] = tuned
     if args.fp64_steps > 0 and \
