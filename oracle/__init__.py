@@ -106,6 +106,9 @@ def lib():
         L.orc_gather_ec2.argtypes = [C.c_int32, C.c_int32, _D, C.c_double]
         L.orc_gather_ec2.restype = C.c_double
         L.orc_chi_weights_ec2.argtypes = [C.c_int32, C.c_int32, C.c_int64, _D, _D]
+        L.orc_chi_operator_ec2.argtypes = [C.c_int32, C.c_int32, C.c_int64, _D, _D, _D]
+        L.orc_solve_chi_tridiag.argtypes = [C.c_int32, C.c_int32, C.c_double, _D, _D, _D,
+                                            C.c_double, _D, _D]
         L.orc_gather_mc_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
         L.orc_gather_mc_nu.restype = C.c_double
         L.orc_gather_ec2_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
@@ -246,6 +249,26 @@ def chi_weights_ec2(N: int, xi, periodic: bool = False) -> np.ndarray:
     w = np.zeros(N)
     lib().orc_chi_weights_ec2(N, int(periodic), xi.size, _dp(xi), _dp(w))
     return w
+
+
+def chi_operator_ec2(N: int, xi, periodic: bool = False):
+    """The m = 2 susceptibility operator (orc_chi_operator_ec2): its
+    diagonal and its couplings of centres j, j + 1 (the last: the wrap)."""
+    xi = _f64(xi)
+    d, o = np.zeros(N), np.zeros(N)
+    lib().orc_chi_operator_ec2(N, int(periodic), xi.size, _dp(xi), _dp(d), _dp(o))
+    return d, o
+
+
+def solve_chi_tridiag(N: int, dx: float, rho, xd, xo, phi0: float = 0.0,
+                      periodic: bool = False):
+    """Field solve with a tridiagonal susceptibility (orc_solve_chi_tridiag):
+    returns (phi, E)."""
+    rho, xd, xo = _f64(rho), _f64(xd), _f64(xo)
+    phi, E = np.zeros(N + 1), np.zeros(N)
+    lib().orc_solve_chi_tridiag(N, int(periodic), dx, _dp(rho), _dp(xd), _dp(xo), phi0,
+                                _dp(phi), _dp(E))
+    return phi, E
 
 
 # ---------------------------------------------------------------------------

@@ -60,7 +60,10 @@ struct orc_sim {
     double inv_log1mp[2];  /* 1 / ln(1 - P_null) */
     /* fields of the most recent solve */
     double *rho, *phi, *E, *chi, *Q[2], *cnt[2];
-    double* chw[2];        /* m = 2 implicit: susceptibility weights of the centres */
+    double* chw[2];        /* m = 2 implicit: the operator's diagonal (uniform grid) or its
+                              row sums (nonuniform grid) per centre */
+    double* cho[2];        /* m = 2 implicit: the operator's coupling of centres j, j+1 */
+    double *xd, *xo;       /* m = 2 implicit: the scaled operator (sum over species) */
     double *cw, *edge;     /* nonuniform grid: cell widths, node positions (m)  */
     double* sigma;         /* nonuniform grid: node charge per area (C/m^2)     */
     double* heat[2];
@@ -357,6 +360,129 @@ void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* x
     }
 }
 
+/* The tridiagonal operator of the m = 2 direct-implicit scheme (see the
+ * header): the S_1 weights of each particle on its two centres, multiplied
+ * pairwise. */
+void orc_chi_operator_ec2(int32_t N, int32_t periodic, int64_t n, const double* xi,
+                          double* diag, double* off)
+{
+    memset(diag, 0, sizeof(double) * (size_t)N);
+    memset(off, 0, sizeof(double) * (size_t)N);
+    for (int64_t p = 0; p < n; ++p) {
+        double k = floor(xi[p] - 0.5);
+        double t = xi[p] - 0.5 - k;
+        int64_t a = (int64_t)k, b = a + 1;
+        double wa = 1.0 - t, wb = t;
+        if (periodic) {
+            a = ((a % N) + N) % N;
+            b = ((b % N) + N) % N;
+        }
+        int ina = periodic || (a >= 0 && a < N);
+        int inb = periodic || (b >= 0 && b < N);
+        if (ina) diag[a] += wa * wa;
+        if (inb) diag[b] += wb * wb;
+        if (ina && inb) off[a] += wa * wb;
+    }
+}
+
+/* Solve (1 + X) y = r for two right-hand sides r0, r1 (tridiagonal X as
+ * in orc_solve_chi_tridiag).  Dirichlet: the Thomas algorithm; periodic:
+ * Gaussian elimination with partial pivoting of the dense matrix. */
+static void solve_one_plus_x(int32_t N, int32_t periodic, const double* xd, const double* xo,
+                             const double* r0, const double* r1, double* y0, double* y1)
+{
+    if (!periodic) {
+        double* cp = (double*)malloc(sizeof(double) * (size_t)N);
+        double* d0 = (double*)malloc(sizeof(double) * (size_t)N);
+        double* d1 = (double*)malloc(sizeof(double) * (size_t)N);
+        for (int32_t j = 0; j < N; ++j) {
+            double a = j > 0 ? xo[j - 1] : 0.0;          /* below the diagonal */
+            double b = 1.0 + xd[j];
+            double c = j < N - 1 ? xo[j] : 0.0;          /* above the diagonal */
+            double den = j > 0 ? b - a * cp[j - 1] : b;
+            cp[j] = c / den;
+            d0[j] = (r0[j] - (j > 0 ? a * d0[j - 1] : 0.0)) / den;
+            d1[j] = (r1[j] - (j > 0 ? a * d1[j - 1] : 0.0)) / den;
+        }
+        y0[N - 1] = d0[N - 1];
+        y1[N - 1] = d1[N - 1];
+        for (int32_t j = N - 2; j >= 0; --j) {
+            y0[j] = d0[j] - cp[j] * y0[j + 1];
+            y1[j] = d1[j] - cp[j] * y1[j + 1];
+        }
+        free(cp); free(d0); free(d1);
+        return;
+    }
+    const size_t n = (size_t)N, w = n + 2;   /* rows of [A | r0 r1] */
+    double* A = (double*)calloc(n * w, sizeof(double));
+    for (int32_t j = 0; j < N; ++j) {
+        int32_t k = j + 1 == N ? 0 : j + 1;
+        A[(size_t)j * w + j] += 1.0 + xd[j];
+        A[(size_t)j * w + k] += xo[j];
+        A[(size_t)k * w + j] += xo[j];
+        A[(size_t)j * w + n] = r0[j];
+        A[(size_t)j * w + n + 1] = r1[j];
+    }
+    for (size_t c = 0; c < n; ++c) {
+        size_t piv = c;
+        for (size_t r = c + 1; r < n; ++r)
+            if (fabs(A[r * w + c]) > fabs(A[piv * w + c])) piv = r;
+        if (piv != c)
+            for (size_t q = 0; q < w; ++q) {
+                double tmp = A[c * w + q];
+                A[c * w + q] = A[piv * w + q];
+                A[piv * w + q] = tmp;
+            }
+        for (size_t r = c + 1; r < n; ++r) {
+            double f = A[r * w + c] / A[c * w + c];
+            if (f == 0.0) continue;
+            for (size_t q = c; q < w; ++q) A[r * w + q] -= f * A[c * w + q];
+        }
+    }
+    for (size_t c = n; c-- > 0;) {
+        double s0 = A[c * w + n], s1 = A[c * w + n + 1];
+        for (size_t q = c + 1; q < n; ++q) {
+            s0 -= A[c * w + q] * y0[q];
+            s1 -= A[c * w + q] * y1[q];
+        }
+        y0[c] = s0 / A[c * w + c];
+        y1[c] = s1 / A[c * w + c];
+    }
+    free(A);
+}
+
+void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double* rho,
+                           const double* xd, const double* xo, double phi0, double* phi,
+                           double* E)
+{
+    /* eps0 (1 + X) E = D0 + R: E = (D0 / eps0) u + v with (1 + X) u = 1 and
+     * (1 + X) v = R / eps0 */
+    double* one = (double*)malloc(sizeof(double) * (size_t)N);
+    double* Re = (double*)malloc(sizeof(double) * (size_t)N);
+    double* u = (double*)malloc(sizeof(double) * (size_t)N);
+    double* v = (double*)malloc(sizeof(double) * (size_t)N);
+    double R = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+        if (j > 0) R += dx * rho[j];
+        one[j] = 1.0;
+        Re[j] = R / EPS0;
+    }
+    solve_one_plus_x(N, periodic, xd, xo, one, Re, u, v);
+    double su = 0.0, sv = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+        su += u[j];
+        sv += v[j];
+    }
+    if (periodic) phi0 = 0.0;
+    double D0e = (phi0 / dx - sv) / su;   /* D0 / eps0 */
+    phi[0] = phi0;
+    for (int32_t j = 0; j < N; ++j) {
+        E[j] = D0e * u[j] + v[j];
+        phi[j + 1] = phi[j] - dx * E[j];
+    }
+    free(one); free(Re); free(u); free(v);
+}
+
 static double gather(const orc_sim* s, double xi);
 
 /* Eq. (3) with m = 2 on a nonuniform grid (electrodes): minus the derivative
@@ -420,10 +546,13 @@ orc_sim* orc_create(const orc_case* c)
     s->phi = (double*)xcalloc((size_t)N + 1, sizeof(double));
     s->E = (double*)xcalloc((size_t)N, sizeof(double));
     s->chi = (double*)xcalloc((size_t)N, sizeof(double));
+    s->xd = (double*)xcalloc((size_t)N, sizeof(double));
+    s->xo = (double*)xcalloc((size_t)N, sizeof(double));
     for (int k = 0; k < 2; ++k) {
         s->Q[k] = (double*)xcalloc((size_t)N + 1, sizeof(double));
         s->cnt[k] = (double*)xcalloc((size_t)N, sizeof(double));
         s->chw[k] = (double*)xcalloc((size_t)N, sizeof(double));
+        s->cho[k] = (double*)xcalloc((size_t)N, sizeof(double));
         s->heat[k] = (double*)xcalloc((size_t)N, sizeof(double));
     }
     if (c->cell_dx_m) {
@@ -445,10 +574,10 @@ void orc_destroy(orc_sim* s)
         species_t* p = &s->sp[k];
         free(p->xi); free(p->vx); free(p->vy); free(p->vz); free(p->abar); free(p->id);
         free(p->wait);
-        free(s->Q[k]); free(s->cnt[k]); free(s->chw[k]); free(s->heat[k]);
+        free(s->Q[k]); free(s->cnt[k]); free(s->chw[k]); free(s->cho[k]); free(s->heat[k]);
     }
     for (int k = 0; k < s->n_proc; ++k) free(s->proc[k].sigma);
-    free(s->rho); free(s->phi); free(s->E); free(s->chi);
+    free(s->rho); free(s->phi); free(s->E); free(s->chi); free(s->xd); free(s->xo);
     free(s->cw); free(s->edge); free(s->sigma);
     free(s);
 }
@@ -640,8 +769,13 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         else
             orc_deposit_linear(N, periodic, s->sp[k].n, s->sp[k].xi, s->Q[k]);
         orc_count_cells(N, s->sp[k].n, s->sp[k].xi, s->cnt[k]);
-        if (use_chi && s->c.gather == ORC_GATHER_EC2)
-            orc_chi_weights_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k]);
+        if (use_chi && s->c.gather == ORC_GATHER_EC2) {
+            if (s->cw)
+                orc_chi_weights_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k]);
+            else
+                orc_chi_operator_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k],
+                                     s->cho[k]);
+        }
     }
     for (int32_t g = 0; g <= N; ++g) {
         double r = s->c.background_rho;
@@ -665,8 +799,35 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
      * chi_g = beta dt^2 / eps0 * sum_s q_s^2 w_s / m_s * Q_{s,g} / V_g (V_g = dx,
      * dx/2 at Dirichlet electrodes), and
      * chi_{j+1/2} = (chi_j + chi_{j+1}) / 2.
-     * EC with m = 2: as EC with N_{s,j} replaced by the susceptibility
-     * weights of the centres (orc_chi_weights_ec2). */
+     * EC with m = 2: the tridiagonal operator beta dt^2 / (eps0 dx) * sum_s
+     * q_s^2 w_s / m_s * M_s (orc_chi_operator_ec2), solved as such; chi
+     * holds its row sums (on a nonuniform grid the solve takes the row sums
+     * of orc_chi_weights_ec2 as a diagonal). */
+    const int ec2_exact = use_chi && s->c.gather == ORC_GATHER_EC2 && !s->cw;
+    if (ec2_exact) {
+        const double coef = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * s->dx);
+        for (int32_t j = 0; j < N; ++j) {
+            double d = 0.0, o = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                if (!(s->sp[k].m > 0.0)) continue;
+                double f = s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m;
+                d += f * s->chw[k][j];
+                o += f * s->cho[k][j];
+            }
+            s->xd[j] = coef * d;
+            s->xo[j] = coef * o;
+        }
+        for (int32_t j = 0; j < N; ++j) {
+            double left = j > 0 ? s->xo[j - 1] : (periodic ? s->xo[N - 1] : 0.0);
+            s->chi[j] = s->xd[j] + s->xo[j] + left;
+        }
+        orc_solve_chi_tridiag(N, periodic, s->dx, s->rho, s->xd, s->xo,
+                              periodic ? 0.0 : rf_volts_at(s, step_for_bc), s->phi, s->E);
+        double we = 0.0;
+        for (int32_t j = 0; j < N; ++j) we += 0.5 * EPS0 * s->E[j] * s->E[j] * s->dx;
+        s->led.WE = we;
+        return;
+    }
     for (int32_t j = 0; j < N; ++j) {
         double x = 0.0;
         if (use_chi && s->c.gather == ORC_GATHER_MC) {

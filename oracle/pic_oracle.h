@@ -30,8 +30,8 @@ enum { ORC_EXPLICIT = 0, ORC_IMPLICIT = 1 };
 /* EC: Eqs. (2)-(3) with m = 1 (S_1 deposit, S_0 gather of the half-grid
  * field); MC: S_1 deposit, S_1 gather of the nodal field; EC2: Eqs. (2)-(3)
  * with m = 2 read as spline degree (S_2 deposit, S_1 gather of the half-grid
- * field); its direct-implicit solve takes the diagonal susceptibility of
- * orc_chi_weights_ec2. */
+ * field); its direct-implicit solve takes the tridiagonal susceptibility
+ * operator of orc_chi_operator_ec2 (orc_solve_chi_tridiag). */
 enum { ORC_GATHER_EC = 0, ORC_GATHER_MC = 1, ORC_GATHER_EC2 = 2 };
 enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONIZATION = 2, ORC_CHARGE_EXCHANGE = 3 };
 
@@ -138,6 +138,27 @@ double orc_gather_ec2(int32_t N, int32_t periodic, const double* E, double xi);
  * diagonal approximation of the implicit m = 2 solve (h, h' over the N
  * centres of the grid, wrapped when periodic). */
 void orc_chi_weights_ec2(int32_t N, int32_t periodic, int64_t n, const double* xi, double* w);
+
+/* The operator itself, M_hh' = sum_p S_1(x_p - x_h) S_1(x_p - x_h'): a
+ * particle between centres a and a + 1 at fraction t from a adds (1 - t)^2
+ * to diag[a], t^2 to diag[a + 1] and t (1 - t) to off[a], the coupling of
+ * centres a and a + 1 (off[N - 1]: of centres N - 1 and 0, periodic only;
+ * no centre beyond an electrode). */
+void orc_chi_operator_ec2(int32_t N, int32_t periodic, int64_t n, const double* xi,
+                          double* diag, double* off);
+
+/* Field solve of the direct-implicit scheme with a tridiagonal
+ * susceptibility (the m = 2 operator): Gauss's law between half-grid
+ * points gives D_{j+1/2} = D0 + R_j, R_j = dx sum_{k=1..j} rho_k, and the
+ * field solves eps0 (E_j + sum_j' X_jj' E_j') = D_{j+1/2} with X_jj = xd[j],
+ * X_{j,j+1} = X_{j+1,j} = xo[j] (xo[N-1]: the wrap, periodic only).  D0 is
+ * fixed by dx sum_j E_j = phi_0 - phi_N (phi_N = 0, or a periodic
+ * potential with phi_0 = 0).  Two solves of (1 + X) (Thomas; periodic:
+ * Gaussian elimination with partial pivoting of the dense matrix), for the
+ * constant and for R. */
+void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double* rho,
+                           const double* xd, const double* xo, double phi0, double* phi,
+                           double* E);
 
 /* ---- the simulation object ---- */
 orc_sim* orc_create(const orc_case* c);

@@ -31,6 +31,292 @@ namespace pic {
 // ---------------------------------------------------------------------------
 constexpr double kEps0 = 8.8541878128e-12;
 
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scans of small summaries (structs of doubles) in the
+// order of the threads, or in the reverse order: comb(a, b) is "a, then b".
+// Lanes combine by shuffles, wavefronts through LDS (wtot: kWv entries).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T shfl_T(const T& v, int d, bool down)
+{
+    T r;
+    const double* s = (const double*)&v;
+    double* o = (double*)&r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i)
+        o[i] = down ? __shfl_down(s[i], d, 64) : __shfl_up(s[i], d, 64);
+    return r;
+}
+
+template <int NT, typename T, typename Comb>
+__device__ __forceinline__ T block_exscan(const T& x, const T& ident, Comb comb, bool rev,
+                                          T* wtot)
+{
+    constexpr int kWv = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pl = rev ? 63 - lane : lane;       // position in the scan order
+    const int pw = rev ? kWv - 1 - wave : wave;
+    T inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T prev = shfl_T(inc, o, rev);
+        if (pl >= o) inc = comb(prev, inc);
+    }
+    T ex = shfl_T(inc, 1, rev);
+    if (pl == 0) ex = ident;
+    if (pl == 63) wtot[pw] = inc;
+    lds_barrier();
+    T pre = ident;
+#pragma unroll
+    for (int w = 0; w < kWv; ++w)
+        if (w < pw) pre = comb(pre, wtot[w]);
+    const T res = comb(pre, ex);
+    lds_barrier();   // wtot may be written again
+    return res;
+}
+
+struct Sum1 { double s; };
+struct Proj2 { double m00, m01, m10, m11; };   // a 2x2 matrix up to a factor
+template <int NR> struct Aff { double A; double B[NR]; };   // y -> A y + B (NR maps)
+
+// ---------------------------------------------------------------------------
+// Field solve with the tridiagonal m = 2 susceptibility (direct-implicit
+// scheme): eps0 (1 + X) E = D0 + R, R_j = sum_{k<=j} sigma_k, X_jj = xd[j],
+// X_{j,j+1} = X_{j+1,j} = xo[j] (xo[N-1]: the wrap, periodic only); D0 from
+// dx sum_j E_j = phi_0 - phi_N.  (1 + X) u = 1 and (1 + X) v = R / eps0 by
+// Gaussian elimination without pivoting (1 + X is symmetric positive
+// definite: X is a sum of outer products of the particles' S_1 weights) in
+// scans: the pivots by a scan of 2x2 matrices (c'_j = c_j / (b_j - a_j
+// c'_{j-1}) is a continued fraction, i.e. a product of matrices up to a
+// factor), the eliminated right-hand sides by an affine scan, the back
+// substitution E_j = d'_j - c'_j E_{j+1} by an affine scan in reverse.  A
+// periodic box takes the wrap coupling by Sherman-Morrison (a third
+// right-hand side).  Thread t owns the Kr cells [t Kr, t Kr + Kr).
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void tridiag_field(const Case& Cc, State* st, long long next_step,
+                                              long long field_step, bool sample_density,
+                                              const double* S, const double* xd,
+                                              const double* xo, double* red)
+{
+    constexpr int kRows = (PIC_MAX_CELLS + NT - 1) / NT;
+    constexpr int NR = 3;   // right-hand sides: 1, R / eps0, the periodic correction
+    const int N = Cc.n_cells, tid = threadIdx.x;
+    const bool periodic = Cc.bc == 1;
+    const double dx = Cc.dx;
+    const int Kr = (N + NT - 1) / NT;
+    const int j0 = tid * Kr;
+    __shared__ double wbuf[(NT / 64) * 4];   // wave totals (up to 4 doubles each)
+    __shared__ double ends[8];               // periodic: the solutions at rows 0 and N-1
+
+    // Sherman-Morrison for the wrap: 1 + X = T + u v^T with u = (g, 0.., o),
+    // v = (1, 0.., o / g), g = -(1 + xd_0); T loses the wrap coupling and
+    // takes b_0 - g, b_{N-1} - o^2 / g
+    const double o_w = periodic ? xo[N - 1] : 0.0;
+    const double g_w = -(1.0 + xd[0]);
+    auto coef = [&](int j, double& a, double& b, double& c) {
+        a = j > 0 ? xo[j - 1] : 0.0;
+        c = j < N - 1 ? xo[j] : 0.0;
+        b = 1.0 + xd[j];
+        if (periodic) {
+            if (j == 0) b -= g_w;
+            if (j == N - 1) b -= o_w * o_w / g_w;
+        }
+    };
+
+    // R_j: prefix sums of the charges per area
+    double sl = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = j0 + k;
+        if (k < Kr && j < N) sl += S[j];
+    }
+    const Sum1 rpre = block_exscan<NT>(Sum1{sl}, Sum1{0.0},
+                                       [](const Sum1& x, const Sum1& y) { return Sum1{x.s + y.s}; },
+                                       false, (Sum1*)wbuf);
+
+    // pivots: (p, q) -> M_j (p, q), M_j = [[0, c_j], [-a_j, b_j]], c'_j = p / q
+    auto pcomb = [](const Proj2& x, const Proj2& y) {
+        // x, then y: the product y x, scaled
+        Proj2 r{y.m00 * x.m00 + y.m01 * x.m10, y.m00 * x.m01 + y.m01 * x.m11,
+                y.m10 * x.m00 + y.m11 * x.m10, y.m10 * x.m01 + y.m11 * x.m11};
+        const double m = fmax(fmax(fabs(r.m00), fabs(r.m01)), fmax(fabs(r.m10), fabs(r.m11)));
+        if (m > 0.0) {
+            const double im = 1.0 / m;
+            r.m00 *= im; r.m01 *= im; r.m10 *= im; r.m11 *= im;
+        }
+        return r;
+    };
+    Proj2 pl{1.0, 0.0, 0.0, 1.0};
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = j0 + k;
+        if (k < Kr && j < N) {
+            double a, b, c;
+            coef(j, a, b, c);
+            pl = pcomb(pl, Proj2{0.0, c, -a, b});
+        }
+    }
+    const Proj2 ppre = block_exscan<NT>(pl, Proj2{1.0, 0.0, 0.0, 1.0}, pcomb, false,
+                                        (Proj2*)wbuf);
+    // c'_{j0 - 1} = (P (0, 1))_0 / (P (0, 1))_1
+    double cprev = ppre.m01 / ppre.m11;
+    if (j0 == 0) cprev = 0.0;
+
+    // elimination: d'_j = alpha_j d'_{j-1} + beta_j, alpha_j = -a_j / den_j,
+    // beta_j = r_j / den_j
+    double cp[kRows], al[kRows], be[NR][kRows];
+    Aff<NR> fl;
+    fl.A = 1.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) fl.B[r] = 0.0;
+    double R = rpre.s;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = j0 + k;
+        cp[k] = 0.0;
+        al[k] = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) be[r][k] = 0.0;
+        if (k < Kr && j < N) {
+            double a, b, c;
+            coef(j, a, b, c);
+            R += S[j];
+            const double den = b - a * cprev;
+            const double id = 1.0 / den;
+            cp[k] = c * id;
+            cprev = cp[k];
+            al[k] = -a * id;
+            be[0][k] = id;
+            be[1][k] = R / kEps0 * id;
+            be[2][k] = periodic ? (j == 0 ? g_w : (j == N - 1 ? o_w : 0.0)) * id : 0.0;
+            fl.A *= al[k];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) fl.B[r] = al[k] * fl.B[r] + be[r][k];
+        }
+    }
+    auto acomb = [](const Aff<NR>& x, const Aff<NR>& y) {
+        Aff<NR> r;
+        r.A = y.A * x.A;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r.B[q] = y.A * x.B[q] + y.B[q];
+        return r;
+    };
+    Aff<NR> idn;
+    idn.A = 1.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) idn.B[r] = 0.0;
+    const Aff<NR> fpre = block_exscan<NT>(fl, idn, acomb, false, (Aff<NR>*)wbuf);
+    // d'_{j0 - 1} = fpre.B (d'_{-1} = 0); the eliminated right-hand sides
+    {
+        double dprev[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) dprev[r] = fpre.B[r];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                be[r][k] = al[k] * dprev[r] + be[r][k];   // d'_j (rows past N: 0)
+                if (k < Kr && j0 + k < N) dprev[r] = be[r][k];
+            }
+        }
+    }
+    // back substitution, last row first: E_j = -c'_j E_{j+1} + d'_j
+    Aff<NR> bl = idn;
+#pragma unroll
+    for (int k = kRows - 1; k >= 0; --k) {
+        if (k < Kr && j0 + k < N) {
+            Aff<NR> rowm;
+            rowm.A = -cp[k];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) rowm.B[r] = be[r][k];
+            bl = acomb(bl, rowm);
+        }
+    }
+    const Aff<NR> bpre = block_exscan<NT>(bl, idn, acomb, true, (Aff<NR>*)wbuf);
+    double y[NR][kRows];   // the solutions for the NR right-hand sides
+    {
+        double enext[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) enext[r] = bpre.B[r];   // E beyond the last row: 0
+#pragma unroll
+        for (int k = kRows - 1; k >= 0; --k) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                y[r][k] = 0.0;
+                if (k < Kr && j0 + k < N) {
+                    y[r][k] = be[r][k] - cp[k] * enext[r];
+                    enext[r] = y[r][k];
+                }
+            }
+        }
+    }
+    if (periodic) {
+        // x = y - (v . y) / (1 + v . z) z for y = the solutions of 1 and R
+        // (z: the third), v = (1, 0.., o / g)
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int j = j0 + k;
+            if (k < Kr && (j == 0 || j == N - 1))
+                for (int r = 0; r < NR; ++r) ends[(j == 0 ? 0 : 4) + r] = y[r][k];
+        }
+        lds_barrier();
+        const double og = o_w / g_w;
+        const double fac = 1.0 + ends[2] + og * ends[6];
+        const double f0 = (ends[0] + og * ends[4]) / fac, f1 = (ends[1] + og * ends[5]) / fac;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            y[0][k] -= f0 * y[2][k];
+            y[1][k] -= f1 * y[2][k];
+        }
+    }
+    // D0 / eps0 from dx sum E = phi_0 - phi_N: E = D0e u + v
+    double su = 0.0, sv = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        su += y[0][k];
+        sv += y[1][k];
+    }
+    su = block_sum<double, NT>(su, red);
+    sv = block_sum<double, NT>(sv, red);
+    double V = 0.0;
+    if (!periodic) {
+        const double cyc = Cc.rf_freq * ((double)next_step * Cc.dt);
+        V = Cc.rf_volts * sinpi(2.0 * (cyc - floor(cyc)));
+    }
+    const double D0e = (V / dx - sv) / su;
+    // potentials: phi_{j+1} = phi_0 - dx sum_{k<=j} E_k
+    double el = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) el += D0e * y[0][k] + y[1][k];
+    const Sum1 epre = block_exscan<NT>(Sum1{el}, Sum1{0.0},
+                                       [](const Sum1& x, const Sum1& z) { return Sum1{x.s + z.s}; },
+                                       false, (Sum1*)wbuf);
+    const double phi0 = periodic ? 0.0 : V;
+    if (tid == 0) gp(Cc.phi)[0] = phi0;
+    double we = 0.0, run = epre.s;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = j0 + k;
+        if (k < Kr && j < N) {
+            const double E = D0e * y[0][k] + y[1][k];
+            run += E;
+            gp(Cc.E)[j] = E;
+            gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
+            gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
+            gp(Cc.phi)[j + 1] = phi0 - dx * run;
+            we += 0.5 * kEps0 * E * E * dx;
+        }
+    }
+    we = block_sum<double, NT>(we, red);
+    if (tid == 0) {
+        st->WE[field_step & 1] = we;
+        if (!isfinite(we)) atomicOr(&st->flags, 1);
+        if (sample_density) st->dens_samples += 1;
+    }
+    lds_barrier();
+}
+
 // kDual: the code of the implicit m = 2 moment words is compiled in (the
 // launches of batches without such a case leave it out: its registers would
 // make the rest spill).
@@ -208,8 +494,25 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                     v[s] = n1 * (1ll << kFixBits) - F(s, e1) + F(s, h);
                 }
                 const double chi = (chi0 * (double)v[0] + chi1 * (double)v[1]) / kFixScale;
-                X[h] = chi;
-                gp(Cc.chi)[h] = chi;
+                gp(Cc.chi)[h] = chi;   // the row sum of the operator
+                // the operator itself: centre h takes (1 - t)^2 = 2 P0 from
+                // the particles of node h + 1 and t^2 = 2 P2 from those of
+                // node h; the particles of node h + 1 couple centres h and
+                // h + 1 by t (1 - t) = 1/2 - P0 - P2 (none beyond an electrode)
+                const bool couples = periodic || h + 1 < N;
+                double dg = 0.0, cpl = 0.0;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const double cs = s == 0 ? chi0 : chi1;
+                    dg += cs * (double)(2 * (long long)dx_w[s][h] + 2 * (long long)dw[s][e1]);
+                    if (couples) {
+                        const long long n1 = (long long)dc[s][e1] + (long long)dx_c[s][e1];
+                        cpl += cs * (double)(n1 * (1ll << (kFixBits - 1)) -
+                                             (long long)dw[s][e1] - (long long)dx_w[s][e1]);
+                    }
+                }
+                X[h] = dg / kFixScale;
+                Y[h] = cpl / kFixScale;
             }
         }
     }
@@ -241,6 +544,11 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                 gp(Cc.chi_w[0])[j] = 0; gp(Cc.chi_w[1])[j] = 0;
             }
         }
+    }
+    if (dual) {
+        // the m = 2 implicit field: the tridiagonal operator, solved as such
+        tridiag_field<NT>(Cc, st, next_step, field_step, sample_density, S, X, Y, red);
+        return;
     }
     // One pass of an associative scan gives every prefix the solve needs.
     // With sigma_j the charge per area of node j (sigma_0 = 0 stands for the

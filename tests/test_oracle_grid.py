@@ -302,3 +302,121 @@ def test_ec2_susceptibility_next_to_an_electrode_closed_form(orc):
     assert np.allclose(chi, u * np.array([0, 0, 0, 0.36]), rtol=1e-12, atol=0.0)
     chi, u = _chi(orc, N, np.array([2.0]), gather=2)
     assert np.allclose(chi, u * np.array([0, 0.5, 0.5, 0]), rtol=1e-12, atol=0.0)
+
+
+# ---------------------------------------------------------------------------
+# The tridiagonal m = 2 susceptibility operator and its solve
+# ---------------------------------------------------------------------------
+def _apply_tridiag(d, o, E, periodic):
+    # (M E)_h for diagonal d and couplings o[h] of centres h, h + 1
+    y = d * E + o * np.roll(E, -1) + np.roll(o * E, 1)
+    if not periodic:
+        y = d * E
+        y[:-1] += o[:-1] * E[1:]
+        y[1:] += o[:-1] * E[:-1]
+    return y
+
+
+@pytest.mark.parametrize("N,periodic", [(6, False), (7, True), (3, True), (2, False)])
+def test_ec2_operator_is_the_gram_matrix_of_the_gather_weights(orc, N, periodic):
+    rng = np.random.default_rng(60 + N)
+    xi = rng.uniform(0.0, N, 300)
+    xi[:5] = [0.0, 0.25, 0.5, N - 0.5, N - 1e-9]
+    d, o = orc.chi_operator_ec2(N, xi, periodic)
+    M = _ec2_operator(N, xi, periodic)
+    np.testing.assert_allclose(d, np.diag(M), rtol=1e-12, atol=1e-12)
+    for h in range(N - (0 if periodic else 1)):
+        assert abs(o[h] - M[h, (h + 1) % N]) < 1e-9, (h, o[h], M[h, (h + 1) % N])
+    if not periodic:
+        assert o[N - 1] == 0.0
+    # the row sums are the diagonal weights of the nonuniform solve
+    E = rng.normal(size=N)
+    np.testing.assert_allclose(_apply_tridiag(d, o, E, periodic), M @ E, rtol=1e-10, atol=1e-9)
+
+
+@pytest.mark.parametrize("N,periodic", [(8, False), (7, True)])
+def test_ec2_operator_is_the_linear_response_of_the_deposit(orc, N, periodic):
+    # Move every particle by eps times the S_1 gather of a half-grid field E
+    # (the direction of the D1 correction).  The quadratic deposit then
+    # changes node g by the flux in from centre g - 1 minus the flux out
+    # through centre g, and to first order in eps the flux through centre h
+    # is eps (M E)_h: the operator is the response of the deposit, not a
+    # formula of its own.  (No flux beyond an electrode: the weights that
+    # reach past it stay on its node.)
+    rng = np.random.default_rng(7 + N)
+    xi = rng.uniform(0.0, N, 200)
+    xi[:4] = [0.05, 0.45, N - 0.3, N - 0.02]
+    E = rng.normal(size=N)
+    d, o = orc.chi_operator_ec2(N, xi, periodic)
+    flux = _apply_tridiag(d, o, E, periodic)
+    for eps in (1e-5, 5e-6):
+        g = np.array([orc.gather_ec2(N, E, x, periodic) for x in xi])
+        moved = xi + eps * g
+        if periodic:
+            moved %= N
+        dq = (orc.deposit_quadratic(N, moved, periodic) -
+              orc.deposit_quadratic(N, xi, periodic)) / eps
+        if periodic:
+            expect = np.roll(flux, 1) - flux          # node g: centres g - 1 and g
+            got = dq[:N]
+        else:
+            fin = np.concatenate([[0.0], flux])       # into node g from centre g - 1
+            fout = np.concatenate([flux, [0.0]])      # out of node g through centre g
+            expect, got = fin - fout, dq
+        assert np.abs(got - expect).max() < 200 * eps * np.abs(flux).max(), eps
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_tridiag_solve_with_a_diagonal_operator_is_the_diagonal_solve(orc, periodic):
+    # without couplings the D-form solve must give the field of the
+    # potential-form (Dirichlet) or periodic solve with chi = the diagonal
+    N, dx = 9, 2e-4
+    rng = np.random.default_rng(11)
+    rho = rng.normal(size=N + 1) * 1e-3
+    if periodic:
+        rho[N] = rho[0]
+        rho -= rho[:N].mean()
+    xd = rng.uniform(0.0, 3.0, N)
+    phi_t, E_t = orc.solve_chi_tridiag(N, dx, rho, xd, np.zeros(N), 1.7, periodic)
+    if periodic:
+        phi, E = orc.solve_periodic(N, dx, rho, chi=xd)
+    else:
+        phi, E = orc.solve_dirichlet(N, dx, rho, 1.7, 0.0, chi=xd)
+    np.testing.assert_allclose(E_t, E, rtol=1e-10, atol=1e-10 * np.abs(E).max())
+    np.testing.assert_allclose(phi_t, phi, rtol=1e-10, atol=1e-10 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_tridiag_solve_satisfies_gauss_and_the_potential(orc, periodic):
+    # random couplings: the field satisfies Gauss's law with the displacement
+    # eps0 (1 + X) E at every interior node, and the potential difference
+    # across the gap (or around the box)
+    N, dx = 12, 1e-4
+    rng = np.random.default_rng(5)
+    xi = rng.uniform(0.0, N, 80)
+    d, o = orc.chi_operator_ec2(N, xi, periodic)
+    xd, xo = 0.3 * d, 0.3 * o
+    rho = rng.normal(size=N + 1) * 1e-3
+    if periodic:
+        rho[N] = rho[0]
+        rho -= rho[:N].mean()
+    V = 0.0 if periodic else 2.5
+    phi, E = orc.solve_chi_tridiag(N, dx, rho, xd, xo, V, periodic)
+    D = EPS0 * (E + _apply_tridiag(xd, xo, E, periodic))
+    gauss = (D[1:] - D[:-1]) - dx * rho[1:N]
+    assert np.abs(gauss).max() < 1e-10 * np.abs(dx * rho).max()
+    if periodic:
+        assert abs(D[0] - D[N - 1] - dx * rho[0]) < 1e-10 * np.abs(dx * rho).max()
+    assert abs(dx * E.sum() - V) < 1e-12 + 1e-12 * abs(V)
+    np.testing.assert_allclose(phi[:-1] - phi[1:], dx * E, rtol=1e-12, atol=1e-20)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_ec2_exported_susceptibility_is_the_row_sum(orc, periodic):
+    # the cell susceptibility exported with the fields is the row sum of the
+    # operator, i.e. the diagonal weights of orc_chi_weights_ec2
+    N = 10
+    xi = np.random.default_rng(3).uniform(0.0, N, 150)
+    chi, u = _chi(orc, N, xi, gather=2, periodic=periodic)
+    w = orc.chi_weights_ec2(N, xi, periodic)
+    np.testing.assert_allclose(chi, u * w, rtol=1e-12, atol=1e-30)

@@ -69,6 +69,22 @@ MUTANTS = [
     ("m=2 chi plain linear weights", "if (in[e]) w[c[e]] += s1[e] * row;",
      "if (in[e]) w[c[e]] += s1[e];", None),
     ("m=2 chi no electrode rule", "if (in[e]) row += s1[e];", "row += s1[e];", None),
+    # m = 2 implicit: the tridiagonal operator and its solve
+    ("m=2 operator without couplings", "if (ina && inb) off[a] += wa * wb;",
+     "if (ina && inb) off[a] += 0.0 * wa * wb;", None),
+    ("m=2 operator coupling weight", "if (ina && inb) off[a] += wa * wb;",
+     "if (ina && inb) off[a] += wb * wb;", None),
+    ("m=2 operator diagonal weight", "if (ina) diag[a] += wa * wa;",
+     "if (ina) diag[a] += wa * wb;", None),
+    ("tridiagonal solve D0 sign", "double D0e = (phi0 / dx - sv) / su;",
+     "double D0e = (phi0 / dx + sv) / su;", None),
+    ("tridiagonal solve sub-diagonal", "double a = j > 0 ? xo[j - 1] : 0.0;",
+     "double a = j > 0 ? xo[j] : 0.0;", None),
+    ("periodic solve one-sided wrap", "A[(size_t)k * w + j] += xo[j];",
+     "A[(size_t)k * w + j] += 0.0 * xo[j];", None),
+    ("m=2 exported chi without its left coupling",
+     "double left = j > 0 ? s->xo[j - 1] : (periodic ? s->xo[N - 1] : 0.0);",
+     "double left = 0.0;", None),
     # explicit push, heating
     ("work without the half kick", "double dK = p->m * p->w * dv * (p->vx[i] + 0.5 * dv);",
      "double dK = p->m * p->w * dv * p->vx[i];", None),
