@@ -67,6 +67,12 @@ def make_workload(name, scale):
         # within 15 % of the gap from either electrode)
         return [W.c4(np_per_species=int(10_000_000 * scale),
                      cell_dx=W.sheath_refined_widths(2048, 0.025))]
+    if name == "ccp2048_nonuniform_ec2_implicit":
+        # D1 implicit with m = 2 weighting on the sheath-refined grid
+        wl = W.c4(np_per_species=int(10_000_000 * scale), scheme=1,
+                  cell_dx=W.sheath_refined_widths(2048, 0.025))
+        wl["case"]["gather"] = 2
+        return [wl]
     if name == "ccp2048_subcycle8":
         # the same discharge with the ions pushed every 8th step with 8 dt
         wl = W.c4(np_per_species=int(10_000_000 * scale))
@@ -340,7 +346,9 @@ def param_study(P, periods, window=10, ppc=400, scale=1.0):
                                 np_per_species=int(ppc * N * scale), gap_m=gap, volts=volts,
                                 freq=freq, dt=dt, p_mtorr=p_mtorr, n0=n0, Te=2.0,
                                 scheme=scheme, gather=gather, seed=0x7AB1E + k,
-                                capacity_factor=4.0)
+                                # the coarse grids may diverge (MC): room to
+                                # grow, so that the batch runs its periods
+                                capacity_factor=40.0 if N <= 100 else 4.0)
             wls.append(wl)
             tags.append(dict(gather=gname, scheme=sname, cells=N))
             k += 1

@@ -108,9 +108,11 @@ typedef struct {
      * gap_m within 1e-9: a nonuniform grid, finer in the sheaths (the
      * multi-scale grid the conclusions propose).  PIC_BC_DIRICHLET_RF only;
      * PIC_GATHER_MC takes as nodal field the centred potential difference
-     * over the node's two cells, PIC_GATHER_EC2 (PIC_EXPLICIT only) gathers
-     * minus the physical gradient of the quadratic deposit's field energy
-     * (else PIC_E_INVAL).
+     * over the node's two cells, PIC_GATHER_EC2 gathers minus the physical
+     * gradient of the quadratic deposit's field energy; with PIC_IMPLICIT_D1
+     * it solves the tridiagonal susceptibility for F_j = (w_j N / gap_m) E_j
+     * and takes at most 3391 cells (the LDS of its moment words); other
+     * combinations: PIC_E_INVAL.
      * Positions stay logical
      * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */
     const double* cell_dx_m;

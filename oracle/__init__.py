@@ -31,7 +31,7 @@ ELASTIC, EXCITATION, IONIZATION, CHARGE_EXCHANGE = 0, 1, 2, 3
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = _LIB + ".%d.tmp" % os.getpid()   # concurrent test workers each build
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
@@ -109,6 +109,9 @@ def lib():
         L.orc_chi_operator_ec2.argtypes = [C.c_int32, C.c_int32, C.c_int64, _D, _D, _D]
         L.orc_solve_chi_tridiag.argtypes = [C.c_int32, C.c_int32, C.c_double, _D, _D, _D,
                                             C.c_double, _D, _D]
+        L.orc_chi_operator_ec2_nu.argtypes = [C.c_int32, _D, C.c_double, C.c_int64, _D, _D, _D]
+        L.orc_solve_chi_tridiag_nu.argtypes = [C.c_int32, _D, C.c_double, _D, _D, _D,
+                                               C.c_double, _D, _D]
         L.orc_gather_mc_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
         L.orc_gather_mc_nu.restype = C.c_double
         L.orc_gather_ec2_nu.argtypes = [C.c_int32, _D, _D, C.c_double]
@@ -258,6 +261,28 @@ def chi_operator_ec2(N: int, xi, periodic: bool = False):
     d, o = np.zeros(N), np.zeros(N)
     lib().orc_chi_operator_ec2(N, int(periodic), xi.size, _dp(xi), _dp(d), _dp(o))
     return d, o
+
+
+def chi_operator_ec2_nu(w, xi):
+    """The m = 2 operator on a nonuniform grid of widths w
+    (orc_chi_operator_ec2_nu)."""
+    w, xi = _f64(w), _f64(xi)
+    N = w.size
+    d, o = np.zeros(N), np.zeros(N)
+    lib().orc_chi_operator_ec2_nu(N, _dp(w), float(w.sum() / N), xi.size, _dp(xi), _dp(d),
+                                  _dp(o))
+    return d, o
+
+
+def solve_chi_tridiag_nu(w, sigma, xd, xo, phi0: float = 0.0):
+    """Field solve with a tridiagonal susceptibility on a nonuniform grid
+    (orc_solve_chi_tridiag_nu): returns (phi, E)."""
+    w, sigma, xd, xo = _f64(w), _f64(sigma), _f64(xd), _f64(xo)
+    N = w.size
+    phi, E = np.zeros(N + 1), np.zeros(N)
+    lib().orc_solve_chi_tridiag_nu(N, _dp(w), float(w.sum() / N), _dp(sigma), _dp(xd), _dp(xo),
+                                   phi0, _dp(phi), _dp(E))
+    return phi, E
 
 
 def solve_chi_tridiag(N: int, dx: float, rho, xd, xo, phi0: float = 0.0,

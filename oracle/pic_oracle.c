@@ -385,11 +385,13 @@ void orc_chi_operator_ec2(int32_t N, int32_t periodic, int64_t n, const double* 
     }
 }
 
-/* Solve (1 + X) y = r for two right-hand sides r0, r1 (tridiagonal X as
- * in orc_solve_chi_tridiag).  Dirichlet: the Thomas algorithm; periodic:
+/* Solve (D + X) y = r for two right-hand sides r0, r1, with the diagonal D
+ * = dg (1 where dg is NULL) and the tridiagonal X as in
+ * orc_solve_chi_tridiag.  Dirichlet: the Thomas algorithm; periodic:
  * Gaussian elimination with partial pivoting of the dense matrix. */
-static void solve_one_plus_x(int32_t N, int32_t periodic, const double* xd, const double* xo,
-                             const double* r0, const double* r1, double* y0, double* y1)
+static void solve_one_plus_x(int32_t N, int32_t periodic, const double* dg, const double* xd,
+                             const double* xo, const double* r0, const double* r1, double* y0,
+                             double* y1)
 {
     if (!periodic) {
         double* cp = (double*)malloc(sizeof(double) * (size_t)N);
@@ -397,7 +399,7 @@ static void solve_one_plus_x(int32_t N, int32_t periodic, const double* xd, cons
         double* d1 = (double*)malloc(sizeof(double) * (size_t)N);
         for (int32_t j = 0; j < N; ++j) {
             double a = j > 0 ? xo[j - 1] : 0.0;          /* below the diagonal */
-            double b = 1.0 + xd[j];
+            double b = (dg ? dg[j] : 1.0) + xd[j];
             double c = j < N - 1 ? xo[j] : 0.0;          /* above the diagonal */
             double den = j > 0 ? b - a * cp[j - 1] : b;
             cp[j] = c / den;
@@ -417,7 +419,7 @@ static void solve_one_plus_x(int32_t N, int32_t periodic, const double* xd, cons
     double* A = (double*)calloc(n * w, sizeof(double));
     for (int32_t j = 0; j < N; ++j) {
         int32_t k = j + 1 == N ? 0 : j + 1;
-        A[(size_t)j * w + j] += 1.0 + xd[j];
+        A[(size_t)j * w + j] += (dg ? dg[j] : 1.0) + xd[j];
         A[(size_t)j * w + k] += xo[j];
         A[(size_t)k * w + j] += xo[j];
         A[(size_t)j * w + n] = r0[j];
@@ -457,8 +459,8 @@ void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double*
 {
     /* eps0 (1 + X) E = D0 + R: E = (D0 / eps0) u + v with (1 + X) u = 1 and
      * (1 + X) v = R / eps0 */
-    double* one = (double*)malloc(sizeof(double) * (size_t)N);
-    double* Re = (double*)malloc(sizeof(double) * (size_t)N);
+    double* one = (double*)calloc((size_t)N, sizeof(double));
+    double* Re = (double*)calloc((size_t)N, sizeof(double));
     double* u = (double*)malloc(sizeof(double) * (size_t)N);
     double* v = (double*)malloc(sizeof(double) * (size_t)N);
     double R = 0.0;
@@ -467,7 +469,7 @@ void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double*
         one[j] = 1.0;
         Re[j] = R / EPS0;
     }
-    solve_one_plus_x(N, periodic, xd, xo, one, Re, u, v);
+    solve_one_plus_x(N, periodic, NULL, xd, xo, one, Re, u, v);
     double su = 0.0, sv = 0.0;
     for (int32_t j = 0; j < N; ++j) {
         su += u[j];
@@ -481,6 +483,64 @@ void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double*
         phi[j + 1] = phi[j] - dx * E[j];
     }
     free(one); free(Re); free(u); free(v);
+}
+
+/* The m = 2 operator on a nonuniform grid (widths w, reference dx = L/N,
+ * r = w / dx): each particle's products of S_1 weights divided by r_c^2 of
+ * its cell c (orc_chi_operator_ec2 on the logical coordinate). */
+void orc_chi_operator_ec2_nu(int32_t N, const double* w, double dx, int64_t n,
+                             const double* xi, double* diag, double* off)
+{
+    memset(diag, 0, sizeof(double) * (size_t)N);
+    memset(off, 0, sizeof(double) * (size_t)N);
+    for (int64_t p = 0; p < n; ++p) {
+        double k = floor(xi[p] - 0.5);
+        double t = xi[p] - 0.5 - k;
+        int64_t a = (int64_t)k, b = a + 1;
+        int64_t c = (int64_t)floor(xi[p]);
+        if (c < 0) c = 0;
+        if (c > N - 1) c = N - 1;
+        double rc = w[c] / dx;
+        double f = 1.0 / (rc * rc);
+        double wa = 1.0 - t, wb = t;
+        int ina = a >= 0 && a < N, inb = b >= 0 && b < N;
+        if (ina) diag[a] += f * wa * wa;
+        if (inb) diag[b] += f * wb * wb;
+        if (ina && inb) off[a] += f * wa * wb;
+    }
+}
+
+void orc_solve_chi_tridiag_nu(int32_t N, const double* w, double dx, const double* sigma,
+                              const double* xd, const double* xo, double phi0, double* phi,
+                              double* E)
+{
+    /* (1/r + X) F = (D0 + R) / eps0, F_j = r_j E_j: F = (D0 / eps0) u + v */
+    double* dg = (double*)calloc((size_t)N, sizeof(double));
+    double* one = (double*)calloc((size_t)N, sizeof(double));
+    double* Re = (double*)calloc((size_t)N, sizeof(double));
+    double* u = (double*)malloc(sizeof(double) * (size_t)N);
+    double* v = (double*)malloc(sizeof(double) * (size_t)N);
+    double R = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+        if (j > 0) R += sigma[j];
+        dg[j] = dx / w[j];
+        one[j] = 1.0;
+        Re[j] = R / EPS0;
+    }
+    solve_one_plus_x(N, 0, dg, xd, xo, one, Re, u, v);
+    double su = 0.0, sv = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+        su += u[j];
+        sv += v[j];
+    }
+    double D0e = (phi0 / dx - sv) / su;   /* from dx sum_j F_j = phi_0 - phi_N */
+    phi[0] = phi0;
+    for (int32_t j = 0; j < N; ++j) {
+        double F = D0e * u[j] + v[j];
+        E[j] = F * dx / w[j];
+        phi[j + 1] = phi[j] - dx * F;
+    }
+    free(dg); free(one); free(Re); free(u); free(v);
 }
 
 static double gather(const orc_sim* s, double xi);
@@ -525,10 +585,8 @@ orc_sim* orc_create(const orc_case* c)
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
     if (c->ion_subcycle < 0 || (c->ion_subcycle > 1 && c->scheme != ORC_EXPLICIT)) return NULL;
     if (c->cell_dx_m) {
-        /* nonuniform grids: between electrodes (m = 2: explicit), widths
-         * summing to L */
+        /* nonuniform grids: between electrodes, widths summing to L */
         if (c->bc != ORC_BC_DIRICHLET) return NULL;
-        if (c->gather == ORC_GATHER_EC2 && c->scheme != ORC_EXPLICIT) return NULL;
         double L = 0.0;
         for (int32_t j = 0; j < c->n_cells; ++j) {
             if (!(c->cell_dx_m[j] > 0.0) || !isfinite(c->cell_dx_m[j])) return NULL;
@@ -771,7 +829,8 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         orc_count_cells(N, s->sp[k].n, s->sp[k].xi, s->cnt[k]);
         if (use_chi && s->c.gather == ORC_GATHER_EC2) {
             if (s->cw)
-                orc_chi_weights_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k]);
+                orc_chi_operator_ec2_nu(N, s->cw, s->dx, s->sp[k].n, s->sp[k].xi, s->chw[k],
+                                        s->cho[k]);
             else
                 orc_chi_operator_ec2(N, periodic, s->sp[k].n, s->sp[k].xi, s->chw[k],
                                      s->cho[k]);
@@ -801,9 +860,10 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
      * chi_{j+1/2} = (chi_j + chi_{j+1}) / 2.
      * EC with m = 2: the tridiagonal operator beta dt^2 / (eps0 dx) * sum_s
      * q_s^2 w_s / m_s * M_s (orc_chi_operator_ec2), solved as such; chi
-     * holds its row sums (on a nonuniform grid the solve takes the row sums
-     * of orc_chi_weights_ec2 as a diagonal). */
-    const int ec2_exact = use_chi && s->c.gather == ORC_GATHER_EC2 && !s->cw;
+     * holds its row sums.  On a nonuniform grid the operator acts on
+     * F_j = r_j E_j (orc_chi_operator_ec2_nu, orc_solve_chi_tridiag_nu) and
+     * chi_j = sum_j' X_jj' r_j' (the susceptibility of a uniform field). */
+    const int ec2_exact = use_chi && s->c.gather == ORC_GATHER_EC2;
     if (ec2_exact) {
         const double coef = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * s->dx);
         for (int32_t j = 0; j < N; ++j) {
@@ -817,14 +877,26 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
             s->xd[j] = coef * d;
             s->xo[j] = coef * o;
         }
-        for (int32_t j = 0; j < N; ++j) {
-            double left = j > 0 ? s->xo[j - 1] : (periodic ? s->xo[N - 1] : 0.0);
-            s->chi[j] = s->xd[j] + s->xo[j] + left;
+        if (s->cw) {
+            for (int32_t j = 0; j < N; ++j) {
+                double x = s->xd[j] * s->cw[j];
+                if (j > 0) x += s->xo[j - 1] * s->cw[j - 1];
+                if (j < N - 1) x += s->xo[j] * s->cw[j + 1];
+                s->chi[j] = x / s->dx;
+            }
+            orc_solve_chi_tridiag_nu(N, s->cw, s->dx, s->sigma, s->xd, s->xo,
+                                     rf_volts_at(s, step_for_bc), s->phi, s->E);
+        } else {
+            for (int32_t j = 0; j < N; ++j) {
+                double left = j > 0 ? s->xo[j - 1] : (periodic ? s->xo[N - 1] : 0.0);
+                s->chi[j] = s->xd[j] + s->xo[j] + left;
+            }
+            orc_solve_chi_tridiag(N, periodic, s->dx, s->rho, s->xd, s->xo,
+                                  periodic ? 0.0 : rf_volts_at(s, step_for_bc), s->phi, s->E);
         }
-        orc_solve_chi_tridiag(N, periodic, s->dx, s->rho, s->xd, s->xo,
-                              periodic ? 0.0 : rf_volts_at(s, step_for_bc), s->phi, s->E);
         double we = 0.0;
-        for (int32_t j = 0; j < N; ++j) we += 0.5 * EPS0 * s->E[j] * s->E[j] * s->dx;
+        for (int32_t j = 0; j < N; ++j)
+            we += 0.5 * EPS0 * s->E[j] * s->E[j] * (s->cw ? s->cw[j] : s->dx);
         s->led.WE = we;
         return;
     }

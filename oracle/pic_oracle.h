@@ -58,7 +58,7 @@ typedef struct {
     double opal_B_eV;       /* energy-sharing parameter of ionization              */
     uint64_t seed;          /* Philox key                                          */
     /* NULL: N equal cells of L/N.  Otherwise the N cell widths (m, summing to
-     * L; electrodes only, m = 2 explicit only): a nonuniform grid, finer in the
+     * L; electrodes only): a nonuniform grid, finer in the
      * sheaths.  Positions stay logical (cell index + offset in the cell). */
     const double* cell_dx_m;
 } orc_case;
@@ -159,6 +159,19 @@ void orc_chi_operator_ec2(int32_t N, int32_t periodic, int64_t n, const double* 
 void orc_solve_chi_tridiag(int32_t N, int32_t periodic, double dx, const double* rho,
                            const double* xd, const double* xo, double phi0, double* phi,
                            double* E);
+
+/* The same on a nonuniform grid (cell widths w, between electrodes; dx =
+ * L/N, r_j = w_j / dx).  A particle's D1 displacement along the gathered
+ * field, (1/w_c) sum_h E_h w_h S_1, moves it by that over w_c in the
+ * logical coordinate, so the operator carries 1/r_c^2 of its cell c
+ * (orc_chi_operator_ec2_nu) and acts on F_j = r_j E_j, which keeps it
+ * symmetric: (1/r + X) F = (D0 + R) / eps0 with R_j = sum_{k=1..j} sigma_k
+ * (charges per area) and dx sum_j F_j = phi_0 - phi_N. */
+void orc_chi_operator_ec2_nu(int32_t N, const double* w, double dx, int64_t n,
+                             const double* xi, double* diag, double* off);
+void orc_solve_chi_tridiag_nu(int32_t N, const double* w, double dx, const double* sigma,
+                              const double* xd, const double* xo, double phi0, double* phi,
+                              double* E);
 
 /* ---- the simulation object ---- */
 orc_sim* orc_create(const orc_case* c);

@@ -106,6 +106,11 @@ struct Case {
     // summed fractions towards centre k + 1 (null otherwise)
     unsigned long long* chi_cnt[2];  // [N+1]
     unsigned long long* chi_w[2];    // [N+1]
+    // m = 2 implicit on a nonuniform grid: the sums of P0 and of P2 over the
+    // particles left of their nearest node (in the cell before it), so that
+    // each side of a node can carry its own cell width (null otherwise)
+    unsigned long long* chl_w0[2];   // [N+1]
+    unsigned long long* chl_w2[2];   // [N+1]
     // nonuniform grid (null otherwise): r_c = dx / w_c for the moves and
     // w_c / dx for the solve
     float* cell_r;                   // [N]
@@ -204,7 +209,8 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 //   field[N+1] float  (EC: ehat of the cells; MC: nodal field)
 //   dep[N+1] u64      (privatised deposit, count << 40 | summed weight)
 //   DIAG: heat[N] float, eedf[kEedfBins] u32
-// (dual: the susceptibility words of the m = 2 implicit scheme follow dep;
+// (dual: the susceptibility words of the m = 2 implicit scheme follow dep,
+// on a nonuniform grid with the left-side sums of P0 and P2 after them;
 // nu: the width ratios r_c of a nonuniform grid, N floats, and the runs of
 // equal widths, N u32, follow those)
 struct StepLds {
@@ -216,7 +222,7 @@ __host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual =
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
     L.dual = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
-    L.ratio = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
+    L.ratio = L.dual + (dual ? (nu ? 3 : 1) * align16(8 * ((size_t)N + 1)) : 0);
     L.heat = L.ratio + (nu ? 2 * align16(4 * (size_t)N) : 0);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
@@ -224,16 +230,17 @@ __host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual =
 }
 
 // Shared-memory layout of k_collide: dep[N+1] u64 (predicted positions of
-// the implicit candidates) | (dual: susceptibility words[N+1] u64) |
+// the implicit candidates) | (dual: susceptibility words[N+1] u64; on a
+// nonuniform grid also the left-side sums, 2 x [N+1] u64) |
 // eedf[kEedfBins] u32
 struct CollideLds {
     size_t dual, eedf, total;
 };
-__host__ __device__ inline CollideLds collide_lds_layout(int N, bool dual)
+__host__ __device__ inline CollideLds collide_lds_layout(int N, bool dual, bool nu = false)
 {
     CollideLds L;
     L.dual = align16(8 * ((size_t)N + 1));
-    L.eedf = L.dual + (dual ? align16(8 * ((size_t)N + 1)) : 0);
+    L.eedf = L.dual + (dual ? (nu ? 3 : 1) * align16(8 * ((size_t)N + 1)) : 0);
     L.total = L.eedf + align16(4 * (size_t)kEedfBins);
     return L;
 }

@@ -91,13 +91,16 @@ template <int NR> struct Aff { double A; double B[NR]; };   // y -> A y + B (NR 
 // factor), the eliminated right-hand sides by an affine scan, the back
 // substitution E_j = d'_j - c'_j E_{j+1} by an affine scan in reverse.  A
 // periodic box takes the wrap coupling by Sherman-Morrison (a third
-// right-hand side).  Thread t owns the Kr cells [t Kr, t Kr + Kr).
+// right-hand side).  Thread t owns the Kr cells [t Kr, t Kr + Kr).  On a
+// nonuniform grid (wr: w_j / dx, electrodes only) the operator acts on
+// F_j = r_j E_j: (1/r + X) F = (D0 + R) / eps0, dx sum_j F_j = phi_0 - phi_N.
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void tridiag_field(const Case& Cc, State* st, long long next_step,
                                               long long field_step, bool sample_density,
                                               const double* S, const double* xd,
-                                              const double* xo, double* red)
+                                              const double* xo, double* red,
+                                              const PIC_GLOBAL double* wr)
 {
     constexpr int kRows = (PIC_MAX_CELLS + NT - 1) / NT;
     constexpr int NR = 3;   // right-hand sides: 1, R / eps0, the periodic correction
@@ -113,11 +116,11 @@ __device__ __forceinline__ void tridiag_field(const Case& Cc, State* st, long lo
     // v = (1, 0.., o / g), g = -(1 + xd_0); T loses the wrap coupling and
     // takes b_0 - g, b_{N-1} - o^2 / g
     const double o_w = periodic ? xo[N - 1] : 0.0;
-    const double g_w = -(1.0 + xd[0]);
+    const double g_w = -((wr ? 1.0 / wr[0] : 1.0) + xd[0]);
     auto coef = [&](int j, double& a, double& b, double& c) {
         a = j > 0 ? xo[j - 1] : 0.0;
         c = j < N - 1 ? xo[j] : 0.0;
-        b = 1.0 + xd[j];
+        b = (wr ? 1.0 / wr[j] : 1.0) + xd[j];
         if (periodic) {
             if (j == 0) b -= g_w;
             if (j == N - 1) b -= o_w * o_w / g_w;
@@ -299,13 +302,15 @@ __device__ __forceinline__ void tridiag_field(const Case& Cc, State* st, long lo
     for (int k = 0; k < kRows; ++k) {
         const int j = j0 + k;
         if (k < Kr && j < N) {
-            const double E = D0e * y[0][k] + y[1][k];
-            run += E;
+            const double F = D0e * y[0][k] + y[1][k];   // E; r E on a nonuniform grid
+            const double r = wr ? wr[j] : 1.0;
+            const double E = F / r;
+            run += F;
             gp(Cc.E)[j] = E;
             gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
             gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
             gp(Cc.phi)[j + 1] = phi0 - dx * run;
-            we += 0.5 * kEps0 * E * E * dx;
+            we += 0.5 * kEps0 * E * E * dx * r;
         }
     }
     we = block_sum<double, NT>(we, red);
@@ -494,21 +499,47 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                     v[s] = n1 * (1ll << kFixBits) - F(s, e1) + F(s, h);
                 }
                 const double chi = (chi0 * (double)v[0] + chi1 * (double)v[1]) / kFixScale;
-                gp(Cc.chi)[h] = chi;   // the row sum of the operator
+                if (!nu) gp(Cc.chi)[h] = chi;   // the row sum of the operator
                 // the operator itself: centre h takes (1 - t)^2 = 2 P0 from
                 // the particles of node h + 1 and t^2 = 2 P2 from those of
                 // node h; the particles of node h + 1 couple centres h and
-                // h + 1 by t (1 - t) = 1/2 - P0 - P2 (none beyond an electrode)
+                // h + 1 by t (1 - t) = 1/2 - P0 - P2 (none beyond an electrode).
+                // On a nonuniform grid (electrodes only) each particle also
+                // carries 1/r^2 of its cell: cell g - 1 for the particles left
+                // of node g, cell g for those right of it.
                 const bool couples = periodic || h + 1 < N;
                 double dg = 0.0, cpl = 0.0;
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const double cs = s == 0 ? chi0 : chi1;
-                    dg += cs * (double)(2 * (long long)dx_w[s][h] + 2 * (long long)dw[s][e1]);
-                    if (couples) {
-                        const long long n1 = (long long)dc[s][e1] + (long long)dx_c[s][e1];
-                        cpl += cs * (double)(n1 * (1ll << (kFixBits - 1)) -
-                                             (long long)dw[s][e1] - (long long)dx_w[s][e1]);
+                    if (!nu) {
+                        dg += cs * (double)(2 * (long long)dx_w[s][h] + 2 * (long long)dw[s][e1]);
+                        if (couples) {
+                            const long long n1 = (long long)dc[s][e1] + (long long)dx_c[s][e1];
+                            cpl += cs * (double)(n1 * (1ll << (kFixBits - 1)) -
+                                                 (long long)dw[s][e1] - (long long)dx_w[s][e1]);
+                        }
+                    } else {
+                        const PIC_GLOBAL unsigned long long* l0 = gp(Cc.chl_w0[s]);
+                        const PIC_GLOBAL unsigned long long* l2 = gp(Cc.chl_w2[s]);
+                        const double rh = wjr[h];
+                        const double ih = 1.0 / (rh * rh);
+                        const double il = h > 0 ? 1.0 / (wjr[h - 1] * wjr[h - 1]) : 0.0;
+                        const double ir = h + 1 < N ? 1.0 / (wjr[h + 1] * wjr[h + 1]) : 0.0;
+                        // node h: P2 of its left (cell h-1) and right (cell h) sides
+                        const long long w2l = (long long)l2[h], w2 = (long long)dx_w[s][h];
+                        // node h+1: P0 of its left (cell h) and right (cell h+1) sides
+                        const long long w0l = (long long)l0[e1], w0 = (long long)dw[s][e1];
+                        dg += cs * (2.0 * ((double)w2l * il + (double)(w2 - w2l) * ih) +
+                                    2.0 * ((double)w0l * ih + (double)(w0 - w0l) * ir));
+                        if (couples) {
+                            const long long nl = (long long)dx_c[s][e1], nr = (long long)dc[s][e1];
+                            const long long w2e = (long long)dx_w[s][e1], w2el = (long long)l2[e1];
+                            const double left = (double)(nl * (1ll << (kFixBits - 1)) - w0l - w2el);
+                            const double right =
+                                (double)(nr * (1ll << (kFixBits - 1)) - (w0 - w0l) - (w2e - w2el));
+                            cpl += cs * (left * ih + right * ir);
+                        }
                     }
                 }
                 X[h] = dg / kFixScale;
@@ -517,6 +548,15 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
         }
     }
     lds_barrier();   // every deposit word has been read
+    if (dual && nu) {
+        // the response to a uniform field: chi_h = sum_h' X_hh' r_h'
+        for (int h = tid; h < N; h += NT) {
+            double x = X[h] * wjr[h];
+            if (h > 0) x += Y[h - 1] * wjr[h - 1];
+            if (h + 1 < N) x += Y[h] * wjr[h + 1];
+            gp(Cc.chi)[h] = x;
+        }
+    }
     if (node_chi) {
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -542,12 +582,17 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
             if (dual) {
                 gp(Cc.chi_cnt[0])[j] = 0; gp(Cc.chi_cnt[1])[j] = 0;
                 gp(Cc.chi_w[0])[j] = 0; gp(Cc.chi_w[1])[j] = 0;
+                if (nu) {
+                    gp(Cc.chl_w0[0])[j] = 0; gp(Cc.chl_w0[1])[j] = 0;
+                    gp(Cc.chl_w2[0])[j] = 0; gp(Cc.chl_w2[1])[j] = 0;
+                }
             }
         }
     }
     if (dual) {
         // the m = 2 implicit field: the tridiagonal operator, solved as such
-        tridiag_field<NT>(Cc, st, next_step, field_step, sample_density, S, X, Y, red);
+        tridiag_field<NT>(Cc, st, next_step, field_step, sample_density, S, X, Y, red,
+                          nu ? wjr : nullptr);
         return;
     }
     // One pass of an associative scan gives every prefix the solve needs.
@@ -1127,9 +1172,17 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
     const bool dual = dual_chi(C->scheme, C->gather);
     unsigned long long* dep = (unsigned long long*)smem;
     unsigned long long* dch = dep + (N + 1);   // dual: susceptibility words
+    // and on a nonuniform grid the left-side P0 and P2 sums
+    const bool duo = dual && C->nonuniform;
+    unsigned long long* dl0 = duo ? dch + (N + 1) : nullptr;
+    unsigned long long* dl2 = duo ? dl0 + (N + 1) : nullptr;
     for (int j = threadIdx.x; j <= N; j += kBlock) {
         dep[j] = 0ull;
         if (dual) dch[j] = 0ull;
+        if (duo) {
+            dl0[j] = 0ull;
+            dl2[j] = 0ull;
+        }
     }
     if (threadIdx.x == 0) {
         s_lo = kNoCell;
@@ -1145,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         const int c = cell_of(S.cell[i]);
         if (c < 0) continue;
         if (dual) {
-            deposit_moments(dep, dch, true, c, S.off[i], N, periodic, lo, hi);
+            deposit_moments(dep, dch, true, c, S.off[i], N, periodic, lo, hi, false, dl0, dl2);
         } else if (ec2) {
             deposit_quad(dep, true, c, S.off[i], N, periodic, lo, hi);
         } else {
@@ -1168,6 +1221,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Params P)
         if (d) {
             atomicAdd(&C->chi_cnt[w.s][j], d >> 40);
             atomicAdd(&C->chi_w[w.s][j], d & kWMask);
+        }
+        if (duo) {
+            if (dl0[j]) atomicAdd(&C->chl_w0[w.s][j], dl0[j]);
+            if (dl2[j]) atomicAdd(&C->chl_w2[w.s][j], dl2[j]);
         }
     }
 }

@@ -107,9 +107,9 @@ struct pic_ctx {
     std::vector<CollideWork> cwork;                 // k_collide work table
     int cgrp_off[2] = {0, 0}, cgrp_cnt[2] = {0, 0};
     CollideWork* d_cwork = nullptr;
-    int grp_maxN[2] = {0, 0};
-    bool grp_dual[2] = {false, false};   // a case of the group has the dual grid
-    bool grp_nu[2] = {false, false};     // a case of the group has a nonuniform grid
+    size_t grp_slds[2][2] = {{0, 0}, {0, 0}};   // k_step LDS of a group ([diag])
+    size_t grp_clds[2] = {0, 0};                // k_collide LDS of a group
+    size_t dep_lds_max = 0;                     // k_deposit LDS over all cases
     bool any_dual = false;
     int maxN = 0;
     int tile = 8192;
@@ -230,15 +230,26 @@ size_t step_lds(int N, bool diag, bool dual, bool nu)
     return step_lds_layout(N, diag, dual, nu).total;
 }
 
-size_t collide_lds(int N, bool dual)
+size_t collide_lds(int N, bool dual, bool nu)
 {
-    return collide_lds_layout(N, dual).total;
+    return collide_lds_layout(N, dual, nu).total;
 }
 
-// k_deposit: node words dep[N+1] | (dual) susceptibility words [N+1]
-size_t deposit_lds(int N, bool dual)
+// k_deposit: node words dep[N+1] | (dual) susceptibility words [N+1] |
+// (dual, nonuniform) left-side sums 2 x [N+1]
+size_t deposit_lds(int N, bool dual, bool nu)
 {
-    return 8 * ((size_t)N + 1) * (dual ? 2 : 1);
+    return 8 * ((size_t)N + 1) * (dual ? (nu ? 4 : 2) : 1);
+}
+
+// the most dynamic LDS one workgroup may hold
+constexpr size_t kLdsMax = 160 * 1024;
+
+// the largest LDS any kernel of one case asks for
+size_t case_lds(int N, bool dual, bool nu)
+{
+    return std::max(std::max(step_lds(N, true, dual, nu), collide_lds(N, dual, nu)),
+                    deposit_lds(N, dual, nu));
 }
 
 // k_finalize / k_solve: rho prefix S[N+1], chi per cell X[N], chi per node
@@ -290,9 +301,8 @@ int build_work(pic_ctx* c)
     c->cwork.clear();
     for (int g = 0; g < 2; ++g) {
         c->grp_off[g] = (int)c->work.size();
-        c->grp_maxN[g] = 0;
-        c->grp_dual[g] = false;
-        c->grp_nu[g] = false;
+        c->grp_slds[g][0] = c->grp_slds[g][1] = 0;
+        c->grp_clds[g] = 0;
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
@@ -304,9 +314,13 @@ int build_work(pic_ctx* c)
             }
             C.n_blocks = (int)c->work.size() - C.first_block;
 
-            c->grp_maxN[g] = std::max(c->grp_maxN[g], (int)h.cfg.n_cells);
-            c->grp_dual[g] = c->grp_dual[g] || dual_chi(h.cfg.scheme, h.cfg.gather);
-            c->grp_nu[g] = c->grp_nu[g] || !h.cell_w.empty();
+            // each workgroup lays its LDS out for its own case: the launch
+            // takes the largest
+            const int Nk = h.cfg.n_cells;
+            const bool dk = dual_chi(h.cfg.scheme, h.cfg.gather), nk = !h.cell_w.empty();
+            for (int d = 0; d < 2; ++d)
+                c->grp_slds[g][d] = std::max(c->grp_slds[g][d], step_lds(Nk, d == 1, dk, nk));
+            c->grp_clds[g] = std::max(c->grp_clds[g], collide_lds(Nk, dk, nk));
         }
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
     }
@@ -460,8 +474,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
              g.gather != PIC_GATHER_EC2) ||
             g.history_steps < 0 || g.ion_subcycle < 0 || g.ion_subcycle > 4096 ||
             (g.ion_subcycle > 1 && g.scheme != PIC_EXPLICIT) ||
-            (g.cell_dx_m && (g.bc != PIC_BC_DIRICHLET_RF ||
-                             (g.gather == PIC_GATHER_EC2 && g.scheme != PIC_EXPLICIT))) ||
+            (g.cell_dx_m && g.bc != PIC_BC_DIRICHLET_RF) ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
             return bail(PIC_E_INVAL);
@@ -476,6 +489,16 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             }
             if (!ok || !(std::fabs(L - g.gap_m) <= 1e-9 * g.gap_m)) {
                 fprintf(stderr, "pic_init: case %d: bad cell widths\n", k);
+                return bail(PIC_E_INVAL);
+            }
+        }
+        {
+            // (m = 2 implicit on a nonuniform grid: above 3391 cells)
+            const size_t need = case_lds(g.n_cells, dual_chi(g.scheme, g.gather),
+                                         g.cell_dx_m != nullptr);
+            if (need > kLdsMax) {
+                fprintf(stderr, "pic_init: case %d: %d cells need %zu bytes of LDS\n", k,
+                        g.n_cells, need);
                 return bail(PIC_E_INVAL);
             }
         }
@@ -553,6 +576,8 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         C.key1 = (uint32_t)(g.seed >> 32);
         c->maxN = std::max(c->maxN, N);
         c->any_dual = c->any_dual || dual_chi(g.scheme, g.gather);
+        c->dep_lds_max = std::max(c->dep_lds_max, deposit_lds(N, dual_chi(g.scheme, g.gather),
+                                                              g.cell_dx_m != nullptr));
         // Eq. (1): omega_p dt < 2 for the explicit leap-frog
         if (g.scheme == PIC_EXPLICIT && !(flags & PIC_FLAG_ALLOW_UNSTABLE)) {
             const pic_species_init& e = species[2 * k];
@@ -757,6 +782,10 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             if (dual_chi(C.scheme, C.gather)) {
                 rc |= dalloc(c, h.allocs, &C.chi_cnt[s], N + 1);
                 rc |= dalloc(c, h.allocs, &C.chi_w[s], N + 1);
+                if (C.nonuniform) {
+                    rc |= dalloc(c, h.allocs, &C.chl_w0[s], N + 1);
+                    rc |= dalloc(c, h.allocs, &C.chl_w2[s], N + 1);
+                }
             }
             rc |= dalloc(c, h.allocs, &C.ehat[s], N);
             rc |= dalloc(c, h.allocs, &C.qfix[s], N + 1);
@@ -802,9 +831,12 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         h.hist_off[1] = hist_total + N;
         hist_total += 2 * (size_t)N;
     }
-    if (set_lds_limits(c, std::max(std::max(step_lds(c->maxN, true, c->any_dual, true),
-                                            collide_lds(c->maxN, c->any_dual)),
-                                   std::max(deposit_lds(c->maxN, c->any_dual), fin_lds(c->maxN)))))
+    size_t lds_need = fin_lds(c->maxN);
+    for (int k = 0; k < n_cases; ++k)
+        lds_need = std::max(lds_need, case_lds(cases[k].n_cells,
+                                               dual_chi(cases[k].scheme, cases[k].gather),
+                                               cases[k].cell_dx_m != nullptr));
+    if (set_lds_limits(c, lds_need))
         return bail(PIC_E_INVAL);
     // ---- context arrays ----
     c->hist_total = hist_total;
@@ -860,7 +892,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
         if (compaction(c)) return bail(PIC_E_DEVICE);
         Params p = params(c, 0);
         hipLaunchKernelGGL(k_deposit, dim3(c->n_blocks), dim3(kBlock),
-                           deposit_lds(c->maxN, c->any_dual), c->stream, p);
+                           c->dep_lds_max, c->stream, p);
         hipLaunchKernelGGL(k_solve, dim3(n_cases), dim3(kFinBlock), fin_lds(c->maxN),
                            c->stream, p);
         INITCHK(hipGetLastError());
@@ -932,7 +964,6 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
         if (!c->grp_cnt[g]) continue;
         Params p = params(c, c->grp_off[g]);
         Params pc = params(c, c->cgrp_off[g]);
-        const int N = c->grp_maxN[g];
         auto ks = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
                          : (diag ? k_step<1, true> : k_step<1, false>);
         auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
@@ -943,11 +974,10 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             if (rec) HIPCHK(c, record(pool->ev[pool->used]));
             if (kind == 0)
                 hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock),
-                                   step_lds(N, diag, c->grp_dual[g], c->grp_nu[g]), c->stream,
-                                   p);
+                                   c->grp_slds[g][diag ? 1 : 0], c->stream, p);
             else
                 hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
-                                   collide_lds(N, c->grp_dual[g]), c->stream, pc);
+                                   c->grp_clds[g], c->stream, pc);
             if (rec) {
                 HIPCHK(c, record(pool->ev[pool->used + 1]));
                 pool->used += 2;

@@ -231,6 +231,10 @@ __device__ __forceinline__ void deposit_global(const Case* C, int s, int c, floa
         add(&gw[i], (unsigned long long)w[0]);
         add(gp(&C->chi_cnt[s][i]), left ? 1ull : 0ull);
         add(gp(&C->chi_w[s][i]), (unsigned long long)w[2]);
+        if (C->chl_w0[s] && left) {   // nonuniform grid: the left-side sums
+            add(gp(&C->chl_w0[s][i]), (unsigned long long)w[0]);
+            add(gp(&C->chl_w2[s][i]), (unsigned long long)w[2]);
+        }
         return;
     }
     if (C->gather == 2) {
@@ -303,6 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     float* eh = (float*)smem;
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
     unsigned long long* dch = (unsigned long long*)(smem + L.dual);
+    // m = 2 implicit on a nonuniform grid: the left-side P0 and P2 sums
+    const bool duo = dual && nu;
+    unsigned long long* dl0 =
+        duo ? (unsigned long long*)(smem + L.dual + align16(8 * ((size_t)N + 1))) : nullptr;
+    unsigned long long* dl2 =
+        duo ? (unsigned long long*)(smem + L.dual + 2 * align16(8 * ((size_t)N + 1))) : nullptr;
     float* rl = (float*)(smem + L.ratio);   // nonuniform: dx / w_c
     uint32_t* ul = (uint32_t*)(smem + L.ratio + align16(4 * (size_t)N));   // and the runs
     float* heat = (float*)(smem + L.heat);
@@ -335,7 +345,13 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     }
     if (tid == 0) dep[N] = 0ull;   // node N of the quadratic deposit
     if (dual)
-        for (int j = tid; j <= N; j += kBlock) dch[j] = 0ull;
+        for (int j = tid; j <= N; j += kBlock) {
+            dch[j] = 0ull;
+            if (duo) {
+                dl0[j] = 0ull;
+                dl2[j] = 0ull;
+            }
+        }
     if (nu) {
         const PIC_GLOBAL float* rg = gp(C->cell_r);
         const PIC_GLOBAL uint32_t* ug = gp(C->cell_run);
@@ -531,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 dep_now = !kImp || kept;
             }
             if (dual)
-                deposit_moments(dep, dch, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
+                deposit_moments(dep, dch, dep_now, c2, o2, N, periodic, lo, hi, s == 1, dl0, dl2);
             else if (ec2)
                 deposit_quad(dep, dep_now, c2, o2, N, periodic, lo, hi, s == 1);
             else
@@ -582,6 +598,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 if (d) {
                     gatomic_add(gp(&C->chi_cnt[s][j]), d >> 40);
                     gatomic_add(gp(&C->chi_w[s][j]), d & kWMask);
+                }
+                if (duo) {
+                    if (dl0[j]) gatomic_add(gp(&C->chl_w0[s][j]), dl0[j]);
+                    if (dl2[j]) gatomic_add(gp(&C->chl_w2[s][j]), dl2[j]);
                 }
             }
             // the range covers nodes (up to N for the quadratic deposit);
@@ -678,9 +698,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     const PIC_GLOBAL float* rg = gp(uniform_ptr((const float*)C->cell_r));   // nu: dx / w_c
     const PIC_GLOBAL uint32_t* ug = gp(uniform_ptr((const uint32_t*)C->cell_run));   // and runs
     const uint32_t k0 = C->key0, k1 = C->key1;
-    const CollideLds L = collide_lds_layout(N, dual);
+    const CollideLds L = collide_lds_layout(N, dual, nu);
     unsigned long long* dep = (unsigned long long*)smem;
     unsigned long long* dch = (unsigned long long*)(smem + L.dual);
+    const bool duo = dual && nu;   // the left-side sums (nonuniform grid)
+    unsigned long long* dl0 =
+        duo ? (unsigned long long*)(smem + L.dual + align16(8 * ((size_t)N + 1))) : nullptr;
+    unsigned long long* dl2 =
+        duo ? (unsigned long long*)(smem + L.dual + 2 * align16(8 * ((size_t)N + 1))) : nullptr;
     unsigned* eedf = (unsigned*)(smem + L.eedf);
     __shared__ float lbound[kBoundBins];
     if (s == 0 && C->sp[0].n_proc > 0)
@@ -689,6 +714,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
         for (int j = tid; j <= N; j += kBlock) {
             dep[j] = 0ull;
             if (dual) dch[j] = 0ull;
+            if (duo) {
+                dl0[j] = 0ull;
+                dl2[j] = 0ull;
+            }
         }
     if (DIAG)
         for (int j = tid; j < kEedfBins; j += kBlock) eedf[j] = 0u;
@@ -935,7 +964,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
         }
         if (kImp) {
             if (ec2) {
-                deposit_moments(dep, dch, dep_ok, c2, o2, N, periodic, lo, hi);
+                deposit_moments(dep, dch, dep_ok, c2, o2, N, periodic, lo, hi, false, dl0, dl2);
             } else {
                 deposit_wave(dep, dep_ok, c2, o2, lo, hi);
             }
@@ -1005,6 +1034,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                 if (d) {
                     gatomic_add(gp(&C->chi_cnt[s][j]), d >> 40);
                     gatomic_add(gp(&C->chi_w[s][j]), d & kWMask);
+                }
+                if (duo) {
+                    if (dl0[j]) gatomic_add(gp(&C->chl_w0[s][j]), dl0[j]);
+                    if (dl2[j]) gatomic_add(gp(&C->chl_w2[s][j]), dl2[j]);
                 }
             }
         }

@@ -167,9 +167,13 @@ __device__ __forceinline__ unsigned long long packw(float o)
 // 2 P2 2^-24, (1 - t)^2 = 2 P0 2^-24 per particle).  sorted: the lanes of a
 // cell-sorted species share at most two nodes; their words are summed
 // across the wavefront first (called by whole wavefronts then).
+// L0, L2 (nonuniform grid, else null): the P0 and P2 sums of the particles
+// left of their nearest node.
 __device__ __forceinline__ void deposit_moments(unsigned long long* A, unsigned long long* B,
                                                 bool want, int c, float o, int N, bool periodic,
-                                                int& lo, int& hi, bool sorted = false)
+                                                int& lo, int& hi, bool sorted = false,
+                                                unsigned long long* L0 = nullptr,
+                                                unsigned long long* L2 = nullptr)
 {
     uint32_t w[3] = {0u, 0u, 0u};
     int i = c;
@@ -194,10 +198,19 @@ __device__ __forceinline__ void deposit_moments(unsigned long long* A, unsigned 
                 const bool mine = ((mg >> lane) & 1ull) != 0ull;
                 const unsigned t0 = wave_total_u32(mine ? w[0] : 0u);
                 const unsigned t2 = wave_total_u32(mine ? w[2] : 0u);
+                unsigned l0 = 0u, l2 = 0u;
+                if (L0) {
+                    l0 = wave_total_u32(mine && left ? w[0] : 0u);
+                    l2 = wave_total_u32(mine && left ? w[2] : 0u);
+                }
                 if (lane == __ffsll((long long)mg) - 1) {
                     const int ig = g == 0 ? ia : ib;
                     atomicAdd(&A[ig], (unsigned long long)__popcll(mg & ~ml) * kCountOne + t0);
                     atomicAdd(&B[ig], (unsigned long long)__popcll(mg & ml) * kCountOne + t2);
+                    if (L0) {
+                        if (l0) atomicAdd(&L0[ig], (unsigned long long)l0);
+                        if (l2) atomicAdd(&L2[ig], (unsigned long long)l2);
+                    }
                     range_note(lo, hi, ig);
                 }
             }
@@ -207,6 +220,10 @@ __device__ __forceinline__ void deposit_moments(unsigned long long* A, unsigned 
     if (!want) return;
     atomicAdd(&A[i], (left ? 0ull : kCountOne) + (unsigned long long)w[0]);
     atomicAdd(&B[i], (left ? kCountOne : 0ull) + (unsigned long long)w[2]);
+    if (L0 && left) {
+        atomicAdd(&L0[i], (unsigned long long)w[0]);
+        atomicAdd(&L2[i], (unsigned long long)w[2]);
+    }
     range_note(lo, hi, i);
 }
 

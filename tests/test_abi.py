@@ -85,13 +85,16 @@ def test_init_rejects_bad_input_without_a_gpu():
     # nonuniform grids: EC gather between electrodes, positive widths summing
     # to the gap
     good = (C.c_double * 8)(*([0.01 / 8] * 8))
-    for field, value in (("gather", 2), ("bc", 1)):
-        setattr(cfg[0], field, value)
-        cfg[0].scheme = 1          # m = 2 on a nonuniform grid: explicit only
-        cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
-        assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL, field
-        setattr(cfg[0], field, 0)
-        cfg[0].scheme = 0
+    cfg[0].bc = 1
+    cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
+    assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
+    cfg[0].bc = 0
+    # m = 2 implicit on a nonuniform grid: its LDS words fit up to 3391 cells
+    big = (C.c_double * 3392)(*([0.01 / 3392] * 3392))
+    cfg[0].n_cells, cfg[0].scheme, cfg[0].gather = 3392, 1, 2
+    cfg[0].cell_dx_m = C.cast(big, C.POINTER(C.c_double))
+    assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
+    cfg[0].n_cells, cfg[0].scheme, cfg[0].gather = 8, 0, 0
     for widths in ([0.01 / 8] * 7 + [0.0], [0.01 / 7] * 8, [0.02] + [-0.01 / 7] * 7):
         arr = (C.c_double * 8)(*widths)
         cfg[0].cell_dx_m = C.cast(arr, C.POINTER(C.c_double))

@@ -162,12 +162,12 @@ def test_periodic_ec2_implicit_teacher_forced():
 
 @pytest.mark.parametrize("scheme,steps_per_period,gather", [(0, 400, 0), (1, 100, 0),
                                                            (0, 400, 1), (1, 100, 1),
-                                                           (0, 400, 2)])
+                                                           (0, 400, 2), (1, 100, 2)])
 def test_ccp64_nonuniform_teacher_forced(scheme, steps_per_period, gather):
     # sheath-refined grid: cells about 4x narrower within 15 % of the gap
     # from either electrode; the implicit run takes 4x the time step, so that
-    # fast electrons cross several narrow cells in one move (EC and MC
-    # gathers; m = 2 explicit)
+    # fast electrons cross several narrow cells in one move (EC, MC and
+    # m = 2 gathers)
     f = 13.56e6
     wl = W.ccp_workload("ccp64_nonuniform", n_cells=64, np_per_species=16384 + 77,
                         volts=100.0, p_mtorr=50.0, dt=1.0 / (steps_per_period * f),

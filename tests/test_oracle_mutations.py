@@ -76,12 +76,21 @@ MUTANTS = [
      "if (ina && inb) off[a] += wb * wb;", None),
     ("m=2 operator diagonal weight", "if (ina) diag[a] += wa * wa;",
      "if (ina) diag[a] += wa * wb;", None),
-    ("tridiagonal solve D0 sign", "double D0e = (phi0 / dx - sv) / su;",
+    ("tridiagonal solve D0 sign", "double D0e = (phi0 / dx - sv) / su;   /* D0 / eps0 */",
      "double D0e = (phi0 / dx + sv) / su;", None),
     ("tridiagonal solve sub-diagonal", "double a = j > 0 ? xo[j - 1] : 0.0;",
      "double a = j > 0 ? xo[j] : 0.0;", None),
     ("periodic solve one-sided wrap", "A[(size_t)k * w + j] += xo[j];",
      "A[(size_t)k * w + j] += 0.0 * xo[j];", None),
+    ("m=2 nonuniform operator with one power of the width", "double f = 1.0 / (rc * rc);",
+     "double f = 1.0 / rc;", None),
+    ("m=2 nonuniform field without the width ratio", "E[j] = F * dx / w[j];", "E[j] = F;", None),
+    ("m=2 nonuniform diagonal of the reference width", "dg[j] = dx / w[j];", "dg[j] = 1.0;", None),
+    ("m=2 nonuniform D0 sign",
+     "double D0e = (phi0 / dx - sv) / su;   /* from dx sum_j F_j = phi_0 - phi_N */",
+     "double D0e = (phi0 / dx + sv) / su;", None),
+    ("m=2 nonuniform potential from E", "phi[j + 1] = phi[j] - dx * F;",
+     "phi[j + 1] = phi[j] - dx * E[j];", None),
     ("m=2 exported chi without its left coupling",
      "double left = j > 0 ? s->xo[j - 1] : (periodic ? s->xo[N - 1] : 0.0);",
      "double left = 0.0;", None),
