@@ -78,6 +78,11 @@ def make_workload(name, scale):
         wl = W.c4(np_per_species=int(10_000_000 * scale))
         wl["case"]["ion_subcycle"] = 8
         return [wl]
+    if name == "ccp2048_implicit_subcycle8":
+        # the D1 implicit discharge with the ions pushed every 8th step with 8 dt
+        wl = W.c4(np_per_species=int(10_000_000 * scale), scheme=1)
+        wl["case"]["ion_subcycle"] = 8
+        return [wl]
     if name == "ccp64_explicit":
         return [W.c1()]
     if name == "ccp256_implicit":

@@ -574,6 +574,17 @@ static int moves(const orc_sim* s, int sp)
     return !(sp == 1 && s->c.ion_subcycle > 1) || s->step % s->c.ion_subcycle == 0;
 }
 
+/* The weight of species sp in the D1 susceptibility, q^2 w / m (h dt)^2 / dt^2
+ * with h its time step in units of dt: a subcycled species responds only to
+ * the field of the steps in which it moves (zero otherwise). */
+static double chi_weight(const orc_sim* s, int sp)
+{
+    const species_t* p = &s->sp[sp];
+    if (!(p->m > 0.0) || !moves(s, sp)) return 0.0;
+    double h = substep(s, sp);
+    return p->q * p->q * p->w / p->m * h * h;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Simulation object                                                        */
 /* ------------------------------------------------------------------------ */
@@ -583,7 +594,7 @@ orc_sim* orc_create(const orc_case* c)
 {
     if (c->n_cells < 2) return NULL;
     if (c->gather < ORC_GATHER_EC || c->gather > ORC_GATHER_EC2) return NULL;
-    if (c->ion_subcycle < 0 || (c->ion_subcycle > 1 && c->scheme != ORC_EXPLICIT)) return NULL;
+    if (c->ion_subcycle < 0) return NULL;
     if (c->cell_dx_m) {
         /* nonuniform grids: between electrodes, widths summing to L */
         if (c->bc != ORC_BC_DIRICHLET) return NULL;
@@ -869,8 +880,7 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
         for (int32_t j = 0; j < N; ++j) {
             double d = 0.0, o = 0.0;
             for (int k = 0; k < 2; ++k) {
-                if (!(s->sp[k].m > 0.0)) continue;
-                double f = s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m;
+                double f = chi_weight(s, k);
                 d += f * s->chw[k][j];
                 o += f * s->cho[k][j];
             }
@@ -908,22 +918,14 @@ static void fields(orc_sim* s, int use_chi, int64_t step_for_bc)
                 if (!periodic && (g == 0 || g == N)) vol = 0.5 * s->dx;
                 if (s->cw)   /* half of each adjacent cell */
                     vol = 0.5 * ((g > 0 ? s->cw[g - 1] : 0.0) + (g < N ? s->cw[g] : 0.0));
-                for (int k = 0; k < 2; ++k) {
-                    if (!(s->sp[k].m > 0.0)) continue;
-                    /* the periodic deposit holds the folded node in Q_0 and Q_N */
-                    x += 0.5 * s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m *
-                         s->Q[k][g] / vol;
-                }
+                /* the periodic deposit holds the folded node in Q_0 and Q_N */
+                for (int k = 0; k < 2; ++k) x += 0.5 * chi_weight(s, k) * s->Q[k][g] / vol;
             }
             s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / EPS0 * x;
             continue;
         }
         if (use_chi)
-            for (int k = 0; k < 2; ++k) {
-                const double* nj = s->c.gather == ORC_GATHER_EC2 ? s->chw[k] : s->cnt[k];
-                if (s->sp[k].m > 0.0)
-                    x += s->sp[k].q * s->sp[k].q * s->sp[k].w / s->sp[k].m * nj[j];
-            }
+            for (int k = 0; k < 2; ++k) x += chi_weight(s, k) * s->cnt[k][j];
         s->chi[j] = 0.5 * s->c.dt_s * s->c.dt_s / (EPS0 * (s->cw ? s->cw[j] : s->dx)) * x;
     }
     if (periodic)
@@ -1166,22 +1168,29 @@ static void begin_ledger(orc_sim* s, int implicit)
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
         double K = 0.0;
+        /* implicit state stores v~ = v_{n-1/2} + h dt abar/2 */
+        double hdt = s->c.dt_s * substep(s, k);
         for (int64_t i = 0; i < p->n; ++i) {
-            /* implicit state stores v~ = v_{n-1/2} + dt abar/2 */
-            double vx = implicit ? p->vx[i] - 0.5 * s->c.dt_s * p->abar[i] : p->vx[i];
+            double vx = implicit ? p->vx[i] - 0.5 * hdt * p->abar[i] : p->vx[i];
             K += kin(p, vx, p->vy[i], p->vz[i]);
         }
         s->led.K_before[k] = K;
     }
 }
 
-static void end_ledger(orc_sim* s, const double* vhalf_x[2])
+/* Kinetic energy at n+1/2; a species that stood in an implicit step still
+ * holds its prediction, v~ = v + h dt abar/2. */
+static void end_ledger(orc_sim* s, int implicit)
 {
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
+        const int held = implicit && !moves(s, k);
+        double hdt = s->c.dt_s * substep(s, k);
         double K = 0.0;
-        for (int64_t i = 0; i < p->n; ++i)
-            K += kin(p, vhalf_x[k] ? vhalf_x[k][i] : p->vx[i], p->vy[i], p->vz[i]);
+        for (int64_t i = 0; i < p->n; ++i) {
+            double vx = held ? p->vx[i] - 0.5 * hdt * p->abar[i] : p->vx[i];
+            K += kin(p, vx, p->vy[i], p->vz[i]);
+        }
         s->led.K_after[k] = K;
     }
 }
@@ -1235,8 +1244,7 @@ static void step_explicit(orc_sim* s)
         }
     }
     if (s->c.collisions) mcc_all(s);
-    const double* vh[2] = {NULL, NULL};
-    end_ledger(s, vh);
+    end_ledger(s, 0);
     s->step++;
 }
 
@@ -1250,14 +1258,18 @@ static void step_explicit(orc_sim* s)
 /* absorb at x_{n+1}, MCC on v_{n+1/2}, and predict the next step:          */
 /*   v~' = v_{n+1/2} + dt abar_n / 2,  x~_{n+2} = x_{n+1} + dt v~'           */
 /* (a prediction outside the gap is absorbed at once).                      */
+/* Subcycled ions take the cycle with h dt in place of dt in the steps in   */
+/* which they move and stand in the others (their prediction held, their    */
+/* susceptibility left out of the solve).                                   */
 /* ------------------------------------------------------------------------ */
 static void step_implicit(orc_sim* s)
 {
-    double dt = s->c.dt_s, dt_dx = s->c.dt_s / s->dx;
     fields(s, 1, s->step + 1);
     begin_ledger(s, 1);
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
+        if (!moves(s, k)) continue;
+        double dt = s->c.dt_s * substep(s, k);
         double qm = p->q / p->m;
         int64_t i = 0;
         while (i < p->n) {
@@ -1285,10 +1297,11 @@ static void step_implicit(orc_sim* s)
     }
     if (s->c.collisions) mcc_all(s);
     /* kinetic energy at n+1/2 is taken before the prediction */
-    const double* vh[2] = {NULL, NULL};
-    end_ledger(s, vh);
+    end_ledger(s, 1);
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
+        if (!moves(s, k)) continue;
+        double dt = s->c.dt_s * substep(s, k), dt_dx = dt / s->dx;
         int64_t i = 0;
         while (i < p->n) {
             double vt = p->vx[i] + 0.5 * dt * p->abar[i];
@@ -1313,13 +1326,13 @@ static void step_implicit(orc_sim* s)
 
 int orc_implicit_startup(orc_sim* s)
 {
-    double dt_dx = s->c.dt_s / s->dx;
     for (int k = 0; k < 2; ++k) {
         species_t* p = &s->sp[k];
+        double dt = s->c.dt_s * substep(s, k), dt_dx = dt / s->dx;
         int64_t i = 0;
         while (i < p->n) {
             p->abar[i] = 0.0;
-            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * s->c.dt_s);
+            if (s->cw) move_nonuniform(s, &p->xi[i], p->vx[i] * dt);
             else p->xi[i] += p->vx[i] * dt_dx;
             if (boundary(s, &p->xi[i]) >= 0) { remove_particle(p, i); continue; }
             ++i;

@@ -294,10 +294,13 @@ __device__ __forceinline__ void renorm(int& c, float& o)
 // D1 prediction from x_{n+1} = (c, o) with v_{n+1/2} and abar_n (cells per
 // step): v~ = v + abar/2, x~ = x + v~.  One rounding per operation, so that
 // k_step and k_collide reproduce the same prediction bit for bit.  Returns v~.
-__device__ __forceinline__ float predict(int& c, float& o, float vn, float abn)
+//
+// kf: the species' time step in units of dt (K for subcycled ions, else 1):
+// v~ = v + kf abar / 2, x~ = x + kf v~.
+__device__ __forceinline__ float predict(int& c, float& o, float vn, float abn, float kf = 1.0f)
 {
-    const float vst = fmaf(0.5f, abn, vn);
-    o = __fadd_rn(o, vst);
+    const float vst = fmaf(0.5f * kf, abn, vn);
+    o = __fadd_rn(o, kf * vst);
     renorm(c, o);
     return vst;
 }
@@ -379,10 +382,10 @@ __device__ __forceinline__ void walk(int& c, float& o, float d, RP r, UP run, in
 // The D1 prediction on a nonuniform grid (the walk in place of renorm).
 template <class RP, class UP>
 __device__ __forceinline__ float predict_nu(int& c, float& o, float vn, float abn, RP r, UP run,
-                                            int N)
+                                            int N, float kf = 1.0f)
 {
-    const float vst = fmaf(0.5f, abn, vn);
-    walk(c, o, vst, r, run, N);
+    const float vst = fmaf(0.5f * kf, abn, vn);
+    walk(c, o, kf * vst, r, run, N);
     return vst;
 }
 

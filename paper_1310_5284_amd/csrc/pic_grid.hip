@@ -354,15 +354,18 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // selected afterwards, so that none waits behind a branch).
     constexpr int kB = kDual ? 1 : 3;   // (3 with the moment path would spill)
     const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
-    const double chi0 = Cc.sp[0].chi_coef, chi1 = Cc.sp[1].chi_coef;
+    // subcycled ions keep their deposit until the step in which they move
+    // (and deposit again); they respond only to the field they are
+    // corrected with, the one of the solve before that step (field_step:
+    // the index of the step that uses this field; next_step is the time of
+    // the boundary voltage, one later for the implicit field)
+    const bool ions_move = Cc.ion_sub <= 1 || field_step % Cc.ion_sub == 0;
+    const double chi0 = Cc.sp[0].chi_coef, chi1 = ions_move ? Cc.sp[1].chi_coef : 0.0;
     const double rho_bg = Cc.background_rho;
     const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
     const bool dual = kDual && implicit && ec2;   // moment words (deposit_moments)
     const bool nu = Cc.nonuniform != 0;
     const PIC_GLOBAL double* wjr = gp((const double*)Cc.cell_wr);   // nu: w_j / dx
-    // subcycled ions keep their deposit until the step in which they move
-    // (and deposit again)
-    const bool ions_move = Cc.ion_sub <= 1 || next_step % Cc.ion_sub == 0;
     // m = 2 implicit: the second moment words (counts of the particles left
     // of their nearest node, sums of their weights to the node after it)
     const PIC_GLOBAL unsigned long long* dx_c[2] = {
@@ -580,11 +583,19 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                 gp(Cc.dep_w[1])[j] = 0;
             }
             if (dual) {
-                gp(Cc.chi_cnt[0])[j] = 0; gp(Cc.chi_cnt[1])[j] = 0;
-                gp(Cc.chi_w[0])[j] = 0; gp(Cc.chi_w[1])[j] = 0;
+                gp(Cc.chi_cnt[0])[j] = 0;
+                gp(Cc.chi_w[0])[j] = 0;
                 if (nu) {
-                    gp(Cc.chl_w0[0])[j] = 0; gp(Cc.chl_w0[1])[j] = 0;
-                    gp(Cc.chl_w2[0])[j] = 0; gp(Cc.chl_w2[1])[j] = 0;
+                    gp(Cc.chl_w0[0])[j] = 0;
+                    gp(Cc.chl_w2[0])[j] = 0;
+                }
+                if (ions_move) {
+                    gp(Cc.chi_cnt[1])[j] = 0;
+                    gp(Cc.chi_w[1])[j] = 0;
+                    if (nu) {
+                        gp(Cc.chl_w0[1])[j] = 0;
+                        gp(Cc.chl_w2[1])[j] = 0;
+                    }
                 }
             }
         }
@@ -897,11 +908,13 @@ __global__ __launch_bounds__(kBlock) void k_init_species(Params P, double vscale
         }
         float o = S.off[i];
         if (startup) {
+            // the first prediction x~ = x + K v, K the species' step
+            const float kf = w.s == 1 ? (float)C->ion_sub : 1.0f;
             S.abar[i] = 0.0f;
             if (C->nonuniform) {
-                walk(c, o, S.vx[i], C->cell_r, C->cell_run, N);
+                walk(c, o, kf * S.vx[i], C->cell_r, C->cell_run, N);
             } else {
-                o += S.vx[i];
+                o += kf * S.vx[i];
                 renorm(c, o);
             }
             if (C->bc == 1) {
@@ -1042,6 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
     const int sh = bucket_shift(w.s);
     const int NB = n_buckets(C->n_cells, w.s);
     const bool imp = C->scheme == 1;
+    const float hk = 0.5f * (w.s == 1 ? (float)C->ion_sub : 1.0f);   // K/2
     PIC_GLOBAL uint32_t* cur = gp(cursor_all + hist_off[2 * w.c + w.s]);
     unsigned* lh = (unsigned*)smem;
     unsigned* lb = lh + NB;
@@ -1121,7 +1135,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(Params P, uint32_t* 
             float vh = vx[k];
             if (imp) {
                 ab2[d] = ab[k];
-                vh = vx[k] - 0.5f * ab[k];   // v_{n-1/2} from the stored prediction
+                vh = vx[k] - hk * ab[k];   // v_{n-1/2} from the stored prediction
             }
             const float vy = rec_vy(rc[k]), vz = rec_vz(rc[k]);
             v2 += (double)(vh * vh + vy * vy + vz * vz);

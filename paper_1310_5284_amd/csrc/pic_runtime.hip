@@ -473,7 +473,6 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             (g.gather != PIC_GATHER_EC && g.gather != PIC_GATHER_MC &&
              g.gather != PIC_GATHER_EC2) ||
             g.history_steps < 0 || g.ion_subcycle < 0 || g.ion_subcycle > 4096 ||
-            (g.ion_subcycle > 1 && g.scheme != PIC_EXPLICIT) ||
             (g.cell_dx_m && g.bc != PIC_BC_DIRICHLET_RF) ||
             g.start_step < 0) {
             fprintf(stderr, "pic_init: case %d: bad configuration\n", k);
@@ -610,7 +609,9 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             S.accel = q / m * dt * dt / dx;
             S.qw_dx = q * w / dx;
             S.kin_unit = 0.5 * m * w * (dx / dt) * (dx / dt);
-            S.chi_coef = 0.5 * dt * dt * q * q * w / (m * EPS0 * dx);
+            // subcycled ions respond over their own step K dt
+            const double hs = (s == 1 && g.ion_subcycle > 1) ? (double)g.ion_subcycle : 1.0;
+            S.chi_coef = 0.5 * dt * dt * hs * hs * q * q * w / (m * EPS0 * dx);
             S.dens_unit = w / dx;
             const double eps_unit = 0.5 * m * (dx / dt) * (dx / dt) / QE;
             S.eps_unit = (float)eps_unit;

@@ -383,6 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const int ksub = s == 1 ? C->ion_sub : 1;
     const bool stands = ksub > 1 && (st->step % ksub) != 0;
     const float kf = (float)ksub;
+    const float hk = 0.5f * kf, hk2 = hk * kf;   // D1 with the step K dt: K/2, K^2/2
     const uint32_t clk = clock_from(st->step, ksub, coll);   // the species' clock
     const int end = stands ? start : min(n, start + chunk);
 
@@ -439,10 +440,10 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                                     : eh[cc]);
             float vn, vold, abn = 0.0f, o1, mv;
             if (kImp) {
-                vold = v[k] - 0.5f * ab[k];
-                vn = v[k] + 0.5f * a;
+                vold = v[k] - hk * ab[k];
+                vn = v[k] + hk * a;
                 abn = 0.5f * (ab[k] + a);
-                mv = 0.5f * a;
+                mv = hk2 * a;
             } else {
                 vold = v[k];
                 vn = fmaf(kf, a, v[k]);   // kf = 1 but for subcycled ions
@@ -485,7 +486,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
             uint32_t lflag = 0u;   // list flag of a candidate
             if (live && !isc) {
                 if (kImp) {
-                    vst = nu ? predict_nu(c2, o2, vn, abn, rl, ul, N) : predict(c2, o2, vn, abn);
+                    vst = nu ? predict_nu(c2, o2, vn, abn, rl, ul, N, kf)
+                             : predict(c2, o2, vn, abn, kf);
                     if (periodic) {
                         c2 %= N;
                         if (c2 < 0) c2 += N;
@@ -522,8 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                     // k_collide.
                     int cp = c1;
                     float op = o1;
-                    const float vp =
-                        nu ? predict_nu(cp, op, vn, abn, rl, ul, N) : predict(cp, op, vn, abn);
+                    const float vp = nu ? predict_nu(cp, op, vn, abn, rl, ul, N, kf)
+                                        : predict(cp, op, vn, abn, kf);
                     if (periodic) {
                         cp %= N;
                         if (cp < 0) cp += N;
@@ -744,6 +746,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     // (k_collide runs only for species with trials; an ion species without a
     // process keeps its clock at 0)
     const uint32_t clk1 = clock_from(st->step, ksub, true) + 1u;
+    const float kf = (float)ksub;   // the species' D1 step in units of dt
+    // implicit: an ion child is predicted with the ions' step when the ions
+    // move in this step; otherwise it stands where it was created
+    const bool ions_move = C->ion_sub <= 1 || st->step % C->ion_sub == 0;
+    const float kfi = ions_move ? (float)C->ion_sub : 0.0f;
     const uint32_t clk_e = clock_from(st->step + 1, 1, true),
                    clk_i = clock_from(st->step + 1, C->ion_sub, C->sp[1].n_proc > 0);
     const int ns0 = st->n_slots[0], ns1 = st->n_slots[1];
@@ -782,11 +789,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
             if (kImp) {
                 if (nu) {
                     walk(ce, oe, ch.vx, rg, ug, N);
-                    walk(ci, oi, ch.ix, rg, ug, N);
+                    if (kfi > 0.0f) walk(ci, oi, kfi * ch.ix, rg, ug, N);
                 } else {
                     oe = o1 + ch.vx;
                     renorm(ce, oe);
-                    oi = o1 + ch.ix;
+                    oi = o1 + kfi * ch.ix;
                     renorm(ci, oi);
                 }
                 if (periodic) {
@@ -914,8 +921,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
             if (kImp && pred && kind < 0) {
                 // a null collision: the prediction k_step stored and
                 // deposited stands; only the waiting time is new
-                if (nu) predict_nu(c2, o2, vn, abn, rg, ug, N);
-                else predict(c2, o2, vn, abn);
+                if (nu) predict_nu(c2, o2, vn, abn, rg, ug, N, kf);
+                else predict(c2, o2, vn, abn, kf);
                 if (periodic) {
                     c2 %= N;
                     if (c2 < 0) c2 += N;
@@ -927,8 +934,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                     // prediction (integer words, so exactly)
                     int cp = c1;
                     float op = o1;
-                    if (nu) predict_nu(cp, op, vn0, abn, rg, ug, N);
-                    else predict(cp, op, vn0, abn);
+                    if (nu) predict_nu(cp, op, vn0, abn, rg, ug, N, kf);
+                    else predict(cp, op, vn0, abn, kf);
                     if (periodic) {
                         cp %= N;
                         if (cp < 0) cp += N;
@@ -940,8 +947,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                         gatomic_add(&gdep_w[cp], 0ull - (packw(op) & kWMask));
                     }
                 }
-                const float vst =
-                    nu ? predict_nu(c2, o2, vn, abn, rg, ug, N) : predict(c2, o2, vn, abn);
+                const float vst = nu ? predict_nu(c2, o2, vn, abn, rg, ug, N, kf)
+                                     : predict(c2, o2, vn, abn, kf);
                 bool gone = false;
                 if (periodic) {
                     c2 %= N;

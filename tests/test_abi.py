@@ -100,8 +100,8 @@ def test_init_rejects_bad_input_without_a_gpu():
         cfg[0].cell_dx_m = C.cast(arr, C.POINTER(C.c_double))
         assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     cfg[0].cell_dx_m = None
-    # ion subcycling: explicit only, 0 <= K <= 4096
-    for K, scheme in ((-1, 0), (4097, 0), (2, 1)):
+    # ion subcycling: 0 <= K <= 4096
+    for K, scheme in ((-1, 0), (4097, 0), (-1, 1)):
         cfg[0].ion_subcycle = K
         cfg[0].scheme = scheme
         assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL, K

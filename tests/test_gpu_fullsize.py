@@ -103,11 +103,12 @@ def test_ccp2048_full_size():
 
 
 @pytest.mark.parametrize("name", ["ccp2048_ec2_implicit", "ccp2048_nonuniform",
-                                  "ccp2048_nonuniform_ec2_implicit", "ccp2048_subcycle8"])
+                                  "ccp2048_nonuniform_ec2_implicit", "ccp2048_subcycle8",
+                                  "ccp2048_implicit_subcycle8"])
 def test_widened_workloads_full_size(name):
     # the benchmark's other 2048-cell discharges (m = 2 implicit, the
     # sheath-refined grid with EC explicit and with m = 2 implicit, ions
-    # subcycled at K = 8) at tile 16384, sort 64;
+    # subcycled at K = 8 with either scheme) at tile 16384, sort 64;
     # the subcycled one is sampled in a step where the ions stand (65) and in
     # one where they move (72)
     import bench
@@ -118,7 +119,7 @@ def test_widened_workloads_full_size(name):
     rep = sampled_step(ctx, wls, [0], 8192, seed=43)
     print(name, rep)
     check(rep)
-    if name == "ccp2048_subcycle8":
+    if name.endswith("subcycle8"):
         ctx.step(6)
         assert ctx.state()["step"] % 8 == 0
         rep = sampled_step(ctx, wls, [0], 8192, seed=44)

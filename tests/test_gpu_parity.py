@@ -179,12 +179,13 @@ def test_ccp64_nonuniform_teacher_forced(scheme, steps_per_period, gather):
     assert_report(rep)
 
 
-@pytest.mark.parametrize("K,step0", [(4, 0), (7, 5)])
-def test_ccp64_subcycled_ions_teacher_forced(K, step0):
+@pytest.mark.parametrize("K,step0,scheme", [(4, 0, 0), (7, 5, 0), (4, 0, 1), (7, 5, 1)])
+def test_ccp64_subcycled_ions_teacher_forced(K, step0, scheme):
     # ions pushed, absorbed and collided every K-th step with K dt; in
     # between their deposit stays on the grid (high pressure: ion
-    # collisions in most push steps)
-    wl = W.c1(collisions=1, np_per_species=16384 + 77)
+    # collisions in most push steps).  D1: the ions' susceptibility, with
+    # (K dt)^2, only in the solve before a push step
+    wl = W.c1(collisions=1, np_per_species=16384 + 77, scheme=scheme)
     wl["case"]["ion_subcycle"] = K
     wl["case"]["step0"] = step0
     wl["case"]["gas_density_m3"] = W.gas_density(500.0)

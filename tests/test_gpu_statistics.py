@@ -2,7 +2,8 @@
 
 Both start from the same 64-cell capacitive discharge (16k electrons and 16k
 ions, 50 mTorr, 100 V at 13.56 MHz; on a uniform and on a sheath-refined
-grid, with subcycled ions, and with the m = 2 implicit scheme) and run 10 RF
+grid, with subcycled ions under either scheme, and with the m = 2 implicit
+scheme) and run 10 RF
 periods on their own.
 Float32 particle state against float64 makes the two microstates drift apart
 (the motion is chaotic), so they are compared through statistics over the
@@ -26,7 +27,8 @@ PERIOD = 400          # steps per RF period at dt = 1/(400 f)
 TOL = 0.02
 
 
-@pytest.mark.parametrize("grid", ["uniform", "sheath_refined", "subcycle4", "ec2_implicit"])
+@pytest.mark.parametrize("grid", ["uniform", "sheath_refined", "subcycle4", "implicit_subcycle4",
+                                  "ec2_implicit"])
 def test_ccp64_ten_periods_statistics_match_oracle(grid):
     import paper_1310_5284_amd as P
     if grid == "sheath_refined":
@@ -35,8 +37,8 @@ def test_ccp64_ten_periods_statistics_match_oracle(grid):
                             volts=100.0, p_mtorr=50.0, seed=0xC1,
                             cell_dx=W.sheath_refined_widths(64, 0.025))
     else:
-        wl = W.c1(collisions=1, np_per_species=16384, scheme=1 if grid == "ec2_implicit" else 0)
-        if grid == "subcycle4":
+        wl = W.c1(collisions=1, np_per_species=16384, scheme=1 if "implicit" in grid else 0)
+        if grid.endswith("subcycle4"):
             wl["case"]["ion_subcycle"] = 4      # ions every 4th step with 4 dt
         if grid == "ec2_implicit":
             wl["case"]["gather"] = 2            # m = 2, D1 implicit

@@ -86,6 +86,24 @@ MUTANTS = [
      "double f = 1.0 / rc;", None),
     ("m=2 nonuniform field without the width ratio", "E[j] = F * dx / w[j];", "E[j] = F;", None),
     ("m=2 nonuniform diagonal of the reference width", "dg[j] = dx / w[j];", "dg[j] = 1.0;", None),
+    ("implicit subcycled ions' susceptibility with one power of K",
+     "return p->q * p->q * p->w / p->m * h * h;", "return p->q * p->q * p->w / p->m * h;", None),
+    ("subcycled ions' susceptibility in every solve",
+     "if (!(p->m > 0.0) || !moves(s, sp)) return 0.0;", "if (!(p->m > 0.0)) return 0.0;", None),
+    ("implicit subcycled ions corrected with dt",
+     "        double dt = s->c.dt_s * substep(s, k);\n        double qm = p->q / p->m;\n        int64_t i = 0;",
+     "        double dt = s->c.dt_s;\n        double qm = p->q / p->m;\n        int64_t i = 0;", None),
+    ("implicit subcycled ions corrected in every step",
+     "        if (!moves(s, k)) continue;\n        double dt = s->c.dt_s * substep(s, k);\n        double qm",
+     "        double dt = s->c.dt_s * substep(s, k);\n        double qm", None),
+    ("implicit subcycled ions predicted with dt",
+     "double dt = s->c.dt_s * substep(s, k), dt_dx = dt / s->dx;\n        int64_t i = 0;\n        while (i < p->n) {\n            double vt",
+     "double dt = s->c.dt_s, dt_dx = dt / s->dx;\n        int64_t i = 0;\n        while (i < p->n) {\n            double vt", None),
+    ("implicit start-up of subcycled ions with dt",
+     "double dt = s->c.dt_s * substep(s, k), dt_dx = dt / s->dx;\n        int64_t i = 0;\n        while (i < p->n) {\n            p->abar[i] = 0.0;",
+     "double dt = s->c.dt_s, dt_dx = dt / s->dx;\n        int64_t i = 0;\n        while (i < p->n) {\n            p->abar[i] = 0.0;", None),
+    ("standing ions' kinetic energy from their prediction",
+     "const int held = implicit && !moves(s, k);", "const int held = 0;", None),
     ("m=2 nonuniform D0 sign",
      "double D0e = (phi0 / dx - sv) / su;   /* from dx sum_j F_j = phi_0 - phi_N */",
      "double D0e = (phi0 / dx + sv) / su;", None),
@@ -133,7 +151,7 @@ MUTANTS = [
      "double vti = sqrt(KB_J * s->c.gas_temp_K / me->m);", None),
     ("anisotropic scattering", "double ct = 1.0 - 2.0 * ua;", "double ct = 1.0 - ua;", None),
     # ledger
-    ("K_before of the implicit state", "double vx = implicit ? p->vx[i] - 0.5 * s->c.dt_s * p->abar[i] : p->vx[i];",
+    ("K_before of the implicit state", "double vx = implicit ? p->vx[i] - 0.5 * hdt * p->abar[i] : p->vx[i];",
      "double vx = p->vx[i];", None),
     ("field energy doubled", "we += 0.5 * EPS0 * s->E[j] * s->E[j] * (s->cw ? s->cw[j] : s->dx);\n    s->led.WE",
      "we += EPS0 * s->E[j] * s->E[j] * (s->cw ? s->cw[j] : s->dx);\n    s->led.WE", None),
