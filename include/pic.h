@@ -111,7 +111,7 @@ typedef struct {
      * over the node's two cells, PIC_GATHER_EC2 gathers minus the physical
      * gradient of the quadratic deposit's field energy; with PIC_IMPLICIT_D1
      * it solves the tridiagonal susceptibility for F_j = (w_j N / gap_m) E_j
-     * and takes at most 3391 cells (the LDS of its moment words); other
+     * and takes at most 4069 cells (the LDS of its moment words); other
      * combinations: PIC_E_INVAL.
      * Positions stay logical
      * (cell index + offset); velocities are in units of (gap_m / N) / dt_s. */

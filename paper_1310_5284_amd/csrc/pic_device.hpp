@@ -212,18 +212,19 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 // (dual: the susceptibility words of the m = 2 implicit scheme follow dep,
 // on a nonuniform grid with the left-side sums of P0 and P2 after them;
 // nu: the width ratios r_c of a nonuniform grid, N floats, and the runs of
-// equal widths, N u32, follow those)
+// equal widths, N u32, follow those, unless the launch reads them from
+// global memory: tables = false)
 struct StepLds {
     size_t dep, dual, ratio, heat, eedf, total;
 };
 __host__ __device__ inline StepLds step_lds_layout(int N, bool diag, bool dual = false,
-                                                   bool nu = false)
+                                                   bool nu = false, bool tables = true)
 {
     StepLds L;
     L.dep = align16(4 * ((size_t)N + 1));
     L.dual = L.dep + align16(8 * ((size_t)N + 1));   // N+1: the quadratic node grid
     L.ratio = L.dual + (dual ? (nu ? 3 : 1) * align16(8 * ((size_t)N + 1)) : 0);
-    L.heat = L.ratio + (nu ? 2 * align16(4 * (size_t)N) : 0);
+    L.heat = L.ratio + (nu && tables ? 2 * align16(4 * (size_t)N) : 0);
     L.eedf = L.heat + (diag ? align16(4 * (size_t)N) : 0);
     L.total = L.eedf + (diag ? align16(4 * (size_t)kEedfBins) : 0);
     return L;

@@ -19,7 +19,7 @@
 #include "pic_device.hpp"
 
 namespace pic {
-template <int SCHEME, bool DIAG>
+template <int SCHEME, bool DIAG, bool GT>
 __global__ void k_step(Params P);
 template <int SCHEME, bool DIAG>
 __global__ void k_collide(Params P);
@@ -108,6 +108,7 @@ struct pic_ctx {
     int cgrp_off[2] = {0, 0}, cgrp_cnt[2] = {0, 0};
     CollideWork* d_cwork = nullptr;
     size_t grp_slds[2][2] = {{0, 0}, {0, 0}};   // k_step LDS of a group ([diag])
+    bool grp_gt[2] = {false, false};   // k_step reads the grid tables from global memory
     size_t grp_clds[2] = {0, 0};                // k_collide LDS of a group
     size_t dep_lds_max = 0;                     // k_deposit LDS over all cases
     bool any_dual = false;
@@ -225,9 +226,16 @@ size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Dynamic LDS of k_step: field[N+1] float | dep[N+1] u64 | (m = 2 implicit:
 // susceptibility words[N+1] u64) | (DIAG: heat[N] float | eedf[kEedfBins] u32).
-size_t step_lds(int N, bool diag, bool dual, bool nu)
+size_t step_lds(int N, bool diag, bool dual, bool nu, bool tables = true)
 {
-    return step_lds_layout(N, diag, dual, nu).total;
+    return step_lds_layout(N, diag, dual, nu, tables).total;
+}
+
+// A group with an m = 2 implicit case on a nonuniform grid launches the
+// k_step variant that reads the width ratios and runs from global memory.
+bool global_tables(bool dual, bool nu)
+{
+    return dual && nu;
 }
 
 size_t collide_lds(int N, bool dual, bool nu)
@@ -248,7 +256,8 @@ constexpr size_t kLdsMax = 160 * 1024;
 // the largest LDS any kernel of one case asks for
 size_t case_lds(int N, bool dual, bool nu)
 {
-    return std::max(std::max(step_lds(N, true, dual, nu), collide_lds(N, dual, nu)),
+    return std::max(std::max(step_lds(N, true, dual, nu, !global_tables(dual, nu)),
+                             collide_lds(N, dual, nu)),
                     deposit_lds(N, dual, nu));
 }
 
@@ -303,6 +312,13 @@ int build_work(pic_ctx* c)
         c->grp_off[g] = (int)c->work.size();
         c->grp_slds[g][0] = c->grp_slds[g][1] = 0;
         c->grp_clds[g] = 0;
+        c->grp_gt[g] = false;
+        for (int k = 0; k < c->n_cases; ++k) {
+            const HostCase& h = c->hc[k];
+            if (h.cfg.scheme == g)
+                c->grp_gt[g] = c->grp_gt[g] || global_tables(dual_chi(h.cfg.scheme, h.cfg.gather),
+                                                             !h.cell_w.empty());
+        }
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
@@ -319,7 +335,8 @@ int build_work(pic_ctx* c)
             const int Nk = h.cfg.n_cells;
             const bool dk = dual_chi(h.cfg.scheme, h.cfg.gather), nk = !h.cell_w.empty();
             for (int d = 0; d < 2; ++d)
-                c->grp_slds[g][d] = std::max(c->grp_slds[g][d], step_lds(Nk, d == 1, dk, nk));
+                c->grp_slds[g][d] =
+                    std::max(c->grp_slds[g][d], step_lds(Nk, d == 1, dk, nk, !c->grp_gt[g]));
             c->grp_clds[g] = std::max(c->grp_clds[g], collide_lds(Nk, dk, nk));
         }
         c->grp_cnt[g] = (int)c->work.size() - c->grp_off[g];
@@ -422,8 +439,9 @@ int set_lds_limits(pic_ctx* c, size_t need)
 {
     if (need <= 65536) return PIC_OK;
     const int v = (int)need;
-    const void* ks[] = {(const void*)k_step<0, false>, (const void*)k_step<0, true>,
-                        (const void*)k_step<1, false>, (const void*)k_step<1, true>,
+    const void* ks[] = {(const void*)k_step<0, false, false>, (const void*)k_step<0, true, false>,
+                        (const void*)k_step<1, false, false>, (const void*)k_step<1, true, false>,
+                        (const void*)k_step<1, false, true>, (const void*)k_step<1, true, true>,
                         (const void*)k_collide<0, false>, (const void*)k_collide<0, true>,
                         (const void*)k_collide<1, false>, (const void*)k_collide<1, true>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
@@ -492,7 +510,7 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             }
         }
         {
-            // (m = 2 implicit on a nonuniform grid: above 3391 cells)
+            // (m = 2 implicit on a nonuniform grid: above 4069 cells)
             const size_t need = case_lds(g.n_cells, dual_chi(g.scheme, g.gather),
                                          g.cell_dx_m != nullptr);
             if (need > kLdsMax) {
@@ -965,8 +983,9 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
         if (!c->grp_cnt[g]) continue;
         Params p = params(c, c->grp_off[g]);
         Params pc = params(c, c->cgrp_off[g]);
-        auto ks = g == 0 ? (diag ? k_step<0, true> : k_step<0, false>)
-                         : (diag ? k_step<1, true> : k_step<1, false>);
+        auto ks = g == 0 ? (diag ? k_step<0, true, false> : k_step<0, false, false>)
+                  : c->grp_gt[g] ? (diag ? k_step<1, true, true> : k_step<1, false, true>)
+                                 : (diag ? k_step<1, true, false> : k_step<1, false, false>);
         auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
                          : (diag ? k_collide<1, true> : k_collide<1, false>);
         for (int kind = 0; kind < 2; ++kind) {

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pic.h"
 #include "pic_common.hpp"
 #include "pic_device.hpp"
@@ -268,7 +270,11 @@ __device__ __forceinline__ void deposit_global(const Case* C, int s, int c, floa
 // packs count and summed weight), flushed over the cell range the workgroup
 // touched.  The workgroup's ledger partial is a row of plain stores.
 // ---------------------------------------------------------------------------
-template <int SCHEME, bool DIAG>
+// GT: the width ratios and runs of nonuniform grids are read from global
+// memory (cached) instead of LDS: the launch variant for batches with an
+// m = 2 implicit case on a nonuniform grid, whose four moment words per
+// node would otherwise leave one workgroup per CU.
+template <int SCHEME, bool DIAG, bool GT>
 __global__ __launch_bounds__(kBlock) void k_step(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const bool nu = C->nonuniform != 0;
     const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
-    const StepLds L = step_lds_layout(N, DIAG, dual, nu);
+    const StepLds L = step_lds_layout(N, DIAG, dual, nu, !GT);
     float* eh = (float*)smem;
     unsigned long long* dep = (unsigned long long*)(smem + L.dep);
     unsigned long long* dch = (unsigned long long*)(smem + L.dual);
@@ -313,8 +319,18 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
         duo ? (unsigned long long*)(smem + L.dual + align16(8 * ((size_t)N + 1))) : nullptr;
     unsigned long long* dl2 =
         duo ? (unsigned long long*)(smem + L.dual + 2 * align16(8 * ((size_t)N + 1))) : nullptr;
-    float* rl = (float*)(smem + L.ratio);   // nonuniform: dx / w_c
-    uint32_t* ul = (uint32_t*)(smem + L.ratio + align16(4 * (size_t)N));   // and the runs
+    // nonuniform: dx / w_c and the runs of equal widths
+    using RT = typename std::conditional<GT, const PIC_GLOBAL float*, float*>::type;
+    using UT = typename std::conditional<GT, const PIC_GLOBAL uint32_t*, uint32_t*>::type;
+    RT rl;
+    UT ul;
+    if constexpr (GT) {
+        rl = gp((const float*)C->cell_r);
+        ul = gp((const uint32_t*)C->cell_run);
+    } else {
+        rl = (float*)(smem + L.ratio);
+        ul = (uint32_t*)(smem + L.ratio + align16(4 * (size_t)N));
+    }
     float* heat = (float*)(smem + L.heat);
     unsigned* eedf = (unsigned*)(smem + L.eedf);
     {
@@ -352,12 +368,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
                 dl2[j] = 0ull;
             }
         }
-    if (nu) {
-        const PIC_GLOBAL float* rg = gp(C->cell_r);
-        const PIC_GLOBAL uint32_t* ug = gp(C->cell_run);
-        for (int j = tid; j < N; j += kBlock) {
-            rl[j] = rg[j];
-            ul[j] = ug[j];
+    if constexpr (!GT) {
+        if (nu) {
+            const PIC_GLOBAL float* rg = gp(C->cell_r);
+            const PIC_GLOBAL uint32_t* ug = gp(C->cell_run);
+            for (int j = tid; j < N; j += kBlock) {
+                rl[j] = rg[j];
+                ul[j] = ug[j];
+            }
         }
     }
     if (DIAG)
@@ -1099,10 +1117,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     }
 }
 
-template __global__ void k_step<0, false>(Params);
-template __global__ void k_step<0, true>(Params);
-template __global__ void k_step<1, false>(Params);
-template __global__ void k_step<1, true>(Params);
+template __global__ void k_step<0, false, false>(Params);
+template __global__ void k_step<0, true, false>(Params);
+template __global__ void k_step<1, false, false>(Params);
+template __global__ void k_step<1, true, false>(Params);
+template __global__ void k_step<1, false, true>(Params);
+template __global__ void k_step<1, true, true>(Params);
 template __global__ void k_collide<0, false>(Params);
 template __global__ void k_collide<0, true>(Params);
 template __global__ void k_collide<1, false>(Params);

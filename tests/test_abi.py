@@ -89,9 +89,9 @@ def test_init_rejects_bad_input_without_a_gpu():
     cfg[0].cell_dx_m = C.cast(good, C.POINTER(C.c_double))
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     cfg[0].bc = 0
-    # m = 2 implicit on a nonuniform grid: its LDS words fit up to 3391 cells
-    big = (C.c_double * 3392)(*([0.01 / 3392] * 3392))
-    cfg[0].n_cells, cfg[0].scheme, cfg[0].gather = 3392, 1, 2
+    # m = 2 implicit on a nonuniform grid: its LDS words fit up to 4069 cells
+    big = (C.c_double * 4070)(*([0.01 / 4070] * 4070))
+    cfg[0].n_cells, cfg[0].scheme, cfg[0].gather = 4070, 1, 2
     cfg[0].cell_dx_m = C.cast(big, C.POINTER(C.c_double))
     assert L.pic_init(C.byref(h), 1, cfg, sp, None, 0, None, 0) == P.PIC_E_INVAL
     cfg[0].n_cells, cfg[0].scheme, cfg[0].gather = 8, 0, 0

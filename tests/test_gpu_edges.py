@@ -108,10 +108,11 @@ def _variant(name, np_per_species=4096):
     # the 64-cell discharge as is, implicit, with ions subcycled (K = 3;
     # explicit or implicit), on a sheath-refined grid (implicit), or m = 2
     # implicit
-    if name == "nonuniform_implicit":
+    if name in ("nonuniform_implicit", "nonuniform_ec2_implicit"):
         return W.ccp_workload("ccp64_nonuniform", n_cells=64, np_per_species=np_per_species,
                               volts=100.0, p_mtorr=50.0, scheme=1, seed=0x65,
-                              cell_dx=W.sheath_refined_widths(64, 0.025))
+                              cell_dx=W.sheath_refined_widths(64, 0.025),
+                              gather=2 if "ec2" in name else 0)
     wl = W.c1(collisions=1, np_per_species=np_per_species,
               scheme=1 if "implicit" in name else 0)
     if "subcycle3" in name:
@@ -209,12 +210,14 @@ def test_graph_replay_equals_host_launches(timing_every):
 
 
 def test_graph_replay_with_every_grid_variant():
-    # one batch of subcycled (explicit and implicit), sheath-refined and
-    # m = 2 implicit cases:
+    # one batch of subcycled (explicit and implicit), sheath-refined (EC and
+    # m = 2 implicit; the implicit launch then reads every case's grid tables
+    # from global memory) and m = 2 implicit cases:
     # the subcycling phase is read on the device, so replays of a captured
     # sort period step exactly as host launches do
     wls = [_variant("subcycle3", 3000), _variant("nonuniform_implicit", 3000),
-           _variant("ec2_implicit", 3000), _variant("implicit_subcycle3", 3000)]
+           _variant("ec2_implicit", 3000), _variant("implicit_subcycle3", 3000),
+           _variant("nonuniform_ec2_implicit", 3000)]
     outs = []
     for graph in (0, 1):
         ctx = P().PicContext(wls)
