@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pic.h"
@@ -301,7 +302,7 @@ uint32_t candidate_threshold(double pnull)
 // k_collide rounds: candidates per thread aimed at, and the most rounds
 // (8 and 16 measured slower than 32 on a batch of high-pressure cases, where
 // most particles are candidates; lists of a few % of a tile take one round)
-constexpr double kCandPerThread = 32.0;
+constexpr double kCandPerThread = 64.0;
 constexpr int kMaxRounds = 32;
 
 int build_work(pic_ctx* c)
@@ -345,9 +346,13 @@ int build_work(pic_ctx* c)
     // k_collide: for every k_step workgroup that can list candidates, as
     // many workgroups (rounds) as its expected list needs at about
     // kCandPerThread candidates per thread; they add their collision terms
-    // to the ledger row of that k_step workgroup
+    // to the ledger row of that k_step workgroup.  The workgroups of a group
+    // are ordered by their expected candidates per thread, largest first, so
+    // that the long rounds of dense lists start first and the short ones
+    // fill in behind them.
     for (int g = 0; g < 2; ++g) {
         c->cgrp_off[g] = (int)c->cwork.size();
+        std::vector<std::pair<double, CollideWork>> order;
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
             if (h.cfg.scheme != g) continue;
@@ -359,10 +364,15 @@ int build_work(pic_ctx* c)
                 const double per_wg = (double)std::min<int64_t>(c->tile, h.cap[w.s]);
                 const int rounds = (int)std::min<double>(
                     kMaxRounds, std::max(1.0, std::ceil(p * per_wg / (kBlock * kCandPerThread))));
+                const double load = p * per_wg / (rounds * (double)kBlock);
                 for (int r = 0; r < rounds; ++r)
-                    c->cwork.push_back(CollideWork{b, r, rounds, 0});
+                    order.emplace_back(load, CollideWork{b, r, rounds, 0});
             }
         }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<double, CollideWork>& a,
+                            const std::pair<double, CollideWork>& b) { return a.first > b.first; });
+        for (const auto& e : order) c->cwork.push_back(e.second);
         c->cgrp_cnt[g] = (int)c->cwork.size() - c->cgrp_off[g];
     }
     return PIC_OK;

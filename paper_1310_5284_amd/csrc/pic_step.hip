@@ -260,7 +260,9 @@ __device__ __forceinline__ void deposit_global(const Case* C, int s, int c, floa
 // Per particle (implicit, D1, beta = 1/2; stored x~, v~, abar):
 //   a = ehat[cell of x~];  x = x~ + a/2;  v = v~ + a/2;  abar = (abar + a)/2;
 //   absorb; candidacy; non-candidates predict v~' = v + abar/2,
-//   x~' = x + v~', absorb and deposit x~'.
+//   x~' = x + v~', absorb and deposit x~'.  Subcycled ions move only in the
+//   steps n % K == 0, with K dt: x = x~ + K^2 a/2, v = v~ + K a/2,
+//   v~' = v + K abar/2, x~' = x + K v~'.
 //
 // The streaming loop issues the loads of kILP particles per thread together
 // (indices past the chunk are clamped to its last slot and treated as dead).

@@ -179,6 +179,20 @@ def test_ccp64_nonuniform_teacher_forced(scheme, steps_per_period, gather):
     assert_report(rep)
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_dense_candidate_lists_teacher_forced(scheme):
+    # one workgroup per species at tile 16384: at 50 mTorr over half of the
+    # electrons are candidates every step, so the first workgroup's list
+    # holds thousands of candidates (the k_collide workgroup of a dense list
+    # loops over many blocks); the 77-particle tail is a list of its own
+    wl = W.c1(collisions=1, np_per_species=16384 + 77, scheme=scheme)
+    ctx = ctx_for(wl, tile=16384)
+    rep = teacher_forced(ctx, wl, 30)
+    print(rep)
+    assert_report(rep)
+    assert ctx.ledger()["n_candidates"][0] >= 4096 + 77
+
+
 @pytest.mark.parametrize("K,step0,scheme", [(4, 0, 0), (7, 5, 0), (4, 0, 1), (7, 5, 1)])
 def test_ccp64_subcycled_ions_teacher_forced(K, step0, scheme):
     # ions pushed, absorbed and collided every K-th step with K dt; in
