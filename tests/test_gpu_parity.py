@@ -179,6 +179,23 @@ def test_ccp64_nonuniform_teacher_forced(scheme, steps_per_period, gather):
     assert_report(rep)
 
 
+@pytest.mark.parametrize("gather,nonuniform", [(1, False), (2, False), (0, True), (2, True)])
+def test_ccp64_subcycled_ions_implicit_gathers_teacher_forced(gather, nonuniform):
+    # D1 with ions every 4th step under the MC and m = 2 weightings and on the
+    # sheath-refined grid: the ions' node charges, moment words (m = 2) and
+    # left-side sums (m = 2, nonuniform) stand between their pushes, and
+    # their susceptibility enters only the solve before a push
+    kw = dict(cell_dx=W.sheath_refined_widths(64, 0.025)) if nonuniform else {}
+    wl = W.ccp_workload("ccp64_sub_d1", n_cells=64, np_per_species=16384 + 77, volts=100.0,
+                        p_mtorr=500.0, scheme=1, collisions=1, seed=0x5D1 + gather,
+                        gather=gather, **kw)
+    wl["case"]["ion_subcycle"] = 4
+    ctx = ctx_for(wl)
+    rep = teacher_forced(ctx, wl, 14)
+    print(rep)
+    assert_report(rep)
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_dense_candidate_lists_teacher_forced(scheme):
     # one workgroup per species at tile 16384: at 50 mTorr over half of the
