@@ -20,9 +20,9 @@
 #include "pic_device.hpp"
 
 namespace pic {
-template <int SCHEME, bool DIAG, bool GT>
+template <int SCHEME, bool DIAG, bool GT, bool DUAL, bool PLAIN>
 __global__ void k_step(Params P);
-template <int SCHEME, bool DIAG>
+template <int SCHEME, bool DIAG, bool DUAL, bool PLAIN>
 __global__ void k_collide(Params P);
 __global__ void k_init_species(Params P, double vscale0, double vscale1);
 __global__ void k_compact_hist(Params P, uint32_t* hist_all, const int64_t* hist_off);
@@ -110,6 +110,8 @@ struct pic_ctx {
     CollideWork* d_cwork = nullptr;
     size_t grp_slds[2][2] = {{0, 0}, {0, 0}};   // k_step LDS of a group ([diag])
     bool grp_gt[2] = {false, false};   // k_step reads the grid tables from global memory
+    bool grp_dual[2] = {false, false};   // a case of the group has the m = 2 moment words
+    bool grp_plain[2] = {true, true};    // every case of the group: EC gather, uniform grid
     size_t grp_clds[2] = {0, 0};                // k_collide LDS of a group
     size_t dep_lds_max = 0;                     // k_deposit LDS over all cases
     bool any_dual = false;
@@ -314,11 +316,15 @@ int build_work(pic_ctx* c)
         c->grp_slds[g][0] = c->grp_slds[g][1] = 0;
         c->grp_clds[g] = 0;
         c->grp_gt[g] = false;
+        c->grp_dual[g] = false;
+        c->grp_plain[g] = true;
         for (int k = 0; k < c->n_cases; ++k) {
             const HostCase& h = c->hc[k];
-            if (h.cfg.scheme == g)
-                c->grp_gt[g] = c->grp_gt[g] || global_tables(dual_chi(h.cfg.scheme, h.cfg.gather),
-                                                             !h.cell_w.empty());
+            if (h.cfg.scheme != g) continue;
+            const bool dk = dual_chi(h.cfg.scheme, h.cfg.gather);
+            c->grp_gt[g] = c->grp_gt[g] || global_tables(dk, !h.cell_w.empty());
+            c->grp_dual[g] = c->grp_dual[g] || dk;
+            c->grp_plain[g] = c->grp_plain[g] && h.cfg.gather == PIC_GATHER_EC && h.cell_w.empty();
         }
         for (int k = 0; k < c->n_cases; ++k) {
             HostCase& h = c->hc[k];
@@ -445,15 +451,54 @@ int compaction(pic_ctx* c)
 }
 
 // Dynamic LDS above the default 64 KiB needs an explicit opt-in per kernel.
+// The k_step variant of a scheme group (see k_step: PLAIN, DUAL, GT).
+using StepKernel = void (*)(Params);
+StepKernel step_kernel(int g, bool diag, bool gt, bool dual, bool plain)
+{
+    if (g == 0) {
+        if (plain) return diag ? k_step<0, true, false, false, true> : k_step<0, false, false, false, true>;
+        return diag ? k_step<0, true, false, false, false> : k_step<0, false, false, false, false>;
+    }
+    if (gt) return diag ? k_step<1, true, true, true, false> : k_step<1, false, true, true, false>;
+    if (dual) return diag ? k_step<1, true, false, true, false> : k_step<1, false, false, true, false>;
+    if (plain) return diag ? k_step<1, true, false, false, true> : k_step<1, false, false, false, true>;
+    return diag ? k_step<1, true, false, false, false> : k_step<1, false, false, false, false>;
+}
+
+// The k_collide variant of a scheme group.
+StepKernel collide_kernel(int g, bool diag, bool dual, bool plain)
+{
+    // (the explicit kernel reaches no grid- or weighting-specific code)
+    if (g == 0) return diag ? k_collide<0, true, false, false> : k_collide<0, false, false, false>;
+    if (dual) return diag ? k_collide<1, true, true, false> : k_collide<1, false, true, false>;
+    if (plain) return diag ? k_collide<1, true, false, true> : k_collide<1, false, false, true>;
+    return diag ? k_collide<1, true, false, false> : k_collide<1, false, false, false>;
+}
+
 int set_lds_limits(pic_ctx* c, size_t need)
 {
     if (need <= 65536) return PIC_OK;
     const int v = (int)need;
-    const void* ks[] = {(const void*)k_step<0, false, false>, (const void*)k_step<0, true, false>,
-                        (const void*)k_step<1, false, false>, (const void*)k_step<1, true, false>,
-                        (const void*)k_step<1, false, true>, (const void*)k_step<1, true, true>,
-                        (const void*)k_collide<0, false>, (const void*)k_collide<0, true>,
-                        (const void*)k_collide<1, false>, (const void*)k_collide<1, true>,
+    const void* ks[] = {(const void*)k_step<0, false, false, false, true>,
+                        (const void*)k_step<0, true, false, false, true>,
+                        (const void*)k_step<0, false, false, false, false>,
+                        (const void*)k_step<0, true, false, false, false>,
+                        (const void*)k_step<1, false, false, false, true>,
+                        (const void*)k_step<1, true, false, false, true>,
+                        (const void*)k_step<1, false, false, false, false>,
+                        (const void*)k_step<1, true, false, false, false>,
+                        (const void*)k_step<1, false, false, true, false>,
+                        (const void*)k_step<1, true, false, true, false>,
+                        (const void*)k_step<1, false, true, true, false>,
+                        (const void*)k_step<1, true, true, true, false>,
+                        (const void*)k_collide<0, false, false, false>,
+                        (const void*)k_collide<0, true, false, false>,
+                        (const void*)k_collide<1, false, false, true>,
+                        (const void*)k_collide<1, true, false, true>,
+                        (const void*)k_collide<1, false, false, false>,
+                        (const void*)k_collide<1, true, false, false>,
+                        (const void*)k_collide<1, false, true, false>,
+                        (const void*)k_collide<1, true, true, false>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
                         (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve,
                         (const void*)k_finalize<false>, (const void*)k_finalize<true>};
@@ -993,11 +1038,8 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
         if (!c->grp_cnt[g]) continue;
         Params p = params(c, c->grp_off[g]);
         Params pc = params(c, c->cgrp_off[g]);
-        auto ks = g == 0 ? (diag ? k_step<0, true, false> : k_step<0, false, false>)
-                  : c->grp_gt[g] ? (diag ? k_step<1, true, true> : k_step<1, false, true>)
-                                 : (diag ? k_step<1, true, false> : k_step<1, false, false>);
-        auto kc = g == 0 ? (diag ? k_collide<0, true> : k_collide<0, false>)
-                         : (diag ? k_collide<1, true> : k_collide<1, false>);
+        auto ks = step_kernel(g, diag, c->grp_gt[g], c->grp_dual[g], c->grp_plain[g]);
+        auto kc = collide_kernel(g, diag, c->grp_dual[g], c->grp_plain[g]);
         for (int kind = 0; kind < 2; ++kind) {
             if (kind == 1 && !c->cgrp_cnt[g]) continue;
             const bool rec = pool && pool->used + 2 <= (int)pool->ev.size();

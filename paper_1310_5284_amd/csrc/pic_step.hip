@@ -272,11 +272,15 @@ __device__ __forceinline__ void deposit_global(const Case* C, int s, int c, floa
 // packs count and summed weight), flushed over the cell range the workgroup
 // touched.  The workgroup's ledger partial is a row of plain stores.
 // ---------------------------------------------------------------------------
-// GT: the width ratios and runs of nonuniform grids are read from global
-// memory (cached) instead of LDS: the launch variant for batches with an
-// m = 2 implicit case on a nonuniform grid, whose four moment words per
-// node would otherwise leave one workgroup per CU.
-template <int SCHEME, bool DIAG, bool GT>
+// Launch variants by what the cases of a batch need, so that no kernel
+// carries code its cases cannot reach (a shorter kernel measured faster):
+// PLAIN: every case has the EC gather (m = 1) on a uniform grid.  DUAL: the
+// moment words of m = 2 implicit are compiled in.  GT: the width ratios and
+// runs of nonuniform grids are read from global memory (cached) instead of
+// LDS: the variant for batches with an m = 2 implicit case on a nonuniform
+// grid, whose four moment words per node would otherwise leave one
+// workgroup per CU.
+template <int SCHEME, bool DIAG, bool GT, bool DUAL, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_step(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -305,10 +309,11 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
     const float eedf_k = C->sp[s].eps_unit * C->sp[s].eedf_scale;
     const double kin_unit = C->sp[s].kin_unit;
     const bool periodic = C->bc == 1;
-    const bool mc = C->gather == 1;
-    const bool ec2 = C->gather == 2;
-    const bool dual = kImp && ec2;   // susceptibility words of its own
-    const bool nu = C->nonuniform != 0;
+    const bool mc = !PLAIN && C->gather == 1;
+    // (an implicit m = 2 case is launched only in the DUAL variant)
+    const bool ec2 = !PLAIN && C->gather == 2 && (!kImp || DUAL);
+    const bool dual = DUAL && kImp && ec2;   // susceptibility words of its own
+    const bool nu = !PLAIN && C->nonuniform != 0;
     const bool coll = C->collisions != 0 && C->sp[s].n_proc > 0;
 
     const StepLds L = step_lds_layout(N, DIAG, dual, nu, !GT);
@@ -676,7 +681,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Params P)
 // terms of the ledger are added to the row of the k_step workgroup.
 // ---------------------------------------------------------------------------
 // (at most 128 VGPRs: 4 wavefronts per SIMD; it fits without spilling)
-template <int SCHEME, bool DIAG>
+// DUAL, PLAIN: the launch variants of k_step.
+template <int SCHEME, bool DIAG, bool DUAL, bool PLAIN>
 __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
 {
     const CollideWork cw = P.cwork[P.mode + (int)blockIdx.x];
@@ -714,9 +720,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     for (int t = tid; t < (int)(sizeof(Species) / 4); t += kBlock)
         ((uint32_t*)&S)[t] = ((const uint32_t*)&C->sp[s])[t];
     const bool periodic = C->bc == 1;
-    const bool ec2 = C->gather == 2;
+    // (an implicit m = 2 case is launched only in the DUAL variant)
+    const bool ec2 = !PLAIN && C->gather == 2 && (!kImp || DUAL);
     const bool dual = kImp && ec2;   // susceptibility words of its own
-    const bool nu = C->nonuniform != 0;
+    const bool nu = !PLAIN && C->nonuniform != 0;
     const PIC_GLOBAL float* rg = gp(uniform_ptr((const float*)C->cell_r));   // nu: dx / w_c
     const PIC_GLOBAL uint32_t* ug = gp(uniform_ptr((const uint32_t*)C->cell_run));   // and runs
     const uint32_t k0 = C->key0, k1 = C->key1;
@@ -1119,15 +1126,25 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     }
 }
 
-template __global__ void k_step<0, false, false>(Params);
-template __global__ void k_step<0, true, false>(Params);
-template __global__ void k_step<1, false, false>(Params);
-template __global__ void k_step<1, true, false>(Params);
-template __global__ void k_step<1, false, true>(Params);
-template __global__ void k_step<1, true, true>(Params);
-template __global__ void k_collide<0, false>(Params);
-template __global__ void k_collide<0, true>(Params);
-template __global__ void k_collide<1, false>(Params);
-template __global__ void k_collide<1, true>(Params);
+template __global__ void k_step<0, false, false, false, true>(Params);
+template __global__ void k_step<0, true, false, false, true>(Params);
+template __global__ void k_step<0, false, false, false, false>(Params);
+template __global__ void k_step<0, true, false, false, false>(Params);
+template __global__ void k_step<1, false, false, false, true>(Params);
+template __global__ void k_step<1, true, false, false, true>(Params);
+template __global__ void k_step<1, false, false, false, false>(Params);
+template __global__ void k_step<1, true, false, false, false>(Params);
+template __global__ void k_step<1, false, false, true, false>(Params);
+template __global__ void k_step<1, true, false, true, false>(Params);
+template __global__ void k_step<1, false, true, true, false>(Params);
+template __global__ void k_step<1, true, true, true, false>(Params);
+template __global__ void k_collide<0, false, false, false>(Params);
+template __global__ void k_collide<0, true, false, false>(Params);
+template __global__ void k_collide<1, false, false, true>(Params);
+template __global__ void k_collide<1, true, false, true>(Params);
+template __global__ void k_collide<1, false, false, false>(Params);
+template __global__ void k_collide<1, true, false, false>(Params);
+template __global__ void k_collide<1, false, true, false>(Params);
+template __global__ void k_collide<1, true, true, false>(Params);
 
 }  // namespace pic
