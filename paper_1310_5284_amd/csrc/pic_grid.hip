@@ -324,8 +324,9 @@ __device__ __forceinline__ void tridiag_field(const Case& Cc, State* st, long lo
 
 // kDual: the code of the implicit m = 2 moment words is compiled in (the
 // launches of batches without such a case leave it out: its registers would
-// make the rest spill).
-template <int NT, bool kDual>
+// make the rest spill).  kPlain: every case has the EC gather (m = 1) on a
+// uniform grid (no MC, m = 2 or nonuniform code).
+template <int NT, bool kDual, bool kPlain = false>
 __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_step,
                                            long long field_step, bool sample_density, double* S,
                                            double* red)
@@ -343,7 +344,7 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // a half cell at an electrode node, averaged to the cells)
     double* X = S + N + 1;
     double* Y = X + N;
-    const bool node_chi = implicit && Cc.gather == 1;
+    const bool node_chi = !kPlain && implicit && Cc.gather == 1;
     // node g = tid + k NT needs the counts and weights of cells g and g-1
     const PIC_GLOBAL unsigned long long* dc[2] = {gp((const unsigned long long*)Cc.dep_cnt[0]),
                                                   gp((const unsigned long long*)Cc.dep_cnt[1])};
@@ -362,9 +363,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const bool ions_move = Cc.ion_sub <= 1 || field_step % Cc.ion_sub == 0;
     const double chi0 = Cc.sp[0].chi_coef, chi1 = ions_move ? Cc.sp[1].chi_coef : 0.0;
     const double rho_bg = Cc.background_rho;
-    const bool ec2 = Cc.gather == 2;   // quadratic deposit: node words
+    const bool ec2 = !kPlain && Cc.gather == 2;   // quadratic deposit: node words
     const bool dual = kDual && implicit && ec2;   // moment words (deposit_moments)
-    const bool nu = Cc.nonuniform != 0;
+    const bool nu = !kPlain && Cc.nonuniform != 0;
     const PIC_GLOBAL double* wjr = gp((const double*)Cc.cell_wr);   // nu: w_j / dx
     // m = 2 implicit: the second moment words (counts of the particles left
     // of their nearest node, sums of their weights to the node after it)
@@ -835,7 +836,7 @@ __device__ __forceinline__ void finish_ledger(Case* C, State* st, const double* 
 // workgroup partials), the even one solves the FP64 field of the next step.
 // They write disjoint fields of the case state (flags through atomics).
 // ---------------------------------------------------------------------------
-template <bool kDual>
+template <bool kDual, bool kPlain>
 __global__ __launch_bounds__(kFinStep) void k_finalize(Params P, int sample)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -853,15 +854,16 @@ __global__ __launch_bounds__(kFinStep) void k_finalize(Params P, int sample)
     // field of the next step (every thread reads st->step; thread 0 writes it
     // after the solve's last barrier)
     const long long next = *(volatile long long*)&st->step + 1;
-    solve_case<kFinStep, kDual>(C, st, next + (C->scheme == 1 ? 1 : 0), next, sample != 0,
-                                 (double*)smem, red);
+    solve_case<kFinStep, kDual, kPlain>(C, st, next + (C->scheme == 1 ? 1 : 0), next,
+                                        sample != 0, (double*)smem, red);
     if (threadIdx.x == 0) {
         if (sample) st->eedf_samples += 1;
         st->step = next;
     }
 }
-template __global__ void k_finalize<false>(Params, int);
-template __global__ void k_finalize<true>(Params, int);
+template __global__ void k_finalize<false, true>(Params, int);
+template __global__ void k_finalize<false, false>(Params, int);
+template __global__ void k_finalize<true, false>(Params, int);
 
 // ---------------------------------------------------------------------------
 // Set-up: velocities from m/s to cells/step (unless given in internal

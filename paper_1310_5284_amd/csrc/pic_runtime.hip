@@ -32,7 +32,7 @@ __global__ void k_compact_scatter(Params P, uint32_t* cursor_all, const int64_t*
 __global__ void k_compact_finish(Params P);
 __global__ void k_deposit(Params P);
 __global__ void k_solve(Params P);
-template <bool kDual>
+template <bool kDual, bool kPlain>
 __global__ void k_finalize(Params P, int sample);
 }  // namespace pic
 
@@ -501,7 +501,9 @@ int set_lds_limits(pic_ctx* c, size_t need)
                         (const void*)k_collide<1, true, true, false>,
                         (const void*)k_compact_scatter, (const void*)k_compact_hist,
                         (const void*)k_compact_scan, (const void*)k_deposit, (const void*)k_solve,
-                        (const void*)k_finalize<false>, (const void*)k_finalize<true>};
+                        (const void*)k_finalize<false, true>,
+                        (const void*)k_finalize<false, false>,
+                        (const void*)k_finalize<true, false>};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v);
         if (e != hipSuccess) {
@@ -1057,7 +1059,10 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             }
         }
     }
-    hipLaunchKernelGGL(c->any_dual ? k_finalize<true> : k_finalize<false>, dim3(2 * c->n_cases),
+    void (*kfin)(Params, int) = c->any_dual ? k_finalize<true, false>
+                                : (c->grp_plain[0] && c->grp_plain[1]) ? k_finalize<false, true>
+                                                                      : k_finalize<false, false>;
+    hipLaunchKernelGGL(kfin, dim3(2 * c->n_cases),
                        dim3(kFinStep), fin_lds(c->maxN),
                        c->stream, params(c, 0), diag ? 1 : 0);
     HIPCHK(c, hipGetLastError());
