@@ -48,6 +48,16 @@ def make_workload(name, scale):
     import workloads as W
     if name == "ccp2048_explicit":
         return [W.c4(np_per_species=int(10_000_000 * scale))]
+    if name == "ccp2048_mc":
+        # the same discharge with the momentum-conserving gather (scheme (1))
+        wl = W.c4(np_per_species=int(10_000_000 * scale))
+        wl["case"]["gather"] = 1
+        return [wl]
+    if name == "ccp2048_mc_implicit":
+        # the D1 implicit discharge with the momentum-conserving gather
+        wl = W.c4(np_per_species=int(10_000_000 * scale), scheme=1)
+        wl["case"]["gather"] = 1
+        return [wl]
     if name == "ccp2048_ec2":
         # the same discharge with m = 2 weighting (quadratic deposit)
         wl = W.c4(np_per_species=int(10_000_000 * scale))

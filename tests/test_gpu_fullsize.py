@@ -102,13 +102,14 @@ def test_ccp2048_full_size():
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["ccp2048_ec2_implicit", "ccp2048_nonuniform",
-                                  "ccp2048_nonuniform_ec2_implicit", "ccp2048_subcycle8",
-                                  "ccp2048_implicit_subcycle8"])
+@pytest.mark.parametrize("name", ["ccp2048_mc", "ccp2048_mc_implicit", "ccp2048_ec2_implicit",
+                                  "ccp2048_nonuniform", "ccp2048_nonuniform_ec2_implicit",
+                                  "ccp2048_subcycle8", "ccp2048_implicit_subcycle8"])
 def test_widened_workloads_full_size(name):
-    # the benchmark's other 2048-cell discharges (m = 2 implicit, the
-    # sheath-refined grid with EC explicit and with m = 2 implicit, ions
-    # subcycled at K = 8 with either scheme) at tile 16384, sort 64;
+    # the benchmark's other 2048-cell discharges (the MC gather with either
+    # scheme, m = 2 implicit, the sheath-refined grid with EC explicit and
+    # with m = 2 implicit, ions subcycled at K = 8 with either scheme) at
+    # tile 16384, sort 64;
     # the subcycled one is sampled in a step where the ions stand (65) and in
     # one where they move (72)
     import bench
