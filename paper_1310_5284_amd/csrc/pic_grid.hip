@@ -353,7 +353,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // Nodes in batches of kB per thread; inside a batch every load is issued
     // before any result is used (unconditional loads from clamped indices,
     // selected afterwards, so that none waits behind a branch).
-    constexpr int kB = kDual ? 1 : 3;   // (3 with the moment path would spill)
+    // (5 covers 2048 cells at NT = 512 in one batch; more than 1 with the
+    // moment path would spill)
+    constexpr int kB = kDual ? 1 : 5;
     const double qs0 = Cc.sp[0].qw_dx / kFixScale, qs1 = Cc.sp[1].qw_dx / kFixScale;
     // subcycled ions keep their deposit until the step in which they move
     // (and deposit again); they respond only to the field they are
@@ -413,7 +415,9 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
                 double chi = implicit ? chi0 * (double)c0 + chi1 * (double)c1 : 0.0;
                 if (nu) chi /= wjr[g];
                 X[g] = chi;
-                gp(Cc.chi)[g] = chi;
+                // an explicit case's chi stays zero, as allocated (a case
+                // keeps its scheme)
+                if (implicit) gp(Cc.chi)[g] = chi;
             }
         }
     };
@@ -621,18 +625,31 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     // by shuffles, wavefronts through LDS.
     constexpr int kWv = NT / 64;
     const int lane = tid & 63, wave = tid >> 6;
-    const int Kr = (N + NT - 1) / NT;   // cells per thread (<= kPer)
+    const int Kr = (N + NT - 1) / NT;   // cells per thread (<= kPer, uniform)
     const int j0 = tid * Kr;
-    double rs = 0.0, bs = 0.0, ts = 0.0;   // this thread's run
-#pragma unroll 1
+    // the thread's cells, read once and kept for the second pass: every
+    // read of a cell is issued before the first is used
+    double sj[kPer], kap[kPer], cj[kPer], omj[kPer];
+#pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int j = j0 + k;
-        if (k < Kr && j < N) {
-            const double om = nu ? wjr[j] : 1.0;
-            const double c = om / (kEps0 * (1.0 + X[j]));
-            rs += S[j];
-            bs += c;
-            ts += rs * c;
+        if (k < Kr) {
+            const int j = min(j0 + k, N - 1);
+            sj[k] = S[j];
+            kap[k] = X[j];
+            omj[k] = nu ? wjr[j] : 1.0;
+        }
+    }
+    double rs = 0.0, bs = 0.0, ts = 0.0;   // this thread's run
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (k < Kr) {
+            kap[k] = kEps0 * (1.0 + kap[k]);
+            cj[k] = omj[k] / kap[k];
+            if (j0 + k < N) {
+                rs += sj[k];
+                bs += cj[k];
+                ts += rs * cj[k];
+            }
         }
     }
     // inclusive scan over the lanes of the wavefront
@@ -683,26 +700,37 @@ __device__ __forceinline__ void solve_case(Case* C, State* st, long long next_st
     const double D0 = (V / dx - tt) / bt;
     const double phi0 = periodic ? 0.0 : V;
     if (tid == 0) gp(Cc.phi)[0] = phi0;
+    // E_j and phi_{j+1} of the thread's cells are staged in LDS over S and X
+    // (every read of those precedes the last barrier) and stored by
+    // consecutive threads: one line per 16 lanes instead of one per 4
+    double* Es = S;
+    double* Ps = X;
     double we = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int j = j0 + k;
         if (k < Kr && j < N) {
-            const double om = nu ? wjr[j] : 1.0;
-            const double kap = kEps0 * (1.0 + X[j]);
-            const double c = om / kap;
-            R += S[j];
-            B += c;
-            T += R * c;
-            const double E = (D0 + R) / kap;
+            R += sj[k];
+            B += cj[k];
+            T += R * cj[k];
+            const double E = (D0 + R) / kap[k];
+            Es[j] = E;
+            Ps[j] = phi0 - dx * (D0 * B + T);
+            we += 0.5 * kEps0 * E * E * dx * omj[k];
+        }
+    }
+    we = block_sum<double, NT>(we, red);   // its barriers publish Es and Ps
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * NT;
+        if (j < N) {
+            const double E = Es[j];
             gp(Cc.E)[j] = E;
             gp(Cc.ehat[0])[j] = (float)(Cc.sp[0].accel * E);
             gp(Cc.ehat[1])[j] = (float)(Cc.sp[1].accel * E);
-            gp(Cc.phi)[j + 1] = phi0 - dx * (D0 * B + T);
-            we += 0.5 * kEps0 * E * E * dx * om;
+            gp(Cc.phi)[j + 1] = Ps[j];
         }
     }
-    we = block_sum<double, NT>(we, red);
     if (tid == 0) {
         st->WE[field_step & 1] = we;
         if (!isfinite(we)) atomicOr(&st->flags, 1);
@@ -851,9 +879,12 @@ __global__ __launch_bounds__(kFinStep) void k_finalize(Params P, int sample)
         finish_ledger(C, st, sd, si);
         return;
     }
-    // field of the next step (every thread reads st->step; thread 0 writes it
-    // after the solve's last barrier)
-    const long long next = *(volatile long long*)&st->step + 1;
+    // field of the next step (every thread reads st->step once; thread 0
+    // writes it after the solve's last barrier).  A relaxed atomic load is
+    // read exactly once without the wait a volatile load carries, so it
+    // travels with the case's own loads.
+    const long long next =
+        __hip_atomic_load(&st->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
     solve_case<kFinStep, kDual, kPlain>(C, st, next + (C->scheme == 1 ? 1 : 0), next,
                                         sample != 0, (double*)smem, red);
     if (threadIdx.x == 0) {
