@@ -869,13 +869,53 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
         }
     };
 
-    // the rounds of a list take its blocks of kBlock candidates in turn
-    // (loading several candidates per thread ahead of their processing
-    // measured slower: the loads are scattered, not latency-bound)
-    for (int e0 = cw.round * kBlock; e0 < ncand; e0 += cw.rounds * kBlock) {
+    // the rounds of a list take its blocks of kBlock candidates in turn, so
+    // a thread's candidates follow at a stride of rounds * kBlock.  A dense
+    // list gives a thread many of them: the next one's list entries and
+    // record, and the slot of the one after, are loaded while the current
+    // one is processed (one candidate ahead: more ahead measured slower on
+    // sparse lists, where a thread has one candidate and the registers cost
+    // occupancy)
+    struct Pay {
+        u32x4 r;   // the 16-byte record: id, vy, vz
+        float vn, ab, o;
+        int32_t w;
+    };
+    auto load_pay = [&](int e, int i) {
+        Pay p;
+        const uint32_t q4 = (uint32_t)(region + e) << 2;
+        p.vn = ldg(cq_vn, q4);
+        p.ab = kImp ? ldg(cq_ab, q4) : 0.0f;
+        // the list carries x_{n+1}
+        p.w = ldg(cq_w, q4);
+        p.o = kImp ? ldg(cq_o, q4) : 0.0f;
+        // a candidate's record is one scattered 16-byte read: loaded with
+        // the non-temporal policy, which on gfx950 moves about half the
+        // bytes of a cached line fill for such reads
+        p.r = ldg_nt((const PIC_GLOBAL u32x4*)recp, (uint32_t)i << 4);
+        return p;
+    };
+    const int estep = cw.rounds * kBlock;
+    int i_nx = 0, i_nx2 = 0;
+    Pay p_nx{};
+    {
+        const int ef = cw.round * kBlock + tid;
+        if (ef < ncand) {
+            i_nx = ldg(cq_idx, (uint32_t)(region + ef) << 2);
+            p_nx = load_pay(ef, i_nx);
+        }
+        if (ef + estep < ncand) i_nx2 = ldg(cq_idx, (uint32_t)(region + ef + estep) << 2);
+    }
+    for (int e0 = cw.round * kBlock; e0 < ncand; e0 += estep) {
         const int e = e0 + tid;
         const bool act = e < ncand;
-        int i = 0, c1 = 0;
+        const Pay pc = p_nx;
+        int i = i_nx, c1 = 0;
+        if (e + estep < ncand) {
+            i_nx = i_nx2;
+            p_nx = load_pay(e + estep, i_nx);
+        }
+        if (e + 2 * estep < ncand) i_nx2 = ldg(cq_idx, (uint32_t)(region + e + 2 * estep) << 2);
         float o1 = 0.0f, vn = 0.0f, vn0 = 0.0f, abn = 0.0f, vy = 0.0f, vz = 0.0f;
         uint64_t id = 0;
         bool pred = false;  // implicit: k_step deposited the null prediction
@@ -883,18 +923,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
         int kind = -1;
         Child ch;
         if (act) {
-            const uint32_t q4 = (uint32_t)(region + e) << 2;
-            i = ldg(cq_idx, q4);
-            vn = ldg(cq_vn, q4);
-            if (kImp) abn = ldg(cq_ab, q4);
+            vn = pc.vn;
+            if (kImp) abn = pc.ab;
             const uint32_t i4 = (uint32_t)i << 2;
-            // the list carries x_{n+1}; one 16-byte record holds id, vy, vz
-            const int32_t w1 = ldg(cq_w, q4);
-            if (kImp) o1 = ldg(cq_o, q4);
-            // a candidate's record is one scattered 16-byte read: loaded with
-            // the non-temporal policy, which on gfx950 moves about half the
-            // bytes of a cached line fill for such reads
-            const u32x4 r = ldg_nt((const PIC_GLOBAL u32x4*)recp, i4 << 2);
+            const int32_t w1 = pc.w;
+            if (kImp) o1 = pc.o;
+            const u32x4 r = pc.r;
             id = rec_id(r);
             vy = rec_vy(r);
             vz = rec_vz(r);
