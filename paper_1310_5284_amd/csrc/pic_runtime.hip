@@ -88,6 +88,11 @@ struct PeriodGraph {
 struct pic_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // a batch holding both schemes runs the implicit group's kernels on a
+    // second stream, forked after the previous step and joined before the
+    // finalizer (the groups touch disjoint cases)
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool failed = false;
     std::string err;
     int n_cases = 0;
@@ -617,6 +622,10 @@ extern "C" int pic_init(pic_ctx** out, int32_t n_cases, const pic_case_config* c
             return bail(fail(c, PIC_E_DEVICE, "stream"));
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(c, PIC_E_DEVICE, "second stream"));
     (void)hipGetLastError();   // start from a clean error state
     if (resolve_fixed_scratch(c)) return bail(PIC_E_DEVICE);
     // ---- per case ----
@@ -996,6 +1005,9 @@ void destroy_ctx(pic_ctx* c)
     drop_graph(c);
     for (hipEvent_t e : c->ev.ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->graph.ev.ev) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1030,14 +1042,25 @@ int reserve_events(pic_ctx* c, EventPool& pool, int pairs)
 // particle pass and the collision kernel, then the finalizer of every case;
 // the compaction follows when the sort period ends.  With `pool`, HIP events
 // bracket the particle and collision kernels (as event nodes under capture).
+// A batch with both schemes runs the implicit group on the second stream
+// (not while events bracket the kernels, under capture or in the call that
+// allocates nothing), so that the tails of the two groups overlap.
 int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
 {
     auto record = [&](hipEvent_t e) {
         return capturing ? hipEventRecordWithFlags(e, c->stream, hipEventRecordExternal)
                          : hipEventRecord(e, c->stream);
     };
-    for (int g = 0; g < 2; ++g) {
+    const bool split = c->grp_cnt[0] && c->grp_cnt[1] && !pool && !capturing && !c->use_fixed;
+    if (split) {
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    }
+    for (int gi = 0; gi < 2; ++gi) {
+        // the implicit group first, so that it starts on its stream first
+        const int g = split ? 1 - gi : gi;
         if (!c->grp_cnt[g]) continue;
+        hipStream_t sg = split && g == 1 ? c->stream2 : c->stream;
         Params p = params(c, c->grp_off[g]);
         Params pc = params(c, c->cgrp_off[g]);
         auto ks = step_kernel(g, diag, c->grp_gt[g], c->grp_dual[g], c->grp_plain[g]);
@@ -1048,17 +1071,19 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
             if (rec) HIPCHK(c, record(pool->ev[pool->used]));
             if (kind == 0)
                 hipLaunchKernelGGL(ks, dim3(c->grp_cnt[g]), dim3(kBlock),
-                                   c->grp_slds[g][diag ? 1 : 0], c->stream, p);
+                                   c->grp_slds[g][diag ? 1 : 0], sg, p);
             else
                 hipLaunchKernelGGL(kc, dim3(c->cgrp_cnt[g]), dim3(kBlock),
-                                   c->grp_clds[g], c->stream, pc);
+                                   c->grp_clds[g], sg, pc);
             if (rec) {
                 HIPCHK(c, record(pool->ev[pool->used + 1]));
                 pool->used += 2;
                 pool->kind.push_back(kind);
             }
         }
+        if (split && g == 1) HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
     }
+    if (split) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     void (*kfin)(Params, int) = c->any_dual ? k_finalize<true, false>
                                 : (c->grp_plain[0] && c->grp_plain[1]) ? k_finalize<false, true>
                                                                       : k_finalize<false, false>;
