@@ -258,7 +258,11 @@ typedef struct pic_ctx pic_ctx;
 /* Creates a context holding n_cases discharges.  species points to
  * 2*n_cases entries: [case][0 = electrons, 1 = ions].  hip_stream is a
  * hipStream_t that every launch goes to (NULL = a non-blocking stream that
- * the context creates and destroys).  Validation: N range, dt > 0,
+ * the context creates and destroys); a batch holding both schemes also runs
+ * the implicit cases' particle kernels on a second stream of the context's
+ * own, which waits on hip_stream at the start of each step and which
+ * hip_stream waits on before the step's field solve, so that work on
+ * hip_stream stays ordered with every step.  Validation: N range, dt > 0,
  * positions in range, ids present, tables consistent, capacity >= n, and for
  * explicit cases omega_p,max dt < 2 (Eq. (1)) unless PIC_FLAG_ALLOW_UNSTABLE.
  * On error *out is NULL and nothing is leaked. */

@@ -162,6 +162,7 @@ struct CollideWork {
     int32_t round;
     int32_t rounds;
     int32_t pad;
+    Work w;   // the k_step workgroup's own entry (read with this one, not after it)
 };
 
 // Ledger partial sums of one workgroup, stored field-major: field f of

@@ -377,7 +377,7 @@ int build_work(pic_ctx* c)
                     kMaxRounds, std::max(1.0, std::ceil(p * per_wg / (kBlock * kCandPerThread))));
                 const double load = p * per_wg / (rounds * (double)kBlock);
                 for (int r = 0; r < rounds; ++r)
-                    order.emplace_back(load, CollideWork{b, r, rounds, 0});
+                    order.emplace_back(load, CollideWork{b, r, rounds, 0, w});
             }
         }
         std::stable_sort(order.begin(), order.end(),

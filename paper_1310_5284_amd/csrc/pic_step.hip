@@ -687,8 +687,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
 {
     const CollideWork cw = P.cwork[P.mode + (int)blockIdx.x];
     const int gblk = cw.step_blk;
+    // the list's length is checked after the case's loads have been issued
+    // beside its load
     const int ncand = P.cand_n[gblk];
-    if (cw.round * kBlock >= ncand) return;   // nothing in this round
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockAcc acc;
     __shared__ Species S;
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     __shared__ int q_n;
     constexpr bool kImp = SCHEME == 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const Work w = P.work[gblk];
+    const Work w = cw.w;
     Case* C = P.cases + w.c;
     State* st = P.state + w.c;
     const int N = C->n_cells;
@@ -765,6 +766,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
         acc.cmax = -1;
         q_n = 0;
     }
+    if (cw.round * kBlock >= ncand) return;   // nothing in this round
     lds_barrier();
 
     const uint32_t step32 = (uint32_t)st->step;
