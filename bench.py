@@ -287,15 +287,25 @@ def batch_record(P, steps=256, seq_steps=64):
     species, explicit and implicit mixed) stepped by one context, against the
     same cases stepped one context after another (the sequential per-case
     baseline).  Both at tile 16384 and sort period 128, timed over whole sort
-    periods after a warm-up; returns the sub-record of the JSON line."""
+    periods after a warm-up; the batch with the collision kernel's store
+    policy that the autotuner picks for it (the sequential contexts keep the
+    default); returns the sub-record of the JSON line."""
     wls = make_workload("sweep64", 1.0)
     schemes = [int(w["case"]["scheme"]) for w in wls]
 
-    def run(ctx_wls, n, warm):
+    policy = [None]
+
+    def run(ctx_wls, n, warm, tune=False):
         ctx = P.PicContext(ctx_wls)
         ctx.set_schedule(sort_every=1, diag_every=0, tile=16384)
         ctx.set_launch(graph=0, timing_every=0)
         ctx.step(warm)
+        if tune:
+            # one tile and one period: the trials that count are the store policies
+            _, _, ms = ctx.autotune(tiles=[16384], sorts=[128], steps_per_trial=128)
+            policy[0] = dict(chosen=("cached", "nontemporal")[int(ms[3] < ms[2])],
+                             ms_per_step={"cached": round(ms[2], 4),
+                                          "nontemporal": round(ms[3], 4)})
         ctx.set_schedule(sort_every=128 if n % 128 == 0 else n, diag_every=0, tile=16384)
         live = lambda: [sum(ctx.counts(k)["n"]) for k in range(len(ctx_wls))]
         a = live()
@@ -309,7 +319,7 @@ def batch_record(P, steps=256, seq_steps=64):
         return [0.5 * (x + y) for x, y in zip(a, b)], t
 
     log("[bench] batch: 64 cases in one context")
-    per, t = run(wls, steps, 64)
+    per, t = run(wls, steps, 64, tune=True)
     value = sum(per) * steps / t
     stream = sum((48.0 if schemes[k] else 40.0) * per[k] for k in range(len(wls))) / sum(per)
     log("[bench] batch: the same cases one context after another")
@@ -321,6 +331,7 @@ def batch_record(P, steps=256, seq_steps=64):
     seq = seq_ps / seq_t
     return dict(workload="sweep64", cases=len(wls), particles=int(sum(per)),
                 implicit_cases=int(sum(schemes)), tile=16384, sort_every=128, steps=steps,
+                store_policy=policy[0],
                 ms_per_step=t * 1e3 / steps, value=value, unit="particle-steps/s",
                 step_equivalent=dict(bytes_per_particle_step=round(stream, 2),
                                      GBps=round(value * stream / 1e9, 1),
@@ -504,10 +515,15 @@ def main():
         # the autotuner's trials are real steps before the warm-up
         tile, sort_every, ms = ctx.autotune(steps_per_trial=args.autotune)
         tiles, sorts = (1024, 2048, 4096, 8192, 16384, 32512), (16, 32, 64, 128)
+        policy = int(ms[11] < ms[10])
         tuned = dict(steps_per_trial=args.autotune,
                      tile_ms_per_step={str(t): round(m, 4) for t, m in zip(tiles, ms[:6])},
-                     sort_ms_per_step={str(t): round(m, 4) for t, m in zip(sorts, ms[6:])})
-        log(f"[bench] autotune: tile {tile}, sort every {sort_every}")
+                     sort_ms_per_step={str(t): round(m, 4) for t, m in zip(sorts, ms[6:10])},
+                     store_policy_ms_per_step={"cached": round(ms[10], 4),
+                                               "nontemporal": round(ms[11], 4)},
+                     store_policy=("cached", "nontemporal")[policy])
+        log(f"[bench] autotune: tile {tile}, sort every {sort_every}, "
+            f"{tuned['store_policy']} collision stores")
     schemes = [int(w["case"]["scheme"]) for w in wls]
     implicit = all(sc == 1 for sc in schemes)
     groups = len(set(schemes))          # one k_step and one k_collide launch per group

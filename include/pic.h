@@ -323,17 +323,26 @@ int pic_set_schedule(pic_ctx* ctx, int32_t sort_every, int32_t diag_every, int32
  *   and count of the timed launches.
  * Errors: PIC_E_INVAL (bad values), PIC_E_STATE (failed context). */
 int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every);
+/* Store policy of the collision kernel for a candidate's new state (cell
+ * word, velocity, record; implicit: offset and abar): 0 = the default cache
+ * policy (lines stay cached for the next step's particle pass), 1 =
+ * non-temporal stores (they do not evict what that pass reads).  Results are
+ * identical; only the speed differs with the workload.  Default 0.
+ * Errors: PIC_E_INVAL (not 0 or 1), PIC_E_STATE (failed context). */
+int pic_set_store_policy(pic_ctx* ctx, int32_t nontemporal);
 /* Autotuner of the launch schedule.  Runs real steps of the context (they
  * advance every case exactly as pic_step does, diagnostics cadence
  * included): first `steps_per_trial` steps at each tile of
  * tiles[0..n_tiles) at the current sort period, then whole sort periods
  * (at least steps_per_trial steps, from a period boundary) at each period of
- * sorts[0..n_sorts) with the fastest tile.  Each trial is timed by two HIP
- * events around its launches on the context's stream and follows two
- * untimed steps at the new tile.  The fastest tile and period are applied
- * (pic_set_schedule) and returned in tile_out / sort_out (may be NULL).
- * ms_out (NULL or n_tiles + n_sorts entries, resp. of the defaults) receives
- * the device milliseconds per step of every trial.
+ * sorts[0..n_sorts) with the fastest tile, then whole periods at the fastest
+ * tile and period with store policy 0 and 1 (pic_set_store_policy).  Each
+ * trial is timed by two HIP events around its launches on the context's
+ * stream and follows two untimed steps at the new tile.  The fastest tile,
+ * period and store policy are applied and the tile and period returned in
+ * tile_out / sort_out (may be NULL).  ms_out (NULL or n_tiles + n_sorts + 2
+ * entries, resp. of the defaults) receives the device milliseconds per step
+ * of every trial, the two store policies last.
  * tiles == NULL: {1024, 2048, 4096, 8192, 16384, 32512}; sorts == NULL:
  * {16, 32, 64, 128} (the counts are then ignored).  Tiles must be positive
  * multiples of 256 up to 32512, periods positive.

@@ -119,6 +119,7 @@ def lib():
         L.pic_diagnostics.argtypes = [_P, C.c_int32, C.c_uint32, C.POINTER(Diag)]
         L.pic_set_schedule.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
         L.pic_set_launch.argtypes = [_P, C.c_int32, C.c_int32]
+        L.pic_set_store_policy.argtypes = [_P, C.c_int32]
         L.pic_autotune.argtypes = [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                    C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _D]
@@ -209,13 +210,18 @@ def pic_set_launch(h, graph, timing_every):
     _ok(h, lib().pic_set_launch(h, int(graph), int(timing_every)), "pic_set_launch")
 
 
+def pic_set_store_policy(h, nontemporal):
+    _ok(h, lib().pic_set_store_policy(h, int(nontemporal)), "pic_set_store_policy")
+
+
 def pic_autotune(h, tiles=None, sorts=None, steps_per_trial=32):
-    """Returns (tile, sort_every, device ms per step of each trial)."""
+    """Returns (tile, sort_every, device ms per step of each trial; the
+    last two are the store policies 0 and 1)."""
     def arr(v):
         return (None, 0) if v is None else ((C.c_int32 * len(v))(*v), len(v))
     t, nt = arr(tiles)
     so, ns = arr(sorts)
-    n_ms = (nt if tiles is not None else 6) + (ns if sorts is not None else 4)
+    n_ms = (nt if tiles is not None else 6) + (ns if sorts is not None else 4) + 2
     ms = (C.c_double * n_ms)()
     tile, sort = C.c_int32(0), C.c_int32(0)
     _ok(h, lib().pic_autotune(h, t, nt, so, ns, int(steps_per_trial), C.byref(tile),
@@ -386,9 +392,15 @@ class PicContext:
         (graph=1); HIP-event timing of every timing_every-th step."""
         pic_set_launch(self._h, graph, timing_every)
 
+    def set_store_policy(self, nontemporal):
+        """Store policy of the collision kernel: 0 cached (default), 1
+        non-temporal; results are identical."""
+        pic_set_store_policy(self._h, nontemporal)
+
     def autotune(self, tiles=None, sorts=None, steps_per_trial=32):
-        """Pick the fastest tile and sort period by timing real steps;
-        returns (tile, sort_every, ms per step of each trial)."""
+        """Pick the fastest tile, sort period and store policy by timing real
+        steps; returns (tile, sort_every, ms per step of each trial, the two
+        store policies last)."""
         return pic_autotune(self._h, tiles, sorts, steps_per_trial)
 
     def reset_accumulators(self):

@@ -197,6 +197,7 @@ struct Params {
     int32_t mode;        // kernel-specific
     int32_t* cand_n;     // candidates listed by each workgroup of the work table
     const CollideWork* cwork;   // k_collide work table
+    int32_t nt_store;    // k_collide stores a candidate's new state non-temporally
 };
 
 constexpr int kBoundBins = 256;   // bins of the null-collision bound table

@@ -93,6 +93,7 @@ struct pic_ctx {
     // finalizer (the groups touch disjoint cases)
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool nt_store = false;   // store policy of k_collide (pic_set_store_policy)
     bool failed = false;
     std::string err;
     int n_cases = 0;
@@ -433,6 +434,7 @@ Params params(pic_ctx* c, int mode)
     p.mode = mode;
     p.cand_n = c->use_fixed ? c->fx_cand_n : c->d_cand_n;
     p.cwork = c->d_cwork;
+    p.nt_store = c->nt_store ? 1 : 0;
 
     return p;
 }
@@ -1345,6 +1347,16 @@ extern "C" int pic_set_launch(pic_ctx* ctx, int32_t graph, int32_t timing_every)
     return PIC_OK;
 }
 
+extern "C" int pic_set_store_policy(pic_ctx* ctx, int32_t nontemporal)
+{
+    if (!ctx) return PIC_E_INVAL;
+    if (ctx->failed) return fail(ctx, PIC_E_STATE, ctx->err);
+    if (nontemporal != 0 && nontemporal != 1) return fail(ctx, PIC_E_INVAL, "bad store policy");
+    if (ctx->nt_store != (nontemporal == 1)) drop_graph(ctx);   // captured launches hold the old one
+    ctx->nt_store = nontemporal == 1;
+    return PIC_OK;
+}
+
 namespace {
 
 // Device milliseconds per step of `steps` real steps at the current schedule,
@@ -1429,10 +1441,30 @@ extern "C" int pic_autotune(pic_ctx* ctx, const int32_t* tiles, int32_t n_tiles,
             }
         }
     }
+    // the store policy of the collision kernel at the best tile and period
+    bool best_nt = ctx->nt_store;
+    if (rc == PIC_OK) rc = pic_set_schedule(ctx, best_sort, diag, best_tile);
+    best = 1e300;
+    for (int j = 0; j < 2 && rc == PIC_OK; ++j) {
+        double t = 0.0;
+        rc = pic_set_store_policy(ctx, j);
+        if (rc != PIC_OK) break;
+        const int64_t to_boundary = (best_sort - ctx->since_sort % best_sort) % best_sort;
+        const int64_t periods = (steps_per_trial + best_sort - 1) / best_sort;
+        rc = timed_trial(ctx, (int)to_boundary, periods * best_sort, ev, &t);
+        if (rc == PIC_OK) {
+            if (ms_out) ms_out[n_tiles + n_sorts + j] = t;
+            if (t < best) {
+                best = t;
+                best_nt = j == 1;
+            }
+        }
+    }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (rc != PIC_OK) return rc;
     rc = pic_set_schedule(ctx, best_sort, diag, best_tile);
+    if (rc == PIC_OK) rc = pic_set_store_policy(ctx, best_nt ? 1 : 0);
     if (rc != PIC_OK) return rc;
     if (tile_out) *tile_out = best_tile;
     if (sort_out) *sort_out = best_sort;

@@ -788,6 +788,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
     chunk = (chunk + 63) & ~63;
     const int region = w.b * chunk;   // the candidate list of this workgroup
     const float eedf_k = S.eps_unit * S.eedf_scale;
+    // stores of a candidate's new state, with the context's store policy:
+    // the default one leaves the lines in the caches for the next step's
+    // pass, the non-temporal one keeps them from evicting what that pass
+    // reads; which is faster depends on the workload (the autotuner measures)
+    const bool nts = P.nt_store != 0;
+    auto put = [&](auto* base, uint32_t off, auto v) {
+        if (nts) stg_nt(base, off, v);
+        else stg(base, off, v);
+    };
 
     double cdk = 0.0;
     unsigned cand = 0u;
@@ -967,7 +976,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                 u32x2 yz;
                 yz.x = __float_as_uint(vy);
                 yz.y = __float_as_uint(vz);
-                stg((PIC_GLOBAL u32x2*)recp, (i4 << 2) + 8u, yz);
+                put((PIC_GLOBAL u32x2*)recp, (i4 << 2) + 8u, yz);
             }
             if (DIAG && s == 0) {
                 const float fb = (vn * vn + vy * vy + vz * vz) * eedf_k;
@@ -990,7 +999,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                     c2 %= N;
                     if (c2 < 0) c2 += N;
                 }
-                stg(cellp, i4, pack_cell(c2, nw));
+                put(cellp, i4, pack_cell(c2, nw));
             } else if (kImp) {
                 if (pred) {
                     // a real collision: undo k_step's deposit of the null
@@ -1021,15 +1030,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_collide(Params P)
                     gone = true;
                 }
                 if (!gone) {
-                    stg(cellp, i4, pack_cell(c2, nw));
-                    stg(offp, i4, o2);
-                    stg(vxp, i4, vst);
-                    stg(abp, i4, abn);
+                    put(cellp, i4, pack_cell(c2, nw));
+                    put(offp, i4, o2);
+                    put(vxp, i4, vst);
+                    put(abp, i4, abn);
                     dep_ok = true;
                 }
             } else {
-                if (kind >= 0) stg(vxp, i4, vn);   // the pass stored v_{n+1/2}
-                stg(cellp, i4, pack_cell(c1, nw));
+                if (kind >= 0) put(vxp, i4, vn);   // the pass stored v_{n+1/2}
+                put(cellp, i4, pack_cell(c1, nw));
             }
         }
         if (kImp) {

@@ -235,6 +235,39 @@ def test_graph_replay_with_every_grid_variant():
             assert np.array_equal(f1[k], f2[k]), k
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_store_policies_step_identically(graph):
+    # the collision kernel's store policy changes only the cache behaviour:
+    # a mixed batch (both schemes, collisions, ionization) steps to the same
+    # state and fields with either, also when the policy changes between
+    # calls (a captured graph holds the policy it was captured with)
+    wls = [W.c1(collisions=1, np_per_species=6144, scheme=0),
+           W.c1(collisions=1, np_per_species=4096, scheme=1)]
+    outs = []
+    for pol in ((0, 0, 0), (1, 1, 1), (1, 0, 1)):
+        ctx = P().PicContext(wls)
+        ctx.set_schedule(sort_every=7, diag_every=0, tile=1024)
+        ctx.set_launch(graph=graph, timing_every=0)
+        for p, n in zip(pol, (9, 23, 12)):
+            ctx.set_store_policy(p)
+            ctx.step(n)
+        outs.append([(sorted_state(ctx, k), ctx.fields(k)) for k in range(2)])
+        ctx.close()
+    for other in outs[1:]:
+        for (s1, f1), (s2, f2) in zip(outs[0], other):
+            for a, b in zip(s1, s2):
+                for k in a:
+                    assert np.array_equal(a[k], b[k]), k
+            for k in ("rho", "phi", "E"):
+                assert np.array_equal(f1[k], f2[k]), k
+    ctx = P().PicContext(wls[:1])
+    for bad in (-1, 2):
+        with pytest.raises(P().PicError) as ei:
+            ctx.set_store_policy(bad)
+        assert ei.value.code == P().PIC_E_INVAL
+    ctx.close()
+
+
 def test_launch_mode_rejects_bad_values():
     ctx = ctx_for(W.c1(collisions=0, np_per_species=1024))
     for g, t in ((2, 1), (-1, 1), (0, -1)):
@@ -249,9 +282,9 @@ def test_autotune_picks_a_candidate_and_steps_like_pic_step():
     ctx.step(3)
     tile, sort, ms = ctx.autotune(tiles=[256, 1024, 4096], sorts=[5, 16], steps_per_trial=6)
     assert tile in (256, 1024, 4096) and sort in (5, 16)
-    assert len(ms) == 5 and all(m > 0.0 for m in ms)
+    assert len(ms) == 7 and all(m > 0.0 for m in ms)
     assert ms[[256, 1024, 4096].index(tile)] == min(ms[:3])
-    assert ms[3 + [5, 16].index(sort)] == min(ms[3:])
+    assert ms[3 + [5, 16].index(sort)] == min(ms[3:5])   # then the two store policies
     ctx.step(4)
     n = ctx.state()["step"] - wl["case"].get("step0", 0)
     # the same number of plain steps at another schedule gives the same state
