@@ -260,9 +260,10 @@ typedef struct pic_ctx pic_ctx;
  * hipStream_t that every launch goes to (NULL = a non-blocking stream that
  * the context creates and destroys); a batch holding both schemes also runs
  * the implicit cases' particle kernels on a second stream of the context's
- * own, which waits on hip_stream at the start of each step and which
- * hip_stream waits on before the step's field solve, so that work on
- * hip_stream stays ordered with every step.  Validation: N range, dt > 0,
+ * own, together with the field solve of those cases; it waits on
+ * hip_stream before its first step after a join, and hip_stream waits on it
+ * before every compaction and graph replay and at the end of every step
+ * call, so that work on hip_stream stays ordered with every call.  Validation: N range, dt > 0,
  * positions in range, ids present, tables consistent, capacity >= n, and for
  * explicit cases omega_p,max dt < 2 (Eq. (1)) unless PIC_FLAG_ALLOW_UNSTABLE.
  * On error *out is NULL and nothing is leaked. */

@@ -873,6 +873,8 @@ __global__ __launch_bounds__(kFinStep) void k_finalize(Params P, int sample)
     __shared__ long long si[PU_N];
     Case* C = P.cases + (blockIdx.x >> 1);
     State* st = P.state + (blockIdx.x >> 1);
+    // a launch for one scheme group (mode = its scheme; -1 = every case)
+    if (P.mode >= 0 && C->scheme != P.mode) return;
     if (blockIdx.x & 1) {
         // ledger of the step just taken
         reduce_partials<kFinStep>(P.pd, P.pu, P.stride, C->first_block, C->n_blocks, sd, si);

@@ -88,11 +88,13 @@ struct PeriodGraph {
 struct pic_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // a batch holding both schemes runs the implicit group's kernels on a
-    // second stream, forked after the previous step and joined before the
-    // finalizer (the groups touch disjoint cases)
+    // a batch holding both schemes runs the implicit group's kernels, and
+    // the finalizer of its cases, on a second stream (the groups touch
+    // disjoint cases); the streams are joined before a compaction, a step
+    // on one stream, a graph replay and the end of a call
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool forked = false;   // stream2 has work that the context's stream has not joined
     bool nt_store = false;   // store policy of k_collide (pic_set_store_policy)
     bool failed = false;
     std::string err;
@@ -1044,9 +1046,25 @@ int reserve_events(pic_ctx* c, EventPool& pool, int pairs)
 // particle pass and the collision kernel, then the finalizer of every case;
 // the compaction follows when the sort period ends.  With `pool`, HIP events
 // bracket the particle and collision kernels (as event nodes under capture).
-// A batch with both schemes runs the implicit group on the second stream
-// (not while events bracket the kernels, under capture or in the call that
-// allocates nothing), so that the tails of the two groups overlap.
+// A batch with both schemes runs the implicit group, with the finalizer of
+// its cases, on the second stream (not while events bracket the kernels,
+// under capture or in the call that allocates nothing), so that the two
+// groups overlap and need no join in every step.
+int join_streams(pic_ctx* c)
+{
+    if (!c->forked) return PIC_OK;
+    HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    c->forked = false;
+    return PIC_OK;
+}
+
+using FinKernel = void (*)(Params, int);
+FinKernel fin_kernel(bool dual, bool plain)
+{
+    return dual ? k_finalize<true, false> : plain ? k_finalize<false, true> : k_finalize<false, false>;
+}
+
 int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
 {
     auto record = [&](hipEvent_t e) {
@@ -1054,9 +1072,11 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
                          : hipEventRecord(e, c->stream);
     };
     const bool split = c->grp_cnt[0] && c->grp_cnt[1] && !pool && !capturing && !c->use_fixed;
-    if (split) {
+    if (!split && join_streams(c)) return PIC_E_DEVICE;
+    if (split && !c->forked) {
         HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+        c->forked = true;
     }
     for (int gi = 0; gi < 2; ++gi) {
         // the implicit group first, so that it starts on its stream first
@@ -1083,18 +1103,21 @@ int enqueue_step(pic_ctx* c, bool diag, EventPool* pool, bool capturing)
                 pool->kind.push_back(kind);
             }
         }
-        if (split && g == 1) HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
+        // split: the finalizer of the group's cases (the workgroups of the
+        // other group's cases return at once)
+        if (split)
+            hipLaunchKernelGGL(fin_kernel(c->grp_dual[g], c->grp_plain[g]), dim3(2 * c->n_cases),
+                               dim3(kFinStep), fin_lds(c->maxN), sg, params(c, g), diag ? 1 : 0);
     }
-    if (split) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    void (*kfin)(Params, int) = c->any_dual ? k_finalize<true, false>
-                                : (c->grp_plain[0] && c->grp_plain[1]) ? k_finalize<false, true>
-                                                                      : k_finalize<false, false>;
-    hipLaunchKernelGGL(kfin, dim3(2 * c->n_cases),
-                       dim3(kFinStep), fin_lds(c->maxN),
-                       c->stream, params(c, 0), diag ? 1 : 0);
+    if (!split)
+        hipLaunchKernelGGL(fin_kernel(c->any_dual, c->grp_plain[0] && c->grp_plain[1]),
+                           dim3(2 * c->n_cases), dim3(kFinStep), fin_lds(c->maxN), c->stream,
+                           params(c, -1), diag ? 1 : 0);
     HIPCHK(c, hipGetLastError());
-    if (++c->since_sort >= c->sort_every)
+    if (++c->since_sort >= c->sort_every) {
+        if (join_streams(c)) return PIC_E_DEVICE;
         if (compaction(c)) return PIC_E_DEVICE;
+    }
     return PIC_OK;
 }
 
@@ -1181,6 +1204,7 @@ int run_steps(pic_ctx* c, int64_t n, int which, hipEvent_t* bracket = nullptr)
     if (bracket) HIPCHK(c, hipEventRecord(bracket[0], c->stream));
     for (int64_t it = 0; it < n;) {
         if (graphs && c->since_sort == 0 && n - it >= c->sort_every) {
+            if (join_streams(c)) return PIC_E_DEVICE;
             if (c->graph.period != c->sort_every || !c->graph.exec)
                 if (capture_period(c)) return PIC_E_DEVICE;
             HIPCHK(c, hipGraphLaunch(c->graph.exec, c->stream));
@@ -1196,6 +1220,7 @@ int run_steps(pic_ctx* c, int64_t n, int which, hipEvent_t* bracket = nullptr)
         c->steps_taken++;
         ++it;
     }
+    if (join_streams(c)) return PIC_E_DEVICE;
     if (bracket) HIPCHK(c, hipEventRecord(bracket[1], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double ms[2] = {0.0, 0.0};
